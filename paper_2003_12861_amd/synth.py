@@ -1,0 +1,211 @@
+"""Seeded synthetic inputs for the likelihood workloads.
+
+This module only draws random numbers: it holds no likelihood, normalisation
+or gradient arithmetic, and it is the one module that the GPU path and the
+oracle both consume.  Every sampler is exact for the model it names and uses
+``numpy.random.default_rng(seed)`` (PCG64), so a seed fixes every value.
+
+Data precision: values are drawn in FP64, rounded once to FP32 (round to
+nearest even), and only then checked against the observable range (and the
+ARGUS endpoint); draws that fail are replaced.  The returned FP64 arrays hold
+FP32-representable values, so the FP32 and FP64 paths and the oracle all see
+bit-identical events.
+"""
+import math
+
+import numpy as np
+
+
+def _fill(n, seed, draw):
+    """Collect n accepted FP32-representable draws from draw(rng, m)."""
+    rng = np.random.default_rng(seed)
+    parts, have = [], 0
+    while have < n:
+        m = max(1024, int(1.15 * (n - have)) + 64)
+        got = draw(rng, m)
+        parts.append(got)
+        have += len(got if not isinstance(got, tuple) else got[0])
+    if isinstance(parts[0], tuple):
+        return tuple(np.concatenate([p[k] for p in parts])[:n] for k in range(len(parts[0])))
+    return np.concatenate(parts)[:n]
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def _inside(a, lo, hi):
+    return (a >= lo) & (a <= hi)
+
+
+# --------------------------------------------------------------------------
+# 1-D: fraction f of a Gaussian, 1-f of an order-2 Chebyshev polynomial
+# --------------------------------------------------------------------------
+GAUSS_CHEB_TRUTH = dict(mu=0.0, sigma=1.0, f=0.3, c1=0.2, c2=-0.1)
+GAUSS_CHEB_RANGE = (-10.0, 10.0)
+
+
+def sample_gauss_cheb(n, seed, mu=0.0, sigma=1.0, f=0.3, c1=0.2, c2=-0.1,
+                      lo=-10.0, hi=10.0):
+    """Component by Bernoulli(f); Gaussian by rejection of N(mu, sigma)
+    outside [lo, hi]; polynomial 1 + c1 T1 + c2 T2 by accept-reject against
+    its maximum over [-1, 1] (mapped linearly onto [lo, hi])."""
+    # maximum of the polynomial on [-1,1]: at an end point or the vertex
+    cand = [-1.0, 1.0]
+    if c2 != 0.0:
+        v = -c1 / (4.0 * c2)
+        if -1.0 <= v <= 1.0:
+            cand.append(v)
+    hmax = max(1.0 + c1 * t + c2 * (2 * t * t - 1) for t in cand)
+
+    def draw(rng, m):
+        pick = rng.random(m) < f
+        g = rng.normal(mu, sigma, m)
+        t = rng.uniform(-1.0, 1.0, m)
+        acc = rng.random(m) * hmax <= 1.0 + c1 * t + c2 * (2 * t * t - 1)
+        c = 0.5 * (hi - lo) * t + 0.5 * (hi + lo)
+        x = _f32(np.where(pick, g, c))
+        keep = np.where(pick, True, acc) & _inside(x, lo, hi)
+        return x[keep]
+
+    return _fill(n, seed, draw)
+
+
+def jitter_gauss_cheb(k, truth=GAUSS_CHEB_TRUTH, base_seed=1000):
+    """Parameter point k of the +-10% jitter: theta_j = truth_j + 0.1 s_j U(-1,1),
+    s_j = |truth_j| (1 for a zero truth value), one uniform per parameter in the
+    order (mu, sigma, f, c1, c2), seed base_seed + k."""
+    rng = np.random.default_rng(base_seed + k)
+    out = []
+    for name in ("mu", "sigma", "f", "c1", "c2"):
+        t = truth[name]
+        s = abs(t) if t != 0 else 1.0
+        out.append(t + 0.1 * s * rng.uniform(-1.0, 1.0))
+    return np.array(out)
+
+
+# --------------------------------------------------------------------------
+# 2-D: decay (x) resolution times Gaussian mass, over exponential times ARGUS
+# --------------------------------------------------------------------------
+DECAY_TRUTH = dict(tau_s=1.5, sigma_t=0.05, bias_t=0.0, mu_m=5.28, sigma_m=0.003,
+                   tau_b=0.4, c=-20.0, f=0.2)
+DECAY_T_RANGE = (0.0, 10.0)
+DECAY_M_RANGE = (5.2, 5.29)
+ARGUS_M0 = 5.29
+
+
+def sample_decay_argus(n, seed, tau_s=1.5, sigma_t=0.05, bias_t=0.0, mu_m=5.28,
+                       sigma_m=0.003, tau_b=0.4, c=-20.0, f=0.2, m0=ARGUS_M0,
+                       t_range=DECAY_T_RANGE, m_range=DECAY_M_RANGE):
+    """Signal (prob. f): t = Exp(tau_s) + N(bias_t, sigma_t), m = N(mu_m, sigma_m).
+    Background: t = Exp(tau_b); m = m0 sqrt(1 - U) with U ~ Gamma(3/2, 1/k),
+    k = -c (the ARGUS law with power 1/2 in the variable U = 1 - (m/m0)^2).
+    Draws outside the box, or with m >= m0 after FP32 rounding, are redrawn."""
+    tlo, thi = t_range
+    mlo, mhi = m_range
+    k = -c
+
+    def draw(rng, mm):
+        sig = rng.random(mm) < f
+        ts = rng.exponential(tau_s, mm) + rng.normal(bias_t, sigma_t, mm)
+        ms = rng.normal(mu_m, sigma_m, mm)
+        tb = rng.exponential(tau_b, mm)
+        U = rng.gamma(1.5, 1.0 / k, mm)
+        mb = m0 * np.sqrt(np.clip(1.0 - U, 0.0, None))
+        t = _f32(np.where(sig, ts, tb))
+        m = _f32(np.where(sig, ms, mb))
+        keep = _inside(t, tlo, thi) & _inside(m, mlo, mhi) & (m < m0)
+        keep &= np.where(sig, True, U < 1.0)
+        return t[keep], m[keep]
+
+    return _fill(n, seed, draw)
+
+
+def jitter_decay(k, truth=DECAY_TRUTH, base_seed=3000):
+    """theta*(1 + 0.01 U(-1,1)) per parameter; the resolution bias moves by
+    +-0.001 (additive, its truth is 0).  Order as DECAY_TRUTH."""
+    rng = np.random.default_rng(base_seed + k)
+    out = []
+    for name, t in truth.items():
+        u = rng.uniform(-1.0, 1.0)
+        out.append(t + 0.001 * u if name == "bias_t" else t * (1.0 + 0.01 * u))
+    return np.array(out)
+
+
+# --------------------------------------------------------------------------
+# Breit-Wigner (x) Crystal Ball signal over an exponential background
+# --------------------------------------------------------------------------
+BWCB_TRUTH = dict(M=91.19, Gamma=2.5, sigma=1.5, alpha=1.5, n=3.0, lam=-0.02, f=0.8)
+BWCB_RANGE = (60.0, 120.0)
+BWCB_WINDOW = (-30.0, 30.0)
+# box of the surrogate's inputs (x, M, Gamma, sigma, alpha, n)
+BWCB_BOX = ((60.0, 120.0), (89.19, 93.19), (1.5, 3.5), (0.5, 3.0), (0.5, 3.0), (1.0, 10.0))
+
+
+def _sample_cb(rng, m, sigma, alpha, n, ylo, yhi):
+    """Crystal Ball (mean 0, low tail) restricted to [ylo, yhi]: accept-reject
+    of a uniform proposal against the shape's maximum (1, at y = 0)."""
+    out, have = [], 0
+    while have < m:
+        y = rng.uniform(ylo, yhi, 4 * m)
+        z = y / sigma
+        A = (n / alpha) ** n * math.exp(-0.5 * alpha * alpha)
+        B = n / alpha - alpha
+        with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+            shape = np.where(z > -alpha, np.exp(-0.5 * z * z), A * np.power(np.maximum(B - z, 1e-300), -n))
+        acc = rng.random(4 * m) <= shape
+        out.append(y[acc])
+        have += int(acc.sum())
+    return np.concatenate(out)[:m]
+
+
+def sample_bw_cb(n, seed, M=91.19, Gamma=2.5, sigma=1.5, alpha=1.5, nn=3.0, lam=-0.02,
+                 f=0.8, x_range=BWCB_RANGE, window=BWCB_WINDOW):
+    """Signal (prob. f): x = M + (Gamma/2) tan(pi (u - 1/2)) + y with y ~ Crystal Ball
+    on the window; background: exp(lam x) on the range by inverse CDF."""
+    lo, hi = x_range
+
+    def draw(rng, m):
+        sig = rng.random(m) < f
+        y = _sample_cb(rng, m, sigma, alpha, nn, window[0], window[1])
+        xs = M + 0.5 * Gamma * np.tan(np.pi * (rng.random(m) - 0.5)) + y
+        u = rng.random(m)
+        if abs(lam) < 1e-12:
+            xb = lo + (hi - lo) * u
+        else:
+            xb = lo + np.log1p(u * np.expm1(lam * (hi - lo))) / lam
+        x = _f32(np.where(sig, xs, xb))
+        return x[_inside(x, lo, hi)]
+
+    return _fill(n, seed, draw)
+
+
+def sobol_design(n, seed=7, box=BWCB_BOX, skip=0):
+    """Scrambled 6-D Sobol points (x, M, Gamma, sigma, alpha, n) in the box."""
+    from scipy.stats import qmc
+    eng = qmc.Sobol(d=6, scramble=True, seed=seed)
+    if skip:
+        eng.fast_forward(skip)
+    u = eng.random(n)
+    lo = np.array([b[0] for b in box])
+    hi = np.array([b[1] for b in box])
+    return lo + u * (hi - lo)
+
+
+# --------------------------------------------------------------------------
+# Binned templates: channels x samples x bins, +-1 sigma variations
+# --------------------------------------------------------------------------
+def make_binned(seed=5, C=200, S=4, B=100, J=60, delta_max=0.05):
+    """lambda_cs ~ log-uniform[50, 5000]; T_csb ~ Poisson(lambda_cs) (>= 1);
+    T+- = T (1 +- delta+-), delta+- ~ U(0, delta_max) per (c, s, j, b);
+    observed n_cb ~ Poisson(sum_s T_csb) (signal strength 1, nuisances 0).
+    Returns FP64 arrays T[C,S,B], Tp/Tm[C,S,J,B], nobs[C,B]."""
+    rng = np.random.default_rng(seed)
+    lam = np.exp(rng.uniform(np.log(50.0), np.log(5000.0), (C, S)))
+    T = np.maximum(rng.poisson(lam[:, :, None], (C, S, B)), 1).astype(np.float64)
+    dp = rng.uniform(0.0, delta_max, (C, S, J, B))
+    dm = rng.uniform(0.0, delta_max, (C, S, J, B))
+    Tp = T[:, :, None, :] * (1.0 + dp)
+    Tm = T[:, :, None, :] * (1.0 - dm)
+    nobs = rng.poisson(T.sum(axis=1)).astype(np.float64)
+    return dict(T=T, Tp=Tp, Tm=Tm, nobs=nobs)

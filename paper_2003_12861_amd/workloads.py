@@ -1,0 +1,86 @@
+"""Declarative model graphs of the benchmark workloads.
+
+A spec is a list of ``(kind, name, inputs, attrs)`` entries in dependency
+order; the last entry is the top PDF.  ``Graph.from_spec`` turns a spec into a
+compiled-ready graph.  OBS attrs are the range (lo, hi); PARAM attrs are the
+declared bounds (lo, hi); CONST attrs are (value,).  Parameter order (the
+layout of theta) is the order of the PARAM entries.
+"""
+from . import synth
+
+
+def spec_gauss_cheb(lo=-10.0, hi=10.0):
+    """f * Gauss(x; mu, sigma) + (1 - f) * Chebyshev2(x; c1, c2) on [lo, hi];
+    theta = (mu, sigma, f, c1, c2)."""
+    return [
+        ("obs", "x", [], [lo, hi]),
+        ("param", "mu", [], [-5.0, 5.0]),
+        ("param", "sigma", [], [0.05, 10.0]),
+        ("param", "f", [], [0.0, 1.0]),
+        ("param", "c1", [], [-1.0, 1.0]),
+        ("param", "c2", [], [-1.0, 1.0]),
+        ("gauss", "sig", ["x", "mu", "sigma"], []),
+        ("cheb", "bkg", ["x", "c1", "c2"], []),
+        ("add", "model", ["sig", "bkg", "f"], []),
+    ]
+
+
+def spec_decay_argus():
+    """Signal: [decay(tau_s) (x) Gauss resolution(sigma_t, bias_t)](t) * Gauss(m; mu_m, sigma_m);
+    background: exp(-t/tau_b) * ARGUS(m; m0 = 5.29 constant, c); fraction f.
+    theta = (tau_s, sigma_t, bias_t, mu_m, sigma_m, tau_b, c, f)."""
+    tlo, thi = synth.DECAY_T_RANGE
+    mlo, mhi = synth.DECAY_M_RANGE
+    return [
+        ("obs", "t", [], [tlo, thi]),
+        ("obs", "m", [], [mlo, mhi]),
+        ("param", "tau_s", [], [0.1, 10.0]),
+        ("param", "sigma_t", [], [0.005, 1.0]),
+        ("param", "bias_t", [], [-0.5, 0.5]),
+        ("param", "mu_m", [], [5.2, 5.29]),
+        ("param", "sigma_m", [], [0.0005, 0.05]),
+        ("param", "tau_b", [], [0.05, 5.0]),
+        ("param", "c", [], [-100.0, 0.0]),
+        ("param", "f", [], [0.0, 1.0]),
+        ("const", "m0", [], [synth.ARGUS_M0]),
+        ("decay_gauss", "sig_t", ["t", "tau_s", "sigma_t", "bias_t"], []),
+        ("gauss", "sig_m", ["m", "mu_m", "sigma_m"], []),
+        ("prod", "sig", ["sig_t", "sig_m"], []),
+        ("exp", "bkg_t", ["t", "tau_b"], [0.0]),
+        ("argus", "bkg_m", ["m", "m0", "c"], []),
+        ("prod", "bkg", ["bkg_t", "bkg_m"], []),
+        ("add", "model", ["sig", "bkg", "f"], []),
+    ]
+
+
+def spec_bwcb(surrogate=False, K=1024):
+    """Signal: Breit-Wigner(M, Gamma) (x) Crystal Ball(sigma, alpha, n) by a K-point
+    Gauss-Legendre rule on the resolution window (or the MLP surrogate of its
+    log density), background exp(lam x); fraction f of signal.
+    theta = (M, Gamma, sigma, alpha, n, lam, f)."""
+    lo, hi = synth.BWCB_RANGE
+    spec = [
+        ("obs", "x", [], [lo, hi]),
+        ("param", "M", [], [85.0, 97.0]),
+        ("param", "Gamma", [], [0.5, 6.0]),
+        ("param", "sigma", [], [0.5, 3.0]),
+        ("param", "alpha", [], [0.5, 3.0]),
+        ("param", "n", [], [1.0, 10.0]),
+        ("param", "lam", [], [-0.2, 0.2]),
+        ("param", "f", [], [0.0, 1.0]),
+    ]
+    if surrogate:
+        box = [v for b in synth.BWCB_BOX for v in b]
+        spec.append(("mlp", "sig", ["x", "M", "Gamma", "sigma", "alpha", "n"], box + [float(K)]))
+    else:
+        spec.append(("numconv_bw_cb", "sig", ["x", "M", "Gamma", "sigma", "alpha", "n"],
+                     [synth.BWCB_WINDOW[0], synth.BWCB_WINDOW[1], float(K)]))
+    spec += [
+        ("exp", "bkg", ["x", "lam"], [1.0]),
+        ("add", "model", ["sig", "bkg", "f"], []),
+    ]
+    return spec
+
+
+def truth_vector(truth):
+    return [float(v) for v in truth.values()]

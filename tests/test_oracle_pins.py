@@ -1,0 +1,460 @@
+"""Pins of the oracle against values fixed by mathematics, not by itself.
+
+Every normalisation is checked against adaptive quadrature and, where one
+exists, against an independent library distribution (scipy.stats); every
+analytic gradient against Richardson-extrapolated central differences;
+special cases against the textbook function they reduce to.  These tests run
+on the CPU only.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+from oracle import rfo
+from paper_2003_12861_amd import synth, workloads
+
+
+def quad(f, a, b, points=None):
+    v, err = integrate.quad(f, a, b, epsabs=0, epsrel=1e-13, limit=500, points=points)
+    return v
+
+
+def single_leaf(kind, lo, hi, n_params, consts=(), attrs=()):
+    """Model with one leaf: inputs = x, then params p0..p{n-1}, then constants."""
+    m = rfo.Model()
+    x = m.node("obs", [], [lo, hi])
+    ins = [x] + [m.node("param") for _ in range(n_params)]
+    ins += [m.node("const", [], [c]) for c in consts]
+    if kind == "argus":  # inputs: m, m0 (const), c (param)
+        ins = [x, ins[2], ins[1]]
+    top = m.node(kind, ins, attrs)
+    return m, top
+
+
+def richardson_grad(f, theta, h=1e-4):
+    theta = np.asarray(theta, float)
+    g = np.empty_like(theta)
+    for k in range(theta.size):
+        def d(hh):
+            tp, tm = theta.copy(), theta.copy()
+            tp[k] += hh
+            tm[k] -= hh
+            return (f(tp) - f(tm)) / (2 * hh)
+        g[k] = (4 * d(h / 2) - d(h)) / 3
+    return g
+
+
+# ---------------------------------------------------------------- Gaussian
+@pytest.mark.parametrize("mu,sig,lo,hi", [(0.0, 1.0, -10, 10), (5.28, 0.003, 5.2, 5.29),
+                                          (0.3, 2.0, -1.0, 4.0), (3.0, 0.5, -10, 0.5)])
+def test_gauss_norm(mu, sig, lo, hi):
+    m, top = single_leaf("gauss", lo, hi, 2)
+    N, dN = m.norm(top, [mu, sig])
+    ref = sig * math.sqrt(2 * math.pi) * (stats.norm.cdf(hi, mu, sig) - stats.norm.cdf(lo, mu, sig))
+    if lo > mu:
+        ref = sig * math.sqrt(2 * math.pi) * (stats.norm.sf(lo, mu, sig) - stats.norm.sf(hi, mu, sig))
+    assert N == pytest.approx(ref, rel=1e-13)
+    u = lambda x: math.exp(-0.5 * ((x - mu) / sig) ** 2)
+    pts = [mu] if lo < mu < hi else None
+    assert N == pytest.approx(quad(u, lo, hi, pts), rel=1e-11)
+    dmu = quad(lambda x: u(x) * (x - mu) / sig**2, lo, hi, pts)
+    dsg = quad(lambda x: u(x) * (x - mu) ** 2 / sig**3, lo, hi, pts)
+    assert dN[0] == pytest.approx(dmu, rel=1e-9, abs=1e-14 * abs(N))
+    assert dN[1] == pytest.approx(dsg, rel=1e-9)
+
+
+def test_gauss_wide_range_limit():
+    m, top = single_leaf("gauss", -60, 60, 2)
+    N, _ = m.norm(top, [0.7, 1.3])
+    assert N == pytest.approx(1.3 * math.sqrt(2 * math.pi), rel=1e-15)
+
+
+def test_gauss_values_truncnorm():
+    lo, hi, mu, sig = -2.0, 3.0, 0.4, 0.8
+    m, top = single_leaf("gauss", lo, hi, 2)
+    x = np.linspace(lo, hi, 37)
+    v = m.values(top, [mu, sig], [x])
+    ref = stats.truncnorm.pdf(x, (lo - mu) / sig, (hi - mu) / sig, loc=mu, scale=sig)
+    np.testing.assert_allclose(v, ref, rtol=1e-12)
+
+
+# ------------------------------------------------------------- Chebyshev
+@pytest.mark.parametrize("coef", [(0.2, -0.1), (0.0, 0.0), (0.3, 0.1, -0.2, 0.05)])
+def test_cheb(coef):
+    lo, hi = -10.0, 7.0
+    m, top = single_leaf("cheb", lo, hi, len(coef))
+    N, dN = m.norm(top, list(coef))
+    shape = lambda x: np.polynomial.chebyshev.chebval((2 * x - lo - hi) / (hi - lo), [1.0, *coef])
+    assert N == pytest.approx(quad(shape, lo, hi), rel=1e-13)
+    if not any(coef):
+        assert N == pytest.approx(hi - lo, rel=1e-15)
+    for k in range(len(coef)):
+        Tk = lambda x, k=k: np.polynomial.chebyshev.chebval((2 * x - lo - hi) / (hi - lo), [0] * (k + 1) + [1])
+        assert dN[k] == pytest.approx(quad(Tk, lo, hi), abs=1e-12)
+    x = np.linspace(lo, hi, 11)
+    np.testing.assert_allclose(m.values(top, list(coef), [x]), shape(x) / N, rtol=1e-13)
+
+
+# ----------------------------------------------------------- exponential
+def test_exp_tau_form():
+    lo, hi, tau = 0.0, 10.0, 0.4
+    m, top = single_leaf("exp", lo, hi, 1, attrs=[0.0])
+    N, dN = m.norm(top, [tau])
+    assert N == pytest.approx(quad(lambda t: math.exp(-t / tau), lo, hi), rel=1e-13)
+    assert N == pytest.approx(tau * (1 - math.exp(-hi / tau)), rel=1e-15)
+    assert dN[0] == pytest.approx(quad(lambda t: math.exp(-t / tau) * t / tau**2, lo, hi), rel=1e-11)
+    x = np.linspace(lo, hi, 9)
+    ref = stats.truncexpon.pdf(x, (hi - lo) / tau, loc=lo, scale=tau)
+    np.testing.assert_allclose(m.values(top, [tau], [x]), ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("lam", [-0.02, 0.03, 0.0, 1e-14])
+def test_exp_rate_form(lam):
+    lo, hi = 60.0, 120.0
+    m, top = single_leaf("exp", lo, hi, 1, attrs=[1.0])
+    N, dN = m.norm(top, [lam])
+    assert N == pytest.approx(quad(lambda x: math.exp(lam * x), lo, hi), rel=1e-12)
+    assert dN[0] == pytest.approx(quad(lambda x: x * math.exp(lam * x), lo, hi), rel=1e-9)
+
+
+# ------------------------------------------------ decay (x) Gaussian resolution
+def decay_ref(t, tau, s, b):
+    """tau * exponentially-modified-Gaussian density (scipy.stats.exponnorm)."""
+    return tau * stats.exponnorm.pdf(t, tau / s, loc=b, scale=s)
+
+
+@pytest.mark.parametrize("tau,s,b", [(1.5, 0.05, 0.0), (1.2, 0.3, 0.1), (0.8, 0.02, -0.01)])
+def test_decay_gauss(tau, s, b):
+    lo, hi = 0.0, 10.0
+    m, top = single_leaf("decay_gauss", lo, hi, 3)
+    N, dN = m.norm(top, [tau, s, b])
+    ref = tau * (stats.exponnorm.cdf(hi, tau / s, loc=b, scale=s) - stats.exponnorm.cdf(lo, tau / s, loc=b, scale=s))
+    assert N == pytest.approx(ref, rel=1e-11)
+    assert N == pytest.approx(quad(lambda t: decay_ref(t, tau, s, b), lo, hi, [b, b + s]), rel=1e-10)
+    x = np.linspace(lo, hi, 23)
+    np.testing.assert_allclose(m.values(top, [tau, s, b], [x]), decay_ref(x, tau, s, b) / N, rtol=1e-10)
+    # normalisation derivatives vs differences of the library CDF
+    def Nof(th):
+        t2, s2, b2 = th
+        return t2 * (stats.exponnorm.cdf(hi, t2 / s2, loc=b2, scale=s2) - stats.exponnorm.cdf(lo, t2 / s2, loc=b2, scale=s2))
+    np.testing.assert_allclose(dN, richardson_grad(Nof, [tau, s, b], 1e-4), rtol=1e-6, atol=1e-9)
+
+
+def test_decay_total_is_tau():
+    m, top = single_leaf("decay_gauss", -20.0, 80.0, 3)
+    N, _ = m.norm(top, [1.5, 0.3, 0.2])
+    assert N == pytest.approx(1.5, rel=1e-12)
+
+
+def test_decay_small_resolution_is_exponential():
+    lo, hi, tau = 0.0, 10.0, 1.5
+    m, top = single_leaf("decay_gauss", lo, hi, 3)
+    x = np.linspace(0.5, 9.5, 10)
+    v = m.values(top, [tau, 1e-7, 0.0], [x])
+    ref = stats.truncexpon.pdf(x, (hi - lo) / tau, loc=lo, scale=tau)
+    np.testing.assert_allclose(v, ref, rtol=1e-6)
+
+
+# ------------------------------------------------------------------ ARGUS
+def argus_series_J(U, k, terms=60):
+    return sum((-k) ** n * U ** (n + 1.5) / (math.factorial(n) * (n + 1.5)) for n in range(terms))
+
+
+@pytest.mark.parametrize("c,lo,hi", [(-20.0, 5.2, 5.29), (-2.0, 4.0, 5.29), (-60.0, 5.0, 5.25), (0.0, 5.0, 5.29)])
+def test_argus(c, lo, hi):
+    m0 = 5.29
+    m, top = single_leaf("argus", lo, hi, 1, consts=[m0])
+    N, dN = m.norm(top, [c])
+    shape = lambda x: x * math.sqrt(max(0.0, 1 - (x / m0) ** 2)) * math.exp(c * (1 - (x / m0) ** 2)) if x < m0 else 0.0
+    assert N == pytest.approx(quad(shape, lo, min(hi, m0)), rel=1e-11)
+    # closed form of the paper-independent series in U = 1 - (m/m0)^2
+    Ul, Uh = 1 - (lo / m0) ** 2, 1 - (min(hi, m0) / m0) ** 2
+    assert N == pytest.approx(0.5 * m0 * m0 * (argus_series_J(Ul, -c) - argus_series_J(Uh, -c)), rel=1e-12)
+    dshape = lambda x: shape(x) * (1 - (x / m0) ** 2)
+    assert dN[0] == pytest.approx(quad(dshape, lo, min(hi, m0)), rel=1e-9)
+    if c < 0:
+        chi = math.sqrt(-2 * c)
+        x = np.linspace(lo, min(hi, m0) - 1e-6, 15)
+        rv = stats.argus(chi, scale=m0)
+        ref = rv.pdf(x) / (rv.cdf(min(hi, m0)) - rv.cdf(lo))
+        np.testing.assert_allclose(m.values(top, [c], [x]), ref, rtol=1e-9)
+
+
+# ------------------------------------------------- Breit-Wigner, Crystal Ball
+def test_breit_wigner():
+    lo, hi, M, G = 60.0, 120.0, 91.19, 2.5
+    m, top = single_leaf("bw", lo, hi, 2)
+    N, dN = m.norm(top, [M, G])
+    ref = math.pi / (G / 2) * (stats.cauchy.cdf(hi, M, G / 2) - stats.cauchy.cdf(lo, M, G / 2))
+    assert N == pytest.approx(ref, rel=1e-13)
+    x = np.linspace(lo, hi, 31)
+    v = m.values(top, [M, G], [x])
+    np.testing.assert_allclose(v, stats.cauchy.pdf(x, M, G / 2) / (ref * G / 2 / math.pi), rtol=1e-12)
+    Nof = lambda th: math.pi / (th[1] / 2) * (stats.cauchy.cdf(hi, th[0], th[1] / 2) - stats.cauchy.cdf(lo, th[0], th[1] / 2))
+    np.testing.assert_allclose(dN, richardson_grad(Nof, [M, G], 1e-3), rtol=1e-8)
+
+
+def numconv_model(K=1024, window=(-30.0, 30.0), lo=60.0, hi=120.0):
+    m = rfo.Model()
+    x = m.node("obs", [], [lo, hi])
+    ps = [m.node("param") for _ in range(5)]
+    top = m.node("numconv_bw_cb", [x] + ps, [window[0], window[1], float(K)])
+    return m, top
+
+
+def cb_shape(y, s, a, n):
+    """Crystal Ball shape from scipy.stats.crystalball, scaled to 1 at y = 0."""
+    return stats.crystalball.pdf(y / s, a, n) / stats.crystalball.pdf(0.0, a, n)
+
+
+@pytest.mark.parametrize("theta", [(91.19, 2.5, 1.5, 1.5, 3.0), (90.0, 3.0, 0.7, 0.8, 1.5), (92.0, 2.0, 2.5, 2.5, 8.0)])
+def test_numconv_normalised_and_close_to_exact(theta):
+    M, G, s, a, n = theta
+    lo, hi = 60.0, 120.0
+    m, top = numconv_model()
+    N, _ = m.norm(top, list(theta))
+    # the rule's normalisation is the exact x-integral of its own sum
+    xs = np.linspace(lo, hi, 4001)
+    p = m.values(top, list(theta), [xs])
+    total = integrate.simpson(p, x=xs)
+    assert total == pytest.approx(1.0, rel=2e-6)
+    # distance from the adaptive convolution integral (rule error, small)
+    def conv(x):
+        f = lambda y: cb_shape(y, s, a, n) / ((x - y - M) ** 2 + G * G / 4)
+        return quad(f, -30.0, 30.0, points=[-a * s, 0.0, x - M])
+    for x in (80.0, 89.0, 91.0, 93.5, 110.0):
+        exact = conv(x)
+        ours = m.values(top, list(theta), [np.array([x])])[0] * N
+        assert ours == pytest.approx(exact, rel=3e-4 if s < 1 else 2e-5)
+
+
+def test_crystal_ball_continuity_via_numconv_tables():
+    # C1 continuity of the shape at the junction z = -alpha, checked on the
+    # library reference the oracle is compared against below
+    s, a, n = 1.3, 1.1, 2.5
+    z0 = -a * s
+    e = 1e-7
+    left, right = cb_shape(z0 - e, s, a, n), cb_shape(z0 + e, s, a, n)
+    assert left == pytest.approx(right, rel=1e-6)
+
+
+def test_numconv_value_vs_direct_rule():
+    """S(x) = sum_k w_k CB(y_k) BW(x - y_k) written out with numpy's Gauss-Legendre
+    nodes and scipy's Crystal Ball: agrees with the oracle to rounding."""
+    theta = [91.19, 2.5, 1.5, 1.5, 3.0]
+    M, G, s, a, n = theta
+    m, top = numconv_model(K=256)
+    N, _ = m.norm(top, theta)
+    t, w = np.polynomial.legendre.leggauss(256)
+    y, w = 30.0 * t, 30.0 * w
+    c = w * cb_shape(y, s, a, n)
+    xs = np.array([70.0, 91.0, 95.5])
+    S = np.array([(c / ((x - y - M) ** 2 + G * G / 4)).sum() for x in xs])
+    np.testing.assert_allclose(m.values(top, theta, [xs]) * N, S, rtol=1e-12)
+
+
+# ------------------------------------------------------------ Gauss-Legendre
+def test_gauss_legendre_nodes():
+    x, w = rfo.gauss_legendre(64, -1.0, 1.0)
+    xr, wr = np.polynomial.legendre.leggauss(64)
+    np.testing.assert_allclose(x, xr, atol=1e-15)
+    np.testing.assert_allclose(w, wr, rtol=1e-11)  # numpy weights carry ~1e-12 error
+    x, w = rfo.gauss_legendre(1024, -1.0, 1.0)
+    assert np.all(np.diff(x) > 0)
+    for j in (0, 1, 5, 50, 400, 1000):
+        assert (w * x ** (2 * j)).sum() == pytest.approx(2.0 / (2 * j + 1), rel=1e-12)
+    x, w = rfo.gauss_legendre(1024, -30.0, 30.0)
+    assert (w * np.cos(x)).sum() == pytest.approx(2 * math.sin(30.0), rel=1e-12)
+
+
+# ---------------------------------------------------------------------- MLP
+def _torch_mlp(w, u):
+    import torch
+    W = torch.tensor(w, dtype=torch.float64, requires_grad=True)
+    U = torch.tensor(u, dtype=torch.float64, requires_grad=True)
+    W1 = W[0:384].view(64, 6); b1 = W[384:448]
+    W2 = W[448:4544].view(64, 64); b2 = W[4544:4608]
+    W3 = W[4608:8704].view(64, 64); b3 = W[8704:8768]
+    W4 = W[8768:8832].view(1, 64); b4 = W[8832:8833]
+    h = torch.tanh(U @ W1.T + b1)
+    h = torch.tanh(h @ W2.T + b2)
+    h = torch.tanh(h @ W3.T + b3)
+    s = (h @ W4.T + b4)[:, 0]
+    return W, U, s
+
+
+def test_mlp_forward_backward_vs_torch():
+    rng = np.random.default_rng(0)
+    w = rng.normal(0, 0.3, 8833)
+    u = rng.uniform(-1, 1, (17, 6))
+    dout = rng.normal(size=17)
+    W, U, s = _torch_mlp(w, u)
+    np.testing.assert_allclose(rfo.mlp_forward(w, u), s.detach().numpy(), rtol=1e-13, atol=1e-14)
+    import torch
+    (s * torch.tensor(dout)).sum().backward()
+    dw, din = rfo.mlp_backward(w, u, dout)
+    np.testing.assert_allclose(dw, W.grad.numpy(), rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(din, U.grad.numpy(), rtol=1e-11, atol=1e-13)
+
+
+def test_mlp_leaf_normalisation_vs_quadrature():
+    rng = np.random.default_rng(1)
+    w = rng.normal(0, 0.2, 8833)
+    spec = workloads.spec_bwcb(surrogate=True)
+    m, top, ids = rfo.from_spec(spec)
+    m.set_mlp_weights(ids["sig"], w)
+    th = [91.0, 2.4, 1.2, 1.3, 4.0]
+    box = synth.BWCB_BOX
+    def s_of_x(x):
+        raw = np.array([[x] + th])
+        u = 2 * (raw - [b[0] for b in box]) / np.array([b[1] - b[0] for b in box]) - 1
+        return math.exp(_torch_mlp(w, u)[2].item())
+    N, _ = m.norm(ids["sig"], th + [-0.02, 0.8])
+    assert N == pytest.approx(quad(s_of_x, 60.0, 120.0), rel=1e-11)
+
+
+# ------------------------------------------------------------ binned model
+def _binned_small(seed=3, C=3, S=2, B=5, J=4):
+    d = synth.make_binned(seed, C, S, B, J)
+    Lp = np.log(d["Tp"] / d["T"][:, :, None, :])
+    Lm = np.log(d["Tm"] / d["T"][:, :, None, :])
+    return d, Lp, Lm
+
+
+def test_binned_reduces_to_poisson():
+    d, Lp, Lm = _binned_small()
+    J = Lp.shape[2]
+    nll, g = rfo.binned_nll(d["T"], Lp, Lm, d["nobs"], [1.0] + [0.0] * J)
+    nu = d["T"].sum(axis=1)
+    ref = -(stats.poisson.logpmf(d["nobs"], nu).sum()) - special.gammaln(d["nobs"] + 1).sum()
+    assert nll == pytest.approx(ref, rel=1e-13)
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_binned_interpolation_hits_variations(sign):
+    d, Lp, Lm = _binned_small()
+    J = Lp.shape[2]
+    j = 2
+    th = [1.0] + [0.0] * J
+    th[1 + j] = sign
+    nll, _ = rfo.binned_nll(d["T"], Lp, Lm, d["nobs"], th)
+    Tv = (d["Tp"] if sign > 0 else d["Tm"])[:, :, j, :]
+    nu = Tv.sum(axis=1)
+    ref = -(stats.poisson.logpmf(d["nobs"], nu).sum()) - special.gammaln(d["nobs"] + 1).sum() + 0.5
+    assert nll == pytest.approx(ref, rel=1e-12)
+
+
+def test_binned_gradient_fd_and_single_bin_minimum():
+    d, Lp, Lm = _binned_small()
+    J = Lp.shape[2]
+    rng = np.random.default_rng(4)
+    al = rng.uniform(-1, 1, J)
+    al[np.abs(al) < 0.05] = 0.3
+    th = np.concatenate([[1.07], al])
+    f = lambda t: rfo.binned_nll(d["T"], Lp, Lm, d["nobs"], t, grad=False)[0]
+    _, g = rfo.binned_nll(d["T"], Lp, Lm, d["nobs"], th)
+    np.testing.assert_allclose(g, richardson_grad(f, th, 1e-4), rtol=1e-7, atol=1e-7)
+    # one bin, one sample scaled by mu: minimum of nu - n log nu at nu = n
+    T = np.array([[[40.0]]]); L0 = np.zeros((1, 1, 0, 1)); n = np.array([[52.0]])
+    _, g1 = rfo.binned_nll(T, L0, L0, n, [52.0 / 40.0])
+    assert abs(g1[0]) < 1e-12
+
+
+# ------------------------------------------------------- mixture and NLL
+TH0 = [0.0, 1.0, 0.3, 0.2, -0.1]
+
+
+def cfg0_pdf_ref(x, mu, sig, f, c1, c2, lo=-10.0, hi=10.0):
+    g = stats.truncnorm.pdf(x, (lo - mu) / sig, (hi - mu) / sig, loc=mu, scale=sig)
+    xp = (2 * x - lo - hi) / (hi - lo)
+    h = np.polynomial.chebyshev.chebval(xp, [1.0, c1, c2])
+    Nc = quad(lambda t: np.polynomial.chebyshev.chebval((2 * t - lo - hi) / (hi - lo), [1.0, c1, c2]), lo, hi)
+    return f * g + (1 - f) * h / Nc
+
+
+def test_cfg0_tiny_samples():
+    m, top, _ = rfo.from_spec(workloads.spec_gauss_cheb())
+    for xs in ([0.0], [-1.0, 0.5, 2.0], [-9.99, 9.99, 3.3, -0.25]):
+        x = np.array(xs)
+        nll, _, nb = m.nll(top, TH0, [x])
+        assert nb == 0
+        assert nll == pytest.approx(-np.log(cfg0_pdf_ref(x, *TH0)).sum(), rel=1e-13)
+
+
+def test_mixture_fraction_limits():
+    x = synth.sample_gauss_cheb(500, 11)
+    m, top, _ = rfo.from_spec(workloads.spec_gauss_cheb())
+    th1 = [0.2, 1.1, 1.0, 0.2, -0.1]
+    nll1, _, _ = m.nll(top, th1, [x])
+    g = stats.truncnorm.pdf(x, (-10 - 0.2) / 1.1, (10 - 0.2) / 1.1, loc=0.2, scale=1.1)
+    assert nll1 == pytest.approx(-np.log(g).sum(), rel=1e-12)
+    th0 = [0.2, 1.1, 0.0, 0.2, -0.1]
+    nll0, _, _ = m.nll(top, th0, [x])
+    assert nll0 == pytest.approx(-np.log(cfg0_pdf_ref(x, 0.2, 1.1, 0.0, 0.2, -0.1)).sum(), rel=1e-12)
+
+
+def test_decay_argus_small_sample_vs_scipy():
+    tr = synth.DECAY_TRUTH
+    t, mm = synth.sample_decay_argus(50, 12)
+    m, top, _ = rfo.from_spec(workloads.spec_decay_argus())
+    th = list(tr.values())
+    nll, _, nb = m.nll(top, th, [t, mm])
+    assert nb == 0
+    tau_s, st, bt, mu, sm, tb, c, f = th
+    tlo, thi = synth.DECAY_T_RANGE
+    mlo, mhi = synth.DECAY_M_RANGE
+    ed = stats.exponnorm(tau_s / st, loc=bt, scale=st)
+    pst = ed.pdf(t) / (ed.cdf(thi) - ed.cdf(tlo))
+    psm = stats.truncnorm.pdf(mm, (mlo - mu) / sm, (mhi - mu) / sm, loc=mu, scale=sm)
+    pbt = stats.truncexpon.pdf(t, (thi - tlo) / tb, loc=tlo, scale=tb)
+    ra = stats.argus(math.sqrt(-2 * c), scale=synth.ARGUS_M0)
+    pbm = ra.pdf(mm) / (ra.cdf(mhi) - ra.cdf(mlo))
+    ref = -np.log(f * pst * psm + (1 - f) * pbt * pbm).sum()
+    assert nll == pytest.approx(ref, rel=1e-11)
+
+
+@pytest.mark.parametrize("which", ["gauss_cheb", "decay_argus", "bwcb", "mlp"])
+def test_gradient_vs_richardson(which):
+    rng = np.random.default_rng(5)
+    if which == "gauss_cheb":
+        spec, cols, th = workloads.spec_gauss_cheb(), [synth.sample_gauss_cheb(300, 2)], [0.05, 0.95, 0.33, 0.18, -0.12]
+    elif which == "decay_argus":
+        spec, cols, th = workloads.spec_decay_argus(), list(synth.sample_decay_argus(300, 3)), synth.jitter_decay(1)
+    elif which == "bwcb":
+        spec, cols, th = workloads.spec_bwcb(K=128), [synth.sample_bw_cb(60, 4)], [91.0, 2.6, 1.4, 1.6, 3.2, -0.021, 0.78]
+    else:
+        spec, cols, th = workloads.spec_bwcb(surrogate=True, K=64), [synth.sample_bw_cb(40, 4)], [91.0, 2.6, 1.4, 1.6, 3.2, -0.021, 0.78]
+    m, top, ids = rfo.from_spec(spec)
+    if which == "mlp":
+        m.set_mlp_weights(ids["sig"], rng.normal(0, 0.2, 8833))
+    nll, g, nb = m.nll(top, th, cols)
+    assert nb == 0
+    f = lambda t: m.nll(top, t, cols, grad=False)[0]
+    h = np.maximum(1e-4 * np.abs(np.asarray(th, float)), 1e-5)
+    if which == "decay_argus":
+        h[3] = 2e-5  # the mass mean moves on the scale of its 0.003 width
+    fd = np.array([richardson_grad(lambda tt: f(tt), th, hk)[k] for k, hk in enumerate(h)])
+    scale = np.abs(fd).max()
+    np.testing.assert_allclose(g, fd, rtol=2e-6, atol=2e-7 * scale)
+
+
+def test_additivity_and_permutation():
+    x = synth.sample_gauss_cheb(1000, 8)
+    m, top, _ = rfo.from_spec(workloads.spec_gauss_cheb())
+    a, ga, _ = m.nll(top, TH0, [x[:400]])
+    b, gb, _ = m.nll(top, TH0, [x[400:]])
+    ab, gab, _ = m.nll(top, TH0, [x])
+    assert ab == pytest.approx(a + b, rel=1e-14)
+    np.testing.assert_allclose(gab, ga + gb, rtol=1e-12, atol=1e-12)
+    perm = np.random.default_rng(0).permutation(x.size)
+    pp, _, _ = m.nll(top, TH0, [x[perm]])
+    assert pp == pytest.approx(ab, rel=1e-14)
+
+
+def test_bad_events_make_nll_infinite():
+    m, top, _ = rfo.from_spec(workloads.spec_gauss_cheb())
+    x = np.linspace(-10, 10, 101)
+    nll, _, nb = m.nll(top, [0.0, 1.0, 0.0, 1.5, 0.0], [x])  # 1 + 1.5 x' < 0 for x' < -2/3
+    assert math.isinf(nll) and nb == np.sum((x / 10.0) * 1.5 + 1 <= 0)
