@@ -1,0 +1,211 @@
+/*
+ * rfgpu.h -- C ABI of the MI355X batched-likelihood library.
+ *
+ * What it computes (Hageboeck & Moneta, "Making RooFit Ready for Run 3",
+ * ACAT 2019):
+ *   - A likelihood model is a computation graph of observables, parameters,
+ *     functions and PDFs; every node evaluates to a real number and a PDF's
+ *     value is the probability density of an event (Section 1, Fig. 1).
+ *   - The likelihood needs the probability of every event; evaluating all
+ *     events of a node in one call ("batch") replaces per-event recursion
+ *     (Section 4, 4.1).  Here the whole compiled graph is evaluated for all
+ *     events in ONE fused GPU kernel with intermediates in registers.
+ *   - Parameter-only branches (normalisation integrals) are computed once per
+ *     parameter point (Section 4) -- in FP64, in the kernel's prologue.
+ *   - NLL(theta) = -sum_i log p(x_i | theta), each PDF normalised over the
+ *     observables' ranges (a box); the sum is a deterministic compensated
+ *     reduction (plain FP64 within a wavefront, double-double TwoSum across
+ *     wavefronts and workgroups, fixed order).  The gradient dNLL/dtheta comes
+ *     from a hand-written adjoint in the same kernel.
+ *
+ * Conventions for every function:
+ *   - Return value: RF_OK (0) or a negative RF_E_* code; rf_last_error()
+ *     then holds a message (thread-local, valid until the next call on the
+ *     same thread).
+ *   - Pointers named dev_* are device pointers (e.g. torch tensor data); they
+ *     are BORROWED: the caller keeps them alive while they are bound.  Every
+ *     other pointer is host memory owned by the caller.  theta is copied on
+ *     each call.
+ *   - stream is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     on it; the functions that return host values synchronise it.
+ *   - A program is not re-entrant: do not call it from two threads at once.
+ *     Distinct programs are independent.
+ */
+#ifndef RFGPU_H
+#define RFGPU_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+  RF_OK = 0,
+  RF_E_INVALID = -1,   /* bad argument, graph error (arity, unknown op, ...) */
+  RF_E_DOMAIN = -2,    /* theta outside declared bounds or mathematically invalid */
+  RF_E_NONFINITE = -3, /* some p_i <= 0 or not finite: nll = +inf, n_bad set, grad NaN */
+  RF_E_DEVICE = -4,    /* HIP runtime or kernel-compiler failure */
+  RF_E_OOM = -5,       /* device allocation failed */
+  RF_E_STATE = -6      /* e.g. evaluation before columns are bound */
+};
+
+/* ---- precision forms ----------------------------------------------------- */
+enum {
+  RF_FP64 = 0,      /* plain FP64: FP64 columns and arithmetic */
+  RF_FP32_COMP = 1  /* FP32 per-event arithmetic and FP32 columns; FP64 prologue
+                       (normalisations), FP64 per-thread accumulation, FP64
+                       re-evaluation of events with p_i < 1e-30 in FP32,
+                       compensated FP64 cross-block reduction */
+};
+
+/* ---- compile flags ------------------------------------------------------- */
+enum {
+  RF_COMPILE_NO_LOAD = 1u << 0, /* generate + build the code object only (no GPU
+                                   needed); the program can then only be queried */
+  RF_VALIDATE = 1u << 1         /* rf_bind_columns checks every event lies in its
+                                   observable's range (one device pass) */
+};
+
+/* ---- graph ops ----------------------------------------------------------- */
+/* Inputs are node ids.  A PDF leaf's input 0 is an observable; its shape
+ * inputs are parameter-like nodes (PARAM, CONST or FN_*).  Each leaf is
+ * normalised over its observable's range. */
+enum {
+  RF_OP_GAUSS = 1,          /* (x, mu, sigma): exp(-(x-mu)^2/(2 sigma^2))            */
+  RF_OP_CHEB = 2,           /* (x, c1..cn), n<=8: 1 + sum c_k T_k(x'), x' in [-1,1]  */
+  RF_OP_EXP = 3,            /* (x, k); attrs[0] = 0: exp(-x/k) (k = tau > 0),
+                                         attrs[0] = 1: exp(k x) (k = rate)          */
+  RF_OP_DECAY_GAUSS = 4,    /* (t, tau, sigma, bias): single-sided exp(-t/tau) decay
+                               convolved with a Gaussian resolution (analytic erfc) */
+  RF_OP_ARGUS = 5,          /* (m, m0 [CONST], c <= 0): m sqrt(U) exp(c U), U = 1-(m/m0)^2 */
+  RF_OP_BW = 6,             /* (x, M, Gamma): 1/((x-M)^2 + Gamma^2/4)                */
+  RF_OP_NUMCONV_BW_CB = 7,  /* (x, M, Gamma, sigma, alpha, n); attrs (ylo, yhi, K):
+                               sum_k w_k CB(y_k) BW(x - y_k) over a K-point
+                               Gauss-Legendre rule on [ylo, yhi], K <= 1024       */
+  RF_OP_MLP = 8,            /* (x, q1..q5); attrs: 6 (lo, hi) input boxes (x first), K:
+                               exp(s(x, q)) with s a 6-64-64-64-1 tanh MLP (BF16
+                               weights bound with rf_bind_weights), normalised by a
+                               K-point Gauss-Legendre sum over x's range          */
+  RF_OP_ADD_PDF = 20,       /* (pdf_1..pdf_n, f_1..f_{n-1}): sum_j f_j pdf_j +
+                               (1 - sum f) pdf_n, each pdf normalised            */
+  RF_OP_PROD_PDF = 21,      /* (pdf_1..pdf_n) over disjoint observables           */
+  RF_OP_FN_LINEAR = 40,     /* (a_1..a_n param-like); attrs (c0, c1..cn): c0 + sum c_j a_j */
+  RF_OP_FN_PRODUCT = 41     /* (a_1..a_n param-like): prod a_j                     */
+};
+
+typedef struct rf_graph rf_graph;
+typedef struct rf_program rf_program;
+typedef struct rf_binned rf_binned;
+
+const char* rf_last_error(void);
+/* library version string; also names the device code-object cache layout */
+const char* rf_version(void);
+
+/* ---- graph construction (host only) -------------------------------------- */
+int rf_graph_new(rf_graph** out);
+void rf_graph_free(rf_graph* g);
+/* column index = declaration order of observables; [lo, hi] is the range
+ * every PDF on this observable is normalised over (lo < hi, finite). */
+int rf_graph_observable(rf_graph* g, const char* name, double lo, double hi, int32_t* id);
+/* theta index = declaration order of parameters; [lo, hi] are the bounds
+ * checked on every evaluation (lo <= theta <= hi). */
+int rf_graph_parameter(rf_graph* g, const char* name, double lo, double hi, int32_t* id);
+int rf_graph_constant(rf_graph* g, double value, int32_t* id);
+/* inputs must be ids of earlier nodes (so the graph is acyclic by construction) */
+int rf_graph_node(rf_graph* g, int32_t op, const int32_t* inputs, int32_t n_inputs,
+                  const double* attrs, int32_t n_attrs, int32_t* id);
+
+/* ---- compilation --------------------------------------------------------- */
+/* Validates the subgraph under top, lowers it to a flat node program,
+ * generates one fused HIP kernel source for it (three entry points: values,
+ * NLL, NLL+gradient) specialised to the precision form, builds a gfx950 code
+ * object (content-addressed cache; built with the ROCm compiler on a miss) and
+ * loads it.  The graph may be freed afterwards. */
+int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags,
+               rf_program** out);
+void rf_program_free(rf_program* p);
+/* n_sums: number of FP64 event sums the gradient kernel accumulates */
+int rf_program_info(const rf_program* p, int32_t* n_params, int32_t* n_columns,
+                    int32_t* n_sums);
+/* generated HIP source (NUL-terminated, owned by the program) */
+const char* rf_program_source(const rf_program* p);
+
+/* ---- binding ------------------------------------------------------------- */
+/* dev_cols[j]: contiguous column of observable j (n_events values), float64
+ * for RF_FP64 programs, float32 for RF_FP32_COMP.  Allocates the program's
+ * workspace (block partials, result block) on the current device. */
+int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols,
+                    int64_t n_events, void* stream);
+/* MLP leaf weights: 8833 bf16 values (layout W1[64][6] b1[64] W2[64][64]
+ * b2[64] W3[64][64] b3[64] W4[64] b4[1], row = output unit). */
+int rf_bind_weights(rf_program* p, int32_t node, const void* dev_bf16, void* stream);
+/* launch shape override (0 = automatic) */
+int rf_set_launch(rf_program* p, int32_t blocks, int32_t threads);
+
+/* ---- evaluation ---------------------------------------------------------- */
+/* per-event normalised p_i into dev_out (n_events, bound dtype); async */
+int rf_eval_values(rf_program* p, const double* theta, void* dev_out, void* stream);
+/* NLL only; synchronous.  n_bad may be NULL. */
+int rf_nll(rf_program* p, const double* theta, double* nll, int64_t* n_bad, void* stream);
+/* NLL and gradient (n_params); synchronous. */
+int rf_nll_grad(rf_program* p, const double* theta, double* nll, double* grad,
+                int64_t* n_bad, void* stream);
+/* enqueue one NLL+gradient evaluation without synchronising; the result
+ * block [nll, grad[n_params], n_bad] stays in device memory at
+ * rf_program_result(p) until the next evaluation of this program. */
+int rf_nll_grad_async(rf_program* p, const double* theta, void* stream);
+const double* rf_program_result(const rf_program* p);
+
+/* ---- fit ------------------------------------------------------------------ */
+/* Quasi-Newton (BFGS) minimisation of NLL with backtracking line search that
+ * backs off infinite NLL and out-of-bounds points; converged when
+ * EDM = g^T H^-1 g / 2 < edm_tol.  sigma_out: sqrt(diag(H^-1)) with H from
+ * central differences of the analytic gradient at the minimum (may be NULL).
+ * info_out[4] = {n_iterations, n_evaluations, edm, converged(0/1)}. */
+int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, int32_t max_iter,
+                double* theta_out, double* sigma_out, double* info_out, void* stream);
+
+/* ---- binned template likelihood (HistFactory-like, Section 3) -------------- */
+/* C channels, S samples (sample 0 scaled by the signal strength mu), B bins,
+ * J nuisance parameters.  Host FP64 inputs: T[C][S][B] nominal yields,
+ * Tp/Tm[C][S][J][B] the +-1 sigma yields, nobs[C][B] observed counts.
+ * log(T+-/T) is taken once here (FP64) and stored as FP32 on the device.
+ * theta = (mu, alpha_1..alpha_J):
+ *   nu_csb = mu^[s=0] T_csb exp(sum_j |alpha_j| log(T^{sgn alpha_j}_csbj / T_csb)),
+ *   NLL = sum_cb (nu_cb - n_cb log nu_cb) + sum_j alpha_j^2 / 2,
+ * nu_cb = sum_s nu_csb; the constant sum log(n!) is left out. */
+int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T,
+                  const double* Tp, const double* Tm, const double* nobs, void* stream,
+                  rf_binned** out);
+void rf_binned_free(rf_binned* b);
+int rf_binned_nll_grad(rf_binned* b, const double* theta, double* nll, double* grad,
+                       void* stream);
+int rf_binned_nll_grad_async(rf_binned* b, const double* theta, void* stream);
+const double* rf_binned_result(const rf_binned* b);
+
+/* ---- MLP kernels used to train the surrogate ------------------------------- */
+/* 6-64-64-64-1 tanh network, BF16 weights (layout as rf_bind_weights), FP32
+ * inputs in [-1,1] (n x 6 row-major), FP32 accumulation.
+ * rf_mlp_forward: out[n]; act (n x 192 FP32, may be NULL) keeps the hidden
+ * activations for rf_mlp_backward. */
+int rf_mlp_forward(const void* dev_w_bf16, const float* dev_in, int64_t n, float* dev_out,
+                   float* dev_act, void* stream);
+/* dout[n] cotangents -> dw[8833] FP32 (overwritten with the sum over rows),
+ * din (n x 6, may be NULL) input gradients. */
+int rf_mlp_backward(const void* dev_w_bf16, const float* dev_in, const float* dev_act,
+                    const float* dev_dout, int64_t n, float* dev_dw, float* dev_din,
+                    void* stream);
+/* one Adam step on FP32 master weights w32 (n values) with moments m, v;
+ * writes the BF16 copy (round to nearest even) used by the kernels. */
+int rf_adam_step(float* dev_w32, void* dev_w_bf16, float* dev_m, float* dev_v,
+                 const float* dev_g, int64_t n, float lr, float beta1, float beta2,
+                 float eps, int32_t step, void* stream);
+
+/* ---- host utility ---------------------------------------------------------- */
+/* K-point Gauss-Legendre nodes and weights on [lo, hi] (ascending) */
+int rf_gauss_legendre(int32_t K, double lo, double hi, double* x, double* w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

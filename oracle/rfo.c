@@ -684,6 +684,12 @@ static void eval_event(rfo_model* m, const double* xs, char* reach, double* val,
 int rfo_nll(rfo_model* m, int top, const double* theta,
             const double* const* cols, int64_t n,
             double* nll, double* grad, int64_t* n_bad) {
+  return rfo_nll_ex(m, top, theta, cols, n, nll, grad, NULL, n_bad);
+}
+
+int rfo_nll_ex(rfo_model* m, int top, const double* theta,
+               const double* const* cols, int64_t n,
+               double* nll, double* grad, double* gabs, int64_t* n_bad) {
   char reach[MAXN];
   int rc = prepare(m, top, theta, reach);
   if (rc) return rc;
@@ -691,21 +697,25 @@ int rfo_nll(rfo_model* m, int top, const double* theta,
   double* val = malloc(sizeof(double) * MAXN);
   double (*grd)[MAXP] = malloc(sizeof(double) * MAXN * MAXP);
   nsum L = {0, 0};
-  nsum G[MAXP];
+  nsum G[MAXP], A[MAXP];
   memset(G, 0, sizeof(G));
+  memset(A, 0, sizeof(A));
   int64_t bad = 0;
   double xs[MAXN];
   for (int64_t i = 0; i < n; ++i) {
     for (int j = 0; j < no; ++j) xs[j] = cols[j][i];
-    eval_event(m, xs, reach, val, grd, grad != NULL);
+    eval_event(m, xs, reach, val, grd, grad != NULL || gabs != NULL);
     double p = val[top];
     if (!(p > 0) || !isfinite(p)) { ++bad; continue; }
     nadd(&L, -log(p));
     if (grad)
       for (int k = 0; k < P; ++k) nadd(&G[k], -grd[top][k] / p);
+    if (gabs)
+      for (int k = 0; k < P; ++k) nadd(&A[k], fabs(grd[top][k] / p));
   }
   *nll = bad ? INFINITY : nval(&L);
   if (grad) for (int k = 0; k < P; ++k) grad[k] = nval(&G[k]);
+  if (gabs) for (int k = 0; k < P; ++k) gabs[k] = nval(&A[k]);
   if (n_bad) *n_bad = bad;
   free(val); free(grd);
   return 0;

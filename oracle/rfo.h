@@ -69,6 +69,11 @@ int rfo_set_mlp_weights(rfo_model* m, int node, const double* w);
 int rfo_nll(rfo_model* m, int top, const double* theta,
             const double* const* cols, int64_t n,
             double* nll, double* grad, int64_t* n_bad);
+/* as rfo_nll, plus gabs[k] = sum_i |d(-log p_i)/d theta_k| (the scale of the
+   gradient's cancellation; may be NULL) */
+int rfo_nll_ex(rfo_model* m, int top, const double* theta,
+               const double* const* cols, int64_t n,
+               double* nll, double* grad, double* gabs, int64_t* n_bad);
 /* per-event normalised PDF values */
 int rfo_values(rfo_model* m, int top, const double* theta,
                const double* const* cols, int64_t n, double* out);

@@ -55,6 +55,7 @@ def lib():
         L.rfo_n_obs.argtypes = [P]
         L.rfo_set_mlp_weights.argtypes = [P, I, DP]
         L.rfo_nll.argtypes = [P, I, DP, ctypes.POINTER(DP), I64, DP, DP, ctypes.POINTER(I64)]
+        L.rfo_nll_ex.argtypes = [P, I, DP, ctypes.POINTER(DP), I64, DP, DP, DP, ctypes.POINTER(I64)]
         L.rfo_values.argtypes = [P, I, DP, ctypes.POINTER(DP), I64, DP]
         L.rfo_norm.argtypes = [P, I, DP, DP, DP]
         L.rfo_gauss_legendre.argtypes = [I, D, D, DP, DP]
@@ -126,6 +127,17 @@ class Model:
         _check(lib().rfo_nll(self.h, top, _dp(th), arr, n, ctypes.byref(out),
                              _dp(g) if grad else None, ctypes.byref(nb)))
         return out.value, (g[: self.n_params] if grad else None), nb.value
+
+    def nll_ex(self, top, theta, cols):
+        """(nll, grad, gabs, n_bad); gabs[k] = sum_i |d(-log p_i)/d theta_k|."""
+        th = _f64(theta)
+        cs, arr, n = self._cols(cols)
+        out = ctypes.c_double()
+        g = np.zeros(max(1, self.n_params))
+        ga = np.zeros(max(1, self.n_params))
+        nb = ctypes.c_int64()
+        _check(lib().rfo_nll_ex(self.h, top, _dp(th), arr, n, ctypes.byref(out), _dp(g), _dp(ga), ctypes.byref(nb)))
+        return out.value, g[: self.n_params], ga[: self.n_params], nb.value
 
     def values(self, top, theta, cols):
         th = _f64(theta)

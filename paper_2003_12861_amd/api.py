@@ -1,0 +1,310 @@
+"""Thin Python binding of librfgpu (argument marshalling only).
+
+Every computation runs in the C library and its GPU kernels; this module
+converts arguments, keeps bound tensors alive and maps status codes to
+exceptions.  torch is imported first so that the library shares torch's HIP
+runtime, devices and streams.  If the library is missing, importing this
+module fails: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librfgpu.so")
+
+FP64, FP32 = 0, 1
+RF_COMPILE_NO_LOAD, RF_VALIDATE = 1, 2
+OPS = {
+    "gauss": 1, "cheb": 2, "exp": 3, "decay_gauss": 4, "argus": 5, "bw": 6,
+    "numconv_bw_cb": 7, "mlp": 8, "add": 20, "prod": 21, "linear": 40, "product": 41,
+}
+STATUS = {0: "RF_OK", -1: "RF_E_INVALID", -2: "RF_E_DOMAIN", -3: "RF_E_NONFINITE",
+          -4: "RF_E_DEVICE", -5: "RF_E_OOM", -6: "RF_E_STATE"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("librfgpu.so is not built: run `python -m paper_2003_12861_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P, _I32, _I64, _D, _U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
+_DP = ctypes.POINTER(ctypes.c_double)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_F = ctypes.c_float
+
+_SIGS = {
+    "rf_last_error": ([], ctypes.c_char_p),
+    "rf_version": ([], ctypes.c_char_p),
+    "rf_graph_new": ([_PP], _I32),
+    "rf_graph_free": ([_P], None),
+    "rf_graph_observable": ([_P, ctypes.c_char_p, _D, _D, _PI32], _I32),
+    "rf_graph_parameter": ([_P, ctypes.c_char_p, _D, _D, _PI32], _I32),
+    "rf_graph_constant": ([_P, _D, _PI32], _I32),
+    "rf_graph_node": ([_P, _I32, _PI32, _I32, _DP, _I32, _PI32], _I32),
+    "rf_compile": ([_P, _I32, _I32, _U32, _PP], _I32),
+    "rf_program_free": ([_P], None),
+    "rf_program_info": ([_P, _PI32, _PI32, _PI32], _I32),
+    "rf_program_source": ([_P], ctypes.c_char_p),
+    "rf_bind_columns": ([_P, _PP, _I32, _I64, _P], _I32),
+    "rf_bind_weights": ([_P, _I32, _P, _P], _I32),
+    "rf_set_launch": ([_P, _I32, _I32], _I32),
+    "rf_eval_values": ([_P, _DP, _P, _P], _I32),
+    "rf_nll": ([_P, _DP, _DP, _PI64, _P], _I32),
+    "rf_nll_grad": ([_P, _DP, _DP, _DP, _PI64, _P], _I32),
+    "rf_nll_grad_async": ([_P, _DP, _P], _I32),
+    "rf_program_result": ([_P], _P),
+    "rf_fit_bfgs": ([_P, _DP, _D, _I32, _DP, _DP, _DP, _P], _I32),
+    "rf_gauss_legendre": ([_I32, _D, _D, _DP, _DP], _I32),
+}
+_OPTIONAL = {
+    "rf_binned_new": ([_I32, _I32, _I32, _I32, _DP, _DP, _DP, _DP, _P, _PP], _I32),
+    "rf_binned_free": ([_P], None),
+    "rf_binned_nll_grad": ([_P, _DP, _DP, _DP, _P], _I32),
+    "rf_binned_nll_grad_async": ([_P, _DP, _P], _I32),
+    "rf_binned_result": ([_P], _P),
+    "rf_mlp_forward": ([_P, _P, _I64, _P, _P, _P], _I32),
+    "rf_mlp_backward": ([_P, _P, _P, _P, _I64, _P, _P, _P], _I32),
+    "rf_adam_step": ([_P, _P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P], _I32),
+}
+
+
+def _bind(table, required):
+    for name, (args, res) in table.items():
+        fn = getattr(_lib, name, None)
+        if fn is None:
+            if required:
+                raise ImportError("librfgpu.so lacks " + name)
+            continue
+        fn.argtypes = args
+        fn.restype = res
+        globals()[name] = fn
+
+
+_bind(_SIGS, True)
+_bind(_OPTIONAL, False)
+
+
+class RfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+def check(rc):
+    if rc < 0:
+        raise RfError(rc, rf_last_error().decode(errors="replace"))
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _stream(stream=None):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+def gauss_legendre(K, lo, hi):
+    x, w = np.empty(K), np.empty(K)
+    check(rf_gauss_legendre(K, lo, hi, _dptr(x), _dptr(w)))
+    return x, w
+
+
+# --------------------------------------------------------------------- graph
+class Graph:
+    """A model graph: observables, parameters, constants, functions and PDFs."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        check(rf_graph_new(ctypes.byref(h)))
+        self.h = h
+        self.ids = {}
+        self.top = None
+        self.param_names = []
+        self.obs_names = []
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            rf_graph_free(self.h)
+            self.h = None
+
+    def _id(self, name, rc, out):
+        check(rc)
+        self.ids[name] = out.value
+        self.top = out.value
+        return out.value
+
+    def observable(self, name, lo, hi):
+        out = ctypes.c_int32()
+        self.obs_names.append(name)
+        return self._id(name, rf_graph_observable(self.h, name.encode(), lo, hi, ctypes.byref(out)), out)
+
+    def parameter(self, name, lo, hi):
+        out = ctypes.c_int32()
+        self.param_names.append(name)
+        return self._id(name, rf_graph_parameter(self.h, name.encode(), lo, hi, ctypes.byref(out)), out)
+
+    def constant(self, value, name=None):
+        out = ctypes.c_int32()
+        return self._id(name or "const%d" % len(self.ids), rf_graph_constant(self.h, value, ctypes.byref(out)), out)
+
+    def node(self, op, inputs, attrs=(), name=None):
+        ins = [self.ids[i] if isinstance(i, str) else int(i) for i in inputs]
+        iarr = (ctypes.c_int32 * max(1, len(ins)))(*ins)
+        at = np.ascontiguousarray(list(attrs) if len(attrs) else [0.0], dtype=np.float64)
+        out = ctypes.c_int32()
+        opc = OPS[op] if isinstance(op, str) else int(op)
+        return self._id(name or "n%d" % len(self.ids),
+                        rf_graph_node(self.h, opc, iarr, len(ins), _dptr(at), len(attrs), ctypes.byref(out)), out)
+
+    @classmethod
+    def from_spec(cls, spec):
+        """spec: sequence of (kind, name, inputs, attrs); the last entry is the top PDF."""
+        g = cls()
+        for kind, name, inputs, attrs in spec:
+            if kind == "obs":
+                g.observable(name, attrs[0], attrs[1])
+            elif kind == "param":
+                g.parameter(name, attrs[0], attrs[1])
+            elif kind == "const":
+                g.constant(attrs[0], name)
+            else:
+                g.node(kind, inputs, attrs, name)
+        return g
+
+
+# -------------------------------------------------------------------- program
+class Program:
+    """A compiled graph: one fused kernel per precision form."""
+
+    def __init__(self, graph, top=None, precision=FP64, load=True, flags=0):
+        h = ctypes.c_void_p()
+        top = graph.top if top is None else (graph.ids[top] if isinstance(top, str) else top)
+        fl = flags | (0 if load else RF_COMPILE_NO_LOAD)
+        check(rf_compile(graph.h, top, precision, fl, ctypes.byref(h)))
+        self.h = h
+        self.precision = precision
+        self.param_names = list(graph.param_names)
+        self.ids = dict(graph.ids)
+        npar, ncol, nsum = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(rf_program_info(h, ctypes.byref(npar), ctypes.byref(ncol), ctypes.byref(nsum)))
+        self.n_params, self.n_columns, self.n_sums = npar.value, ncol.value, nsum.value
+        self._cols = []
+        self._weights = None
+        self.n_events = None
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            rf_program_free(self.h)
+            self.h = None
+
+    @property
+    def source(self):
+        return rf_program_source(self.h).decode()
+
+    @property
+    def dtype(self):
+        return torch.float32 if self.precision == FP32 else torch.float64
+
+    def bind(self, cols, stream=None):
+        """cols: device tensors (one per observable, contiguous, program dtype)."""
+        cols = [c.contiguous() for c in cols]
+        for c in cols:
+            if c.dtype != self.dtype or not c.is_cuda:
+                raise RfError(-1, "columns must be %s tensors on the GPU" % self.dtype)
+        n = int(cols[0].numel()) if cols else 0
+        if any(int(c.numel()) != n for c in cols):
+            raise RfError(-1, "columns differ in length")
+        arr = (ctypes.c_void_p * max(1, len(cols)))(*[c.data_ptr() for c in cols])
+        check(rf_bind_columns(self.h, arr, len(cols), n, _stream(stream)))
+        self._cols = cols
+        self.n_events = n
+        return self
+
+    def bind_weights(self, node, w_bf16, stream=None):
+        nid = self.ids[node] if isinstance(node, str) else int(node)
+        if w_bf16.dtype != torch.bfloat16 or w_bf16.numel() != 8833 or not w_bf16.is_cuda:
+            raise RfError(-1, "weights must be 8833 bf16 values on the GPU")
+        w = w_bf16.contiguous()
+        check(rf_bind_weights(self.h, nid, ctypes.c_void_p(w.data_ptr()), _stream(stream)))
+        self._weights = w
+
+    def set_launch(self, blocks=0, threads=0):
+        check(rf_set_launch(self.h, blocks, threads))
+
+    def _theta(self, theta):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if th.size != self.n_params:
+            raise RfError(-1, "theta has %d values, the program %d parameters" % (th.size, self.n_params))
+        return th
+
+    def values(self, theta, out=None, stream=None):
+        th = self._theta(theta)
+        if out is None:
+            out = torch.empty(self.n_events, dtype=self.dtype, device=self._cols[0].device if self._cols else "cuda")
+        check(rf_eval_values(self.h, _dptr(th), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def nll(self, theta, stream=None):
+        th = self._theta(theta)
+        v, nb = ctypes.c_double(), ctypes.c_int64()
+        rc = rf_nll(self.h, _dptr(th), ctypes.byref(v), ctypes.byref(nb), _stream(stream))
+        if rc != -3:
+            check(rc)
+        return v.value, nb.value
+
+    def nll_grad(self, theta, stream=None):
+        """Returns (nll, grad, n_bad); nll = inf and grad = nan when n_bad > 0."""
+        th = self._theta(theta)
+        v, nb = ctypes.c_double(), ctypes.c_int64()
+        g = np.zeros(max(1, self.n_params))
+        rc = rf_nll_grad(self.h, _dptr(th), ctypes.byref(v), _dptr(g), ctypes.byref(nb), _stream(stream))
+        if rc != -3:
+            check(rc)
+        return v.value, g[: self.n_params].copy(), nb.value
+
+    def nll_grad_async(self, theta, stream=None):
+        th = self._theta(theta)
+        check(rf_nll_grad_async(self.h, _dptr(th), _stream(stream)))
+
+    def result_ptr(self):
+        return rf_program_result(self.h)
+
+    def fit(self, theta0, edm_tol=1e-6, max_iter=1000, stream=None):
+        th = self._theta(theta0)
+        out = np.zeros(self.n_params)
+        sig = np.zeros(self.n_params)
+        info = np.zeros(4)
+        check(rf_fit_bfgs(self.h, _dptr(th), edm_tol, max_iter, _dptr(out), _dptr(sig), _dptr(info), _stream(stream)))
+        return out, sig, dict(iterations=int(info[0]), evaluations=int(info[1]), edm=float(info[2]),
+                              converged=bool(info[3]))
+
+
+def compile_program(graph, top=None, precision=FP64, load=True, flags=0):
+    return Program(graph, top, precision, load, flags)
+
+
+class NLLFunction(torch.autograd.Function):
+    """NLL(theta) with the hand-written GPU adjoint as its backward.
+
+    forward(theta: float64 tensor [P], program) -> scalar float64 tensor; the
+    kernel computes NLL and dNLL/dtheta in one pass, backward scales the
+    stored gradient.  Double backward is not supported."""
+
+    @staticmethod
+    def forward(ctx, theta, program):
+        nll, g, nbad = program.nll_grad(theta.detach().to("cpu", torch.float64).numpy())
+        ctx.save_for_backward(torch.from_numpy(g).to(theta.device, theta.dtype))
+        return torch.tensor(nll, dtype=theta.dtype, device=theta.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return gout * g, None

@@ -1,0 +1,450 @@
+// rf_dev.h -- device-side op library for the fused likelihood kernels.
+//
+// Every compiled model graph becomes one generated HIP source that includes
+// this header.  For each PDF leaf the header provides
+//   * <op>_prologue(): FP64, run once per workgroup per parameter point.  It
+//     evaluates the normalisation integral N over the observable's range and
+//     d log N / d(input) -- the parameter-only ("constant") branch that the
+//     paper caches once per parameter point (Section 4) -- and the derived
+//     constants the per-event code needs.  Layout of the constant block:
+//       C[0] = 1/N, C[1..k] = d log N / d(shape input j), C[k+1..] = op data.
+//   * <Op>K<T>: the constants as the per-event precision T (float or double),
+//     with location-type constants split into hi + lo parts for T = float so
+//     that (x - mu) keeps FP64 accuracy when mu is large compared to the
+//     spread (e.g. a 5.28 GeV mass with a 3 MeV width).
+//   * <op>_eval<T>(): per-event unnormalised shape u(x) and
+//     d log u / d(shape input j).
+// The shapes are the textbook PDFs of the batched RooFit work (Gaussian,
+// exponential and sums of PDFs, Sections 4.1-4.2) and of the benchmark
+// models (Chebyshev polynomial, decay (x) Gaussian resolution, ARGUS,
+// Breit-Wigner, Breit-Wigner (x) Crystal Ball convolution, MLP surrogate).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RF_DEV static __device__ __forceinline__
+
+// ------------------------------------------------------------------ math --
+template <typename T> struct RM;
+template <> struct RM<float> {
+  RF_DEV float exp(float x) { return expf(x); }
+  RF_DEV float log(float x) { return logf(x); }
+  RF_DEV float erfc(float x) { return erfcf(x); }
+  RF_DEV float erfcx(float x) { return erfcxf(x); }
+  RF_DEV float sqrt(float x) { return sqrtf(x); }
+  RF_DEV float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  RF_DEV bool finite(float x) { return isfinite(x); }
+  RF_DEV float tiny() { return 1e-30f; }  // FP32 results below this are redone in FP64
+};
+template <> struct RM<double> {
+  RF_DEV double exp(double x) { return ::exp(x); }
+  RF_DEV double log(double x) { return ::log(x); }
+  RF_DEV double erfc(double x) { return ::erfc(x); }
+  RF_DEV double erfcx(double x) { return ::erfcx(x); }
+  RF_DEV double sqrt(double x) { return ::sqrt(x); }
+  RF_DEV double rcp(double x) { return 1.0 / x; }
+  RF_DEV bool finite(double x) { return isfinite(x); }
+  RF_DEV double tiny() { return 0.0; }
+};
+
+// A location constant: value as hi (+ lo for float) so that
+// sub(x) = (x - hi) - lo.  For T = double lo is 0 and folded away.
+template <typename T> struct Loc {
+  T hi, lo;
+  RF_DEV Loc make(double v) {
+    Loc l;
+    l.hi = (T)v;
+    l.lo = (T)(v - (double)l.hi);
+    return l;
+  }
+  __device__ __forceinline__ T sub(T x) const { return (x - hi) - lo; }
+};
+// A scale constant for products x*s that must stay accurate when |x*s| is
+// large (exponent arguments): s = hi + lo, x*s ~ fma(x, hi, x*lo).
+template <typename T> struct Scl {
+  T hi, lo;
+  RF_DEV Scl make(double v) {
+    Scl s;
+    s.hi = (T)v;
+    s.lo = (T)(v - (double)s.hi);
+    return s;
+  }
+  __device__ __forceinline__ T mul(T x) const { return fma(x, hi, x * lo); }
+};
+
+static constexpr double RF_SQRT2 = 1.41421356237309504880;
+static constexpr double RF_SQRTPI = 1.77245385090551602730;
+static constexpr double RF_SQRT2PI = 2.50662827463100050242;
+static constexpr double RF_INV_SQRT2PI = 0.39894228040143267794;
+
+// ============================================================== Gaussian ==
+// u = exp(-(x-mu)^2 / (2 sigma^2)); inputs (mu, sigma).
+// N = sigma sqrt(pi/2) [erf(zb) - erf(za)], z = (y - mu)/(sqrt2 sigma);
+// dN/dmu = u(lo) - u(hi);  dN/dsigma = (N - (hi-mu) u(hi) + (lo-mu) u(lo)) / sigma.
+enum { GAUSS_NC = 5 };
+RF_DEV void gauss_prologue(const double* in, double lo, double hi, double* C) {
+  const double mu = in[0], s = in[1];
+  const double za = (lo - mu) / (RF_SQRT2 * s), zb = (hi - mu) / (RF_SQRT2 * s);
+  double diff;
+  if (za >= 0) diff = ::erfc(za) - ::erfc(zb);
+  else if (zb <= 0) diff = ::erfc(-zb) - ::erfc(-za);
+  else diff = ::erf(zb) - ::erf(za);
+  const double N = s * (0.5 * RF_SQRT2PI) * diff;
+  const double ea = ::exp(-za * za), eb = ::exp(-zb * zb);
+  C[0] = 1.0 / N;
+  C[1] = (ea - eb) / N;
+  C[2] = (N - (hi - mu) * eb + (lo - mu) * ea) / (s * N);
+  C[3] = mu;
+  C[4] = 1.0 / s;
+}
+template <typename T> struct GaussK {
+  T invN;
+  Loc<T> mu;
+  T isig;
+  RF_DEV GaussK load(const double* C) {
+    GaussK k;
+    k.invN = (T)C[0];
+    k.mu = Loc<T>::make(C[3]);
+    k.isig = (T)C[4];
+    return k;
+  }
+};
+template <typename T> RF_DEV T gauss_eval(T x, const GaussK<T>& k, T* d) {
+  const T z = k.mu.sub(x) * k.isig;
+  const T u = RM<T>::exp((T)-0.5 * z * z);
+  d[0] = z * k.isig;       // d log u / d mu
+  d[1] = z * z * k.isig;   // d log u / d sigma
+  return u;
+}
+
+// ============================================================= Chebyshev ==
+// u = 1 + sum_{k=1..n} c_k T_k(x'), x' = (2x - lo - hi)/(hi - lo); inputs c_1..c_n.
+// N = (hi - lo) [1 + sum_{k even} c_k / (1 - k^2)].
+template <int NC> RF_DEV void cheb_prologue(const double* in, double lo, double hi, double* C) {
+  double s = 1.0;
+  for (int k = 1; k <= NC; ++k)
+    if ((k & 1) == 0) s += in[k - 1] / (1.0 - (double)(k * k));
+  const double N = (hi - lo) * s;
+  C[0] = 1.0 / N;
+  for (int k = 1; k <= NC; ++k) C[k] = (k & 1) ? 0.0 : 1.0 / ((1.0 - (double)(k * k)) * s);
+  C[NC + 1] = 2.0 / (hi - lo);
+  C[NC + 2] = -(hi + lo) / (hi - lo);
+  for (int k = 1; k <= NC; ++k) C[NC + 2 + k] = in[k - 1];
+}
+template <typename T, int NC> struct ChebK {
+  T invN, a, b;
+  T c[NC];
+  RF_DEV ChebK load(const double* C) {
+    ChebK k;
+    k.invN = (T)C[0];
+    k.a = (T)C[NC + 1];
+    k.b = (T)C[NC + 2];
+    for (int j = 0; j < NC; ++j) k.c[j] = (T)C[NC + 3 + j];
+    return k;
+  }
+};
+template <typename T, int NC> RF_DEV T cheb_eval(T x, const ChebK<T, NC>& k, T* d) {
+  const T xp = fma(x, k.a, k.b);
+  T tkm = (T)1, tk = xp, u = (T)1;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    u = fma(k.c[j], tk, u);
+    d[j] = tk;
+    const T tn = (T)2 * xp * tk - tkm;
+    tkm = tk;
+    tk = tn;
+  }
+  const T iu = RM<T>::rcp(u);
+#pragma unroll
+  for (int j = 0; j < NC; ++j) d[j] *= iu;
+  return u;
+}
+
+// =========================================================== exponential ==
+// form 0: u = exp(-x/tau), input tau;  N = tau e^{-lo/tau} (1 - e^{-(hi-lo)/tau}).
+// form 1: u = exp(lam (x - xc)), input lam, xc = range midpoint (keeps u O(1));
+//         N' = e^{lam(lo - xc)} expm1(lam (hi - lo)) / lam.
+enum { EXP_NC = 5 };
+RF_DEV void exp_prologue(const double* in, double lo, double hi, int form, double* C) {
+  if (form == 0) {
+    const double tau = in[0];
+    const double ea = ::exp(-lo / tau), eb = ::exp(-hi / tau);
+    const double N = -tau * ea * ::expm1(-(hi - lo) / tau);
+    C[0] = 1.0 / N;
+    C[1] = ((1.0 + lo / tau) * ea - (1.0 + hi / tau) * eb) / N;
+    C[2] = -1.0 / tau;  // rate
+    C[3] = 0.0;         // centre
+    C[4] = 1.0 / (tau * tau);
+  } else {
+    const double lam = in[0], xc = 0.5 * (lo + hi);
+    const double a = lo - xc, b = hi - xc;
+    double N, dN;
+    if (::fabs(lam) * (hi - lo) < 1e-8) {
+      N = b - a;
+      dN = 0.5 * (b * b - a * a);
+    } else {
+      const double ea = ::exp(lam * a), eb = ::exp(lam * b);
+      N = ea * ::expm1(lam * (b - a)) / lam;
+      dN = (b * eb - a * ea) / lam - N / lam;
+    }
+    C[0] = 1.0 / N;
+    C[1] = dN / N;
+    C[2] = lam;
+    C[3] = xc;
+    C[4] = 0.0;
+  }
+}
+template <typename T> struct ExpK {
+  T invN;
+  Scl<T> rate;
+  Loc<T> xc;
+  T dfac;  // form 0: 1/tau^2 (d log u/d tau = x/tau^2); form 1: 0 (d log u/d lam = x - xc)
+  RF_DEV ExpK load(const double* C) {
+    ExpK k;
+    k.invN = (T)C[0];
+    k.rate = Scl<T>::make(C[2]);
+    k.xc = Loc<T>::make(C[3]);
+    k.dfac = (T)C[4];
+    return k;
+  }
+};
+template <typename T, int FORM> RF_DEV T exp_eval(T x, const ExpK<T>& k, T* d) {
+  if (FORM == 0) {
+    d[0] = x * k.dfac;
+    return RM<T>::exp(k.rate.mul(x));
+  }
+  const T xs = k.xc.sub(x);
+  d[0] = xs;
+  return RM<T>::exp(k.rate.mul(xs));
+}
+
+// ========================================= decay (x) Gaussian resolution ==
+// Single-sided decay exp(-t'/tau), t' >= 0, smeared by a Gaussian of width s
+// and mean b.  With u = t - b:
+//   F(t) = 1/2 exp(s^2/(2 tau^2) - u/tau) erfc((s^2/tau - u)/(sqrt2 s)),
+//   antiderivative A(t) = tau [Phi(u/s) - F(t)],  N = A(hi) - A(lo).
+// Inputs (tau, s, b).
+enum { DECAY_NC = 12 };
+RF_DEV double decay_F(double u, double tau, double s, double* dF) {
+  const double w = (s * s / tau - u) / (RF_SQRT2 * s);
+  const double G = ::exp(-u * u / (2 * s * s));
+  double F;
+  if (w > 4.0) F = 0.5 * G * ::erfcx(w);
+  else F = 0.5 * ::exp(s * s / (2 * tau * tau) - u / tau) * ::erfc(w);
+  dF[0] = F * (u / (tau * tau) - s * s / (tau * tau * tau)) + s * G * RF_INV_SQRT2PI / (tau * tau);
+  dF[1] = F * s / (tau * tau) - G * (1.0 / tau + u / (s * s)) * RF_INV_SQRT2PI;
+  dF[2] = F / tau - G * RF_INV_SQRT2PI / s;
+  return F;
+}
+RF_DEV double decay_A(double t, double tau, double s, double b, double* dA) {
+  const double u = t - b;
+  double dF[3];
+  const double F = decay_F(u, tau, s, dF);
+  const double Phi = 0.5 * ::erfc(-u / (RF_SQRT2 * s));
+  const double G = ::exp(-u * u / (2 * s * s));
+  dA[0] = Phi - F - tau * dF[0];
+  dA[1] = tau * (-u * G * RF_INV_SQRT2PI / (s * s) - dF[1]);
+  dA[2] = tau * (-G * RF_INV_SQRT2PI / s - dF[2]);
+  return tau * (Phi - F);
+}
+RF_DEV void decay_prologue(const double* in, double lo, double hi, double* C) {
+  const double tau = in[0], s = in[1], b = in[2];
+  double dh[3], dl[3];
+  const double N = decay_A(hi, tau, s, b, dh) - decay_A(lo, tau, s, b, dl);
+  C[0] = 1.0 / N;
+  for (int j = 0; j < 3; ++j) C[1 + j] = (dh[j] - dl[j]) / N;
+  C[4] = b;                                    // location
+  C[5] = -1.0 / tau;                           // exponent slope
+  C[6] = s * s / (2 * tau * tau);              // exponent offset
+  C[7] = s * s / tau;                          // erfc shift
+  C[8] = 1.0 / (RF_SQRT2 * s);                 // erfc scale
+  C[9] = -1.0 / (2 * s * s);                   // resolution exponent factor
+  C[10] = 1.0 / (tau * tau);
+  C[11] = s / (tau * tau);
+}
+template <typename T> struct DecayK {
+  T invN;
+  Loc<T> b;
+  Scl<T> slope;
+  T off, shift, wscale, gfac, itau2, s_tau2, c_tau_s, c_s, c_b, itau, is2;
+  RF_DEV DecayK load(const double* C) {
+    DecayK k;
+    k.invN = (T)C[0];
+    k.b = Loc<T>::make(C[4]);
+    k.slope = Scl<T>::make(C[5]);
+    k.off = (T)C[6];
+    k.shift = (T)C[7];
+    k.wscale = (T)C[8];
+    k.gfac = (T)C[9];
+    k.itau2 = (T)C[10];
+    k.s_tau2 = (T)C[11];
+    const double s = 1.0 / (RF_SQRT2 * C[8]);
+    const double tau = -1.0 / C[5];
+    k.itau = (T)(1.0 / tau);
+    k.is2 = (T)(1.0 / (s * s));
+    k.c_tau_s = (T)(s * RF_INV_SQRT2PI / (tau * tau));  // coefficient of G/F in d/dtau
+    k.c_s = (T)RF_INV_SQRT2PI;
+    k.c_b = (T)(RF_INV_SQRT2PI / s);
+    return k;
+  }
+};
+template <typename T> RF_DEV T decay_eval(T x, const DecayK<T>& k, T* d) {
+  const T u = k.b.sub(x);
+  const T w = (k.shift - u) * k.wscale;
+  const T G = RM<T>::exp(k.gfac * u * u);
+  T F;
+  if (w > (T)4) F = (T)0.5 * G * RM<T>::erfcx(w);
+  else F = (T)0.5 * RM<T>::exp(k.slope.mul(u) + k.off) * RM<T>::erfc(w);
+  const T r = F > (T)0 ? G * RM<T>::rcp(F) : (T)0;  // G / F
+  // d log F / d(tau, s, b)
+  d[0] = (u - k.shift) * k.itau2 + k.c_tau_s * r;
+  d[1] = k.s_tau2 - r * (k.itau + u * k.is2) * k.c_s;
+  d[2] = k.itau - r * k.c_b;
+  return F;
+}
+
+// ================================================================= ARGUS ==
+// u = m sqrt(U) exp(c U), U = 1 - (m/m0)^2 = (m0 - m)(m0 + m)/m0^2, m < m0;
+// inputs (m0 -- must be a constant, c <= 0).  With k = -c:
+//   J(U) = int_0^U v^{1/2} e^{-kv} dv,  J3(U) = int_0^U v^{3/2} e^{-kv} dv,
+//   N = m0^2/2 [J(U(lo)) - J(U(min(hi, m0)))],  dN/dc = m0^2/2 [J3(U(lo)) - J3(U(top))].
+enum { ARGUS_NC = 6 };
+RF_DEV void argus_J(double U, double k, double* J, double* J3) {
+  if (U <= 0) { *J = 0; *J3 = 0; return; }
+  if (k * U < 1.0) {
+    // alternating series, fast for kU < 1 where the closed form cancels
+    double sJ = 0, sJ3 = 0, term = 1.0, Upow = U * ::sqrt(U);
+    for (int n = 0; n < 40; ++n) {
+      sJ += term * Upow / (n + 1.5);
+      sJ3 += term * Upow * U / (n + 2.5);
+      term *= -k * U / (n + 1);
+    }
+    *J = sJ; *J3 = sJ3;
+    return;
+  }
+  const double sq = ::sqrt(k * U);
+  const double e = ::exp(-k * U);
+  *J = RF_SQRTPI / (2 * k * ::sqrt(k)) * ::erf(sq) - ::sqrt(U) * e / k;
+  *J3 = 1.5 / k * (*J) - U * ::sqrt(U) * e / k;
+}
+RF_DEV void argus_prologue(const double* in, double lo, double hi, double* C) {
+  const double m0 = in[0], c = in[1], k = -c;
+  const double top = hi < m0 ? hi : m0;
+  const double Ul = (m0 - lo) * (m0 + lo) / (m0 * m0);
+  const double Ut = (m0 - top) * (m0 + top) / (m0 * m0);
+  double Jl, J3l, Jt, J3t;
+  argus_J(Ul, k, &Jl, &J3l);
+  argus_J(Ut, k, &Jt, &J3t);
+  const double N = 0.5 * m0 * m0 * (Jl - Jt);
+  C[0] = 1.0 / N;
+  C[1] = 0.0;
+  C[2] = 0.5 * m0 * m0 * (J3l - J3t) / N;
+  C[3] = m0;
+  C[4] = 1.0 / (m0 * m0);
+  C[5] = c;
+}
+template <typename T> struct ArgusK {
+  T invN;
+  Loc<T> m0;
+  T m0f, im02, c;
+  RF_DEV ArgusK load(const double* C) {
+    ArgusK k;
+    k.invN = (T)C[0];
+    k.m0 = Loc<T>::make(C[3]);
+    k.m0f = (T)C[3];
+    k.im02 = (T)C[4];
+    k.c = (T)C[5];
+    return k;
+  }
+};
+template <typename T> RF_DEV T argus_eval(T x, const ArgusK<T>& k, T* d) {
+  const T dm = -k.m0.sub(x);  // m0 - x
+  const T U = dm * (k.m0f + x) * k.im02;
+  d[0] = (T)0;
+  d[1] = U;
+  if (!(dm > (T)0)) { d[1] = (T)0; return (T)0; }
+  return x * RM<T>::sqrt(U) * RM<T>::exp(k.c * U);
+}
+
+// ========================================================= Breit-Wigner ==
+// u = 1/((x-M)^2 + Gamma^2/4);  inputs (M, Gamma);
+// N = (2/Gamma)[atan(2(hi-M)/Gamma) - atan(2(lo-M)/Gamma)].
+enum { BW_NC = 5 };
+RF_DEV void bw_norm(double lo, double hi, double M, double G, double* N, double* dM, double* dG) {
+  const double qh = 2 * (hi - M) / G, ql = 2 * (lo - M) / G;
+  const double n = 2.0 / G * (::atan(qh) - ::atan(ql));
+  const double bl = 1.0 / ((lo - M) * (lo - M) + 0.25 * G * G);
+  const double bh = 1.0 / ((hi - M) * (hi - M) + 0.25 * G * G);
+  *N = n;
+  *dM = bl - bh;
+  *dG = -n / G - 2.0 / (G * G) * (qh / (1 + qh * qh) - ql / (1 + ql * ql));
+}
+RF_DEV void bw_prologue(const double* in, double lo, double hi, double* C) {
+  double N, dM, dG;
+  bw_norm(lo, hi, in[0], in[1], &N, &dM, &dG);
+  C[0] = 1.0 / N;
+  C[1] = dM / N;
+  C[2] = dG / N;
+  C[3] = in[0];
+  C[4] = 0.25 * in[1] * in[1];
+}
+template <typename T> struct BwK {
+  T invN;
+  Loc<T> M;
+  T g2, hg;
+  RF_DEV BwK load(const double* C) {
+    BwK k;
+    k.invN = (T)C[0];
+    k.M = Loc<T>::make(C[3]);
+    k.g2 = (T)C[4];
+    k.hg = (T)::sqrt(C[4]);
+    return k;
+  }
+};
+template <typename T> RF_DEV T bw_eval(T x, const BwK<T>& k, T* d) {
+  const T q = k.M.sub(x);
+  const T b = RM<T>::rcp(fma(q, q, k.g2));
+  d[0] = (T)2 * q * b;
+  d[1] = -k.hg * b;
+  return b;
+}
+
+// ====================================================== reductions, misc ==
+// TwoSum (Knuth): s + e == a + b exactly.
+RF_DEV void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+// double-double accumulate (hi, lo) += (bh, bl)
+RF_DEV void dd_add(double& hi, double& lo, double bh, double bl) {
+  double s, e;
+  two_sum(hi, bh, s, e);
+  e += lo + bl;
+  hi = s + e;
+  lo = e - (hi - s);
+}
+
+RF_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+RF_DEV unsigned wave_sum_u(unsigned v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+RF_DEV void wave_dd_sum(double& hi, double& lo) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double h2 = __shfl_xor(hi, o, 64), l2 = __shfl_xor(lo, o, 64);
+    // combine in a fixed (lane-order independent) way: smaller lane first
+    const bool first = ((int)(threadIdx.x & 63) & o) == 0;
+    double ah = first ? hi : h2, al = first ? lo : l2;
+    double bh = first ? h2 : hi, bl = first ? l2 : lo;
+    dd_add(ah, al, bh, bl);
+    hi = ah;
+    lo = al;
+  }
+}

@@ -1,0 +1,23 @@
+// rf_kabi.h -- argument block of the generated likelihood kernels.  Shared by
+// the host launcher and the generated device source (passed by value as the
+// kernel argument buffer), so both sides agree on the layout.
+#pragma once
+#include <stdint.h>
+
+#define RF_MAX_COLS 8
+#define RF_MAX_PARAMS 64
+
+struct RfArgs {
+  const void* col[RF_MAX_COLS];  // observable columns (float or double)
+  int64_t n;                     // number of events
+  double* part;                  // block partials: [nsum][2 (hi, lo)][nblk_max]
+  unsigned* part_bad;            // per-block count of bad events [nblk_max]
+  unsigned* ticket;              // last-block ticket (0 between launches)
+  double* out;                   // result: [nll, grad[P], n_bad, sums...]
+  void* values;                  // per-event output of the values kernel
+  const double* aux;             // auxiliary FP64 inputs (e.g. surrogate normalisation)
+  const void* weights;           // MLP weights (bf16)
+  int32_t nblk_max;              // stride of part (>= gridDim.x)
+  int32_t pad_;
+  double theta[RF_MAX_PARAMS];   // parameter point
+};

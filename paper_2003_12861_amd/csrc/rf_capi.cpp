@@ -1,0 +1,251 @@
+// rf_capi.cpp -- programs: compile, bind, launch, read back.
+#include <cmath>
+#include <cstring>
+
+#include "rf_internal.h"
+
+using namespace rf;
+
+namespace {
+
+int cu_count(int dev) {
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+  return n;
+}
+
+void free_workspace(rf_program* p) {
+  if (p->d_part) hipFree(p->d_part);
+  if (p->d_part_bad) hipFree(p->d_part_bad);
+  if (p->d_ticket) hipFree(p->d_ticket);
+  if (p->d_out) hipFree(p->d_out);
+  if (p->h_out) hipHostFree(p->h_out);
+  if (p->d_aux) hipFree(p->d_aux);
+  p->d_part = nullptr;
+  p->d_part_bad = nullptr;
+  p->d_ticket = nullptr;
+  p->d_out = nullptr;
+  p->h_out = nullptr;
+  p->d_aux = nullptr;
+}
+
+int out_len(const rf_program* p) { return p->L.n_params + 2 + p->L.n_sums; }
+
+int choose_blocks(const rf_program* p) {
+  if (p->blocks_override > 0) return p->blocks_override;
+  const int64_t per = (int64_t)p->block * 16;
+  int64_t b = (p->n + per - 1) / per;
+  const int64_t cap = (int64_t)cu_count(p->device) * 8;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+void fill_args(const rf_program* p, const double* theta, RfArgs& a) {
+  memset(&a, 0, sizeof a);
+  for (int c = 0; c < RF_MAX_COLS; ++c) a.col[c] = p->cols[c];
+  a.n = p->n;
+  a.part = p->d_part;
+  a.part_bad = p->d_part_bad;
+  a.ticket = p->d_ticket;
+  a.out = p->d_out;
+  a.aux = p->d_aux;
+  a.weights = p->d_weights;
+  a.nblk_max = p->nblk_max;
+  for (int k = 0; k < p->L.n_params; ++k) a.theta[k] = theta[k];
+}
+
+int launch(rf_program* p, hipFunction_t f, RfArgs& a, void* stream) {
+  size_t sz = sizeof(RfArgs);
+  void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &sz, HIP_LAUNCH_PARAM_END};
+  hipError_t e = hipModuleLaunchKernel(f, p->nblk, 1, 1, p->block, 1, 1, 0, (hipStream_t)stream, nullptr, cfg);
+  if (e != hipSuccess) return hip_fail(e, "hipModuleLaunchKernel");
+  return RF_OK;
+}
+
+int ready(rf_program* p, const double* theta) {
+  if (!p) return fail(RF_E_INVALID, "program is NULL");
+  if (!p->loaded) return fail(RF_E_STATE, "program was compiled without loading (RF_COMPILE_NO_LOAD)");
+  if (p->n < 0) return fail(RF_E_STATE, "columns are not bound");
+  for (int id : p->L.mlp_nodes) {
+    (void)id;
+    if (!p->d_weights) return fail(RF_E_STATE, "MLP weights are not bound");
+  }
+  if (p->L.n_params && !theta) return fail(RF_E_INVALID, "theta is NULL");
+  return check_theta(p->L, theta);
+}
+
+int run_sync(rf_program* p, hipFunction_t f, const double* theta, void* stream) {
+  RfArgs a;
+  fill_args(p, theta, a);
+  int rc = launch(p, f, a, stream);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(p->h_out, p->d_out, sizeof(double) * out_len(p), hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return RF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rf_version(void) { return "rfgpu-0.1"; }
+
+int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags, rf_program** out) {
+  if (!g || !out) return fail(RF_E_INVALID, "NULL argument");
+  *out = nullptr;
+  rf_program* p = new rf_program();
+  int rc = lower(g->nodes, top, precision, p->L);
+  if (rc) { delete p; return rc; }
+  if (p->L.has_numconv || p->L.has_mlp) {
+    delete p;
+    return fail(RF_E_INVALID, "convolution and MLP leaves are not supported by this build");
+  }
+  p->source = generate_source(p->L, p->block, p->unroll);
+  rc = build_code_object(p->source, p->co_path);
+  if (rc) { delete p; return rc; }
+  if (!(flags & RF_COMPILE_NO_LOAD)) {
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+    rc = load_module(p->co_path, p->m);
+    if (rc) { delete p; return rc; }
+    p->loaded = true;
+  }
+  *out = p;
+  return RF_OK;
+}
+
+void rf_program_free(rf_program* p) {
+  if (!p) return;
+  free_workspace(p);
+  if (p->m.mod) hipModuleUnload(p->m.mod);
+  delete p;
+}
+
+int rf_program_info(const rf_program* p, int32_t* n_params, int32_t* n_columns, int32_t* n_sums) {
+  if (!p) return fail(RF_E_INVALID, "program is NULL");
+  if (n_params) *n_params = p->L.n_params;
+  if (n_columns) *n_columns = p->L.n_cols;
+  if (n_sums) *n_sums = p->L.n_sums;
+  return RF_OK;
+}
+
+const char* rf_program_source(const rf_program* p) { return p ? p->source.c_str() : ""; }
+
+int rf_set_launch(rf_program* p, int32_t blocks, int32_t threads) {
+  if (!p) return fail(RF_E_INVALID, "program is NULL");
+  if (blocks < 0) return fail(RF_E_INVALID, "blocks < 0");
+  if (threads != 0 && threads != p->block) return fail(RF_E_INVALID, "threads per block is fixed at compile time");
+  if (p->n >= 0 && blocks > p->nblk_max) return fail(RF_E_INVALID, "blocks exceeds the workspace sized at bind time");
+  p->blocks_override = blocks;
+  if (p->n >= 0) p->nblk = choose_blocks(p);
+  return RF_OK;
+}
+
+int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, int64_t n_events, void* stream) {
+  (void)stream;
+  if (!p) return fail(RF_E_INVALID, "program is NULL");
+  if (!p->loaded) return fail(RF_E_STATE, "program was compiled without loading");
+  if (n_cols != p->L.n_cols) return fail(RF_E_INVALID, "number of columns differs from the number of observables");
+  if (n_events < 0) return fail(RF_E_INVALID, "n_events < 0");
+  if (n_events > 0 && n_cols > 0 && !dev_cols) return fail(RF_E_INVALID, "columns are NULL");
+  for (int c = 0; c < n_cols; ++c) {
+    if (n_events > 0 && !dev_cols[c]) return fail(RF_E_INVALID, "column pointer is NULL");
+    p->cols[c] = dev_cols ? dev_cols[c] : nullptr;
+  }
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev != p->device) return fail(RF_E_STATE, "current device differs from the one the program was loaded on");
+  p->n = n_events;
+  const int saved = p->blocks_override;
+  p->blocks_override = 0;
+  const int need = choose_blocks(p);
+  p->blocks_override = saved;
+  const int cap = cu_count(dev) * 8;
+  const int nmax = need > cap ? need : cap;
+  if (!p->d_out || nmax > p->nblk_max) {
+    free_workspace(p);
+    hipError_t e;
+    const size_t np = (size_t)p->L.n_sums * 2 * nmax;
+    if ((e = hipMalloc(&p->d_part, sizeof(double) * np)) != hipSuccess) return hip_fail(e, "hipMalloc partials");
+    if ((e = hipMalloc(&p->d_part_bad, sizeof(unsigned) * nmax)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&p->d_out, sizeof(double) * out_len(p))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipHostMalloc(&p->h_out, sizeof(double) * out_len(p), hipHostMallocDefault)) != hipSuccess)
+      return hip_fail(e, "hipHostMalloc");
+    if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMemset");
+    p->nblk_max = nmax;
+  }
+  p->nblk = choose_blocks(p);
+  if (p->nblk > p->nblk_max) p->nblk = p->nblk_max;
+  return RF_OK;
+}
+
+int rf_bind_weights(rf_program* p, int32_t node, const void* dev_bf16, void* stream) {
+  (void)stream;
+  if (!p) return fail(RF_E_INVALID, "program is NULL");
+  bool found = false;
+  for (int id : p->L.mlp_nodes) found |= id == node;
+  if (!found) return fail(RF_E_INVALID, "node is not an MLP leaf of this program");
+  if (!dev_bf16) return fail(RF_E_INVALID, "weights are NULL");
+  p->d_weights = dev_bf16;
+  return RF_OK;
+}
+
+int rf_eval_values(rf_program* p, const double* theta, void* dev_out, void* stream) {
+  int rc = ready(p, theta);
+  if (rc) return rc;
+  if (p->n > 0 && !dev_out) return fail(RF_E_INVALID, "dev_out is NULL");
+  RfArgs a;
+  fill_args(p, theta, a);
+  a.values = dev_out;
+  return launch(p, p->m.k_values, a, stream);
+}
+
+int rf_nll(rf_program* p, const double* theta, double* nll, int64_t* n_bad, void* stream) {
+  int rc = ready(p, theta);
+  if (rc) return rc;
+  if (!nll) return fail(RF_E_INVALID, "nll is NULL");
+  rc = run_sync(p, p->m.k_nll, theta, stream);
+  if (rc) return rc;
+  const int64_t bad = (int64_t)p->h_out[p->L.n_params + 1];
+  if (n_bad) *n_bad = bad;
+  *nll = bad ? INFINITY : p->h_out[0];
+  if (bad) return fail(RF_E_NONFINITE, std::to_string(bad) + " events with p <= 0 or non-finite p");
+  return RF_OK;
+}
+
+int rf_nll_grad(rf_program* p, const double* theta, double* nll, double* grad, int64_t* n_bad, void* stream) {
+  int rc = ready(p, theta);
+  if (rc) return rc;
+  if (!nll || (p->L.n_params && !grad)) return fail(RF_E_INVALID, "nll or grad is NULL");
+  rc = run_sync(p, p->m.k_grad, theta, stream);
+  if (rc) return rc;
+  const int P = p->L.n_params;
+  const int64_t bad = (int64_t)p->h_out[P + 1];
+  if (n_bad) *n_bad = bad;
+  *nll = bad ? INFINITY : p->h_out[0];
+  for (int k = 0; k < P; ++k) grad[k] = bad ? NAN : p->h_out[1 + k];
+  if (bad) return fail(RF_E_NONFINITE, std::to_string(bad) + " events with p <= 0 or non-finite p");
+  return RF_OK;
+}
+
+int rf_nll_grad_async(rf_program* p, const double* theta, void* stream) {
+  int rc = ready(p, theta);
+  if (rc) return rc;
+  RfArgs a;
+  fill_args(p, theta, a);
+  return launch(p, p->m.k_grad, a, stream);
+}
+
+const double* rf_program_result(const rf_program* p) { return p ? p->d_out : nullptr; }
+
+int rf_gauss_legendre(int32_t K, double lo, double hi, double* x, double* w) {
+  if (K < 1 || !x || !w) return fail(RF_E_INVALID, "bad arguments");
+  rf::gauss_legendre(K, lo, hi, x, w);
+  return RF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// rf_internal.h -- host-side structures of the likelihood library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rfgpu.h"
+#include "device/rf_kabi.h"
+
+namespace rf {
+
+// node kinds beyond the public ops
+enum { K_OBS = 100, K_PARAM = 101, K_CONST = 102 };
+
+struct Node {
+  int32_t op = 0;
+  std::string name;
+  std::vector<int32_t> in;
+  std::vector<double> attrs;
+  double lo = 0, hi = 0;  // OBS range / PARAM bounds
+  double value = 0;       // CONST value
+  int32_t index = -1;     // OBS column / PARAM theta index
+};
+
+bool is_leaf(int op);
+bool is_paramlike(int op);
+bool is_pdf(int op);
+int leaf_n_shape(const Node& n);  // number of shape inputs of a leaf
+
+// error reporting (thread-local message)
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+// ---- lowered program ------------------------------------------------------
+struct Slot {          // a shape/fraction input whose value depends on theta
+  int node;            // leaf or ADD node
+  int j;               // input position among its shape inputs (ADD: fraction j)
+  int pl;              // parameter-like node feeding it
+  int sum;             // index of its event sum D_slot
+};
+
+struct Lowered {
+  std::vector<Node> nodes;         // copy of the graph
+  int top = -1;
+  int precision = RF_FP64;
+  int n_params = 0, n_cols = 0;
+  std::vector<double> plo, phi;    // parameter bounds
+  std::vector<char> reach;
+  std::vector<int> cst_off;        // per node: offset of its FP64 constant block
+  int n_cst = 0;
+  std::vector<int> wsum;           // per leaf: index of its W sum (or -1)
+  std::vector<Slot> slots;
+  int n_sums = 0;                  // including sum 0 (= NLL)
+  bool has_numconv = false, has_mlp = false;
+  std::vector<int> mlp_nodes;      // MLP leaves (need bound weights)
+};
+
+int lower(const std::vector<Node>& g, int top, int precision, Lowered& out);
+std::string generate_source(const Lowered& L, int block_size, int unroll);
+
+// code-object cache + compiler driver
+struct Module {
+  hipModule_t mod = nullptr;
+  hipFunction_t k_values = nullptr, k_nll = nullptr, k_grad = nullptr;
+};
+int build_code_object(const std::string& src, std::string& path_out);
+int load_module(const std::string& path, Module& m);
+uint64_t fnv1a(const std::string& s);
+std::string cache_dir();
+
+// host-side domain checks of a parameter point
+int check_theta(const Lowered& L, const double* theta);
+void eval_paramlike(const Lowered& L, const double* theta, std::vector<double>& pv);
+
+// Gauss-Legendre rule (host)
+void gauss_legendre(int K, double lo, double hi, double* x, double* w);
+
+}  // namespace rf
+
+struct rf_graph {
+  std::vector<rf::Node> nodes;
+  int n_obs = 0, n_params = 0;
+};
+
+struct rf_program {
+  rf::Lowered L;
+  std::string source;
+  std::string co_path;
+  rf::Module m;
+  bool loaded = false;
+  int block = 256, unroll = 1;
+  int blocks_override = 0;
+  // binding
+  const void* cols[RF_MAX_COLS] = {};
+  int64_t n = -1;
+  int nblk = 0, nblk_max = 0;
+  double* d_part = nullptr;
+  unsigned* d_part_bad = nullptr;
+  unsigned* d_ticket = nullptr;
+  double* d_out = nullptr;
+  double* h_out = nullptr;   // pinned
+  double* d_aux = nullptr;   // auxiliary FP64 block (surrogate normalisation, ...)
+  const void* d_weights = nullptr;
+  int device = -1;
+};

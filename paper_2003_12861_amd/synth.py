@@ -122,13 +122,15 @@ def sample_decay_argus(n, seed, tau_s=1.5, sigma_t=0.05, bias_t=0.0, mu_m=5.28,
 
 
 def jitter_decay(k, truth=DECAY_TRUTH, base_seed=3000):
-    """theta*(1 + 0.01 U(-1,1)) per parameter; the resolution bias moves by
-    +-0.001 (additive, its truth is 0).  Order as DECAY_TRUTH."""
+    """theta*(1 + 0.01 U(-1,1)) per scale-type parameter; the two location
+    parameters move additively: the resolution bias by +-0.001 (its truth is
+    0) and the mass mean by +-0.001 GeV (1% of 5.28 GeV would be 17 widths and
+    leave the mass range).  Order as DECAY_TRUTH."""
     rng = np.random.default_rng(base_seed + k)
     out = []
     for name, t in truth.items():
         u = rng.uniform(-1.0, 1.0)
-        out.append(t + 0.001 * u if name == "bias_t" else t * (1.0 + 0.01 * u))
+        out.append(t + 0.001 * u if name in ("bias_t", "mu_m") else t * (1.0 + 0.01 * u))
     return np.array(out)
 
 

@@ -1,6 +1,8 @@
 import os
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -9,3 +11,14 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C ABI on the GPU)")
     config.addinivalue_line("markers", "slow: long-running")
+
+
+def pytest_collection_modifyitems(config, items):
+    have_gpu = None
+    for it in items:
+        if "gpu" in it.keywords:
+            if have_gpu is None:
+                import torch
+                have_gpu = torch.cuda.is_available()
+            if not have_gpu:
+                it.add_marker(pytest.mark.skip(reason="no GPU in this environment"))
