@@ -131,9 +131,13 @@ class Graph:
         self.obs_names = []
 
     def __del__(self):
-        if getattr(self, "h", None):
-            rf_graph_free(self.h)
+        h = getattr(self, "h", None)
+        if h:
             self.h = None
+            try:
+                rf_graph_free(h)
+            except Exception:  # interpreter shutdown: the library may be gone
+                pass
 
     def _id(self, name, rc, out):
         check(rc)
@@ -201,9 +205,13 @@ class Program:
         self.n_events = None
 
     def __del__(self):
-        if getattr(self, "h", None):
-            rf_program_free(self.h)
+        h = getattr(self, "h", None)
+        if h:
             self.h = None
+            try:
+                rf_program_free(h)
+            except Exception:  # interpreter shutdown: the library may be gone
+                pass
 
     @property
     def source(self):
@@ -308,3 +316,42 @@ class NLLFunction(torch.autograd.Function):
     def backward(ctx, gout):
         (g,) = ctx.saved_tensors
         return gout * g, None
+
+
+class Binned:
+    """Binned template likelihood (channels x samples x bins, J nuisances + signal strength)."""
+
+    def __init__(self, T, Tp, Tm, nobs, stream=None):
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        C, S, B = T.shape
+        J = 0 if Tp is None else int(np.asarray(Tp).shape[2])
+        Tp = np.ascontiguousarray(Tp if J else np.ones((C, S, 0, B)), dtype=np.float64)
+        Tm = np.ascontiguousarray(Tm if J else np.ones((C, S, 0, B)), dtype=np.float64)
+        nobs = np.ascontiguousarray(nobs, dtype=np.float64)
+        h = ctypes.c_void_p()
+        check(rf_binned_new(C, S, B, J, _dptr(T), _dptr(Tp), _dptr(Tm), _dptr(nobs), _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.shape = (C, S, B, J)
+        self.n_params = J + 1
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.h = None
+            try:
+                rf_binned_free(h)
+            except Exception:  # interpreter shutdown: the library may be gone
+                pass
+
+    def nll_grad(self, theta, stream=None):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if th.size != self.n_params:
+            raise RfError(-1, "theta needs %d values" % self.n_params)
+        v = ctypes.c_double()
+        g = np.zeros(self.n_params)
+        check(rf_binned_nll_grad(self.h, _dptr(th), ctypes.byref(v), _dptr(g), _stream(stream)))
+        return v.value, g
+
+    def nll_grad_async(self, theta, stream=None):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        check(rf_binned_nll_grad_async(self.h, _dptr(th), _stream(stream)))

@@ -1,7 +1,7 @@
 // rf_body.h -- generic body of a generated likelihood kernel.
 //
 // Included after the generated part, which defines:
-//   RF_T, RF_NCOL, RF_NCST, RF_NSUM, RF_P, RF_BS, RF_UNROLL, RF_TAIL64
+//   RF_T, RF_NCOL, RF_NCST, RF_NSUM, RF_P, RF_BS, RF_PF, RF_TAIL64
 //   struct KS<T>                   per-event constants (loaded from the FP64 block)
 //   rf_prologue(th, cst, a)        FP64 parameter-only branch (normalisations)
 //   rf_eval<T, MODE>(x, k, acc, p) one event: p, -log p and the adjoint sums
@@ -28,6 +28,21 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   __shared__ double fin[NSUM];
   __shared__ int last;
 
+  const int64_t n = a.n;
+  const int64_t step = (int64_t)gridDim.x * RF_BS;
+  const int64_t i0 = (int64_t)blockIdx.x * RF_BS + threadIdx.x;
+  // Prefetch ring: the columns of events i, i+step, ..., i+(RF_PF-1)*step are
+  // in flight while event i is computed (register rotation, no unrolling);
+  // the first loads are issued before the prologue so that their latency
+  // overlaps the FP64 normalisation work.
+  RF_T xq[RF_PF][RF_NCOL > 0 ? RF_NCOL : 1];
+#pragma unroll
+  for (int q = 0; q < RF_PF; ++q) {
+    const int64_t i = i0 + q * step;
+#pragma unroll
+    for (int c = 0; c < RF_NCOL; ++c) xq[q][c] = i < n ? rf_ld<RF_T>(a.col[c], c, i) : (RF_T)0;
+  }
+
   rf_prologue(a.theta, cst, a);
   __syncthreads();
   const KS<RF_T> k = KS<RF_T>::load(cst);
@@ -37,40 +52,37 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   for (int j = 0; j < NSUM; ++j) acc[j] = 0.0;
   unsigned nbad = 0;
 
-  const int64_t n = a.n;
-  const int64_t step = (int64_t)gridDim.x * RF_BS;
-  int64_t i0 = (int64_t)blockIdx.x * RF_BS + threadIdx.x;
-  for (; i0 < n; i0 += step * RF_UNROLL) {
-    RF_T xs[RF_UNROLL][RF_NCOL > 0 ? RF_NCOL : 1];
+  for (int64_t i = i0; i < n; i += step) {
+    RF_T x[RF_NCOL > 0 ? RF_NCOL : 1];
 #pragma unroll
-    for (int u = 0; u < RF_UNROLL; ++u) {
-      const int64_t i = i0 + u * step;
+    for (int c = 0; c < RF_NCOL; ++c) x[c] = xq[0][c];
 #pragma unroll
-      for (int c = 0; c < RF_NCOL; ++c) xs[u][c] = i < n ? rf_ld<RF_T>(a.col[c], c, i) : (RF_T)0;
+    for (int q = 0; q + 1 < RF_PF; ++q)
+#pragma unroll
+      for (int c = 0; c < RF_NCOL; ++c) xq[q][c] = xq[q + 1][c];
+    {
+      const int64_t in = i + RF_PF * step;
+#pragma unroll
+      for (int c = 0; c < RF_NCOL; ++c) xq[RF_PF - 1][c] = in < n ? rf_ld<RF_T>(a.col[c], c, in) : (RF_T)0;
     }
-#pragma unroll
-    for (int u = 0; u < RF_UNROLL; ++u) {
-      const int64_t i = i0 + u * step;
-      if (i >= n) break;
-      RF_T p;
-      const bool ok = rf_eval<RF_T, MODE>(xs[u], k, acc, &p);
-      if (!ok) {
+    RF_T p;
+    const bool ok = rf_eval<RF_T, MODE>(x, k, acc, &p);
+    if (!ok) {
 #if RF_TAIL64
-        // FP32 result too small (or not finite): redo this event in FP64
-        double xd[RF_NCOL > 0 ? RF_NCOL : 1];
+      // FP32 result too small (or not finite): redo this event in FP64
+      double xd[RF_NCOL > 0 ? RF_NCOL : 1];
 #pragma unroll
-        for (int c = 0; c < RF_NCOL; ++c) xd[c] = (double)xs[u][c];
-        const KS<double> kd = KS<double>::load(cst);
-        double pd;
-        const bool okd = rf_eval<double, MODE>(xd, kd, acc, &pd);
-        if (!okd) ++nbad;
-        p = (RF_T)pd;
+      for (int c = 0; c < RF_NCOL; ++c) xd[c] = (double)x[c];
+      const KS<double> kd = KS<double>::load(cst);
+      double pd;
+      const bool okd = rf_eval<double, MODE>(xd, kd, acc, &pd);
+      if (!okd) ++nbad;
+      p = (RF_T)pd;
 #else
-        ++nbad;
+      ++nbad;
 #endif
-      }
-      if (MODE == 0) ((RF_T*)a.values)[i] = p;
     }
+    if (MODE == 0) ((RF_T*)a.values)[i] = p;
   }
   if (MODE == 0) return;
 
@@ -96,7 +108,8 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
     for (int w = 0; w < NW; ++w) t += redbad[w];
     __hip_atomic_store(&a.part_bad[blockIdx.x], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __threadfence();
+  // release this workgroup's partials (only the storing wavefront fences)
+  if ((int)threadIdx.x < NSUM || threadIdx.x == 0) __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) last = (atomicAdd(a.ticket, 1u) == gridDim.x - 1);
   __syncthreads();
@@ -104,19 +117,44 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   __threadfence();
 
   // ---- last workgroup: fixed-order double-double sum of all partials ----
-  for (int j = wid; j < NSUM; j += NW) {
-    double hi = 0.0, lo = 0.0;
-    for (int b = lane; b < (int)gridDim.x; b += 64) {
-      const double ph = __hip_atomic_load(&a.part[(2 * j) * (int64_t)nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const double pl = __hip_atomic_load(&a.part[(2 * j + 1) * (int64_t)nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      dd_add(hi, lo, ph, pl);
+  // Every thread owns the blocks b = tid, tid + RF_BS, ...; eight sums per
+  // pass so that each thread has 16 independent loads in flight.  The
+  // combination order (thread-local, then the wavefront butterfly, then the
+  // wavefronts in index order) does not depend on timing: repeated calls give
+  // bitwise identical results.
+  __shared__ double rh[NW][8], rl[NW][8];
+  const int nb = (int)gridDim.x;
+  for (int j0 = 0; j0 < NSUM; j0 += 8) {
+    double h[8], l[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) { h[u] = 0.0; l[u] = 0.0; }
+    for (int b = threadIdx.x; b < nb; b += RF_BS) {
+      double ph[8], pl[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u < NSUM ? j0 + u : NSUM - 1;
+        ph[u] = __hip_atomic_load(&a.part[(2 * j) * (int64_t)nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pl[u] = __hip_atomic_load(&a.part[(2 * j + 1) * (int64_t)nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) dd_add(h[u], l[u], ph[u], pl[u]);
     }
-    wave_dd_sum(hi, lo);
-    if (lane == 0) fin[j] = hi + lo;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      wave_dd_sum(h[u], l[u]);
+      if (lane == 0) { rh[wid][u] = h[u]; rl[wid][u] = l[u]; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && j0 + (int)threadIdx.x < NSUM) {
+      double H = 0.0, Lo = 0.0;
+      for (int w = 0; w < NW; ++w) dd_add(H, Lo, rh[w][threadIdx.x], rl[w][threadIdx.x]);
+      fin[j0 + threadIdx.x] = H + Lo;
+    }
+    __syncthreads();
   }
   if (wid == 0) {
     unsigned t = 0;
-    for (int b = lane; b < (int)gridDim.x; b += 64)
+    for (int b = lane; b < nb; b += 64)
       t += __hip_atomic_load(&a.part_bad[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     t = wave_sum_u(t);
     if (lane == 0) redbad[0] = t;

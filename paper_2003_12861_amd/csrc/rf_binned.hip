@@ -1,0 +1,298 @@
+// rf_binned.hip -- binned template likelihood (HistFactory-like models,
+// Section 3: per channel and sample a nominal histogram plus +-1 sigma
+// histograms per systematic uncertainty, and a signal strength).
+//
+//   nu_csb = mu^[s=0] T_csb exp(sum_j |alpha_j| L^{sgn alpha_j}_csbj),
+//            L^+- = log(T^+-/T)   (piecewise-exponential interpolation:
+//            alpha = +-1 reproduces the +-1 sigma histogram exactly),
+//   nu_cb  = sum_s nu_csb,
+//   NLL    = sum_cb (nu_cb - n_cb log nu_cb) + sum_j alpha_j^2 / 2.
+//
+// One thread per (channel, bin, sample), the sample index fastest so that
+// the FP32 interpolation tables -- stored as L[c][j][b][s] -- are read with
+// fully coalesced loads; only the table of alpha_j's sign is read.  The 60
+// exponent terms stay in registers and are reused by the adjoint:
+//   dNLL/dalpha_j = sum_cb r_cb sum_s nu_csb dE_csb/dalpha_j + alpha_j,
+//   r_cb = 1 - n_cb / nu_cb.
+// Precision: the tables are FP32 in memory; the 60-term exponent, nu and
+// r are accumulated in FP64 (FP64 FMA runs at the FP32 rate on CDNA4, so this
+// costs no throughput) because near the minimum r ~ 1/sqrt(n) cancels and an
+// FP32 exponent (error ~5e-7) would be amplified ~50x in the gradient.  The
+// per-bin adjoint terms are FP32; each bin's Poisson term and every reduction
+// are FP64; the cross-workgroup reduction is the same deterministic
+// last-workgroup double-double pass as the unbinned kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device/rf_dev.h"
+#include "rf_internal.h"
+
+#define BN_BS 128
+#define BN_MAXJ 64
+
+namespace {
+
+struct BinnedArgs {
+  const float* T;      // [C][B][S]
+  const float* Lp;     // [C][J][B][S]
+  const float* Lm;     // [C][J][B][S]
+  const float* nobs;   // [C][B]
+  double* part;        // [NS][2][nblk]
+  unsigned* ticket;
+  double* out;         // [nll, grad[1+J]]
+  int32_t C, S, B, J;
+  int32_t nblk;
+  int32_t pad_;
+  double theta[1 + BN_MAXJ];
+};
+
+template <int J>
+__global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
+  constexpr int NS = 2 + J;  // NLL, mu, alpha_1..J
+  constexpr int NW = BN_BS / 64;
+  constexpr int RS = ((J + 1) & 1) ? J + 1 : J + 2;  // odd row stride: conflict-free column reads
+  __shared__ float term[BN_BS][RS];  // column 0: d/dmu, column 1 + j: d/dalpha_j
+  __shared__ double nu_s[BN_BS];
+  __shared__ double r_s[BN_BS];
+  __shared__ double nll_w[NW];
+  __shared__ double fin[NS];
+  __shared__ int last;
+  const int S = a.S, B = a.B;
+  const int64_t total = (int64_t)a.C * B * S;
+  const int64_t t = (int64_t)blockIdx.x * BN_BS + threadIdx.x;
+  const bool live = t < total;
+  const int s = live ? (int)(t % S) : 0;
+  const int64_t cb = live ? t / S : 0;  // c * B + b
+  const int c = (int)(cb / B), b = (int)(cb % B);
+
+  // exponent E = sum_j |alpha_j| L^{sgn}_j; keep the 60 table values for the adjoint
+  float Lv[J > 0 ? J : 1];
+  double E = 0.0;
+  const int64_t strideJ = (int64_t)B * S;
+  const int64_t base = ((int64_t)c * J) * strideJ + (int64_t)b * S + s;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const double al = a.theta[1 + j];
+    const float* L = al >= 0.0 ? a.Lp : a.Lm;
+    Lv[j] = live ? L[base + j * strideJ] : 0.f;
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) E = fma(fabs(a.theta[1 + j]), (double)Lv[j], E);
+  const double mu = a.theta[0];
+  const double Tn = live ? (double)a.T[t] : 0.0;  // T laid out [C][B][S] == thread order
+  const double base_nu = Tn * exp(E);             // nu without the signal strength
+  const double nu = (s == 0) ? mu * base_nu : base_nu;
+  nu_s[threadIdx.x] = live ? nu : 0.0;
+  __syncthreads();
+
+  // one thread per (c, b): Poisson term in FP64, r = 1 - n/nu
+  double nllt = 0.0;
+  if (live && s == 0) {
+    double tot = 0.0;
+    for (int q = 0; q < S; ++q) tot += nu_s[threadIdx.x + q];
+    const double n = (double)a.nobs[cb];
+    nllt = tot - n * log(tot);
+    const double r = 1.0 - n / tot;
+    for (int q = 0; q < S; ++q) r_s[threadIdx.x + q] = r;
+  }
+  __syncthreads();
+  const double r = live ? r_s[threadIdx.x] : 0.0;
+  // adjoint terms (FP32): d/dmu (sample 0 only) and d/dalpha_j
+  const float rn = (float)(r * nu);
+  term[threadIdx.x][0] = (live && s == 0) ? (float)(r * base_nu) : 0.f;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const float sg = a.theta[1 + j] >= 0.0 ? 1.f : -1.f;
+    term[threadIdx.x][1 + j] = live ? rn * sg * Lv[j] : 0.f;
+  }
+  const double wn = wave_sum(nllt);
+  if ((threadIdx.x & 63) == 0) nll_w[threadIdx.x >> 6] = wn;
+  __syncthreads();
+  // workgroup partials: column sums in FP64, fixed order
+  for (int k = threadIdx.x; k < NS; k += BN_BS) {
+    double hi = 0.0, lo = 0.0;
+    if (k == 0) {
+      for (int w = 0; w < NW; ++w) dd_add(hi, lo, nll_w[w], 0.0);
+    } else {
+      double sum = 0.0;
+      for (int row = 0; row < BN_BS; ++row) sum += (double)term[row][k - 1];
+      hi = sum;
+    }
+    __hip_atomic_store(&a.part[(2 * k) * (int64_t)a.nblk + blockIdx.x], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&a.part[(2 * k + 1) * (int64_t)a.nblk + blockIdx.x], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if ((int)threadIdx.x < NS) __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(a.ticket, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nb = (int)gridDim.x;
+  for (int k = wid; k < NS; k += NW) {
+    double hi = 0.0, lo = 0.0;
+    for (int q = lane; q < nb; q += 64) {
+      const double ph = __hip_atomic_load(&a.part[(2 * k) * (int64_t)a.nblk + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double pl = __hip_atomic_load(&a.part[(2 * k + 1) * (int64_t)a.nblk + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      dd_add(hi, lo, ph, pl);
+    }
+    wave_dd_sum(hi, lo);
+    if (lane == 0) fin[k] = hi + lo;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double c2 = 0.0;
+    for (int j = 0; j < J; ++j) c2 += 0.5 * a.theta[1 + j] * a.theta[1 + j];
+    a.out[0] = fin[0] + c2;
+    a.out[1] = fin[1];
+    for (int j = 0; j < J; ++j) a.out[2 + j] = fin[2 + j] + a.theta[1 + j];
+    *a.ticket = 0u;
+  }
+}
+
+// kernel instances: the number of nuisance parameters is a template
+// argument so the table values stay in registers
+using BinnedFn = void (*)(const BinnedArgs);
+template <int J> BinnedFn pick() { return rf_binned_kernel<J>; }
+BinnedFn kernel_for(int J) {
+  switch (J) {
+    case 0: return pick<0>();
+    case 1: return pick<1>();
+    case 2: return pick<2>();
+    case 4: return pick<4>();
+    case 8: return pick<8>();
+    case 16: return pick<16>();
+    case 32: return pick<32>();
+    case 60: return pick<60>();
+    case 64: return pick<64>();
+  }
+  return nullptr;
+}
+int padded_J(int J) {
+  const int opts[] = {0, 1, 2, 4, 8, 16, 32, 60, 64};
+  for (int o : opts)
+    if (o >= J) return o;
+  return -1;
+}
+
+}  // namespace
+
+struct rf_binned {
+  int C, S, B, J, Jp;  // Jp: compiled table depth (>= J, extra rows are zero)
+  float *T = nullptr, *Lp = nullptr, *Lm = nullptr, *nobs = nullptr;
+  double *part = nullptr, *out = nullptr, *h_out = nullptr;
+  unsigned* ticket = nullptr;
+  int nblk = 0;
+};
+
+using namespace rf;
+
+extern "C" {
+
+void rf_binned_free(rf_binned* b) {
+  if (!b) return;
+  (void)hipFree(b->T);
+  (void)hipFree(b->Lp);
+  (void)hipFree(b->Lm);
+  (void)hipFree(b->nobs);
+  (void)hipFree(b->part);
+  (void)hipFree(b->out);
+  (void)hipFree(b->ticket);
+  if (b->h_out) (void)hipHostFree(b->h_out);
+  delete b;
+}
+
+int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T, const double* Tp,
+                  const double* Tm, const double* nobs, void* stream, rf_binned** out) {
+  if (!out || !T || !nobs || (J > 0 && (!Tp || !Tm))) return fail(RF_E_INVALID, "NULL argument");
+  if (C < 1 || S < 1 || B < 1 || J < 0) return fail(RF_E_INVALID, "bad shape");
+  if (BN_BS % S != 0) return fail(RF_E_INVALID, "the number of samples must divide 128");
+  const int Jp = padded_J(J);
+  if (Jp < 0) return fail(RF_E_INVALID, "at most 64 nuisance parameters");
+  const size_t nT = (size_t)C * S * B, nL = (size_t)C * Jp * B * S;
+  std::vector<float> hT(nT), hLp(nL > 0 ? nL : 1, 0.f), hLm(nL > 0 ? nL : 1, 0.f), hn((size_t)C * B);
+  for (int c = 0; c < C; ++c)
+    for (int s = 0; s < S; ++s)
+      for (int b = 0; b < B; ++b) {
+        const double t = T[((size_t)c * S + s) * B + b];
+        if (!(t > 0) || !std::isfinite(t)) return fail(RF_E_INVALID, "nominal yields must be finite and > 0");
+        hT[((size_t)c * B + b) * S + s] = (float)t;
+        for (int j = 0; j < J; ++j) {
+          const size_t src = (((size_t)c * S + s) * J + j) * B + b;
+          const size_t dst = (((size_t)c * Jp + j) * B + b) * S + s;
+          if (!(Tp[src] > 0) || !(Tm[src] > 0)) return fail(RF_E_INVALID, "variation yields must be > 0");
+          hLp[dst] = (float)std::log(Tp[src] / t);
+          hLm[dst] = (float)std::log(Tm[src] / t);
+        }
+      }
+  for (size_t i = 0; i < (size_t)C * B; ++i) {
+    if (!(nobs[i] >= 0) || nobs[i] > 16777216.0) return fail(RF_E_INVALID, "observed counts must be in [0, 2^24]");
+    hn[i] = (float)nobs[i];
+  }
+  rf_binned* bn = new rf_binned();
+  bn->C = C; bn->S = S; bn->B = B; bn->J = J; bn->Jp = Jp;
+  const int64_t threads = (int64_t)C * B * S;
+  bn->nblk = (int)((threads + BN_BS - 1) / BN_BS);
+  hipError_t e;
+  hipStream_t st = (hipStream_t)stream;
+  auto up = [&](float** d, const std::vector<float>& h) -> hipError_t {
+    hipError_t r = hipMalloc(d, sizeof(float) * h.size());
+    if (r != hipSuccess) return r;
+    return hipMemcpyAsync(*d, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st);
+  };
+  if ((e = up(&bn->T, hT)) != hipSuccess || (e = up(&bn->Lp, hLp)) != hipSuccess ||
+      (e = up(&bn->Lm, hLm)) != hipSuccess || (e = up(&bn->nobs, hn)) != hipSuccess) {
+    rf_binned_free(bn);
+    return hip_fail(e, "binned upload");
+  }
+  const size_t NS = 2 + Jp;
+  if ((e = hipMalloc(&bn->part, sizeof(double) * NS * 2 * bn->nblk)) != hipSuccess ||
+      (e = hipMalloc(&bn->out, sizeof(double) * (2 + Jp))) != hipSuccess ||
+      (e = hipMalloc(&bn->ticket, sizeof(unsigned))) != hipSuccess ||
+      (e = hipHostMalloc(&bn->h_out, sizeof(double) * (2 + Jp), hipHostMallocDefault)) != hipSuccess ||
+      (e = hipMemsetAsync(bn->ticket, 0, sizeof(unsigned), st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    rf_binned_free(bn);
+    return hip_fail(e, "binned workspace");
+  }
+  *out = bn;
+  return RF_OK;
+}
+
+int rf_binned_nll_grad_async(rf_binned* b, const double* theta, void* stream) {
+  if (!b || !theta) return fail(RF_E_INVALID, "NULL argument");
+  for (int k = 0; k <= b->J; ++k)
+    if (!std::isfinite(theta[k])) return fail(RF_E_DOMAIN, "theta must be finite");
+  if (!(theta[0] >= 0)) return fail(RF_E_DOMAIN, "signal strength must be >= 0");
+  BinnedArgs a;
+  memset(&a, 0, sizeof a);
+  a.T = b->T; a.Lp = b->Lp; a.Lm = b->Lm; a.nobs = b->nobs;
+  a.part = b->part; a.ticket = b->ticket; a.out = b->out;
+  a.C = b->C; a.S = b->S; a.B = b->B; a.J = b->Jp; a.nblk = b->nblk;
+  a.theta[0] = theta[0];
+  for (int j = 0; j < b->J; ++j) a.theta[1 + j] = theta[1 + j];  // padded rows: alpha = 0
+  hipLaunchKernelGGL(kernel_for(b->Jp), dim3(b->nblk), dim3(BN_BS), 0, (hipStream_t)stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "binned launch");
+  return RF_OK;
+}
+
+int rf_binned_nll_grad(rf_binned* b, const double* theta, double* nll, double* grad, void* stream) {
+  if (!nll || !grad) return fail(RF_E_INVALID, "NULL argument");
+  int rc = rf_binned_nll_grad_async(b, theta, stream);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(b->h_out, b->out, sizeof(double) * (2 + b->Jp), hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "binned result");
+  *nll = b->h_out[0];
+  for (int k = 0; k <= b->J; ++k) grad[k] = b->h_out[1 + k];
+  if (!std::isfinite(*nll)) return fail(RF_E_NONFINITE, "non-finite NLL (a bin with nu <= 0)");
+  return RF_OK;
+}
+
+const double* rf_binned_result(const rf_binned* b) { return b ? b->out : nullptr; }
+
+}  // extern "C"

@@ -1,5 +1,6 @@
 // rf_capi.cpp -- programs: compile, bind, launch, read back.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "rf_internal.h"
@@ -102,6 +103,10 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
   if (p->L.has_numconv || p->L.has_mlp) {
     delete p;
     return fail(RF_E_INVALID, "convolution and MLP leaves are not supported by this build");
+  }
+  if (const char* e = getenv("RFGPU_PF")) {  // tuning override of the prefetch distance
+    const int v = atoi(e);
+    if (v >= 1 && v <= 16) p->unroll = v;
   }
   p->source = generate_source(p->L, p->block, p->unroll);
   rc = build_code_object(p->source, p->co_path);

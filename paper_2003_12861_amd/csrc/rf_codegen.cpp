@@ -129,7 +129,7 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   o << "#define RF_NSUM " << L.n_sums << "\n";
   o << "#define RF_P " << L.n_params << "\n";
   o << "#define RF_BS " << BS << "\n";
-  o << "#define RF_UNROLL " << U << "\n";
+  o << "#define RF_PF " << U << "\n";
   o << "#define RF_TAIL64 " << (f32 ? 1 : 0) << "\n\n";
 
   // ---- per-event constants ----

@@ -90,7 +90,7 @@ struct rf_program {
   std::string co_path;
   rf::Module m;
   bool loaded = false;
-  int block = 256, unroll = 1;
+  int block = 256, unroll = 4;  // unroll = prefetch distance (events in flight per thread)
   int blocks_override = 0;
   // binding
   const void* cols[RF_MAX_COLS] = {};
