@@ -42,7 +42,13 @@ template <> struct RM<double> {
   RF_DEV double erfc(double x) { return ::erfc(x); }
   RF_DEV double erfcx(double x) { return ::erfcx(x); }
   RF_DEV double sqrt(double x) { return ::sqrt(x); }
-  RF_DEV double rcp(double x) { return 1.0 / x; }
+  RF_DEV double rcp(double x) {
+    // hardware estimate + two Newton steps (relative error ~1 ulp)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+  }
   RF_DEV bool finite(double x) { return isfinite(x); }
   RF_DEV double tiny() { return 0.0; }
 };
@@ -448,3 +454,136 @@ RF_DEV void wave_dd_sum(double& hi, double& lo) {
     lo = al;
   }
 }
+
+// ================================= Breit-Wigner (x) Crystal Ball, K-point ==
+// S(x) = sum_k w_k CB(y_k) BW(x - y_k), (y_k, w_k) a Gauss-Legendre rule on
+// the resolution window [ylo, yhi]; BW(u) = 1/((u - M)^2 + Gamma^2/4);
+// CB(y) = exp(-z^2/2) for z = y/sigma > -alpha, else A (B - z)^-n with
+// A = (n/alpha)^n exp(-alpha^2/2), B = n/alpha - alpha (mean 0, low tail).
+// N_S = sum_k w_k CB(y_k) I_k with I_k the analytic BW integral over the
+// range, so S/N_S is normalised exactly for the rule.  Inputs
+// (M, Gamma, sigma, alpha, n).
+//
+// The prologue is block-wide: every thread builds table rows for nodes
+// k = tid, tid + RF_BS, ... in LDS:
+//   row k = [ (y_k + M)_hi, (y_k + M)_lo, c_k, dc_k/dsigma, dc_k/dalpha, dc_k/dn ]
+// with c_k = w_k CB(y_k), and N_S and its five derivatives are reduced across
+// the block in a fixed order.  The per-event sweep carries S, dS/dM, dS/dGamma
+// and the three dS/d(CB parameter) sums (forward mode over the rule, so no
+// second pass over the events is needed for the CB parameters).
+enum { NUMCONV_NC = 8 };
+template <typename TT> struct NumconvRow { enum { stride = sizeof(TT) == 4 ? 8 : 6 }; };
+
+RF_DEV double cb_shape(double y, double s, double al, double n, double* d) {
+  const double z = y / s;
+  if (z > -al) {
+    const double v = ::exp(-0.5 * z * z);
+    d[0] = v * z * z / s; d[1] = 0.0; d[2] = 0.0;
+    return v;
+  }
+  const double A = ::pow(n / al, n) * ::exp(-0.5 * al * al);
+  const double B = n / al - al;
+  const double r = B - z;
+  const double v = A * ::pow(r, -n);
+  d[0] = v * (-n * (z / s) / r);
+  d[1] = v * (-n / al - al + n * (n / (al * al) + 1.0) / r);
+  d[2] = v * (::log(n / al) + 1.0 - ::log(r) - n / (al * r));
+  return v;
+}
+
+// block-wide; gl = [x_0..x_{K-1}, w_0..w_{K-1}] on the window (FP64)
+template <int BS, typename TT>
+__device__ void numconv_prologue(const double* in, double lo, double hi, int K, const double* gl,
+                                 double* C, TT* tab, double* scratch /* [BS/64][6] */) {
+  const double M = in[0], G = in[1], s = in[2], al = in[3], n = in[4];
+  constexpr int ST = NumconvRow<TT>::stride;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < K; k += BS) {
+    const double y = gl[k], w = gl[K + k];
+    double dc[3];
+    const double c = w * cb_shape(y, s, al, n, dc);
+    for (int j = 0; j < 3; ++j) dc[j] *= w;
+    const double yM = y + M;
+    const TT hi_ = (TT)yM;
+    TT* row = tab + (size_t)ST * k;
+    row[0] = hi_;
+    row[1] = (TT)(yM - (double)hi_);
+    row[2] = (TT)c;
+    row[3] = (TT)dc[0];
+    row[4] = (TT)dc[1];
+    row[5] = (TT)dc[2];
+    double I, dIM, dIG;
+    bw_norm(lo - y, hi - y, M, G, &I, &dIM, &dIG);
+    acc[0] += c * I;
+    acc[1] += c * dIM;
+    acc[2] += c * dIG;
+    acc[3] += dc[0] * I;
+    acc[4] += dc[1] * I;
+    acc[5] += dc[2] * I;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = 0; j < 6; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) scratch[wid * 6 + j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[6];
+    for (int j = 0; j < 6; ++j) {
+      double h = 0.0, l = 0.0;
+      for (int w = 0; w < BS / 64; ++w) dd_add(h, l, scratch[w * 6 + j], 0.0);
+      t[j] = h + l;
+    }
+    C[0] = 1.0 / t[0];
+    for (int j = 1; j < 6; ++j) C[j] = t[j] / t[0];
+    C[6] = 0.25 * G * G;
+    C[7] = 0.5 * G;
+  }
+}
+template <typename T, typename TT> struct NumconvK {
+  T invN, g2, hg;
+  const TT* tab;
+  RF_DEV NumconvK make(const double* C, const TT* tab) {
+    NumconvK k;
+    k.invN = (T)C[0];
+    k.g2 = (T)C[6];
+    k.hg = (T)C[7];
+    k.tab = tab;
+    return k;
+  }
+};
+// d[0..4] = d log S / d(M, Gamma, sigma, alpha, n)
+template <typename T, typename TT, int K> RF_DEV T numconv_eval(T x, const NumconvK<T, TT>& k, T* d) {
+  constexpr int ST = NumconvRow<TT>::stride;
+  constexpr int CH = 16;  // nodes per FP32 partial before it is added to FP64
+  double S = 0, dM = 0, dG = 0, ds = 0, da = 0, dn = 0;
+  for (int j0 = 0; j0 < K; j0 += CH) {
+    T s1 = 0, m1 = 0, g1 = 0, s3 = 0, a3 = 0, n3 = 0;
+#pragma unroll
+    for (int jj = 0; jj < CH; ++jj) {
+      const int j = j0 + jj;
+      if (K % CH != 0 && j >= K) break;
+      const TT* row = k.tab + ST * j;
+      const T q = ((x - (T)row[0]) - (T)row[1]);
+      const T b = RM<T>::rcp(fma(q, q, k.g2));
+      const T cb = (T)row[2] * b;
+      const T cb2 = cb * b;
+      s1 += cb;
+      m1 = fma(q, cb2, m1);
+      g1 += cb2;
+      s3 = fma((T)row[3], b, s3);
+      a3 = fma((T)row[4], b, a3);
+      n3 = fma((T)row[5], b, n3);
+    }
+    S += (double)s1; dM += (double)m1; dG += (double)g1;
+    ds += (double)s3; da += (double)a3; dn += (double)n3;
+  }
+  const double iS = 1.0 / S;
+  d[0] = (T)(2.0 * dM * iS);
+  d[1] = (T)(-(double)k.hg * dG * iS);
+  d[2] = (T)(ds * iS);
+  d[3] = (T)(da * iS);
+  d[4] = (T)(dn * iS);
+  return (T)S;
+}
+

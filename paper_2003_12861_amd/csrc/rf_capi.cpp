@@ -100,9 +100,9 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
   rf_program* p = new rf_program();
   int rc = lower(g->nodes, top, precision, p->L);
   if (rc) { delete p; return rc; }
-  if (p->L.has_numconv || p->L.has_mlp) {
+  if (p->L.has_mlp) {
     delete p;
-    return fail(RF_E_INVALID, "convolution and MLP leaves are not supported by this build");
+    return fail(RF_E_INVALID, "MLP leaves are not supported by this build");
   }
   if (const char* e = getenv("RFGPU_PF")) {  // tuning override of the prefetch distance
     const int v = atoi(e);
@@ -181,6 +181,11 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
     if ((e = hipHostMalloc(&p->h_out, sizeof(double) * out_len(p), hipHostMallocDefault)) != hipSuccess)
       return hip_fail(e, "hipHostMalloc");
     if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMemset");
+    if (!p->L.aux.empty()) {
+      if ((e = hipMalloc(&p->d_aux, sizeof(double) * p->L.aux.size())) != hipSuccess) return hip_fail(e, "hipMalloc aux");
+      if ((e = hipMemcpy(p->d_aux, p->L.aux.data(), sizeof(double) * p->L.aux.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy aux");
+    }
     p->nblk_max = nmax;
   }
   p->nblk = choose_blocks(p);

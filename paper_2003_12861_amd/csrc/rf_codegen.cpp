@@ -44,6 +44,7 @@ static std::string ktype(const Node& n) {
     case RF_OP_DECAY_GAUSS: return "DecayK<T>";
     case RF_OP_ARGUS: return "ArgusK<T>";
     case RF_OP_BW: return "BwK<T>";
+    case RF_OP_NUMCONV_BW_CB: return "NumconvK<T, RF_TABT>";
   }
   return "void";
 }
@@ -57,9 +58,13 @@ static std::string eval_call(const Node& n, int id, const std::string& x) {
     case RF_OP_DECAY_GAUSS: return "decay_eval<T>(" + x + ", " + k + ", " + d + ")";
     case RF_OP_ARGUS: return "argus_eval<T>(" + x + ", " + k + ", " + d + ")";
     case RF_OP_BW: return "bw_eval<T>(" + x + ", " + k + ", " + d + ")";
+    case RF_OP_NUMCONV_BW_CB:
+      return "numconv_eval<T, RF_TABT, " + std::to_string((int)n.attrs[2]) + ">(" + x + ", " + k + ", " + d + ")";
   }
   return "";
 }
+
+static bool blockwide(const Node& n) { return n.op == RF_OP_NUMCONV_BW_CB; }
 
 static std::string prologue_call(const Node& n, const Lowered& L, const std::string& in) {
   const auto& g = L.nodes;
@@ -130,7 +135,16 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   o << "#define RF_P " << L.n_params << "\n";
   o << "#define RF_BS " << BS << "\n";
   o << "#define RF_PF " << U << "\n";
-  o << "#define RF_TAIL64 " << (f32 ? 1 : 0) << "\n\n";
+  o << "#define RF_TAIL64 " << (f32 ? 1 : 0) << "\n";
+  o << "#define RF_TABT " << (f32 ? "float" : "double") << "\n\n";
+  // LDS tables of block-wide leaves
+  bool any_tab = false;
+  for (int id = 0; id < N; ++id) {
+    if (!L.reach[id] || !blockwide(g[id])) continue;
+    any_tab = true;
+    o << "__shared__ RF_TABT rf_tab_" << id << "[" << (int)g[id].attrs[2] << " * NumconvRow<RF_TABT>::stride];\n";
+  }
+  if (any_tab) o << "__shared__ double rf_scr[RF_BS / 64 * 6];\n\n";
 
   // ---- per-event constants ----
   o << "template <typename T> struct KS {\n";
@@ -143,7 +157,10 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   o << "  RF_DEV KS load(const double* C) {\n    KS k;\n";
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
-    if (is_leaf(g[id].op)) o << "    k.l" << id << " = " << ktype(g[id]) << "::load(C + " << L.cst_off[id] << ");\n";
+    if (blockwide(g[id]))
+      o << "    k.l" << id << " = " << ktype(g[id]) << "::make(C + " << L.cst_off[id] << ", rf_tab_" << id << ");\n";
+    else if (is_leaf(g[id].op))
+      o << "    k.l" << id << " = " << ktype(g[id]) << "::load(C + " << L.cst_off[id] << ");\n";
     if (g[id].op == RF_OP_ADD_PDF) {
       const int nc = ((int)g[id].in.size() + 1) / 2;
       for (int j = 0; j < nc; ++j) o << "    k.a" << id << "[" << j << "] = (T)C[" << L.cst_off[id] + j << "];\n";
@@ -161,6 +178,7 @@ std::string generate_source(const Lowered& L, int BS, int U) {
     if (!L.reach[id]) continue;
     const Node& n = g[id];
     if (!is_leaf(n.op) && n.op != RF_OP_ADD_PDF) continue;
+    if (blockwide(n)) continue;
     const int tid = 64 * (item % NW) + item / NW;
     ++item;
     o << "  if (tid == " << tid << ") {\n";
@@ -178,6 +196,16 @@ std::string generate_source(const Lowered& L, int BS, int U) {
       o << "    cst[" << L.cst_off[id] + nc - 1 << "] = " << rest << ";\n";
     }
     o << "  }\n";
+  }
+  for (int id = 0; id < N; ++id) {
+    if (!L.reach[id] || !blockwide(g[id])) continue;
+    const Node& n = g[id];
+    const Node& ob = g[n.in[0]];
+    o << "  {\n    const double in[] = {";
+    for (size_t j = 1; j < n.in.size(); ++j) o << (j > 1 ? ", " : "") << "pv" << n.in[j];
+    o << "};\n    numconv_prologue<RF_BS, RF_TABT>(in, " << dstr(ob.lo) << ", " << dstr(ob.hi) << ", "
+      << (int)n.attrs[2] << ", a.aux + " << L.aux_off[id] << ", cst + " << L.cst_off[id] << ", rf_tab_" << id
+      << ", rf_scr);\n  }\n";
   }
   o << "  (void)a; (void)tid; (void)cst;\n}\n\n";
 

@@ -184,6 +184,16 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
   }
   L.n_cst = off;
 
+  // auxiliary FP64 inputs: the Gauss-Legendre rule of every convolution leaf
+  L.aux_off.assign(N, -1);
+  for (int id = 0; id < N; ++id) {
+    if (!L.reach[id] || g[id].op != RF_OP_NUMCONV_BW_CB) continue;
+    const int K = (int)g[id].attrs[2];
+    L.aux_off[id] = (int)L.aux.size();
+    L.aux.resize(L.aux.size() + 2 * K);
+    gauss_legendre(K, g[id].attrs[0], g[id].attrs[1], &L.aux[L.aux_off[id]], &L.aux[L.aux_off[id] + K]);
+  }
+
   // event sums: 0 = NLL, then one per theta-dependent input slot, then W per leaf
   int s = 1;
   L.wsum.assign(N, -1);
