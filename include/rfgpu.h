@@ -201,6 +201,16 @@ int rf_adam_step(float* dev_w32, void* dev_w_bf16, float* dev_m, float* dev_v,
                  const float* dev_g, int64_t n, float lr, float beta1, float beta2,
                  float eps, int32_t step, void* stream);
 
+/* dout[i] = scale * (out[i] - target[i])  (gradient of a mean-squared error) */
+int rf_mse_grad(const float* dev_out, const float* dev_target, int64_t n, float scale, float* dev_dout,
+                void* stream);
+/* Exact log p_sig of the Breit-Wigner (x) Crystal Ball signal at per-sample
+ * parameters: dev_xq[n][6] = (x, M, Gamma, sigma, alpha, n) FP64; the same
+ * K-point Gauss-Legendre rule on [ylo, yhi] and normalisation over [lo, hi]
+ * as RF_OP_NUMCONV_BW_CB; dev_out[n] FP64.  The surrogate's training targets. */
+int rf_bwcb_logpdf(const double* dev_xq, int64_t n, int32_t K, double ylo, double yhi, double lo, double hi,
+                   double* dev_out, void* stream);
+
 /* ---- host utility ---------------------------------------------------------- */
 /* K-point Gauss-Legendre nodes and weights on [lo, hi] (ascending) */
 int rf_gauss_legendre(int32_t K, double lo, double hi, double* x, double* w);

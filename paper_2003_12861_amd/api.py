@@ -68,6 +68,8 @@ _OPTIONAL = {
     "rf_mlp_forward": ([_P, _P, _I64, _P, _P, _P], _I32),
     "rf_mlp_backward": ([_P, _P, _P, _P, _I64, _P, _P, _P], _I32),
     "rf_adam_step": ([_P, _P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P], _I32),
+    "rf_mse_grad": ([_P, _P, _I64, _F, _P, _P], _I32),
+    "rf_bwcb_logpdf": ([_P, _I64, _I32, _D, _D, _D, _D, _P, _P], _I32),
 }
 
 
@@ -355,3 +357,44 @@ class Binned:
     def nll_grad_async(self, theta, stream=None):
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
         check(rf_binned_nll_grad_async(self.h, _dptr(th), _stream(stream)))
+
+
+# ----------------------------------------------------------- MLP kernels --
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def mlp_forward(w_bf16, u, out=None, act=None, stream=None):
+    """s = MLP(u) for u (n x 6, FP32 in [-1, 1]) with BF16 weights (8833)."""
+    n = u.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=u.device)
+    check(rf_mlp_forward(_vp(w_bf16), _vp(u), n, _vp(out), _vp(act), _stream(stream)))
+    return out
+
+
+def mlp_backward(w_bf16, u, dout, dw=None, din=None, stream=None):
+    """dw (8833, FP32) = sum over rows of dout * ds/dw; din (n x 6) = dout * ds/du."""
+    n = u.shape[0]
+    if dw is None:
+        dw = torch.empty(8833, dtype=torch.float32, device=u.device)
+    check(rf_mlp_backward(_vp(w_bf16), _vp(u), ctypes.c_void_p(0), _vp(dout), n, _vp(dw), _vp(din), _stream(stream)))
+    return dw, din
+
+
+def adam_step(w32, w_bf16, m, v, g, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(rf_adam_step(_vp(w32), _vp(w_bf16), _vp(m), _vp(v), _vp(g), w32.numel(), lr, beta1, beta2, eps, step,
+                       _stream(stream)))
+
+
+def mse_grad(out, target, scale, dout, stream=None):
+    check(rf_mse_grad(_vp(out), _vp(target), out.numel(), scale, _vp(dout), _stream(stream)))
+
+
+def bwcb_logpdf(xq, K, window, x_range, out=None, stream=None):
+    """Exact log p_sig at per-row parameters; xq: (n x 6) FP64 (x, M, Gamma, sigma, alpha, n)."""
+    n = xq.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=xq.device)
+    check(rf_bwcb_logpdf(_vp(xq), n, K, window[0], window[1], x_range[0], x_range[1], _vp(out), _stream(stream)))
+    return out

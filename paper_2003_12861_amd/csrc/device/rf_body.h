@@ -1,10 +1,10 @@
 // rf_body.h -- generic body of a generated likelihood kernel.
 //
 // Included after the generated part, which defines:
-//   RF_T, RF_NCOL, RF_NCST, RF_NSUM, RF_P, RF_BS, RF_PF, RF_TAIL64
+//   RF_T, RF_NCOL, RF_NCST, RF_NSUM, RF_P, RF_BS, RF_PF, RF_TAIL64, RF_WAVE_UNIFORM
 //   struct KS<T>                   per-event constants (loaded from the FP64 block)
 //   rf_prologue(th, cst, a)        FP64 parameter-only branch (normalisations)
-//   rf_eval<T, MODE>(x, k, acc, p) one event: p, -log p and the adjoint sums
+//   rf_eval<T, MODE>(x, k, acc, p, valid) one event: p, -log p and the adjoint sums
 //   rf_epilogue<MODE>(S, cst, th, out, nbad)  final combination (one thread)
 // MODE 0 = per-event values, 1 = NLL, 2 = NLL + gradient.
 //
@@ -28,6 +28,32 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   __shared__ double fin[NSUM];
   __shared__ int last;
 
+#if RF_WAVE_UNIFORM
+  // whole wavefronts step through the events together (wave-cooperative
+  // leaves); lanes past the end evaluate a valid event and discard it
+  const int64_t n = a.n;
+  const int64_t step = (int64_t)gridDim.x * RF_BS;
+  rf_prologue(a.theta, cst, a);
+  __syncthreads();
+  const KS<RF_T> k = KS<RF_T>::load(cst);
+  double acc[NSUM];
+#pragma unroll
+  for (int j = 0; j < NSUM; ++j) acc[j] = 0.0;
+  unsigned nbad = 0;
+  const int lane0 = threadIdx.x & 63;
+  for (int64_t wb = (int64_t)blockIdx.x * RF_BS + (threadIdx.x & ~63); wb < n; wb += step) {
+    __asm__ volatile("" ::: "memory");
+    const int64_t i = wb + lane0;
+    const bool valid = i < n;
+    RF_T x[RF_NCOL > 0 ? RF_NCOL : 1];
+#pragma unroll
+    for (int c = 0; c < RF_NCOL; ++c) x[c] = rf_ld<RF_T>(a.col[c], c, valid ? i : wb);
+    RF_T p;
+    const bool ok = rf_eval<RF_T, MODE>(x, k, acc, &p, valid);
+    if (valid && !ok) ++nbad;
+    if (MODE == 0 && valid) ((RF_T*)a.values)[i] = p;
+  }
+#else
   const int64_t n = a.n;
   const int64_t step = (int64_t)gridDim.x * RF_BS;
   const int64_t i0 = (int64_t)blockIdx.x * RF_BS + threadIdx.x;
@@ -66,7 +92,7 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
       for (int c = 0; c < RF_NCOL; ++c) xq[RF_PF - 1][c] = in < n ? rf_ld<RF_T>(a.col[c], c, in) : (RF_T)0;
     }
     RF_T p;
-    const bool ok = rf_eval<RF_T, MODE>(x, k, acc, &p);
+    const bool ok = rf_eval<RF_T, MODE>(x, k, acc, &p, true);
     if (!ok) {
 #if RF_TAIL64
       // FP32 result too small (or not finite): redo this event in FP64
@@ -75,7 +101,7 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
       for (int c = 0; c < RF_NCOL; ++c) xd[c] = (double)x[c];
       const KS<double> kd = KS<double>::load(cst);
       double pd;
-      const bool okd = rf_eval<double, MODE>(xd, kd, acc, &pd);
+      const bool okd = rf_eval<double, MODE>(xd, kd, acc, &pd, true);
       if (!okd) ++nbad;
       p = (RF_T)pd;
 #else
@@ -84,6 +110,7 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
     }
     if (MODE == 0) ((RF_T*)a.values)[i] = p;
   }
+#endif
   if (MODE == 0) return;
 
   // ---- workgroup reduction ----

@@ -1,0 +1,319 @@
+// rf_mlp_dev.h -- wave-level engine of the 6-64-64-64-1 tanh MLP (BF16
+// weights, FP32 accumulation) used by the surrogate PDF leaf, its
+// normalisation kernel and the training kernels.  Requires rf_dev.h.
+//
+// Tiles.  A wavefront handles 64 rows (events or training samples) at once;
+// row r belongs to lane r.  A hidden activation tile (64 features x 64 rows)
+// lives in registers in the MFMA accumulator layout of
+// v_mfma_f32_32x32x8bf16_1k: element v of lane l in block (mb, eb) holds
+//     feature 32 mb + 8 (v/4) + 4 (l/32) + v%4,   row 32 eb + l%32,
+// stored at h[(2 mb + eb) * 16 + v].  For out = W h the A operand is a
+// fragment of W (lane l: W[32 mo + l%32][8 s + 4 (l/32) + 0..3]) read from
+// LDS, and the B operand of K-step s is exactly h[(2 (s/4) + eb) * 16 +
+// 4 (s%4) + 0..3] -- the layer output is already the next layer's input
+// layout, so nothing moves between layers.
+//
+// Precision.  Weights are exact in bf16.  FP32 activations enter the MFMA
+// as NSPLIT bf16 parts h = h1 + h2 (+ h3) (each part the round-to-nearest
+// bf16 of the remaining residual); every bf16 x bf16 product is exact in
+// FP32 and the accumulation is FP32, so with NSPLIT = 3 a layer matches an
+// FP32 matrix product (residual below 2^-24 |h|).
+#pragma once
+
+typedef short rf_bf16x4 __attribute__((ext_vector_type(4)));
+typedef float rf_f32x16 __attribute__((ext_vector_type(16)));
+
+#define MLP_NW 8833
+#define MLP_RS 68  // LDS row stride (bf16 elements) of the 64x64 matrices
+enum { MLP_OW1 = 0, MLP_OB1 = 384, MLP_OW2 = 448, MLP_OB2 = 4544, MLP_OW3 = 4608,
+       MLP_OB3 = 8704, MLP_OW4 = 8768, MLP_OB4 = 8832 };
+
+struct MlpLds {
+  unsigned short W2[64 * MLP_RS], W3[64 * MLP_RS];    // [out][in]
+  unsigned short W2T[64 * MLP_RS], W3T[64 * MLP_RS];  // [in][out]
+  float W1[64 * 6], b1[64], b2[64], b3[64], W4[64];
+  float c1[64];  // layer-1 pre-activation of the row-independent inputs
+  float b4;
+};
+
+// Compiler barrier for tile loops: keeps the per-lane weight values in LDS
+// (re-read per tile) instead of letting loop-invariant code motion pin ~300 of
+// them in registers, which would spill.
+#define MLP_TILE_BARRIER() __asm__ volatile("" ::: "memory")
+
+RF_DEV float bf16_bits_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// block-wide: weights (8833 bf16) -> LDS
+RF_DEV void mlp_load(const unsigned short* __restrict__ w, MlpLds& s) {
+  for (int t = threadIdx.x; t < 4096; t += blockDim.x) {
+    const int o = t >> 6, i = t & 63;
+    const unsigned short v2 = w[MLP_OW2 + t], v3 = w[MLP_OW3 + t];
+    s.W2[o * MLP_RS + i] = v2;
+    s.W2T[i * MLP_RS + o] = v2;
+    s.W3[o * MLP_RS + i] = v3;
+    s.W3T[i * MLP_RS + o] = v3;
+  }
+  for (int t = threadIdx.x; t < 384; t += blockDim.x) s.W1[t] = bf16_bits_to_f32(w[MLP_OW1 + t]);
+  for (int t = threadIdx.x; t < 64; t += blockDim.x) {
+    s.b1[t] = bf16_bits_to_f32(w[MLP_OB1 + t]);
+    s.b2[t] = bf16_bits_to_f32(w[MLP_OB2 + t]);
+    s.b3[t] = bf16_bits_to_f32(w[MLP_OB3 + t]);
+    s.W4[t] = bf16_bits_to_f32(w[MLP_OW4 + t]);
+  }
+  if (threadIdx.x == 0) s.b4 = bf16_bits_to_f32(w[MLP_OB4]);
+}
+
+RF_DEV int mlp_feat(int mb, int v, int hl) { return 32 * mb + 8 * (v >> 2) + 4 * hl + (v & 3); }
+
+RF_DEV float mlp_tanh(float x) {
+  // tanh(x) = sign(x) (1 - t) / (1 + t), t = exp(-2|x|) = 2^(-2 log2(e) |x|)
+  const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(x));
+  const float r = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
+  return copysignf(r, x);
+}
+
+// split 4 consecutive activations into NS bf16 parts (packed as MFMA B
+// operands).  Scalar __bf16 values only: element access into vectors of
+// __bf16 combined with a bit cast returned the wrong element.
+RF_DEV short bf16_rne_bits(float x) {
+  const __bf16 h = (__bf16)x;  // round to nearest even (v_cvt_pk_bf16_f32)
+  return __builtin_bit_cast(short, h);
+}
+RF_DEV float bf16_bits_f32(short b) { return __uint_as_float(((unsigned)(unsigned short)b) << 16); }
+
+template <int NS>
+RF_DEV void mlp_split4(const float* h, rf_bf16x4* part) {
+  float r0 = h[0], r1 = h[1], r2 = h[2], r3 = h[3];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const short p0 = bf16_rne_bits(r0), p1 = bf16_rne_bits(r1);
+    const short p2 = bf16_rne_bits(r2), p3 = bf16_rne_bits(r3);
+    if (q + 1 < NS) {
+      r0 -= bf16_bits_f32(p0);
+      r1 -= bf16_bits_f32(p1);
+      r2 -= bf16_bits_f32(p2);
+      r3 -= bf16_bits_f32(p3);
+    }
+    rf_bf16x4 p;
+    p[0] = p0; p[1] = p1; p[2] = p2; p[3] = p3;
+    part[q] = p;
+  }
+}
+
+// One 64x64 layer on a 64-row tile, W a 64x64 LDS matrix (row stride MLP_RS):
+//   MODE 0 (forward):  out = tanh(W in + b)
+//   MODE 1 (backward): out = (W in) * (1 - out^2)   (out holds h on entry)
+// The bf16 parts of the B operand are formed per K-step (12 registers), the
+// four 32x32 accumulators live in the matrix-core accumulator registers.
+template <int NS, int MODE>
+RF_DEV void mlp_layer(const unsigned short* W, const float* b, const float* in, float* out) {
+  const int l = threadIdx.x & 63, hl = l >> 5, lr = l & 31;
+  rf_f32x16 acc[2][2];
+#pragma unroll
+  for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float bv = MODE == 0 ? b[mlp_feat(mo, v, hl)] : 0.0f;
+      acc[mo][0][v] = bv;
+      acc[mo][1][v] = bv;
+    }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    rf_bf16x4 Bq[2][NS];
+#pragma unroll
+    for (int eb = 0; eb < 2; ++eb) mlp_split4<NS>(in + (2 * (s >> 2) + eb) * 16 + 4 * (s & 3), Bq[eb]);
+#pragma unroll
+    for (int mo = 0; mo < 2; ++mo) {
+      const rf_bf16x4 A = *(const rf_bf16x4*)&W[(32 * mo + lr) * MLP_RS + 8 * s + 4 * hl];
+#pragma unroll
+      for (int q = NS - 1; q >= 0; --q) {  // small parts first
+        acc[mo][0] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, Bq[0][q], acc[mo][0], 0, 0, 0);
+        acc[mo][1] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, Bq[1][q], acc[mo][1], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+    for (int eb = 0; eb < 2; ++eb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        float& o = out[(2 * mo + eb) * 16 + v];
+        if (MODE == 0) o = mlp_tanh(acc[mo][eb][v]);
+        else o = acc[mo][eb][v] * (1.0f - o * o);
+      }
+}
+
+// the value of row (32 eb + l%32) held by the partner half: rows of the
+// other half-wave come from lane l ^ 32
+RF_DEV float mlp_rowval(float own, int eb) {
+  const int hl = (threadIdx.x & 63) >> 5;
+  const float other = __shfl_xor(own, 32, 64);
+  return eb == hl ? own : other;
+}
+
+// layer 1 when only input 0 varies per row: a = W1[:,0] u0 + c1
+RF_DEV void mlp_layer1_u0(const MlpLds& s, float u0, float* h1) {
+  const int hl = (threadIdx.x & 63) >> 5;
+  const float ue[2] = {mlp_rowval(u0, 0), mlp_rowval(u0, 1)};
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int o = mlp_feat(mb, v, hl);
+      const float w = s.W1[o * 6], c = s.c1[o];
+      h1[(2 * mb + 0) * 16 + v] = mlp_tanh(fmaf(w, ue[0], c));
+      h1[(2 * mb + 1) * 16 + v] = mlp_tanh(fmaf(w, ue[1], c));
+    }
+}
+
+// layer 1 with all six inputs per row (training)
+RF_DEV void mlp_layer1_full(const MlpLds& s, const float* u, float* h1) {
+  const int hl = (threadIdx.x & 63) >> 5;
+  float ue[2][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    ue[0][j] = mlp_rowval(u[j], 0);
+    ue[1][j] = mlp_rowval(u[j], 1);
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int o = mlp_feat(mb, v, hl);
+#pragma unroll
+      for (int eb = 0; eb < 2; ++eb) {
+        float a = s.b1[o];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a = fmaf(s.W1[o * 6 + j], ue[eb][j], a);
+        h1[(2 * mb + eb) * 16 + v] = mlp_tanh(a);
+      }
+    }
+}
+
+// sum over features of coef[f] * t[f][row] for this lane's own row
+RF_DEV float mlp_rowdot(const float* coef, int stride, const float* t) {
+  const int hl = (threadIdx.x & 63) >> 5;
+  float p[2] = {0.f, 0.f};
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float c = coef[mlp_feat(mb, v, hl) * stride];
+      p[0] = fmaf(c, t[(2 * mb + 0) * 16 + v], p[0]);
+      p[1] = fmaf(c, t[(2 * mb + 1) * 16 + v], p[1]);
+    }
+  const float send = hl ? p[0] : p[1];
+  const float recv = __shfl_xor(send, 32, 64);
+  return (hl ? p[1] : p[0]) + recv;
+}
+
+// forward of a row tile; keeps the hidden activations for a backward pass
+template <int NS>
+RF_DEV float mlp_forward_u0(const MlpLds& s, float u0, float* h1, float* h2, float* h3) {
+  mlp_layer1_u0(s, u0, h1);
+  mlp_layer<NS, 0>(s.W2, s.b2, h1, h2);
+  mlp_layer<NS, 0>(s.W3, s.b3, h2, h3);
+  return mlp_rowdot(s.W4, 1, h3) + s.b4;
+}
+template <int NS>
+RF_DEV float mlp_forward_full(const MlpLds& s, const float* u, float* h1, float* h2, float* h3) {
+  mlp_layer1_full(s, u, h1);
+  mlp_layer<NS, 0>(s.W2, s.b2, h1, h2);
+  mlp_layer<NS, 0>(s.W3, s.b3, h2, h3);
+  return mlp_rowdot(s.W4, 1, h3) + s.b4;
+}
+
+// backward from the per-row cotangent g of the output: leaves
+// d1 = dL/d(pre-activation 1), d2, d3 in the activation arrays' place
+// (h1 <- d1, h2 <- d2, h3 <- d3).
+template <int NS>
+RF_DEV void mlp_backward(const MlpLds& s, float g, float* h1, float* h2, float* h3) {
+  const int hl = (threadIdx.x & 63) >> 5;
+  const float ge[2] = {mlp_rowval(g, 0), mlp_rowval(g, 1)};
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float w = s.W4[mlp_feat(mb, v, hl)];
+#pragma unroll
+      for (int eb = 0; eb < 2; ++eb) {
+        float& t = h3[(2 * mb + eb) * 16 + v];
+        t = ge[eb] * w * (1.0f - t * t);
+      }
+    }
+  mlp_layer<NS, 1>(s.W3T, nullptr, h3, h2);
+  mlp_layer<NS, 1>(s.W2T, nullptr, h2, h1);
+}
+
+// d(output)/d(input j) of the own row from d1 = dL/d(pre-activation 1)
+RF_DEV float mlp_input_grad(const MlpLds& s, const float* d1, int j) { return mlp_rowdot(s.W1 + j, 6, d1); }
+
+// ------------------------------------------------------ surrogate PDF leaf --
+// u(x; q) = exp(s(u0, u1..u5)), u_j = 2 (raw_j - lo_j)/(hi_j - lo_j) - 1 with
+// raw = (x, q1..q5); normalised by Nhat(q) = sum_g w_g exp(s(x_g, q)) over a
+// Gauss-Legendre grid on x's range (computed by rf_mlp_renorm before the
+// likelihood kernel, delivered as [Nhat, dNhat/dq1..5] in the aux block).
+// Constant block: C[0] = 1/Nhat, C[1..5] = d log Nhat / dq_j.
+enum { MLP_NC = 8 };
+
+// block-wide: weights -> LDS, layer-1 constant of the five row-independent
+// inputs q (raw values, box = 6 (lo, hi) pairs, x first), and the scale
+// factors du_j/dq_j
+template <int BS>
+__device__ void mlp_setup(const double* q, const double* box, const unsigned short* w, MlpLds& s, float* qs) {
+  mlp_load(w, s);
+  __syncthreads();
+  for (int o = threadIdx.x; o < 64; o += BS) {
+    float c = s.b1[o];
+    for (int j = 1; j < 6; ++j) {
+      const double u = 2.0 * (q[j - 1] - box[2 * j]) / (box[2 * j + 1] - box[2 * j]) - 1.0;
+      c = fmaf(s.W1[o * 6 + j], (float)u, c);
+    }
+    s.c1[o] = c;
+  }
+  if (threadIdx.x < 5) qs[threadIdx.x] = (float)(2.0 / (box[2 * threadIdx.x + 3] - box[2 * threadIdx.x + 2]));
+}
+
+template <int BS>
+__device__ void mlp_prologue(const double* q, const double* box, const double* nh,
+                             const unsigned short* w, double* C, MlpLds& s, float* qs) {
+  mlp_setup<BS>(q, box, w, s, qs);
+  if (threadIdx.x == 0) {
+    C[0] = 1.0 / nh[0];
+    for (int j = 0; j < 5; ++j) C[1 + j] = nh[1 + j] / nh[0];
+    C[6] = 2.0 / (box[1] - box[0]);
+    C[7] = -(box[1] + box[0]) / (box[1] - box[0]);
+  }
+}
+
+template <typename T> struct MlpK {
+  T invN;
+  float xs, xo;
+  float qs[5];
+  const MlpLds* s;
+  RF_DEV MlpK make(const double* C, const MlpLds* s, const float* qs) {
+    MlpK k;
+    k.invN = (T)C[0];
+    k.xs = (float)C[6];
+    k.xo = (float)C[7];
+    for (int j = 0; j < 5; ++j) k.qs[j] = qs[j];
+    k.s = s;
+    return k;
+  }
+};
+
+// wave-cooperative: every lane of the wavefront must call it together.
+// Returns exp(s) for the lane's event; with GRAD, d[j] = ds/dq_{j+1}.
+template <typename T, int NS, bool GRAD>
+RF_DEV T mlp_leaf_eval(T x, const MlpK<T>& k, T* d) {
+  const float u0 = fmaf((float)x, k.xs, k.xo);
+  float h1[64], h2[64], h3[64];
+  const float sv = mlp_forward_u0<NS>(*k.s, u0, h1, h2, h3);
+  if (GRAD) {
+    mlp_backward<NS>(*k.s, 1.0f, h1, h2, h3);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) d[j] = (T)(mlp_input_grad(*k.s, h1, j + 1) * k.qs[j]);
+  }
+  return (T)expf(sv);
+}

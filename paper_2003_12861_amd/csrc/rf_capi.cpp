@@ -56,7 +56,26 @@ void fill_args(const rf_program* p, const double* theta, RfArgs& a) {
   for (int k = 0; k < p->L.n_params; ++k) a.theta[k] = theta[k];
 }
 
+// parameter-dependent pre-pass: the surrogate leaves' normalisation
+int pre_launch(rf_program* p, const double* theta, void* stream) {
+  if (!p->L.has_mlp) return RF_OK;
+  std::vector<double> pv;
+  eval_paramlike(p->L, theta, pv);
+  for (int id : p->L.mlp_nodes) {
+    const Node& n = p->L.nodes[id];
+    double q[5];
+    for (int j = 0; j < 5; ++j) q[j] = pv[n.in[1 + j]];
+    const int K = (int)n.attrs[12];
+    const double* grid = p->d_aux + p->L.aux_off[id];
+    int rc = mlp_renorm_launch(p->d_weights, q, n.attrs.data(), grid, K, p->d_aux + p->L.aux_off[id] + 2 * K, stream);
+    if (rc) return rc;
+  }
+  return RF_OK;
+}
+
 int launch(rf_program* p, hipFunction_t f, RfArgs& a, void* stream) {
+  int rc = pre_launch(p, a.theta, stream);
+  if (rc) return rc;
   size_t sz = sizeof(RfArgs);
   void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &sz, HIP_LAUNCH_PARAM_END};
   hipError_t e = hipModuleLaunchKernel(f, p->nblk, 1, 1, p->block, 1, 1, 0, (hipStream_t)stream, nullptr, cfg);
@@ -100,10 +119,6 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
   rf_program* p = new rf_program();
   int rc = lower(g->nodes, top, precision, p->L);
   if (rc) { delete p; return rc; }
-  if (p->L.has_mlp) {
-    delete p;
-    return fail(RF_E_INVALID, "MLP leaves are not supported by this build");
-  }
   if (const char* e = getenv("RFGPU_PF")) {  // tuning override of the prefetch distance
     const int v = atoi(e);
     if (v >= 1 && v <= 16) p->unroll = v;

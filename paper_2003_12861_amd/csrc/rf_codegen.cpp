@@ -26,7 +26,7 @@
 
 namespace rf {
 
-#include "_gen/rf_device_src.inc"  // RF_DEV_SRC_KABI, RF_DEV_SRC_OPS, RF_DEV_SRC_BODY
+#include "_gen/rf_device_src.inc"  // RF_DEV_SRC_KABI, _OPS, _MLP, _BODY
 
 static std::string dstr(double v) {
   char b[40];
@@ -45,6 +45,7 @@ static std::string ktype(const Node& n) {
     case RF_OP_ARGUS: return "ArgusK<T>";
     case RF_OP_BW: return "BwK<T>";
     case RF_OP_NUMCONV_BW_CB: return "NumconvK<T, RF_TABT>";
+    case RF_OP_MLP: return "MlpK<T>";
   }
   return "void";
 }
@@ -60,11 +61,12 @@ static std::string eval_call(const Node& n, int id, const std::string& x) {
     case RF_OP_BW: return "bw_eval<T>(" + x + ", " + k + ", " + d + ")";
     case RF_OP_NUMCONV_BW_CB:
       return "numconv_eval<T, RF_TABT, " + std::to_string((int)n.attrs[2]) + ">(" + x + ", " + k + ", " + d + ")";
+    case RF_OP_MLP: return "mlp_leaf_eval<T, RF_NSPLIT, MODE == 2>(" + x + ", " + k + ", " + d + ")";
   }
   return "";
 }
 
-static bool blockwide(const Node& n) { return n.op == RF_OP_NUMCONV_BW_CB; }
+static bool blockwide(const Node& n) { return n.op == RF_OP_NUMCONV_BW_CB || n.op == RF_OP_MLP; }
 
 static std::string prologue_call(const Node& n, const Lowered& L, const std::string& in) {
   const auto& g = L.nodes;
@@ -128,6 +130,7 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   std::ostringstream o;
   o << "// generated by rfgpu: one fused likelihood kernel\n";
   o << RF_DEV_SRC_KABI << "\n" << RF_DEV_SRC_OPS << "\n";
+  if (L.has_mlp) o << RF_DEV_SRC_MLP << "\n#define RF_NSPLIT 3\n";
   o << "#define RF_T " << (f32 ? "float" : "double") << "\n";
   o << "#define RF_NCOL " << L.n_cols << "\n";
   o << "#define RF_NCST " << L.n_cst << "\n";
@@ -135,12 +138,19 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   o << "#define RF_P " << L.n_params << "\n";
   o << "#define RF_BS " << BS << "\n";
   o << "#define RF_PF " << U << "\n";
-  o << "#define RF_TAIL64 " << (f32 ? 1 : 0) << "\n";
+  // programs with an MLP leaf run the event loop in whole wavefronts (the MLP
+  // is wave-cooperative) and evaluate in FP32 only (no FP64 re-evaluation)
+  o << "#define RF_WAVE_UNIFORM " << (L.has_mlp ? 1 : 0) << "\n";
+  o << "#define RF_TAIL64 " << (f32 && !L.has_mlp ? 1 : 0) << "\n";
   o << "#define RF_TABT " << (f32 ? "float" : "double") << "\n\n";
   // LDS tables of block-wide leaves
   bool any_tab = false;
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id] || !blockwide(g[id])) continue;
+    if (g[id].op == RF_OP_MLP) {
+      o << "__shared__ MlpLds rf_mlp_" << id << ";\n__shared__ float rf_mlpqs_" << id << "[5];\n";
+      continue;
+    }
     any_tab = true;
     o << "__shared__ RF_TABT rf_tab_" << id << "[" << (int)g[id].attrs[2] << " * NumconvRow<RF_TABT>::stride];\n";
   }
@@ -157,7 +167,9 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   o << "  RF_DEV KS load(const double* C) {\n    KS k;\n";
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
-    if (blockwide(g[id]))
+    if (g[id].op == RF_OP_MLP)
+      o << "    k.l" << id << " = MlpK<T>::make(C + " << L.cst_off[id] << ", &rf_mlp_" << id << ", rf_mlpqs_" << id << ");\n";
+    else if (blockwide(g[id]))
       o << "    k.l" << id << " = " << ktype(g[id]) << "::make(C + " << L.cst_off[id] << ", rf_tab_" << id << ");\n";
     else if (is_leaf(g[id].op))
       o << "    k.l" << id << " = " << ktype(g[id]) << "::load(C + " << L.cst_off[id] << ");\n";
@@ -203,7 +215,16 @@ std::string generate_source(const Lowered& L, int BS, int U) {
     const Node& ob = g[n.in[0]];
     o << "  {\n    const double in[] = {";
     for (size_t j = 1; j < n.in.size(); ++j) o << (j > 1 ? ", " : "") << "pv" << n.in[j];
-    o << "};\n    numconv_prologue<RF_BS, RF_TABT>(in, " << dstr(ob.lo) << ", " << dstr(ob.hi) << ", "
+    o << "};\n";
+    if (n.op == RF_OP_MLP) {
+      o << "    const double box[12] = {";
+      for (int j = 0; j < 12; ++j) o << (j ? ", " : "") << dstr(n.attrs[j]);
+      o << "};\n    mlp_prologue<RF_BS>(in, box, a.aux + " << L.aux_off[id] + 2 * (int)n.attrs[12]
+        << ", (const unsigned short*)a.weights, cst + " << L.cst_off[id] << ", rf_mlp_" << id << ", rf_mlpqs_" << id
+        << ");\n  }\n";
+      continue;
+    }
+    o << "    numconv_prologue<RF_BS, RF_TABT>(in, " << dstr(ob.lo) << ", " << dstr(ob.hi) << ", "
       << (int)n.attrs[2] << ", a.aux + " << L.aux_off[id] << ", cst + " << L.cst_off[id] << ", rf_tab_" << id
       << ", rf_scr);\n  }\n";
   }
@@ -211,7 +232,7 @@ std::string generate_source(const Lowered& L, int BS, int U) {
 
   // ---- per-event program ----
   o << "template <typename T, int MODE>\n";
-  o << "RF_DEV bool rf_eval(const T* x, const KS<T>& k, double* acc, T* pout) {\n";
+  o << "RF_DEV bool rf_eval(const T* x, const KS<T>& k, double* acc, T* pout, bool valid) {\n";
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
     const Node& n = g[id];
@@ -233,6 +254,7 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   }
   o << "  const T p = v" << L.top << ";\n";
   o << "  *pout = p;\n";
+  o << "  if (!valid) return true;\n";
   o << "  if (!(p > RM<T>::tiny()) || !RM<T>::finite(p)) return false;\n";
   o << "  if (MODE == 0) return true;\n";
   o << "  acc[0] -= (double)RM<T>::log(p);\n";

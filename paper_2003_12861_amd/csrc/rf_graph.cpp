@@ -185,14 +185,26 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
   L.n_cst = off;
 
   // auxiliary FP64 inputs: the Gauss-Legendre rule of every convolution leaf
+  // (on its window); for an MLP leaf the rule on x's range followed by the
+  // six normalisation values [Nhat, dNhat/dq1..5] written before each launch
   L.aux_off.assign(N, -1);
   for (int id = 0; id < N; ++id) {
-    if (!L.reach[id] || g[id].op != RF_OP_NUMCONV_BW_CB) continue;
-    const int K = (int)g[id].attrs[2];
-    L.aux_off[id] = (int)L.aux.size();
-    L.aux.resize(L.aux.size() + 2 * K);
-    gauss_legendre(K, g[id].attrs[0], g[id].attrs[1], &L.aux[L.aux_off[id]], &L.aux[L.aux_off[id] + K]);
+    if (!L.reach[id]) continue;
+    if (g[id].op == RF_OP_NUMCONV_BW_CB) {
+      const int K = (int)g[id].attrs[2];
+      L.aux_off[id] = (int)L.aux.size();
+      L.aux.resize(L.aux.size() + 2 * K);
+      gauss_legendre(K, g[id].attrs[0], g[id].attrs[1], &L.aux[L.aux_off[id]], &L.aux[L.aux_off[id] + K]);
+    } else if (g[id].op == RF_OP_MLP) {
+      const int K = (int)g[id].attrs[12];
+      const Node& ob = g[g[id].in[0]];
+      L.aux_off[id] = (int)L.aux.size();
+      L.aux.resize(L.aux.size() + 2 * K + 6, 0.0);
+      gauss_legendre(K, ob.lo, ob.hi, &L.aux[L.aux_off[id]], &L.aux[L.aux_off[id] + K]);
+    }
   }
+  if (L.has_mlp && precision != RF_FP32_COMP)
+    return fail(RF_E_INVALID, "the MLP leaf runs in FP32 (BF16 weights): compile with RF_FP32_COMP");
 
   // event sums: 0 = NLL, then one per theta-dependent input slot, then W per leaf
   int s = 1;

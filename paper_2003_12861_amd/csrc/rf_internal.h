@@ -76,6 +76,10 @@ std::string cache_dir();
 int check_theta(const Lowered& L, const double* theta);
 void eval_paramlike(const Lowered& L, const double* theta, std::vector<double>& pv);
 
+// surrogate normalisation kernel (rf_mlp.hip)
+int mlp_renorm_launch(const void* w, const double* q5, const double* box12, const double* grid, int K, double* out,
+                      void* stream);
+
 // Gauss-Legendre rule (host)
 void gauss_legendre(int K, double lo, double hi, double* x, double* w);
 

@@ -1,0 +1,394 @@
+// rf_mlp.hip -- kernels of the learned surrogate: the normalisation of the
+// surrogate PDF, training forward/backward/Adam, and the exact convolution
+// targets it is trained on.
+//
+// The surrogate replaces the expensive numerically convolved signal PDF
+// (Breit-Wigner (x) Crystal Ball by a K-point rule) with a 6-64-64-64-1 tanh
+// MLP s(x, M, Gamma, sigma, alpha, n) ~ log p_sig, BF16 weights and FP32
+// accumulation on the matrix cores (see device/rf_mlp_dev.h for the tile
+// layout).  Training uses the project's own kernels end to end:
+//   targets  rf_bwcb_logpdf   exact log p_sig at per-sample parameters (FP64)
+//   forward  rf_mlp_forward   MFMA forward of 64-row tiles per wavefront
+//   loss     rf_mse_grad      dL/ds for a mean-squared-error loss
+//   backward rf_mlp_backward  MFMA backward of the activations; weight
+//                             gradients from LDS-staged tiles, one private
+//                             partial per workgroup, summed in a fixed order
+//   update   rf_adam_step     Adam on FP32 master weights, BF16 copy (RNE)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "device/rf_dev.h"
+#include "device/rf_mlp_dev.h"
+#include "rf_internal.h"
+
+#define MLP_SPLIT 3
+
+namespace {
+
+// ---------------------------------------------------------- normalisation --
+struct RenormArgs {
+  const unsigned short* w;
+  const double* grid;  // [x_0..x_{K-1}, w_0..w_{K-1}] on x's range
+  double* out;         // [Nhat, dNhat/dq1..5]
+  int K;
+  int pad_;
+  double q[5];
+  double box[12];
+};
+
+__global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
+  __shared__ MlpLds s;
+  __shared__ float qs[5];
+  __shared__ double red[4][6];
+  mlp_setup<256>(a.q, a.box, a.w, s, qs);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const float xs = (float)(2.0 / (a.box[1] - a.box[0]));
+  const float xo = (float)(-(a.box[1] + a.box[0]) / (a.box[1] - a.box[0]));
+  for (int t = wid; t * 64 < a.K; t += 4) {  // wave-uniform loop
+    MLP_TILE_BARRIER();
+    const int g = t * 64 + lane;
+    const bool valid = g < a.K;
+    const double xg = a.grid[valid ? g : 0];
+    const double wg = valid ? a.grid[a.K + g] : 0.0;
+    const float u0 = fmaf((float)xg, xs, xo);
+    float h1[64], h2[64], h3[64];
+    const float sv = mlp_forward_u0<MLP_SPLIT>(s, u0, h1, h2, h3);
+    mlp_backward<MLP_SPLIT>(s, 1.0f, h1, h2, h3);
+    const double e = wg * exp((double)sv);
+    acc[0] += e;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) acc[1 + j] += e * (double)(mlp_input_grad(s, h1, j + 1) * qs[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) red[wid][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double h = 0.0, l = 0.0;
+    for (int w = 0; w < 4; ++w) dd_add(h, l, red[w][threadIdx.x], 0.0);
+    a.out[threadIdx.x] = h + l;
+  }
+}
+
+// ----------------------------------------------------------------- forward --
+// act (optional): per row the three hidden layers [h1 | h2 | h3], stored as
+// each layer completes so that no more than two layers are live at a time
+RF_DEV void mlp_store_act(float* act, int64_t t, int64_t n, int L, const float* h) {
+  const int lane = threadIdx.x & 63, hl = lane >> 5, lr = lane & 31;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int eb = 0; eb < 2; ++eb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t r = t * 64 + 32 * eb + lr;
+        if (r < n) act[r * 192 + 64 * L + mlp_feat(mb, v, hl)] = h[(2 * mb + eb) * 16 + v];
+      }
+}
+
+template <bool ACT>
+__global__ __launch_bounds__(256) void mlp_fwd_kernel(const unsigned short* w, const float* in, int64_t n,
+                                                      float* out, float* act) {
+  __shared__ MlpLds s;
+  mlp_load(w, s);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t ntile = (n + 63) / 64;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wid; t < ntile; t += (int64_t)gridDim.x * 4) {
+    MLP_TILE_BARRIER();
+    const int64_t row = t * 64 + lane;
+    const bool valid = row < n;
+    float u[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) u[j] = valid ? in[row * 6 + j] : 0.0f;
+    float ha[64], hb[64];
+    mlp_layer1_full(s, u, ha);
+    if (ACT) mlp_store_act(act, t, n, 0, ha);
+    mlp_layer<MLP_SPLIT, 0>(s.W2, s.b2, ha, hb);
+    if (ACT) mlp_store_act(act, t, n, 1, hb);
+    mlp_layer<MLP_SPLIT, 0>(s.W3, s.b3, hb, ha);
+    if (ACT) mlp_store_act(act, t, n, 2, ha);
+    const float sv = mlp_rowdot(s.W4, 1, ha) + s.b4;
+    if (valid) out[row] = sv;
+  }
+}
+
+// ---------------------------------------------------------------- backward --
+#define TS 65  // LDS row stride of the staged [row][feature] tiles
+struct BwdLds {
+  float HT[3][64 * TS];  // forward activations h1, h2, h3
+  float DT[3][64 * TS];  // dL/d(pre-activation) d1, d2, d3
+  float UT[64 * 6];
+  float G[64];
+};
+
+__global__ __launch_bounds__(64) void mlp_bwd_kernel(const unsigned short* w, const float* in, const float* dout,
+                                                     int64_t n, float* part, float* din) {
+  __shared__ MlpLds s;
+  __shared__ BwdLds b;
+  mlp_load(w, s);
+  const int lane = threadIdx.x, hl = lane >> 5, lr = lane & 31;
+  float* P = part + (size_t)blockIdx.x * MLP_NW;
+  for (int k = lane; k < MLP_NW; k += 64) P[k] = 0.0f;
+  __syncthreads();
+  const int64_t ntile = (n + 63) / 64;
+  for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+    MLP_TILE_BARRIER();
+    const int64_t row = t * 64 + lane;
+    const bool valid = row < n;
+    float u[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) u[j] = valid ? in[row * 6 + j] : 0.0f;
+    const float g = valid ? dout[row] : 0.0f;
+    float h[3][64];
+    (void)mlp_forward_full<MLP_SPLIT>(s, u, h[0], h[1], h[2]);
+    // stage forward activations, inputs and output cotangents
+#pragma unroll
+    for (int L = 0; L < 3; ++L)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int eb = 0; eb < 2; ++eb)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) b.HT[L][(32 * eb + lr) * TS + mlp_feat(mb, v, hl)] = h[L][(2 * mb + eb) * 16 + v];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) b.UT[lane * 6 + j] = u[j];
+    b.G[lane] = g;
+    mlp_backward<MLP_SPLIT>(s, g, h[0], h[1], h[2]);
+#pragma unroll
+    for (int L = 0; L < 3; ++L)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int eb = 0; eb < 2; ++eb)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) b.DT[L][(32 * eb + lr) * TS + mlp_feat(mb, v, hl)] = h[L][(2 * mb + eb) * 16 + v];
+    if (din) {  // uniform: every lane takes part in the cross-lane sums
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const float gj = mlp_input_grad(s, h[0], j);
+        if (valid) din[row * 6 + j] = gj;
+      }
+    }
+    __syncthreads();
+    // weight gradients: lane = output unit o; sums over the 64 rows of the tile
+    {
+      const int o = lane;
+      // layers 3 (d3 x h2) and 2 (d2 x h1)
+#pragma unroll
+      for (int L = 2; L >= 1; --L) {
+        const float* D = b.DT[L];
+        const float* H = b.HT[L - 1];
+        float accw[64], accb = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) accw[i] = 0.0f;
+        for (int e = 0; e < 64; ++e) {
+          const float d = D[e * TS + o];
+          accb += d;
+#pragma unroll
+          for (int i = 0; i < 64; ++i) accw[i] = fmaf(d, H[e * TS + i], accw[i]);
+        }
+        const int ow = L == 2 ? MLP_OW3 : MLP_OW2, ob = L == 2 ? MLP_OB3 : MLP_OB2;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) P[ow + o * 64 + i] += accw[i];
+        P[ob + o] += accb;
+      }
+      // layer 1 (d1 x u)
+      {
+        float acc1[6] = {0, 0, 0, 0, 0, 0}, accb = 0.0f;
+        for (int e = 0; e < 64; ++e) {
+          const float d = b.DT[0][e * TS + o];
+          accb += d;
+#pragma unroll
+          for (int j = 0; j < 6; ++j) acc1[j] = fmaf(d, b.UT[e * 6 + j], acc1[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) P[MLP_OW1 + o * 6 + j] += acc1[j];
+        P[MLP_OB1 + o] += accb;
+      }
+      // output layer (g x h3): lane = input unit i
+      {
+        float acc4 = 0.0f, accg = 0.0f;
+        for (int e = 0; e < 64; ++e) {
+          acc4 = fmaf(b.G[e], b.HT[2][e * TS + o], acc4);
+          accg += b.G[e];
+        }
+        P[MLP_OW4 + o] += acc4;
+        if (o == 0) P[MLP_OB4] += accg;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void mlp_dw_reduce_kernel(const float* part, int nblk, float* dw) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= MLP_NW) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += (double)part[(size_t)b * MLP_NW + k];
+  dw[k] = (float)s;
+}
+
+__global__ void adam_kernel(float* w32, unsigned short* wbf, float* m, float* v, const float* g, int64_t n,
+                            float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w32[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w32[i] = wi;
+  const __bf16 hb = (__bf16)wi;  // round to nearest even
+  wbf[i] = __builtin_bit_cast(unsigned short, hb);
+}
+
+__global__ void mse_grad_kernel(const float* out, const float* y, int64_t n, float scale, float* dout) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dout[i] = scale * (out[i] - y[i]);
+}
+
+// exact log p_sig(x; M, Gamma, sigma, alpha, n) per sample (FP64): the same
+// rule as the convolution leaf, with per-sample parameters
+__global__ void bwcb_logpdf_kernel(const double* xq, int64_t n, const double* gl, int K, double lo, double hi,
+                                   double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = xq[i * 6], M = xq[i * 6 + 1], G = xq[i * 6 + 2];
+  const double sg = xq[i * 6 + 3], al = xq[i * 6 + 4], nn = xq[i * 6 + 5];
+  double S = 0.0, N = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double y = gl[k], wk = gl[K + k];
+    double dc[3];
+    const double c = wk * cb_shape(y, sg, al, nn, dc);
+    const double q = x - y - M;
+    S += c / (q * q + 0.25 * G * G);
+    double I, dIM, dIG;
+    bw_norm(lo - y, hi - y, M, G, &I, &dIM, &dIG);
+    N += c * I;
+  }
+  out[i] = log(S / N);
+}
+
+int launch_err(const char* what) {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? RF_OK : rf::hip_fail(e, what);
+}
+
+std::mutex g_ws_mu;
+float* g_part = nullptr;
+size_t g_part_n = 0;
+double* g_gl = nullptr;
+int g_gl_K = 0;
+double g_gl_lo = 0, g_gl_hi = 0;
+
+}  // namespace
+
+namespace rf {
+int mlp_renorm_launch(const void* w, const double* q5, const double* box12, const double* grid, int K, double* out,
+                      void* stream) {
+  RenormArgs a;
+  memset(&a, 0, sizeof a);
+  a.w = (const unsigned short*)w;
+  a.grid = grid;
+  a.out = out;
+  a.K = K;
+  for (int j = 0; j < 5; ++j) a.q[j] = q5[j];
+  for (int j = 0; j < 12; ++j) a.box[j] = box12[j];
+  hipLaunchKernelGGL(mlp_renorm_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, a);
+  return launch_err("mlp_renorm");
+}
+}  // namespace rf
+
+using namespace rf;
+
+extern "C" {
+
+int rf_mlp_forward(const void* w, const float* in, int64_t n, float* out, float* act, void* stream) {
+  if (!w || (n > 0 && (!in || !out)) || n < 0) return fail(RF_E_INVALID, "bad arguments");
+  if (n == 0) return RF_OK;
+  const int64_t ntile = (n + 63) / 64;
+  int blocks = (int)((ntile + 3) / 4);
+  if (blocks > 2048) blocks = 2048;
+  if (act)
+    hipLaunchKernelGGL(mlp_fwd_kernel<true>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const unsigned short*)w,
+                       in, n, out, act);
+  else
+    hipLaunchKernelGGL(mlp_fwd_kernel<false>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const unsigned short*)w, in, n, out, act);
+  return launch_err("mlp_forward");
+}
+
+int rf_mlp_backward(const void* w, const float* in, const float* act, const float* dout, int64_t n, float* dw,
+                    float* din, void* stream) {
+  (void)act;  // activations are recomputed from the inputs (cheaper than reading them back)
+  if (!w || !dw || n < 0 || (n > 0 && (!in || !dout))) return fail(RF_E_INVALID, "bad arguments");
+  const int64_t ntile = (n + 63) / 64;
+  int nblk = (int)(ntile < 512 ? (ntile > 0 ? ntile : 1) : 512);
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (g_part_n < (size_t)nblk * MLP_NW) {
+    if (g_part) (void)hipFree(g_part);
+    g_part = nullptr;
+    g_part_n = 0;
+    hipError_t e = hipMalloc(&g_part, sizeof(float) * (size_t)nblk * MLP_NW);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc mlp partials");
+    g_part_n = (size_t)nblk * MLP_NW;
+  }
+  hipLaunchKernelGGL(mlp_bwd_kernel, dim3(nblk), dim3(64), 0, (hipStream_t)stream, (const unsigned short*)w, in, dout,
+                     n, g_part, din);
+  int rc = launch_err("mlp_backward");
+  if (rc) return rc;
+  hipLaunchKernelGGL(mlp_dw_reduce_kernel, dim3((MLP_NW + 255) / 256), dim3(256), 0, (hipStream_t)stream, g_part, nblk,
+                     dw);
+  return launch_err("mlp_dw_reduce");
+}
+
+int rf_adam_step(float* w32, void* wbf, float* m, float* v, const float* g, int64_t n, float lr, float beta1,
+                 float beta2, float eps, int32_t step, void* stream) {
+  if (!w32 || !wbf || !m || !v || !g || n < 0 || step < 1) return fail(RF_E_INVALID, "bad arguments");
+  const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w32,
+                     (unsigned short*)wbf, m, v, g, n, lr, beta1, beta2, eps, c1, c2);
+  return launch_err("adam");
+}
+
+int rf_mse_grad(const float* out, const float* target, int64_t n, float scale, float* dout, void* stream) {
+  if (n < 0 || (n > 0 && (!out || !target || !dout))) return fail(RF_E_INVALID, "bad arguments");
+  if (n == 0) return RF_OK;
+  hipLaunchKernelGGL(mse_grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, out, target,
+                     n, scale, dout);
+  return launch_err("mse_grad");
+}
+
+int rf_bwcb_logpdf(const double* xq, int64_t n, int32_t K, double ylo, double yhi, double lo, double hi, double* out,
+                   void* stream) {
+  if (n < 0 || K < 2 || K > 4096 || !(ylo < yhi) || !(lo < hi) || (n > 0 && (!xq || !out)))
+    return fail(RF_E_INVALID, "bad arguments");
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (!g_gl || g_gl_K != K || g_gl_lo != ylo || g_gl_hi != yhi) {
+    if (g_gl) (void)hipFree(g_gl);
+    g_gl = nullptr;
+    std::vector<double> h(2 * K);
+    gauss_legendre(K, ylo, yhi, h.data(), h.data() + K);
+    hipError_t e = hipMalloc(&g_gl, sizeof(double) * 2 * K);
+    if (e == hipSuccess) e = hipMemcpy(g_gl, h.data(), sizeof(double) * 2 * K, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "bwcb rule upload");
+    g_gl_K = K;
+    g_gl_lo = ylo;
+    g_gl_hi = yhi;
+  }
+  if (n == 0) return RF_OK;
+  hipLaunchKernelGGL(bwcb_logpdf_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, (hipStream_t)stream, xq, n,
+                     g_gl, K, lo, hi, out);
+  return launch_err("bwcb_logpdf");
+}
+
+}  // extern "C"

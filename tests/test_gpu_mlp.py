@@ -1,0 +1,118 @@
+"""GPU tests of the learned surrogate: MFMA MLP kernels against the FP64 oracle
+MLP evaluated with the same BF16-rounded weights, the training kernels, the
+exact-target kernel, and the surrogate PDF leaf inside a compiled likelihood."""
+import numpy as np
+import pytest
+
+from helpers import build_pair, rel, scaled_grad_err, to_dev
+from oracle import rfo
+from paper_2003_12861_amd import synth, workloads
+
+pytestmark = pytest.mark.gpu
+api = pytest.importorskip("paper_2003_12861_amd.api")
+torch = pytest.importorskip("torch")
+from paper_2003_12861_amd import surrogate  # noqa: E402
+
+
+def _weights(seed, scale=1.0):
+    w32 = torch.tensor(surrogate.init_weights(seed) * scale, device="cuda")
+    rng = np.random.default_rng(seed + 100)
+    for off in (384, 4544, 8704):  # non-zero biases exercise the bias path
+        w32[off:off + 64] = torch.tensor(rng.uniform(-0.2, 0.2, 64), dtype=torch.float32, device="cuda")
+    w32[8832] = 0.3
+    wbf = w32.to(torch.bfloat16)
+    return wbf, wbf.float().double().cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [1, 64, 1037])
+def test_mlp_forward_backward_vs_oracle(n):
+    print("case mlp fwd/bwd n=%d" % n, flush=True)
+    wbf, w64 = _weights(1)
+    rng = np.random.default_rng(n)
+    u = rng.uniform(-1, 1, (n, 6)).astype(np.float32)
+    dout = rng.normal(size=n).astype(np.float32)
+    ud = torch.tensor(u, device="cuda")
+    s = api.mlp_forward(wbf, ud).double().cpu().numpy()
+    s_ref = rfo.mlp_forward(w64, u.astype(np.float64))
+    np.testing.assert_allclose(s, s_ref, rtol=2e-6, atol=2e-6)
+    din = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+    dw, _ = api.mlp_backward(wbf, ud, torch.tensor(dout, device="cuda"), din=din)
+    dw_ref, din_ref = rfo.mlp_backward(w64, u.astype(np.float64), dout.astype(np.float64))
+    dw = dw.double().cpu().numpy()
+    scale = np.abs(dw_ref).max()
+    np.testing.assert_allclose(dw, dw_ref, rtol=0, atol=2e-5 * scale)
+    np.testing.assert_allclose(din.double().cpu().numpy(), din_ref, rtol=0, atol=2e-5 * np.abs(din_ref).max())
+
+
+def test_mlp_activations_layout():
+    n = 70
+    wbf, w64 = _weights(2)
+    u = torch.rand((n, 6), device="cuda") * 2 - 1
+    act = torch.empty((n, 192), dtype=torch.float32, device="cuda")
+    s1 = api.mlp_forward(wbf, u)
+    s2 = api.mlp_forward(wbf, u, act=act)
+    assert torch.equal(s1, s2)
+    # layer 1 by hand from the stored inputs
+    W1 = w64[:384].reshape(64, 6)
+    b1 = w64[384:448]
+    h1 = np.tanh(u.double().cpu().numpy() @ W1.T + b1)
+    np.testing.assert_allclose(act[:, :64].double().cpu().numpy(), h1, atol=2e-6)
+
+
+def test_adam_step_and_bf16_copy():
+    n = 8833
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=n).astype(np.float32)
+    w32 = torch.tensor(w, device="cuda")
+    wbf = w32.to(torch.bfloat16)
+    m = torch.zeros_like(w32)
+    v = torch.zeros_like(w32)
+    mm, vv, ww = np.zeros(n), np.zeros(n), w.astype(np.float64)
+    for step in (1, 2, 3):
+        g = rng.normal(size=n).astype(np.float32)
+        api.adam_step(w32, wbf, m, v, torch.tensor(g, device="cuda"), 1e-3, step)
+        mm = 0.9 * mm + 0.1 * g
+        vv = 0.999 * vv + 0.001 * g.astype(np.float64) ** 2
+        ww = ww - 1e-3 * (mm / (1 - 0.9 ** step)) / (np.sqrt(vv / (1 - 0.999 ** step)) + 1e-8)
+    np.testing.assert_allclose(w32.double().cpu().numpy(), ww, rtol=1e-6, atol=1e-7)
+    assert torch.equal(wbf, w32.to(torch.bfloat16))  # round to nearest even
+
+
+def test_exact_targets_vs_oracle():
+    raw = synth.sobol_design(200, seed=11)
+    xq = torch.tensor(raw, dtype=torch.float64, device="cuda")
+    y = api.bwcb_logpdf(xq, 1024, synth.BWCB_WINDOW, synth.BWCB_RANGE).cpu().numpy()
+    m, top, ids = rfo.from_spec(workloads.spec_bwcb())
+    ref = np.empty(raw.shape[0])
+    for i, r in enumerate(raw):
+        # p_sig(x) = S(x)/N: the mixture with f = 1 isolates the signal
+        thf = list(r[1:]) + [-0.02, 1.0]
+        ref[i] = np.log(m.values(top, thf, [np.array([r[0]])])[0])
+    np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [1000, 20_001])
+def test_surrogate_leaf_vs_oracle(n):
+    print("case surrogate leaf n=%d" % n, flush=True)
+    wbf, w64 = _weights(4, scale=0.7)
+    x = synth.sample_bw_cb(n, 5)
+    spec = workloads.spec_bwcb(surrogate=True)
+    prog, (om, otop, oids) = build_pair(spec, api.FP32, api)
+    prog.bind(to_dev([x], api.FP32, api))
+    prog.bind_weights("sig", wbf)
+    om.set_mlp_weights(oids["sig"], w64)
+    for th in ([91.19, 2.5, 1.5, 1.5, 3.0, -0.02, 0.8], [90.5, 2.1, 2.2, 0.9, 6.0, -0.015, 0.7]):
+        nll, g, nb = prog.nll_grad(th)
+        onll, og, oga, onb = om.nll_ex(otop, th, [x])
+        assert nb == onb == 0
+        assert rel(nll, onll) <= 2e-6, (nll, onll)
+        err = scaled_grad_err(g, og, oga)
+        assert err.max() <= 2e-5, err
+        v = prog.values(th).double().cpu().numpy()
+        np.testing.assert_allclose(v, om.values(otop, th, [x]), rtol=5e-6)
+
+
+def test_training_reduces_error():
+    res = surrogate.train_surrogate(n_train=65536, epochs=4, batch=4096, lr=3e-3, log=print)
+    h = res["history"]
+    assert h[-1]["holdout_rms"] < 0.5 * h[0]["holdout_rms"], h
