@@ -7,14 +7,15 @@
 //   - start: inverse Hessian = diag(1 / H_kk), H_kk from a one-sided
 //     difference of the analytic gradient (scale-aware for parameters whose
 //     natural scales differ by orders of magnitude);
-//   - line search: Armijo backtracking; a trial point outside the declared
-//     bounds or with NLL = +inf (events with p <= 0) is treated as a failed
-//     step and halved;
+//   - line search on the directional derivative (curvature condition, secant
+//     bracketing); a trial point outside the declared bounds, with NLL = +inf
+//     (events with p <= 0) or a clear rise of NLL counts as an overshoot;
 //   - convergence: EDM = g^T H^-1 g / 2 < edm_tol;
 //   - uncertainties: H from central differences of the analytic gradient at
 //     the minimum, sigma_k = sqrt((H^-1)_kk).
 // Gauss-Legendre nodes for the quadrature leaves are computed here as well.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -166,19 +167,52 @@ extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, 
           if (i != j) H[i * P + j] = 0.0;
       continue;
     }
-    double alpha = 1.0, fn = 0.0;
+    // Line search on phi'(a) = g(x + a d) . d, which the adjoint gives to
+    // ~1e-7 of its scale even in FP32, while FP32 NLL values carry rounding
+    // noise far above the decrease near a minimum.  Accept when the
+    // directional derivative has dropped to half its start (curvature
+    // condition); bracket and interpolate (secant) otherwise.  Points outside
+    // the bounds, with p <= 0 events or with a clear rise of NLL count as
+    // overshoot.
+    double alpha = 1.0, fn = 0.0, lo_a = 0.0, hi_a = -1.0, s_lo = slope;
     bool ok = false;
-    for (int ls = 0; ls < 60; ++ls, alpha *= 0.5) {
+    for (int ls = 0; ls < 40; ++ls) {
       bool inside = true;
       for (int i = 0; i < P; ++i) {
         xn[i] = x[i] + alpha * d[i];
         if (xn[i] < lo[i] || xn[i] > hi[i]) inside = false;
       }
-      if (!inside) continue;
-      rc = ev(xn.data(), &fn, gn.data());
-      if (rc == RF_E_NONFINITE || rc == RF_E_DOMAIN) continue;
-      if (rc) return rc;
-      if (fn <= f + 1e-4 * alpha * slope) { ok = true; break; }
+      bool over = !inside;
+      double sn = 0.0;
+      if (inside) {
+        rc = ev(xn.data(), &fn, gn.data());
+        if (rc && rc != RF_E_NONFINITE && rc != RF_E_DOMAIN) return rc;
+        if (rc) over = true;
+        else {
+          for (int i = 0; i < P; ++i) sn += gn[i] * d[i];
+          const double rise_tol = 1e-6 * std::fabs(f) + 1e-9;
+          if (fn > f + 0.5 * alpha * std::fabs(slope) + rise_tol) over = true;
+        }
+      }
+      if (!over && std::fabs(sn) <= 0.5 * std::fabs(slope)) { ok = true; break; }
+      if (!over && sn < 0) {  // still descending: move the lower end up
+        lo_a = alpha;
+        s_lo = sn;
+        alpha = hi_a < 0 ? 2.0 * alpha : 0.5 * (lo_a + hi_a);
+        if (hi_a < 0 && alpha > 64.0) break;
+        continue;
+      }
+      hi_a = alpha;  // overshoot
+      if (!over && sn > 0) {
+        double a2 = lo_a - s_lo * (hi_a - lo_a) / (sn - s_lo);  // secant zero of phi'
+        const double w = hi_a - lo_a;
+        if (!(a2 > lo_a + 0.1 * w)) a2 = lo_a + 0.1 * w;
+        if (!(a2 < hi_a - 0.1 * w)) a2 = hi_a - 0.1 * w;
+        alpha = a2;
+      } else {
+        alpha = 0.5 * (lo_a + hi_a);
+      }
+      if (hi_a - lo_a < 1e-12) break;
     }
     if (!ok) break;
     double ys = 0.0;
@@ -213,7 +247,10 @@ extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, 
     std::vector<double> Hf(P * P), gp(P), gm(P);
     bool good = true;
     for (int k = 0; k < P && good; ++k) {
-      double h = 1e-3 * std::sqrt(std::fabs(H[k * P + k]));
+      // a tenth of the estimated sigma: large enough that FP32 gradient noise is
+      // negligible, small enough for the quadratic region
+      double h = 0.1 * std::sqrt(std::fabs(H[k * P + k]));
+      if (x[k] + h > hi[k] || x[k] - h < lo[k]) h = 0.5 * std::min(hi[k] - x[k], x[k] - lo[k]);
       if (!(h > 0)) h = 1e-8;
       xn = x;
       xn[k] = x[k] + h;

@@ -49,15 +49,15 @@ def to_bf16(w32):
 
 
 def make_training_set(n, seed=7, K=1024, device="cuda"):
-    """Sobol (x, M, Gamma, sigma, alpha, n) in the box and exact log p_sig targets."""
-    raw = synth.sobol_design(n, seed=seed)
+    """Sobol parameters, importance-sampled x, and exact log p_sig targets."""
+    raw = synth.surrogate_design(n, seed=seed)
     xq = torch.tensor(raw, dtype=torch.float64, device=device)
     y = api.bwcb_logpdf(xq, K, synth.BWCB_WINDOW, synth.BWCB_RANGE)
     u = torch.tensor(normalise(raw), dtype=torch.float32, device=device)
     return u, y.to(torch.float32), raw
 
 
-def train_surrogate(n_train=2_000_000, epochs=60, batch=8192, lr=1e-3, lr_min=1e-5, seed=0, holdout=0.05,
+def train_surrogate(n_train=2_000_000, epochs=60, batch=8192, lr=2e-3, lr_min=1e-5, seed=0, holdout=0.05,
                     K=1024, log=None, device="cuda"):
     """Returns dict(w32, w_bf16, history, holdout_rms, holdout_max)."""
     torch.cuda.set_device(0) if device == "cuda" else None
@@ -105,3 +105,68 @@ def train_surrogate(n_train=2_000_000, epochs=60, batch=8192, lr=1e-3, lr_min=1e
     err = (pred - y_ho).double().abs()
     return dict(w32=w32, w_bf16=wbf, history=hist, holdout_rms=hist[-1]["holdout_rms"] if hist else None,
                 holdout_max=float(err.max()), train_seconds=time.time() - t0)
+
+
+def _kernel_seconds(prog, theta, reps=20):
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for i in range(reps):
+        ev[i][0].record(s)
+        prog.nll_grad_async(theta, stream=s)
+        ev[i][1].record(s)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e-3
+
+
+def experiment(epochs=600, n_train=2_000_000, n_events=10_000_000, seed=0, log=print, weights_out=None):
+    """Train the surrogate, then fit the same events with the exact convolution
+    (FP64 and FP32) and with the surrogate; report the surrogate's error, the
+    fitted values, the bias in units of the exact fit's sigma and the speed."""
+    from . import workloads
+    torch.cuda.set_device(0)
+    res = train_surrogate(n_train=n_train, epochs=epochs, seed=seed, log=log)
+    if weights_out:
+        np.savez(weights_out, w32=res["w32"].cpu().numpy())
+    x = synth.sample_bw_cb(n_events, 4)
+    truth = workloads.truth_vector(synth.BWCB_TRUTH)
+    start = [91.0, 2.7, 1.3, 1.7, 3.5, -0.018, 0.78]
+    out = dict(train_seconds=res["train_seconds"], holdout_rms=res["holdout_rms"], holdout_max=res["holdout_max"],
+               history=res["history"][-5:], events=n_events, truth=truth, start=start)
+    fits = {}
+    for name, spec, prec in (("exact_fp64", workloads.spec_bwcb(), api.FP64),
+                             ("exact_fp32", workloads.spec_bwcb(), api.FP32),
+                             ("surrogate_fp32", workloads.spec_bwcb(surrogate=True), api.FP32)):
+        p = api.Program(api.Graph.from_spec(spec), precision=prec)
+        dt = torch.float64 if prec == api.FP64 else torch.float32
+        p.bind([torch.tensor(x, dtype=dt, device="cuda")])
+        if name.startswith("surrogate"):
+            p.bind_weights("sig", res["w_bf16"])
+        ks = _kernel_seconds(p, truth)
+        t0 = time.time()
+        th, sig, info = p.fit(start, edm_tol=1e-6, max_iter=500)
+        fits[name] = dict(theta=th.tolist(), sigma=sig.tolist(), info=info, fit_seconds=time.time() - t0,
+                          kernel_ms=ks * 1e3, events_per_s=n_events / ks)
+        log("%s: kernel %.3f ms, fit %.2fs %s" % (name, ks * 1e3, time.time() - t0, info))
+        del p
+    ref = fits["exact_fp64"]
+    for name in ("exact_fp32", "surrogate_fp32"):
+        fits[name]["bias_in_sigma"] = ((np.array(fits[name]["theta"]) - np.array(ref["theta"]))
+                                       / np.array(ref["sigma"])).tolist()
+    fits["exact_fp64"]["pull_vs_truth"] = ((np.array(ref["theta"]) - np.array(truth)) / np.array(ref["sigma"])).tolist()
+    out["fits"] = fits
+    out["speedup_surrogate_vs_exact_fp32"] = fits["exact_fp32"]["kernel_ms"] / fits["surrogate_fp32"]["kernel_ms"]
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--epochs", type=int, default=600)
+    ap.add_argument("--n-train", type=int, default=2_000_000)
+    ap.add_argument("--events", type=int, default=10_000_000)
+    ap.add_argument("--weights-out", default=None)
+    a = ap.parse_args()
+    r = experiment(a.epochs, a.n_train, a.events, weights_out=a.weights_out,
+                   log=lambda m: print(m, flush=True))
+    print(json.dumps(r))

@@ -16,18 +16,37 @@ import math
 import numpy as np
 
 
-def _fill(n, seed, draw):
+def _fill(n, seed, draw, rng=None):
     """Collect n accepted FP32-representable draws from draw(rng, m)."""
-    rng = np.random.default_rng(seed)
+    rng = np.random.default_rng(seed) if rng is None else rng
     parts, have = [], 0
     while have < n:
         m = max(1024, int(1.15 * (n - have)) + 64)
         got = draw(rng, m)
         parts.append(got)
         have += len(got if not isinstance(got, tuple) else got[0])
+    if n == 0:
+        return None
     if isinstance(parts[0], tuple):
         return tuple(np.concatenate([p[k] for p in parts])[:n] for k in range(len(parts[0])))
     return np.concatenate(parts)[:n]
+
+
+def _mixture(n, seed, f, draw_sig, draw_bkg):
+    """Exact sampler of f * sig + (1 - f) * bkg with both components normalised
+    over the box: n_sig ~ Binomial(n, f), each component drawn truncated to the
+    box (rejection inside the component), then a random permutation."""
+    rng = np.random.default_rng(seed)
+    ns = int(rng.binomial(n, f))
+    a = _fill(ns, None, draw_sig, rng) if ns else None
+    b = _fill(n - ns, None, draw_bkg, rng) if n - ns else None
+    perm = rng.permutation(n)
+    if isinstance(a if a is not None else b, tuple):
+        k = len(a if a is not None else b)
+        cols = [np.concatenate([c for c in (a[j] if a is not None else None, b[j] if b is not None else None)
+                                if c is not None]) for j in range(k)]
+        return tuple(c[perm] for c in cols)
+    return np.concatenate([c for c in (a, b) if c is not None])[perm]
 
 
 def _f32(a):
@@ -47,9 +66,9 @@ GAUSS_CHEB_RANGE = (-10.0, 10.0)
 
 def sample_gauss_cheb(n, seed, mu=0.0, sigma=1.0, f=0.3, c1=0.2, c2=-0.1,
                       lo=-10.0, hi=10.0):
-    """Component by Bernoulli(f); Gaussian by rejection of N(mu, sigma)
-    outside [lo, hi]; polynomial 1 + c1 T1 + c2 T2 by accept-reject against
-    its maximum over [-1, 1] (mapped linearly onto [lo, hi])."""
+    """Mixture sampled exactly (component counts ~ Binomial(n, f)); Gaussian by
+    rejection of N(mu, sigma) outside [lo, hi]; polynomial 1 + c1 T1 + c2 T2 by
+    accept-reject against its maximum over [-1, 1] (mapped onto [lo, hi])."""
     # maximum of the polynomial on [-1,1]: at an end point or the vertex
     cand = [-1.0, 1.0]
     if c2 != 0.0:
@@ -58,17 +77,17 @@ def sample_gauss_cheb(n, seed, mu=0.0, sigma=1.0, f=0.3, c1=0.2, c2=-0.1,
             cand.append(v)
     hmax = max(1.0 + c1 * t + c2 * (2 * t * t - 1) for t in cand)
 
-    def draw(rng, m):
-        pick = rng.random(m) < f
-        g = rng.normal(mu, sigma, m)
+    def sig(rng, m):
+        x = _f32(rng.normal(mu, sigma, m))
+        return x[_inside(x, lo, hi)]
+
+    def bkg(rng, m):
         t = rng.uniform(-1.0, 1.0, m)
         acc = rng.random(m) * hmax <= 1.0 + c1 * t + c2 * (2 * t * t - 1)
-        c = 0.5 * (hi - lo) * t + 0.5 * (hi + lo)
-        x = _f32(np.where(pick, g, c))
-        keep = np.where(pick, True, acc) & _inside(x, lo, hi)
-        return x[keep]
+        x = _f32(0.5 * (hi - lo) * t + 0.5 * (hi + lo))
+        return x[acc & _inside(x, lo, hi)]
 
-    return _fill(n, seed, draw)
+    return _mixture(n, seed, f, sig, bkg)
 
 
 def jitter_gauss_cheb(k, truth=GAUSS_CHEB_TRUTH, base_seed=1000):
@@ -97,28 +116,30 @@ ARGUS_M0 = 5.29
 def sample_decay_argus(n, seed, tau_s=1.5, sigma_t=0.05, bias_t=0.0, mu_m=5.28,
                        sigma_m=0.003, tau_b=0.4, c=-20.0, f=0.2, m0=ARGUS_M0,
                        t_range=DECAY_T_RANGE, m_range=DECAY_M_RANGE):
-    """Signal (prob. f): t = Exp(tau_s) + N(bias_t, sigma_t), m = N(mu_m, sigma_m).
+    """Mixture sampled exactly (component counts ~ Binomial(n, f)).
+    Signal: t = Exp(tau_s) + N(bias_t, sigma_t), m = N(mu_m, sigma_m).
     Background: t = Exp(tau_b); m = m0 sqrt(1 - U) with U ~ Gamma(3/2, 1/k),
     k = -c (the ARGUS law with power 1/2 in the variable U = 1 - (m/m0)^2).
-    Draws outside the box, or with m >= m0 after FP32 rounding, are redrawn."""
+    Draws outside the box, or with m >= m0 after FP32 rounding, are redrawn
+    within their component."""
     tlo, thi = t_range
     mlo, mhi = m_range
     k = -c
 
-    def draw(rng, mm):
-        sig = rng.random(mm) < f
-        ts = rng.exponential(tau_s, mm) + rng.normal(bias_t, sigma_t, mm)
-        ms = rng.normal(mu_m, sigma_m, mm)
-        tb = rng.exponential(tau_b, mm)
-        U = rng.gamma(1.5, 1.0 / k, mm)
-        mb = m0 * np.sqrt(np.clip(1.0 - U, 0.0, None))
-        t = _f32(np.where(sig, ts, tb))
-        m = _f32(np.where(sig, ms, mb))
+    def sig(rng, mm):
+        t = _f32(rng.exponential(tau_s, mm) + rng.normal(bias_t, sigma_t, mm))
+        m = _f32(rng.normal(mu_m, sigma_m, mm))
         keep = _inside(t, tlo, thi) & _inside(m, mlo, mhi) & (m < m0)
-        keep &= np.where(sig, True, U < 1.0)
         return t[keep], m[keep]
 
-    return _fill(n, seed, draw)
+    def bkg(rng, mm):
+        t = _f32(rng.exponential(tau_b, mm))
+        U = rng.gamma(1.5, 1.0 / k, mm)
+        m = _f32(m0 * np.sqrt(np.clip(1.0 - U, 0.0, None)))
+        keep = _inside(t, tlo, thi) & _inside(m, mlo, mhi) & (m < m0) & (U < 1.0)
+        return t[keep], m[keep]
+
+    return _mixture(n, seed, f, sig, bkg)
 
 
 def jitter_decay(k, truth=DECAY_TRUTH, base_seed=3000):
@@ -163,23 +184,70 @@ def _sample_cb(rng, m, sigma, alpha, n, ylo, yhi):
 
 def sample_bw_cb(n, seed, M=91.19, Gamma=2.5, sigma=1.5, alpha=1.5, nn=3.0, lam=-0.02,
                  f=0.8, x_range=BWCB_RANGE, window=BWCB_WINDOW):
-    """Signal (prob. f): x = M + (Gamma/2) tan(pi (u - 1/2)) + y with y ~ Crystal Ball
-    on the window; background: exp(lam x) on the range by inverse CDF."""
+    """Mixture sampled exactly (component counts ~ Binomial(n, f)).  Signal:
+    x = M + (Gamma/2) tan(pi (u - 1/2)) + y with y ~ Crystal Ball on the window,
+    redrawn until inside the range; background: exp(lam x) on the range by
+    inverse CDF."""
     lo, hi = x_range
 
-    def draw(rng, m):
-        sig = rng.random(m) < f
+    def sig(rng, m):
         y = _sample_cb(rng, m, sigma, alpha, nn, window[0], window[1])
-        xs = M + 0.5 * Gamma * np.tan(np.pi * (rng.random(m) - 0.5)) + y
+        x = _f32(M + 0.5 * Gamma * np.tan(np.pi * (rng.random(m) - 0.5)) + y)
+        return x[_inside(x, lo, hi)]
+
+    def bkg(rng, m):
         u = rng.random(m)
         if abs(lam) < 1e-12:
             xb = lo + (hi - lo) * u
         else:
             xb = lo + np.log1p(u * np.expm1(lam * (hi - lo))) / lam
-        x = _f32(np.where(sig, xs, xb))
+        x = _f32(xb)
         return x[_inside(x, lo, hi)]
 
-    return _fill(n, seed, draw)
+    return _mixture(n, seed, f, sig, bkg)
+
+
+def _sample_cb_vec(rng, sigma, alpha, n, ylo, yhi):
+    """Crystal Ball draws with per-row parameters (accept-reject, uniform proposal)."""
+    m = sigma.size
+    out = np.empty(m)
+    todo = np.arange(m)
+    while todo.size:
+        y = rng.uniform(ylo, yhi, todo.size)
+        s, a, nn = sigma[todo], alpha[todo], n[todo]
+        z = y / s
+        A = (nn / a) ** nn * np.exp(-0.5 * a * a)
+        B = nn / a - a
+        with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+            shape = np.where(z > -a, np.exp(-0.5 * z * z), A * np.power(np.maximum(B - z, 1e-300), -nn))
+        acc = rng.random(todo.size) <= shape
+        out[todo[acc]] = y[acc]
+        todo = todo[~acc]
+    return out
+
+
+def surrogate_design(n, seed=7, box=BWCB_BOX, frac_signal=0.5, window=BWCB_WINDOW):
+    """Training inputs of the surrogate: the five parameters from a scrambled
+    Sobol sequence over the box; x drawn, for a fraction frac_signal of the
+    rows, from the signal law at that row's parameters (Breit-Wigner plus
+    Crystal Ball, redrawn until inside x's range) and uniformly otherwise, so
+    that the training points follow where events fall."""
+    q = sobol_design(n, seed=seed, box=box)
+    rng = np.random.default_rng(seed + 1)
+    lo, hi = box[0]
+    xs = rng.uniform(lo, hi, n)
+    sig = rng.random(n) < frac_signal
+    idx = np.nonzero(sig)[0]
+    todo = idx
+    while todo.size:
+        M, G, s, a, nn = (q[todo, j] for j in range(1, 6))
+        y = _sample_cb_vec(rng, s, a, nn, window[0], window[1])
+        x = M + 0.5 * G * np.tan(np.pi * (rng.random(todo.size) - 0.5)) + y
+        ok = (x >= lo) & (x <= hi)
+        xs[todo[ok]] = x[ok]
+        todo = todo[~ok]
+    q[:, 0] = xs
+    return q
 
 
 def sobol_design(n, seed=7, box=BWCB_BOX, skip=0):
