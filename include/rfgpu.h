@@ -82,10 +82,12 @@ enum {
   RF_OP_NUMCONV_BW_CB = 7,  /* (x, M, Gamma, sigma, alpha, n); attrs (ylo, yhi, K):
                                sum_k w_k CB(y_k) BW(x - y_k) over a K-point
                                Gauss-Legendre rule on [ylo, yhi], K <= 1024       */
-  RF_OP_MLP = 8,            /* (x, q1..q5); attrs: 6 (lo, hi) input boxes (x first), K:
-                               exp(s(x, q)) with s a 6-64-64-64-1 tanh MLP (BF16
-                               weights bound with rf_bind_weights), normalised by a
-                               K-point Gauss-Legendre sum over x's range          */
+  RF_OP_MLP = 8,            /* (x, q1..q5); attrs: 6 (lo, hi) input boxes, K:
+                               exp(s(u)) with s a 6-64-64-64-1 tanh MLP (BF16
+                               weights bound with rf_bind_weights), u = affine maps
+                               onto [-1,1] of (x - q1, q1..q5) with the boxes
+                               (the first box is that of x - q1), normalised by a
+                               K-point Gauss-Legendre sum over x's range; FP32 only */
   RF_OP_ADD_PDF = 20,       /* (pdf_1..pdf_n, f_1..f_{n-1}): sum_j f_j pdf_j +
                                (1 - sum f) pdf_n, each pdf normalised            */
   RF_OP_PROD_PDF = 21,      /* (pdf_1..pdf_n) over disjoint observables           */

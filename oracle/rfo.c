@@ -268,18 +268,24 @@ int rfo_mlp_backward(const double* w, const double* in, int64_t n,
   return 0;
 }
 
-/* MLP surrogate: normalised inputs and d s / d(raw input j) */
+/* MLP surrogate.  Inputs: u0 = affine map of (x - q1) onto [-1, 1] (the
+   position relative to the first shape parameter, the Breit-Wigner mass),
+   u_j = affine map of q_j (j = 1..5), each with its (lo, hi) box.  Returns s
+   and d s / d(raw input j), raw = (x, q1..q5). */
 static double mlp_leaf(const node* d, const double* raw, double* ds /*6*/) {
-  double u[6], du[6];
+  double u[6], du[6], sc[6];
   for (int j = 0; j < 6; ++j) {
     double lo = d->attrs[2 * j], hi = d->attrs[2 * j + 1];
-    u[j] = 2.0 * (raw[j] - lo) / (hi - lo) - 1.0;
+    double r = j == 0 ? raw[0] - raw[1] : raw[j];
+    sc[j] = 2.0 / (hi - lo);
+    u[j] = (r - lo) * sc[j] - 1.0;
   }
   mlp_act a;
   mlp_fwd1(d->mw, u, &a);
   if (ds) {
     mlp_bwd1(d->mw, u, &a, 1.0, NULL, du);
-    for (int j = 0; j < 6; ++j) ds[j] = du[j] * 2.0 / (d->attrs[2 * j + 1] - d->attrs[2 * j]);
+    for (int j = 0; j < 6; ++j) ds[j] = du[j] * sc[j];
+    ds[1] -= du[0] * sc[0];
   }
   return a.s;
 }

@@ -44,7 +44,8 @@ enum {
   RFO_NUMCONV_BW_CB = 16, /* in: x, M, Gamma, sigma, alpha, n ;
                              attrs: ylo, yhi, K                      */
   RFO_MLP = 17,       /* in: x, q1..q5 ; attrs: 12 box bounds (lo,hi per
-                         input, x first), K (grid points)           */
+                         input; the first box is that of x - q1), K (grid
+                         points on x's range)                        */
   RFO_ADD = 30,       /* in: pdf_1..pdf_n, f_1..f_{n-1}             */
   RFO_PROD = 31       /* in: pdf_1..pdf_n (disjoint observables)    */
 };

@@ -250,8 +250,9 @@ RF_DEV void mlp_backward(const MlpLds& s, float g, float* h1, float* h2, float* 
 RF_DEV float mlp_input_grad(const MlpLds& s, const float* d1, int j) { return mlp_rowdot(s.W1 + j, 6, d1); }
 
 // ------------------------------------------------------ surrogate PDF leaf --
-// u(x; q) = exp(s(u0, u1..u5)), u_j = 2 (raw_j - lo_j)/(hi_j - lo_j) - 1 with
-// raw = (x, q1..q5); normalised by Nhat(q) = sum_g w_g exp(s(x_g, q)) over a
+// u(x; q) = exp(s(u0, u1..u5)), u_j = 2 (r_j - lo_j)/(hi_j - lo_j) - 1 with
+// r = (x - q1, q1..q5) (the first input is the position relative to q1, the
+// Breit-Wigner mass); normalised by Nhat(q) = sum_g w_g exp(s(x_g, q)) over a
 // Gauss-Legendre grid on x's range (computed by rf_mlp_renorm before the
 // likelihood kernel, delivered as [Nhat, dNhat/dq1..5] in the aux block).
 // Constant block: C[0] = 1/Nhat, C[1..5] = d log Nhat / dq_j.
@@ -282,8 +283,8 @@ __device__ void mlp_prologue(const double* q, const double* box, const double* n
   if (threadIdx.x == 0) {
     C[0] = 1.0 / nh[0];
     for (int j = 0; j < 5; ++j) C[1 + j] = nh[1 + j] / nh[0];
-    C[6] = 2.0 / (box[1] - box[0]);
-    C[7] = -(box[1] + box[0]) / (box[1] - box[0]);
+    C[6] = 2.0 / (box[1] - box[0]);               // du0/dx
+    C[7] = -(q[0] + box[0]) * C[6] - 1.0;          // u0 = x C[6] + C[7]
   }
 }
 
@@ -314,6 +315,7 @@ RF_DEV T mlp_leaf_eval(T x, const MlpK<T>& k, T* d) {
     mlp_backward<NS>(*k.s, 1.0f, h1, h2, h3);
 #pragma unroll
     for (int j = 0; j < 5; ++j) d[j] = (T)(mlp_input_grad(*k.s, h1, j + 1) * k.qs[j]);
+    d[0] -= (T)(mlp_input_grad(*k.s, h1, 0) * k.xs);  // u0 depends on q1 through x - q1
   }
   return (T)expf(sv);
 }

@@ -47,8 +47,9 @@ __global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  const float xs = (float)(2.0 / (a.box[1] - a.box[0]));
-  const float xo = (float)(-(a.box[1] + a.box[0]) / (a.box[1] - a.box[0]));
+  const double xsd = 2.0 / (a.box[1] - a.box[0]);
+  const float xs = (float)xsd;
+  const float xo = (float)(-(a.q[0] + a.box[0]) * xsd - 1.0);  // u0 = map of (x - q1)
   for (int t = wid; t * 64 < a.K; t += 4) {  // wave-uniform loop
     MLP_TILE_BARRIER();
     const int g = t * 64 + lane;
@@ -63,6 +64,7 @@ __global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
     acc[0] += e;
 #pragma unroll
     for (int j = 0; j < 5; ++j) acc[1 + j] += e * (double)(mlp_input_grad(s, h1, j + 1) * qs[j]);
+    acc[1] -= e * (double)(mlp_input_grad(s, h1, 0) * xs);
   }
 #pragma unroll
   for (int j = 0; j < 6; ++j) {

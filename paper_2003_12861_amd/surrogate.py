@@ -18,7 +18,8 @@ import torch
 
 from . import api, synth
 
-BOX = synth.BWCB_BOX
+BOX = synth.BWCB_BOX          # raw design box (x, M, Gamma, sigma, alpha, n)
+MLP_BOX = synth.BWCB_MLP_BOX  # network input box (x - M, M, Gamma, sigma, alpha, n)
 N_W = 8833
 
 
@@ -38,10 +39,13 @@ def init_weights(seed=0):
     return w
 
 
-def normalise(raw, box=BOX):
+def normalise(raw, box=MLP_BOX):
+    """Network inputs: affine maps onto [-1, 1] of (x - M, M, Gamma, sigma, alpha, n)."""
+    r = np.array(raw, dtype=np.float64, copy=True)
+    r[:, 0] = r[:, 0] - r[:, 1]
     lo = np.array([b[0] for b in box])
     hi = np.array([b[1] for b in box])
-    return 2.0 * (raw - lo) / (hi - lo) - 1.0
+    return 2.0 * (r - lo) / (hi - lo) - 1.0
 
 
 def to_bf16(w32):

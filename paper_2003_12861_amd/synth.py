@@ -161,8 +161,10 @@ def jitter_decay(k, truth=DECAY_TRUTH, base_seed=3000):
 BWCB_TRUTH = dict(M=91.19, Gamma=2.5, sigma=1.5, alpha=1.5, n=3.0, lam=-0.02, f=0.8)
 BWCB_RANGE = (60.0, 120.0)
 BWCB_WINDOW = (-30.0, 30.0)
-# box of the surrogate's inputs (x, M, Gamma, sigma, alpha, n)
+# box of the surrogate's raw inputs (x, M, Gamma, sigma, alpha, n)
 BWCB_BOX = ((60.0, 120.0), (89.19, 93.19), (1.5, 3.5), (0.5, 3.0), (0.5, 3.0), (1.0, 10.0))
+# the network's first input is x - M, on the box of x - M implied by the above
+BWCB_MLP_BOX = ((60.0 - 93.19, 120.0 - 89.19),) + BWCB_BOX[1:]
 
 
 def _sample_cb(rng, m, sigma, alpha, n, ylo, yhi):

@@ -70,7 +70,7 @@ def spec_bwcb(surrogate=False, K=1024):
         ("param", "f", [], [0.0, 1.0]),
     ]
     if surrogate:
-        box = [v for b in synth.BWCB_BOX for v in b]
+        box = [v for b in synth.BWCB_MLP_BOX for v in b]
         spec.append(("mlp", "sig", ["x", "M", "Gamma", "sigma", "alpha", "n"], box + [float(K)]))
     else:
         spec.append(("numconv_bw_cb", "sig", ["x", "M", "Gamma", "sigma", "alpha", "n"],

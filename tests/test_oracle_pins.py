@@ -306,9 +306,9 @@ def test_mlp_leaf_normalisation_vs_quadrature():
     m, top, ids = rfo.from_spec(spec)
     m.set_mlp_weights(ids["sig"], w)
     th = [91.0, 2.4, 1.2, 1.3, 4.0]
-    box = synth.BWCB_BOX
+    box = synth.BWCB_MLP_BOX
     def s_of_x(x):
-        raw = np.array([[x] + th])
+        raw = np.array([[x - th[0]] + th])  # first input: position relative to M
         u = 2 * (raw - [b[0] for b in box]) / np.array([b[1] - b[0] for b in box]) - 1
         return math.exp(_torch_mlp(w, u)[2].item())
     N, _ = m.norm(ids["sig"], th + [-0.02, 0.8])
