@@ -23,6 +23,12 @@
 typedef short rf_bf16x4 __attribute__((ext_vector_type(4)));
 typedef float rf_f32x16 __attribute__((ext_vector_type(16)));
 
+// Compiler barrier (memory clobber) between the engine's phases and at the top
+// of tile loops: the per-lane weight values stay in LDS and are read where they
+// are used, instead of being hoisted early (or out of loops) into registers,
+// which would spill.
+#define MLP_TILE_BARRIER() __asm__ volatile("" ::: "memory")
+
 #define MLP_NW 8833
 #define MLP_RS 68  // LDS row stride (bf16 elements) of the 64x64 matrices
 enum { MLP_OW1 = 0, MLP_OB1 = 384, MLP_OW2 = 448, MLP_OB2 = 4544, MLP_OW3 = 4608,
@@ -32,14 +38,10 @@ struct MlpLds {
   unsigned short W2[64 * MLP_RS], W3[64 * MLP_RS];    // [out][in]
   unsigned short W2T[64 * MLP_RS], W3T[64 * MLP_RS];  // [in][out]
   float W1[64 * 6], b1[64], b2[64], b3[64], W4[64];
-  float c1[64];  // layer-1 pre-activation of the row-independent inputs
+  float c1[64];     // layer-1 pre-activation of the row-independent inputs
+  float gq[5][64];  // d(layer-1 pre-activation o)/d q_j of the surrogate leaf
   float b4;
 };
-
-// Compiler barrier for tile loops: keeps the per-lane weight values in LDS
-// (re-read per tile) instead of letting loop-invariant code motion pin ~300 of
-// them in registers, which would spill.
-#define MLP_TILE_BARRIER() __asm__ volatile("" ::: "memory")
 
 RF_DEV float bf16_bits_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
@@ -100,52 +102,59 @@ RF_DEV void mlp_split4(const float* h, rf_bf16x4* part) {
   }
 }
 
-// One 64x64 layer on a 64-row tile, W a 64x64 LDS matrix (row stride MLP_RS):
+// Event blocks.  A call processes NEB blocks of 32 rows starting at block
+// eb0 (NEB = 2, eb0 = 0: the whole 64-row tile; NEB = 1: one half, which
+// halves the registers holding activations).  Tile storage of a layer:
+// h[(NEB mb + e) * 16 + v] for e < NEB, row 32 (eb0 + e) + l%32.
+
+// One 64x64 layer, W a 64x64 LDS matrix (row stride MLP_RS):
 //   MODE 0 (forward):  out = tanh(W in + b)
 //   MODE 1 (backward): out = (W in) * (1 - out^2)   (out holds h on entry)
-// The bf16 parts of the B operand are formed per K-step (12 registers), the
-// four 32x32 accumulators live in the matrix-core accumulator registers.
-template <int NS, int MODE>
+//   MODE 2 (backward): out = (W in) * fac, fac[i] = b[i * 64 + lane] (LDS)
+template <int NS, int MODE, int NEB>
 RF_DEV void mlp_layer(const unsigned short* W, const float* b, const float* in, float* out) {
+  MLP_TILE_BARRIER();  // phase boundary: keep this layer's LDS reads inside it
   const int l = threadIdx.x & 63, hl = l >> 5, lr = l & 31;
-  rf_f32x16 acc[2][2];
+  rf_f32x16 acc[2][NEB];
 #pragma unroll
   for (int mo = 0; mo < 2; ++mo)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const float bv = MODE == 0 ? b[mlp_feat(mo, v, hl)] : 0.0f;
-      acc[mo][0][v] = bv;
-      acc[mo][1][v] = bv;
+#pragma unroll
+      for (int e = 0; e < NEB; ++e) acc[mo][e][v] = bv;
     }
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    rf_bf16x4 Bq[2][NS];
+    rf_bf16x4 Bq[NEB][NS];
 #pragma unroll
-    for (int eb = 0; eb < 2; ++eb) mlp_split4<NS>(in + (2 * (s >> 2) + eb) * 16 + 4 * (s & 3), Bq[eb]);
+    for (int e = 0; e < NEB; ++e) mlp_split4<NS>(in + (NEB * (s >> 2) + e) * 16 + 4 * (s & 3), Bq[e]);
 #pragma unroll
     for (int mo = 0; mo < 2; ++mo) {
       const rf_bf16x4 A = *(const rf_bf16x4*)&W[(32 * mo + lr) * MLP_RS + 8 * s + 4 * hl];
 #pragma unroll
-      for (int q = NS - 1; q >= 0; --q) {  // small parts first
-        acc[mo][0] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, Bq[0][q], acc[mo][0], 0, 0, 0);
-        acc[mo][1] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, Bq[1][q], acc[mo][1], 0, 0, 0);
-      }
+      for (int q = NS - 1; q >= 0; --q)  // small parts first
+#pragma unroll
+        for (int e = 0; e < NEB; ++e)
+          acc[mo][e] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, Bq[e][q], acc[mo][e], 0, 0, 0);
     }
   }
 #pragma unroll
   for (int mo = 0; mo < 2; ++mo)
 #pragma unroll
-    for (int eb = 0; eb < 2; ++eb)
+    for (int e = 0; e < NEB; ++e)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        float& o = out[(2 * mo + eb) * 16 + v];
-        if (MODE == 0) o = mlp_tanh(acc[mo][eb][v]);
-        else o = acc[mo][eb][v] * (1.0f - o * o);
+        const int idx = (NEB * mo + e) * 16 + v;
+        float& o = out[idx];
+        if (MODE == 0) o = mlp_tanh(acc[mo][e][v]);
+        else if (MODE == 1) o = acc[mo][e][v] * (1.0f - o * o);
+        else o = acc[mo][e][v] * b[idx * 64 + l];
       }
+  MLP_TILE_BARRIER();
 }
 
-// the value of row (32 eb + l%32) held by the partner half: rows of the
-// other half-wave come from lane l ^ 32
+// the value of row (32 eb + l%32), owned by lane 32 eb + l%32
 RF_DEV float mlp_rowval(float own, int eb) {
   const int hl = (threadIdx.x & 63) >> 5;
   const float other = __shfl_xor(own, 32, 64);
@@ -153,21 +162,25 @@ RF_DEV float mlp_rowval(float own, int eb) {
 }
 
 // layer 1 when only input 0 varies per row: a = W1[:,0] u0 + c1
-RF_DEV void mlp_layer1_u0(const MlpLds& s, float u0, float* h1) {
+template <int NEB>
+RF_DEV void mlp_layer1_u0(const MlpLds& s, float u0, float* h1, int eb0) {
+  MLP_TILE_BARRIER();
   const int hl = (threadIdx.x & 63) >> 5;
-  const float ue[2] = {mlp_rowval(u0, 0), mlp_rowval(u0, 1)};
+  float ue[NEB];
+#pragma unroll
+  for (int e = 0; e < NEB; ++e) ue[e] = mlp_rowval(u0, eb0 + e);
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int o = mlp_feat(mb, v, hl);
       const float w = s.W1[o * 6], c = s.c1[o];
-      h1[(2 * mb + 0) * 16 + v] = mlp_tanh(fmaf(w, ue[0], c));
-      h1[(2 * mb + 1) * 16 + v] = mlp_tanh(fmaf(w, ue[1], c));
+#pragma unroll
+      for (int e = 0; e < NEB; ++e) h1[(NEB * mb + e) * 16 + v] = mlp_tanh(fmaf(w, ue[e], c));
     }
 }
 
-// layer 1 with all six inputs per row (training)
+// layer 1 with all six inputs per row (training; whole tile)
 RF_DEV void mlp_layer1_full(const MlpLds& s, const float* u, float* h1) {
   const int hl = (threadIdx.x & 63) >> 5;
   float ue[2][6];
@@ -191,42 +204,48 @@ RF_DEV void mlp_layer1_full(const MlpLds& s, const float* u, float* h1) {
     }
 }
 
-// sum over features of coef[f] * t[f][row] for this lane's own row
-RF_DEV float mlp_rowdot(const float* coef, int stride, const float* t) {
+// sum over features of coef[f] * t[f][row] for this lane's own row; valid on
+// lanes whose row lies in the call's blocks (l/32 in [eb0, eb0 + NEB))
+template <int NEB>
+RF_DEV float mlp_rowdot(const float* coef, int stride, const float* t, int eb0) {
+  MLP_TILE_BARRIER();
   const int hl = (threadIdx.x & 63) >> 5;
-  float p[2] = {0.f, 0.f};
+  float p[NEB];
+#pragma unroll
+  for (int e = 0; e < NEB; ++e) p[e] = 0.f;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const float c = coef[mlp_feat(mb, v, hl) * stride];
-      p[0] = fmaf(c, t[(2 * mb + 0) * 16 + v], p[0]);
-      p[1] = fmaf(c, t[(2 * mb + 1) * 16 + v], p[1]);
+#pragma unroll
+      for (int e = 0; e < NEB; ++e) p[e] = fmaf(c, t[(NEB * mb + e) * 16 + v], p[e]);
     }
-  const float send = hl ? p[0] : p[1];
+  // the partner lane (l ^ 32) holds the other half of the features of the
+  // same rows; it needs the block of its own row, 1 - hl
+  const int ep = 1 - hl - eb0, eo = hl - eb0;
+  float send = 0.f, mine = 0.f;
+#pragma unroll
+  for (int e = 0; e < NEB; ++e) {
+    if (e == ep) send = p[e];
+    if (e == eo) mine = p[e];
+  }
+  MLP_TILE_BARRIER();
   const float recv = __shfl_xor(send, 32, 64);
-  return (hl ? p[1] : p[0]) + recv;
+  return mine + recv;
 }
 
 // forward of a row tile; keeps the hidden activations for a backward pass
 template <int NS>
-RF_DEV float mlp_forward_u0(const MlpLds& s, float u0, float* h1, float* h2, float* h3) {
-  mlp_layer1_u0(s, u0, h1);
-  mlp_layer<NS, 0>(s.W2, s.b2, h1, h2);
-  mlp_layer<NS, 0>(s.W3, s.b3, h2, h3);
-  return mlp_rowdot(s.W4, 1, h3) + s.b4;
-}
-template <int NS>
 RF_DEV float mlp_forward_full(const MlpLds& s, const float* u, float* h1, float* h2, float* h3) {
   mlp_layer1_full(s, u, h1);
-  mlp_layer<NS, 0>(s.W2, s.b2, h1, h2);
-  mlp_layer<NS, 0>(s.W3, s.b3, h2, h3);
-  return mlp_rowdot(s.W4, 1, h3) + s.b4;
+  mlp_layer<NS, 0, 2>(s.W2, s.b2, h1, h2);
+  mlp_layer<NS, 0, 2>(s.W3, s.b3, h2, h3);
+  return mlp_rowdot<2>(s.W4, 1, h3, 0) + s.b4;
 }
 
-// backward from the per-row cotangent g of the output: leaves
-// d1 = dL/d(pre-activation 1), d2, d3 in the activation arrays' place
-// (h1 <- d1, h2 <- d2, h3 <- d3).
+// backward from the per-row cotangent g of the output (whole tile): leaves
+// d1 = dL/d(pre-activation 1), d2, d3 in place of h1, h2, h3
 template <int NS>
 RF_DEV void mlp_backward(const MlpLds& s, float g, float* h1, float* h2, float* h3) {
   const int hl = (threadIdx.x & 63) >> 5;
@@ -242,12 +261,67 @@ RF_DEV void mlp_backward(const MlpLds& s, float g, float* h1, float* h2, float* 
         t = ge[eb] * w * (1.0f - t * t);
       }
     }
-  mlp_layer<NS, 1>(s.W3T, nullptr, h3, h2);
-  mlp_layer<NS, 1>(s.W2T, nullptr, h2, h1);
+  mlp_layer<NS, 1, 2>(s.W3T, nullptr, h3, h2);
+  mlp_layer<NS, 1, 2>(s.W2T, nullptr, h2, h1);
 }
 
 // d(output)/d(input j) of the own row from d1 = dL/d(pre-activation 1)
-RF_DEV float mlp_input_grad(const MlpLds& s, const float* d1, int j) { return mlp_rowdot(s.W1 + j, 6, d1); }
+RF_DEV float mlp_input_grad(const MlpLds& s, const float* d1, int j) { return mlp_rowdot<2>(s.W1 + j, 6, d1, 0); }
+
+// Half-tile forward/backward for the surrogate leaf (NEB = 1, block eb0):
+// layer 1's derivative factor (1 - h1^2) is parked in the wavefront's LDS
+// tile sav[32 * 64] (lane-contiguous) instead of registers.
+template <int NS>
+RF_DEV float mlp_forward_half(const MlpLds& s, float u0, int eb0, float* sav, float* h2, float* h3) {
+  const int l = threadIdx.x & 63;
+  float h1[32];
+  mlp_layer1_u0<1>(s, u0, h1, eb0);
+  mlp_layer<NS, 0, 1>(s.W2, s.b2, h1, h2);
+#pragma unroll
+  for (int i = 0; i < 32; ++i) sav[i * 64 + l] = 1.0f - h1[i] * h1[i];
+  mlp_layer<NS, 0, 1>(s.W3, s.b3, h2, h3);
+  return mlp_rowdot<1>(s.W4, 1, h3, eb0) + s.b4;
+}
+template <int NS>
+RF_DEV void mlp_backward_half(const MlpLds& s, int eb0, const float* sav, float* d1, float* h2, float* h3) {
+  const int hl = (threadIdx.x & 63) >> 5;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float w = s.W4[mlp_feat(mb, v, hl)];
+      float& t = h3[mb * 16 + v];
+      t = w * (1.0f - t * t);  // cotangent 1 per row
+    }
+  mlp_layer<NS, 1, 1>(s.W3T, nullptr, h3, h2);
+  mlp_layer<NS, 2, 1>(s.W2T, sav, h2, d1);
+}
+
+// s and ds/dq_j (GRAD) of the lane's own row, two half-tile passes
+template <int NS, bool GRAD>
+RF_DEV float mlp_eval_u0(const MlpLds& s, float u0, float* sav, float* dq) {
+  const int hl = (threadIdx.x & 63) >> 5;
+  float out = 0.f;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) dq[j] = 0.f;
+#pragma unroll 1
+  for (int eb0 = 0; eb0 < 2; ++eb0) {  // not unrolled: one half's state at a time
+    MLP_TILE_BARRIER();
+    float h2[32], h3[32];
+    const float sv = mlp_forward_half<NS>(s, u0, eb0, sav, h2, h3);
+    if (hl == eb0) out = sv;
+    if (GRAD) {
+      float d1[32];
+      mlp_backward_half<NS>(s, eb0, sav, d1, h2, h3);
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const float gj = mlp_rowdot<1>(s.gq[j], 1, d1, eb0);
+        if (hl == eb0) dq[j] = gj;
+      }
+    }
+  }
+  return out;
+}
 
 // ------------------------------------------------------ surrogate PDF leaf --
 // u(x; q) = exp(s(u0, u1..u5)), u_j = 2 (r_j - lo_j)/(hi_j - lo_j) - 1 with
@@ -274,6 +348,14 @@ __device__ void mlp_setup(const double* q, const double* box, const unsigned sho
     s.c1[o] = c;
   }
   if (threadIdx.x < 5) qs[threadIdx.x] = (float)(2.0 / (box[2 * threadIdx.x + 3] - box[2 * threadIdx.x + 2]));
+  // u0 = map of (x - q1): q1 enters layer 1 through u0 as well
+  const double s0 = 2.0 / (box[1] - box[0]);
+  for (int t = threadIdx.x; t < 5 * 64; t += BS) {
+    const int j = t / 64, o = t % 64;
+    double g = (double)s.W1[o * 6 + j + 1] * 2.0 / (box[2 * j + 3] - box[2 * j + 2]);
+    if (j == 0) g -= (double)s.W1[o * 6] * s0;
+    s.gq[j][o] = (float)g;
+  }
 }
 
 template <int BS>
@@ -291,15 +373,15 @@ __device__ void mlp_prologue(const double* q, const double* box, const double* n
 template <typename T> struct MlpK {
   T invN;
   float xs, xo;
-  float qs[5];
   const MlpLds* s;
-  RF_DEV MlpK make(const double* C, const MlpLds* s, const float* qs) {
+  float* sav;  // this wavefront's LDS tile for (1 - h1^2) of a half tile
+  RF_DEV MlpK make(const double* C, const MlpLds* s, float* sav_base) {
     MlpK k;
     k.invN = (T)C[0];
     k.xs = (float)C[6];
     k.xo = (float)C[7];
-    for (int j = 0; j < 5; ++j) k.qs[j] = qs[j];
     k.s = s;
+    k.sav = sav_base + (threadIdx.x >> 6) * 32 * 64;
     return k;
   }
 };
@@ -309,13 +391,10 @@ template <typename T> struct MlpK {
 template <typename T, int NS, bool GRAD>
 RF_DEV T mlp_leaf_eval(T x, const MlpK<T>& k, T* d) {
   const float u0 = fmaf((float)x, k.xs, k.xo);
-  float h1[64], h2[64], h3[64];
-  const float sv = mlp_forward_u0<NS>(*k.s, u0, h1, h2, h3);
-  if (GRAD) {
-    mlp_backward<NS>(*k.s, 1.0f, h1, h2, h3);
+  float dq[5];
+  const float sv = mlp_eval_u0<NS, GRAD>(*k.s, u0, k.sav, dq);
+  if (GRAD)
 #pragma unroll
-    for (int j = 0; j < 5; ++j) d[j] = (T)(mlp_input_grad(*k.s, h1, j + 1) * k.qs[j]);
-    d[0] -= (T)(mlp_input_grad(*k.s, h1, 0) * k.xs);  // u0 depends on q1 through x - q1
-  }
+    for (int j = 0; j < 5; ++j) d[j] = (T)dq[j];
   return (T)expf(sv);
 }

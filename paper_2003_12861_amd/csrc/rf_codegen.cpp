@@ -149,6 +149,7 @@ std::string generate_source(const Lowered& L, int BS, int U) {
     if (!L.reach[id] || !blockwide(g[id])) continue;
     if (g[id].op == RF_OP_MLP) {
       o << "__shared__ MlpLds rf_mlp_" << id << ";\n__shared__ float rf_mlpqs_" << id << "[5];\n";
+      o << "__shared__ float rf_mlpsav_" << id << "[RF_BS / 64 * 32 * 64];\n";
       continue;
     }
     any_tab = true;
@@ -168,7 +169,7 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
     if (g[id].op == RF_OP_MLP)
-      o << "    k.l" << id << " = MlpK<T>::make(C + " << L.cst_off[id] << ", &rf_mlp_" << id << ", rf_mlpqs_" << id << ");\n";
+      o << "    k.l" << id << " = MlpK<T>::make(C + " << L.cst_off[id] << ", &rf_mlp_" << id << ", rf_mlpsav_" << id << ");\n";
     else if (blockwide(g[id]))
       o << "    k.l" << id << " = " << ktype(g[id]) << "::make(C + " << L.cst_off[id] << ", rf_tab_" << id << ");\n";
     else if (is_leaf(g[id].op))

@@ -43,6 +43,7 @@ __global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
   __shared__ MlpLds s;
   __shared__ float qs[5];
   __shared__ double red[4][6];
+  __shared__ float sav[4 * 32 * 64];
   mlp_setup<256>(a.q, a.box, a.w, s, qs);
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -57,14 +58,12 @@ __global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
     const double xg = a.grid[valid ? g : 0];
     const double wg = valid ? a.grid[a.K + g] : 0.0;
     const float u0 = fmaf((float)xg, xs, xo);
-    float h1[64], h2[64], h3[64];
-    const float sv = mlp_forward_u0<MLP_SPLIT>(s, u0, h1, h2, h3);
-    mlp_backward<MLP_SPLIT>(s, 1.0f, h1, h2, h3);
+    float dq[5];
+    const float sv = mlp_eval_u0<MLP_SPLIT, true>(s, u0, sav + wid * 32 * 64, dq);
     const double e = wg * exp((double)sv);
     acc[0] += e;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) acc[1 + j] += e * (double)(mlp_input_grad(s, h1, j + 1) * qs[j]);
-    acc[1] -= e * (double)(mlp_input_grad(s, h1, 0) * xs);
+    for (int j = 0; j < 5; ++j) acc[1 + j] += e * (double)dq[j];
   }
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
@@ -113,11 +112,11 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const unsigned short* w, c
     float ha[64], hb[64];
     mlp_layer1_full(s, u, ha);
     if (ACT) mlp_store_act(act, t, n, 0, ha);
-    mlp_layer<MLP_SPLIT, 0>(s.W2, s.b2, ha, hb);
+    mlp_layer<MLP_SPLIT, 0, 2>(s.W2, s.b2, ha, hb);
     if (ACT) mlp_store_act(act, t, n, 1, hb);
-    mlp_layer<MLP_SPLIT, 0>(s.W3, s.b3, hb, ha);
+    mlp_layer<MLP_SPLIT, 0, 2>(s.W3, s.b3, hb, ha);
     if (ACT) mlp_store_act(act, t, n, 2, ha);
-    const float sv = mlp_rowdot(s.W4, 1, ha) + s.b4;
+    const float sv = mlp_rowdot<2>(s.W4, 1, ha, 0) + s.b4;
     if (valid) out[row] = sv;
   }
 }

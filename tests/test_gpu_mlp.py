@@ -113,6 +113,6 @@ def test_surrogate_leaf_vs_oracle(n):
 
 
 def test_training_reduces_error():
-    res = surrogate.train_surrogate(n_train=65536, epochs=4, batch=4096, lr=3e-3, log=print)
+    res = surrogate.train_surrogate(n_train=131072, epochs=8, batch=4096, lr=3e-3, log=print)
     h = res["history"]
     assert h[-1]["holdout_rms"] < 0.5 * h[0]["holdout_rms"], h
