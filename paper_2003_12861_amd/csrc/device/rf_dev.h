@@ -106,20 +106,31 @@ RF_DEV void gauss_prologue(const double* in, double lo, double hi, double* C) {
 template <typename T> struct GaussK {
   T invN;
   Loc<T> mu;
-  T isig;
+  Scl<T> isig;
   RF_DEV GaussK load(const double* C) {
     GaussK k;
     k.invN = (T)C[0];
     k.mu = Loc<T>::make(C[3]);
-    k.isig = (T)C[4];
+    k.isig = Scl<T>::make(C[4]);
     return k;
   }
 };
+// exp(a + a_lo) for a small correction a_lo: exp(a) (1 + a_lo).  Large
+// exponent arguments (a Gaussian 9 widths out: -40.5) carry an FP32 rounding
+// of a few 1e-6 absolute, i.e. a relative error of the result; keeping the
+// argument as an exact pair removes it.
+template <typename T> RF_DEV T exp_pair(T a, T a_lo) {
+  const T e = RM<T>::exp(a);
+  return fma(e, a_lo, e);
+}
 template <typename T> RF_DEV T gauss_eval(T x, const GaussK<T>& k, T* d) {
-  const T z = k.mu.sub(x) * k.isig;
-  const T u = RM<T>::exp((T)-0.5 * z * z);
-  d[0] = z * k.isig;       // d log u / d mu
-  d[1] = z * z * k.isig;   // d log u / d sigma
+  const T z = k.isig.mul(k.mu.sub(x));
+  const T q = z * z;
+  const T q_lo = fma(z, z, -q);  // z^2 = q + q_lo exactly
+  const T u = exp_pair<T>((T)-0.5 * q, (T)-0.5 * q_lo);
+  const T is = k.isig.hi;
+  d[0] = z * is;      // d log u / d mu
+  d[1] = q * is;      // d log u / d sigma
   return u;
 }
 
@@ -214,14 +225,20 @@ template <typename T> struct ExpK {
     return k;
   }
 };
+// argument r x as an exact pair: a = fl(r_hi x), a_lo = (r_hi x - a) + r_lo x
+template <typename T> RF_DEV T exp_scaled(const Scl<T>& r, T x) {
+  const T a = r.hi * x;
+  const T a_lo = fma(r.hi, x, -a) + r.lo * x;
+  return exp_pair<T>(a, a_lo);
+}
 template <typename T, int FORM> RF_DEV T exp_eval(T x, const ExpK<T>& k, T* d) {
   if (FORM == 0) {
     d[0] = x * k.dfac;
-    return RM<T>::exp(k.rate.mul(x));
+    return exp_scaled<T>(k.rate, x);
   }
   const T xs = k.xc.sub(x);
   d[0] = xs;
-  return RM<T>::exp(k.rate.mul(xs));
+  return exp_scaled<T>(k.rate, xs);
 }
 
 // ========================================= decay (x) Gaussian resolution ==
