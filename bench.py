@@ -2,18 +2,21 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-A step is one complete NLL+gradient evaluation of the model over all events
-(FP64 prologue with the normalisations, every event through the fused
+A step is one complete NLL+gradient evaluation of the model over all events:
+the FP64 prologue with the normalisations, every event through the fused
 per-event program and its adjoint, the deterministic reduction and the
-epilogue, result copied to the host and the stream synchronised) -- what a
-minimiser waits for on every iteration.  Events are seeded synthetic data
-already resident in HBM.  The headline value is the FP32+adjoint path; the
-plain FP64 path is reported beside it, and both results are checked against
-the oracle (FP32: NLL relative error <= 1e-6, FP64: <= 1e-9).
+epilogue, and the result in host memory -- what a minimiser waits for on
+every iteration (synchronous call).  Events are seeded synthetic data already
+resident in HBM.  The headline value is the FP32+adjoint path; the plain FP64
+path is timed beside it, and both results are checked against the oracle
+(FP32: NLL relative error <= 1e-6, FP64: <= 1e-9).
 
-Prints ONE JSON line.  Extra fields: the fused kernel's roofline (average
-kernel duration from HIP events on the launch stream) and the oracle's CPU
-throughput on a bounded sample.
+Prints ONE JSON line.  Extra fields:
+  roofline      the fused kernel against the VALU issue rate: algorithmic
+                lane-slots per event times events, over the kernel's average
+                launch duration (HIP events on the launch stream, around each
+                launch of the timed region);
+  cpu_baseline  the oracle's throughput on the host, on a bounded sample.
 """
 import argparse
 import json
@@ -27,23 +30,21 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and unit counts
+# MI355X unit counts: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; one lane-slot is
+# one full-rate (non-packed) VALU lane operation
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9  # 3.93e13
 HBM_PEAK_GBS = 8000.0
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 3.93e13 lane-slots/s
 
 WORKLOADS = {
-    # name: (spec builder, sampler, truth, n events, per-event cost model)
     "gauss_cheb_1e7": dict(n=10_000_000, seed=2),
     "decay_argus_5e7": dict(n=50_000_000, seed=3),
 }
 
-# Algorithmic VALU slots per event of the fused NLL+gradient program (one
-# slot = one full-rate lane operation; a transcendental -- exp, log, rcp,
-# sqrt, erfc core -- counts 4, the quarter rate of the transcendental unit).
-# Counted from the formulas (the design doc lists the breakdown).
+# Algorithmic VALU lane-slots per event of an NLL+gradient evaluation (a
+# transcendental counts 4: the quarter-rate unit), and bytes read per event.
 SLOTS = {
-    "gauss_cheb_1e7": {"fp32": 48 + 4 * 4, "fp64": 48 + 4 * 4},
-    "decay_argus_5e7": {"fp32": 120 + 4 * 9, "fp64": 120 + 4 * 9},
+    "gauss_cheb_1e7": {"fp32": 48, "fp64": 90},
+    "decay_argus_5e7": {"fp32": 165, "fp64": 400},
 }
 BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "decay_argus_5e7": {"fp32": 8, "fp64": 16}}
 
@@ -64,17 +65,32 @@ def make(workload):
     return spec, cols, np.asarray(theta), thetas
 
 
-def time_kernel(prog, thetas, reps, torch):
-    """Average duration of the fused NLL+gradient kernel: HIP events recorded
-    on the stream the kernel is launched on, one pair per launch."""
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for i in range(reps):
+def timed_steps(prog, thetas, steps, torch, stream):
+    """K synchronous NLL+gradient evaluations; returns (seconds per step,
+    mean kernel seconds from an event pair around each launch)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
         evs[i][0].record(stream)
-        prog.nll_grad_async(thetas[i % len(thetas)], stream=stream)
+        prog.nll_grad(thetas[i % len(thetas)], stream=stream)
         evs[i][1].record(stream)
     torch.cuda.synchronize()
-    return float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3  # seconds
+    step_s = (time.perf_counter() - t0) / steps
+    kern_s = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
+    return step_s, kern_s
+
+
+def pipelined_kernel(prog, thetas, reps, torch, stream):
+    """Average duration of back-to-back launches (no host round trip between
+    them): the kernel's own time as a profiler reports it."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for i in range(reps):
+        prog.nll_grad_async(thetas[i % len(thetas)], stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e-3 / reps
 
 
 def main():
@@ -84,6 +100,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="gauss_cheb_1e7", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 path (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -95,10 +112,13 @@ def main():
     from paper_2003_12861_amd import api
 
     torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
     spec, cols, theta, thetas = make(args.workload)
     n = cols[0].size
+    precs = (("fp32", api.FP32, torch.float32),) if args.fp32_only else (
+        ("fp32", api.FP32, torch.float32), ("fp64", api.FP64, torch.float64))
     progs = {}
-    for key, prec, dt in (("fp32", api.FP32, torch.float32), ("fp64", api.FP64, torch.float64)):
+    for key, prec, dt in precs:
         p = api.Program(api.Graph.from_spec(spec), precision=prec)
         p.bind([torch.tensor(c, dtype=dt, device="cuda") for c in cols])
         progs[key] = p
@@ -113,25 +133,18 @@ def main():
     res = {}
     for key, p in progs.items():
         for i in range(args.warmup):
-            p.nll_grad(thetas[i % len(thetas)])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            nll, g, nb = p.nll_grad(thetas[i % len(thetas)])
-        torch.cuda.synchronize()
-        dt_s = (time.perf_counter() - t0) / args.steps
-        kern_s = time_kernel(p, thetas, max(20, min(args.steps, 200)), torch)
-        res[key] = dict(step_s=dt_s, kernel_s=kern_s)
+            p.nll_grad(thetas[i % len(thetas)], stream=stream)
+        step_s, kern_s = timed_steps(p, thetas, args.steps, torch, stream)
+        pipe_s = pipelined_kernel(p, thetas, max(20, min(args.steps, 200)), torch, stream)
+        res[key] = dict(step_s=step_s, kernel_s=kern_s, pipelined_s=pipe_s)
 
     # validity of both paths against the oracle at the truth point
-    check = {}
     cpu = None
-    for key, p in progs.items():
-        check[key] = p.nll_grad(theta)
+    check = {key: p.nll_grad(theta) for key, p in progs.items()}
     if not args.no_cpu_baseline:
         from oracle import rfo
         om, otop, _ = rfo.from_spec(spec)
-        # bounded sample: repeat full-size oracle NLL+gradient evaluations for ~10-30 s
+        # bounded sample: full-size oracle NLL+gradient evaluations for ~10 s
         t0 = time.perf_counter()
         reps = 0
         while True:
@@ -141,18 +154,20 @@ def main():
                 break
         cpu_s = (time.perf_counter() - t0) / reps
         cpu = dict(value=n / cpu_s, unit="events/s", cores=1, kind="oracle",
-                   sample="%d full NLL+gradient evaluations of %d events (single-threaded C, -O2)" % (reps, n),
+                   sample="%d full NLL+gradient evaluations of the %d-event workload (single-threaded C, -O2)" % (reps, n),
                    host=platform.processor() or platform.machine(), nproc=os.cpu_count())
         for key, tol in (("fp32", 1e-6), ("fp64", 1e-9)):
+            if key not in check:
+                continue
             nll, g, _ = check[key]
             res[key]["nll_rel_err"] = abs(nll - onll) / abs(onll)
             res[key]["grad_scaled_err"] = float(np.max(np.abs(g - og) / oga))
             res[key]["valid"] = bool(res[key]["nll_rel_err"] <= tol)
 
-    s32, s64 = SLOTS[args.workload], BYTES_PER_EVENT[args.workload]
     k32 = res["fp32"]["kernel_s"]
-    achieved = n * s32["fp32"] / k32 / 1e12
-    peak = VALU_LANE_OPS / 1e12
+    slots = SLOTS[args.workload]["fp32"]
+    achieved = n * slots / k32 / 1e12
+    peak = VALU_SLOTS_PER_S / 1e12
     line = {
         "metric": "events/s for NLL+gradient (FP32+adjoint vs FP64 plain) at <=1e-6 rel NLL error",
         "value": n / res["fp32"]["step_s"],
@@ -167,24 +182,29 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "events": n, "precision": "fp32+adjoint, fp64 reductions",
-                   "step": "one synchronous NLL+gradient evaluation"},
-        "fp64_plain": {"value": n / res["fp64"]["step_s"], "unit": "events/s",
-                       "ms_per_step": res["fp64"]["step_s"] * 1e3,
-                       "kernel_ms": res["fp64"]["kernel_s"] * 1e3,
-                       "kernel_events_per_s": n / res["fp64"]["kernel_s"],
-                       "nll_rel_err": res["fp64"].get("nll_rel_err"),
-                       "grad_scaled_err": res["fp64"].get("grad_scaled_err"),
-                       "valid": res["fp64"].get("valid")},
-        "fp32": {"kernel_ms": k32 * 1e3, "kernel_events_per_s": n / k32,
+                   "step": "one synchronous NLL+gradient evaluation (result in host memory)"},
+        "fp32": {"kernel_ms": k32 * 1e3, "pipelined_kernel_ms": res["fp32"]["pipelined_s"] * 1e3,
+                 "kernel_events_per_s": n / k32,
                  "nll_rel_err": res["fp32"].get("nll_rel_err"),
                  "grad_scaled_err": res["fp32"].get("grad_scaled_err"),
                  "valid": res["fp32"].get("valid")},
         "roofline": {"bound": "alu", "kernel": "rf_k_grad (fp32)", "achieved": achieved, "peak": peak,
                      "unit": "Tslot/s", "frac": achieved / peak, "traffic": None,
-                     "slots_per_event": s32["fp32"], "bytes_per_event": s64["fp32"],
-                     "hbm_GBps": n * s64["fp32"] / k32 / 1e9},
+                     "slots_per_event": slots, "events_per_launch": n,
+                     "bytes_per_event": BYTES_PER_EVENT[args.workload]["fp32"],
+                     "hbm_GBps": n * BYTES_PER_EVENT[args.workload]["fp32"] / k32 / 1e9},
         "cpu_baseline": cpu,
     }
+    if "fp64" in res:
+        line["fp64_plain"] = {"value": n / res["fp64"]["step_s"], "unit": "events/s",
+                              "ms_per_step": res["fp64"]["step_s"] * 1e3,
+                              "kernel_ms": res["fp64"]["kernel_s"] * 1e3,
+                              "pipelined_kernel_ms": res["fp64"]["pipelined_s"] * 1e3,
+                              "kernel_events_per_s": n / res["fp64"]["kernel_s"],
+                              "roofline_frac": n * SLOTS[args.workload]["fp64"] / res["fp64"]["kernel_s"] / VALU_SLOTS_PER_S,
+                              "nll_rel_err": res["fp64"].get("nll_rel_err"),
+                              "grad_scaled_err": res["fp64"].get("grad_scaled_err"),
+                              "valid": res["fp64"].get("valid")}
     print(json.dumps(line))
 
 

@@ -131,6 +131,10 @@ int rf_program_info(const rf_program* p, int32_t* n_params, int32_t* n_columns,
                     int32_t* n_sums);
 /* generated HIP source (NUL-terminated, owned by the program) */
 const char* rf_program_source(const rf_program* p);
+/* Counters of the synchronous calls (rf_nll, rf_nll_grad) of a program: how
+ * many were made and how many waited longer than 20 ms for the result word
+ * and fell back to a stream synchronisation.  Either pointer may be NULL. */
+int rf_program_stats(const rf_program* p, int64_t* sync_calls, int64_t* slow_waits);
 
 /* ---- binding ------------------------------------------------------------- */
 /* dev_cols[j]: contiguous column of observable j (n_events values), float64

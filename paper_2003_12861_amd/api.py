@@ -48,6 +48,7 @@ _SIGS = {
     "rf_program_free": ([_P], None),
     "rf_program_info": ([_P, _PI32, _PI32, _PI32], _I32),
     "rf_program_source": ([_P], ctypes.c_char_p),
+    "rf_program_stats": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I32),
     "rf_bind_columns": ([_P, _PP, _I32, _I64, _P], _I32),
     "rf_bind_weights": ([_P, _I32, _P, _P], _I32),
     "rf_set_launch": ([_P, _I32, _I32], _I32),
@@ -283,6 +284,12 @@ class Program:
     def nll_grad_async(self, theta, stream=None):
         th = self._theta(theta)
         check(rf_nll_grad_async(self.h, _dptr(th), _stream(stream)))
+
+    def stats(self):
+        """(synchronous calls, calls whose wait fell back to a stream sync)"""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        check(rf_program_stats(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def result_ptr(self):
         return rf_program_result(self.h)

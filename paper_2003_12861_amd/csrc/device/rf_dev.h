@@ -12,8 +12,12 @@
 //     with location-type constants split into hi + lo parts for T = float so
 //     that (x - mu) keeps FP64 accuracy when mu is large compared to the
 //     spread (e.g. a 5.28 GeV mass with a 3 MeV width).
-//   * <op>_eval<T>(): per-event unnormalised shape u(x) and
-//     d log u / d(shape input j).
+//   * <op>_eval<T>(): per-event unnormalised shape u(x) and its derivative
+//     with respect to shape input j, without the factors that depend on the
+//     parameters only (those multiply the event sums once, in FP64, after
+//     the reduction).  Most leaves give d log u / d(input) ("log form"); a
+//     leaf that is linear in its inputs gives du / d(input) ("linear form"),
+//     which needs no division by u.
 // The shapes are the textbook PDFs of the batched RooFit work (Gaussian,
 // exponential and sums of PDFs, Sections 4.1-4.2) and of the benchmark
 // models (Chebyshev polynomial, decay (x) Gaussian resolution, ARGUS,
@@ -33,6 +37,11 @@ template <> struct RM<float> {
   RF_DEV float erfcx(float x) { return erfcxf(x); }
   RF_DEV float sqrt(float x) { return sqrtf(x); }
   RF_DEV float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  // hardware square root (one transcendental instruction, ~1 ulp)
+  RF_DEV float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+  // log p as accumulated by the event loop: log2 p (hardware instruction);
+  // the FP64 flush multiplies the partial sums by ln 2
+  RF_DEV float log_acc(float x) { return __builtin_amdgcn_logf(x); }
   RF_DEV bool finite(float x) { return isfinite(x); }
   RF_DEV float tiny() { return 1e-30f; }  // FP32 results below this are redone in FP64
 };
@@ -49,12 +58,14 @@ template <> struct RM<double> {
     r = fma(r, fma(-x, r, 1.0), r);
     return r;
   }
+  RF_DEV double sqrt_fast(double x) { return ::sqrt(x); }
+  RF_DEV double log_acc(double x) { return ::log(x); }
   RF_DEV bool finite(double x) { return isfinite(x); }
   RF_DEV double tiny() { return 0.0; }
 };
 
-// A location constant: value as hi (+ lo for float) so that
-// sub(x) = (x - hi) - lo.  For T = double lo is 0 and folded away.
+// A location constant: for float its value as hi + lo so that
+// sub(x) = (x - hi) - lo keeps the FP64 value of the location.
 template <typename T> struct Loc {
   T hi, lo;
   RF_DEV Loc make(double v) {
@@ -65,8 +76,17 @@ template <typename T> struct Loc {
   }
   __device__ __forceinline__ T sub(T x) const { return (x - hi) - lo; }
 };
+template <> struct Loc<double> {
+  double hi;
+  RF_DEV Loc make(double v) {
+    Loc l;
+    l.hi = v;
+    return l;
+  }
+  __device__ __forceinline__ double sub(double x) const { return x - hi; }
+};
 // A scale constant for products x*s that must stay accurate when |x*s| is
-// large (exponent arguments): s = hi + lo, x*s ~ fma(x, hi, x*lo).
+// large: for float s = hi + lo and x*s ~ fma(x, hi, x*lo).
 template <typename T> struct Scl {
   T hi, lo;
   RF_DEV Scl make(double v) {
@@ -76,6 +96,53 @@ template <typename T> struct Scl {
     return s;
   }
   __device__ __forceinline__ T mul(T x) const { return fma(x, hi, x * lo); }
+};
+template <> struct Scl<double> {
+  double hi;
+  RF_DEV Scl make(double v) {
+    Scl s;
+    s.hi = v;
+    return s;
+  }
+  __device__ __forceinline__ double mul(double x) const { return x * hi; }
+};
+
+static constexpr double RF_LOG2E = 1.44269504088896340736;
+static constexpr double RF_LN2 = 0.69314718055994530942;
+
+// exp(s x) for a parameter-dependent rate s.  In float the rate is held in
+// base-2 units, s log2(e) = hi + lo, and the product t = hi x is split
+// exactly into t + t_lo with an FMA; 2^t comes from the hardware exp2
+// instruction and the small remainder enters to first order,
+// exp(s x) = 2^t (1 + ln2 t_lo + extra).  Without the split, an argument
+// of -40 (a Gaussian 9 widths out) would carry an absolute rounding of
+// 2.4e-6, i.e. that relative error in the result.  extra is an additional
+// small correction in natural units (the low part of a squared argument).
+template <typename T> struct ExpScl;
+template <> struct ExpScl<float> {
+  float hi, lo;
+  RF_DEV ExpScl make(double s) {
+    ExpScl e;
+    const double v = s * RF_LOG2E;
+    e.hi = (float)v;
+    e.lo = (float)(v - (double)e.hi);
+    return e;
+  }
+  __device__ __forceinline__ float exp(float x, float extra = 0.0f) const {
+    const float t = hi * x;
+    const float t_lo = fma(lo, x, fma(hi, x, -t));
+    const float E = __builtin_amdgcn_exp2f(t);
+    return fma(E, fma(t_lo, (float)RF_LN2, extra), E);
+  }
+};
+template <> struct ExpScl<double> {
+  double hi;
+  RF_DEV ExpScl make(double s) {
+    ExpScl e;
+    e.hi = s;
+    return e;
+  }
+  __device__ __forceinline__ double exp(double x, double extra = 0.0) const { return ::exp(fma(hi, x, extra)); }
 };
 
 static constexpr double RF_SQRT2 = 1.41421356237309504880;
@@ -103,35 +170,28 @@ RF_DEV void gauss_prologue(const double* in, double lo, double hi, double* C) {
   C[3] = mu;
   C[4] = 1.0 / s;
 }
+// Log form; d log u/d mu = z/sigma, d log u/d sigma = z^2/sigma with
+// z = (x - mu)/sigma: the event part is (z, z^2), the factor 1/sigma (C[4])
+// is applied to the sums.
 template <typename T> struct GaussK {
-  T invN;
   Loc<T> mu;
   Scl<T> isig;
+  ExpScl<T> e;
   RF_DEV GaussK load(const double* C) {
     GaussK k;
-    k.invN = (T)C[0];
     k.mu = Loc<T>::make(C[3]);
     k.isig = Scl<T>::make(C[4]);
+    k.e = ExpScl<T>::make(-0.5);
     return k;
   }
 };
-// exp(a + a_lo) for a small correction a_lo: exp(a) (1 + a_lo).  Large
-// exponent arguments (a Gaussian 9 widths out: -40.5) carry an FP32 rounding
-// of a few 1e-6 absolute, i.e. a relative error of the result; keeping the
-// argument as an exact pair removes it.
-template <typename T> RF_DEV T exp_pair(T a, T a_lo) {
-  const T e = RM<T>::exp(a);
-  return fma(e, a_lo, e);
-}
 template <typename T> RF_DEV T gauss_eval(T x, const GaussK<T>& k, T* d) {
   const T z = k.isig.mul(k.mu.sub(x));
   const T q = z * z;
-  const T q_lo = fma(z, z, -q);  // z^2 = q + q_lo exactly
-  const T u = exp_pair<T>((T)-0.5 * q, (T)-0.5 * q_lo);
-  const T is = k.isig.hi;
-  d[0] = z * is;      // d log u / d mu
-  d[1] = q * is;      // d log u / d sigma
-  return u;
+  d[0] = z;
+  d[1] = q;
+  // z^2 = q + fma(z, z, -q) exactly; the low part enters the exponent
+  return k.e.exp(q, (T)-0.5 * fma(z, z, -q));
 }
 
 // ============================================================= Chebyshev ==
@@ -148,12 +208,12 @@ template <int NC> RF_DEV void cheb_prologue(const double* in, double lo, double 
   C[NC + 2] = -(hi + lo) / (hi - lo);
   for (int k = 1; k <= NC; ++k) C[NC + 2 + k] = in[k - 1];
 }
+// Linear form: d[j] = du/dc_j = T_j(x').
 template <typename T, int NC> struct ChebK {
-  T invN, a, b;
+  T a, b;
   T c[NC];
   RF_DEV ChebK load(const double* C) {
     ChebK k;
-    k.invN = (T)C[0];
     k.a = (T)C[NC + 1];
     k.b = (T)C[NC + 2];
     for (int j = 0; j < NC; ++j) k.c[j] = (T)C[NC + 3 + j];
@@ -171,9 +231,6 @@ template <typename T, int NC> RF_DEV T cheb_eval(T x, const ChebK<T, NC>& k, T* 
     tkm = tk;
     tk = tn;
   }
-  const T iu = RM<T>::rcp(u);
-#pragma unroll
-  for (int j = 0; j < NC; ++j) d[j] *= iu;
   return u;
 }
 
@@ -211,34 +268,26 @@ RF_DEV void exp_prologue(const double* in, double lo, double hi, int form, doubl
     C[4] = 0.0;
   }
 }
+// Log form.  Form 0: d log u/d tau = x/tau^2 (event part x, factor C[4]);
+// form 1: d log u/d lam = x - xc (factor 1).
 template <typename T> struct ExpK {
-  T invN;
-  Scl<T> rate;
+  ExpScl<T> rate;
   Loc<T> xc;
-  T dfac;  // form 0: 1/tau^2 (d log u/d tau = x/tau^2); form 1: 0 (d log u/d lam = x - xc)
   RF_DEV ExpK load(const double* C) {
     ExpK k;
-    k.invN = (T)C[0];
-    k.rate = Scl<T>::make(C[2]);
+    k.rate = ExpScl<T>::make(C[2]);
     k.xc = Loc<T>::make(C[3]);
-    k.dfac = (T)C[4];
     return k;
   }
 };
-// argument r x as an exact pair: a = fl(r_hi x), a_lo = (r_hi x - a) + r_lo x
-template <typename T> RF_DEV T exp_scaled(const Scl<T>& r, T x) {
-  const T a = r.hi * x;
-  const T a_lo = fma(r.hi, x, -a) + r.lo * x;
-  return exp_pair<T>(a, a_lo);
-}
 template <typename T, int FORM> RF_DEV T exp_eval(T x, const ExpK<T>& k, T* d) {
   if (FORM == 0) {
-    d[0] = x * k.dfac;
-    return exp_scaled<T>(k.rate, x);
+    d[0] = x;
+    return k.rate.exp(x);
   }
   const T xs = k.xc.sub(x);
   d[0] = xs;
-  return exp_scaled<T>(k.rate, xs);
+  return k.rate.exp(xs);
 }
 
 // ========================================= decay (x) Gaussian resolution ==
@@ -286,13 +335,11 @@ RF_DEV void decay_prologue(const double* in, double lo, double hi, double* C) {
   C[11] = s / (tau * tau);
 }
 template <typename T> struct DecayK {
-  T invN;
   Loc<T> b;
   Scl<T> slope;
   T off, shift, wscale, gfac, itau2, s_tau2, c_tau_s, c_s, c_b, itau, is2;
   RF_DEV DecayK load(const double* C) {
     DecayK k;
-    k.invN = (T)C[0];
     k.b = Loc<T>::make(C[4]);
     k.slope = Scl<T>::make(C[5]);
     k.off = (T)C[6];
@@ -366,33 +413,33 @@ RF_DEV void argus_prologue(const double* in, double lo, double hi, double* C) {
   C[4] = 1.0 / (m0 * m0);
   C[5] = c;
 }
+// Log form: d log u/d c = U (input 0, m0, is a constant).
 template <typename T> struct ArgusK {
-  T invN;
   Loc<T> m0;
-  T m0f, im02, c;
+  T m0f, im02;
+  ExpScl<T> c;
   RF_DEV ArgusK load(const double* C) {
     ArgusK k;
-    k.invN = (T)C[0];
     k.m0 = Loc<T>::make(C[3]);
     k.m0f = (T)C[3];
     k.im02 = (T)C[4];
-    k.c = (T)C[5];
+    k.c = ExpScl<T>::make(C[5]);
     return k;
   }
 };
 template <typename T> RF_DEV T argus_eval(T x, const ArgusK<T>& k, T* d) {
   const T dm = -k.m0.sub(x);  // m0 - x
-  const T U = dm * (k.m0f + x) * k.im02;
+  // U < 0 above the endpoint, where the shape is 0: clamping gives u = 0
+  const T U = fmax(dm * (k.m0f + x) * k.im02, (T)0);
   d[0] = (T)0;
   d[1] = U;
-  if (!(dm > (T)0)) { d[1] = (T)0; return (T)0; }
-  return x * RM<T>::sqrt(U) * RM<T>::exp(k.c * U);
+  return x * RM<T>::sqrt_fast(U) * k.c.exp(U);
 }
 
 // ========================================================= Breit-Wigner ==
 // u = 1/((x-M)^2 + Gamma^2/4);  inputs (M, Gamma);
 // N = (2/Gamma)[atan(2(hi-M)/Gamma) - atan(2(lo-M)/Gamma)].
-enum { BW_NC = 5 };
+enum { BW_NC = 6 };
 RF_DEV void bw_norm(double lo, double hi, double M, double G, double* N, double* dM, double* dG) {
   const double qh = 2 * (hi - M) / G, ql = 2 * (lo - M) / G;
   const double n = 2.0 / G * (::atan(qh) - ::atan(ql));
@@ -410,29 +457,42 @@ RF_DEV void bw_prologue(const double* in, double lo, double hi, double* C) {
   C[2] = dG / N;
   C[3] = in[0];
   C[4] = 0.25 * in[1] * in[1];
+  C[5] = -0.5 * in[1];
 }
+// Log form: d log u/d M = 2 q u, d log u/d Gamma = -(Gamma/2) u with
+// q = x - M: event parts (q u, u), factors (2, C[5]).
 template <typename T> struct BwK {
-  T invN;
   Loc<T> M;
-  T g2, hg;
+  T g2;
   RF_DEV BwK load(const double* C) {
     BwK k;
-    k.invN = (T)C[0];
     k.M = Loc<T>::make(C[3]);
     k.g2 = (T)C[4];
-    k.hg = (T)::sqrt(C[4]);
     return k;
   }
 };
 template <typename T> RF_DEV T bw_eval(T x, const BwK<T>& k, T* d) {
   const T q = k.M.sub(x);
   const T b = RM<T>::rcp(fma(q, q, k.g2));
-  d[0] = (T)2 * q * b;
-  d[1] = -k.hg * b;
+  d[0] = q * b;
+  d[1] = b;
   return b;
 }
 
 // ====================================================== reductions, misc ==
+// Cross-workgroup hand-off of the per-workgroup partial sums.  Partials are
+// written with agent-scope atomic stores (written through to the level that
+// is coherent across the whole device) and read back with agent-scope atomic
+// loads, and nothing else is exchanged, so ordering them before the
+// workgroup's ticket only needs the stores to be acknowledged: a wait on the
+// vector-memory counter, with a compiler barrier.  A generic release fence
+// would also write back the XCD's whole L2, once per workgroup.
+RF_DEV void rf_wait_stores() { __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+RF_DEV unsigned rf_take_ticket(unsigned* t) {
+  return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+RF_DEV void rf_reset_ticket(unsigned* t) { __hip_atomic_store(t, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
 // TwoSum (Knuth): s + e == a + b exactly.
 RF_DEV void two_sum(double a, double b, double& s, double& e) {
   s = a + b;
@@ -574,6 +634,7 @@ template <typename T, typename TT, int K> RF_DEV T numconv_eval(T x, const Numco
   constexpr int ST = NumconvRow<TT>::stride;
   constexpr int CH = 16;  // nodes per FP32 partial before it is added to FP64
   double S = 0, dM = 0, dG = 0, ds = 0, da = 0, dn = 0;
+#pragma unroll 1
   for (int j0 = 0; j0 < K; j0 += CH) {
     T s1 = 0, m1 = 0, g1 = 0, s3 = 0, a3 = 0, n3 = 0;
 #pragma unroll

@@ -10,14 +10,16 @@
 struct RfArgs {
   const void* col[RF_MAX_COLS];  // observable columns (float or double)
   int64_t n;                     // number of events
-  double* part;                  // block partials: [nsum][2 (hi, lo)][nblk_max]
-  unsigned* part_bad;            // per-block count of bad events [nblk_max]
+  double* part;                  // block partials: [nsum + 1][2 (hi, lo)][nblk_max] (last: bad-event count)
   unsigned* ticket;              // last-block ticket (0 between launches)
   double* out;                   // result: [nll, grad[P], n_bad, sums...]
   void* values;                  // per-event output of the values kernel
   const double* aux;             // auxiliary FP64 inputs (e.g. surrogate normalisation)
   const void* weights;           // MLP weights (bf16)
+  double* hout;                  // optional copy of out in mapped host memory (or null),
+                                 // followed by a 64-bit completion word set to seq
+  uint64_t seq;
   int32_t nblk_max;              // stride of part (>= gridDim.x)
-  int32_t pad_;
+  int32_t vec;                   // 1: columns (and values) are 16-byte aligned
   double theta[RF_MAX_PARAMS];   // parameter point
 };

@@ -124,12 +124,11 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
     __hip_atomic_store(&a.part[(2 * k) * (int64_t)a.nblk + blockIdx.x], hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&a.part[(2 * k + 1) * (int64_t)a.nblk + blockIdx.x], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if ((int)threadIdx.x < NS) __threadfence();
+  rf_wait_stores();
   __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(a.ticket, 1u) == gridDim.x - 1);
+  if (threadIdx.x == 0) last = (rf_take_ticket(a.ticket) == gridDim.x - 1);
   __syncthreads();
   if (!last) return;
-  __threadfence();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nb = (int)gridDim.x;
   for (int k = wid; k < NS; k += NW) {
@@ -149,7 +148,7 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
     a.out[0] = fin[0] + c2;
     a.out[1] = fin[1];
     for (int j = 0; j < J; ++j) a.out[2 + j] = fin[2 + j] + a.theta[1 + j];
-    *a.ticket = 0u;
+    rf_reset_ticket(a.ticket);
   }
 }
 

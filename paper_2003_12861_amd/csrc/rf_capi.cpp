@@ -1,4 +1,6 @@
 // rf_capi.cpp -- programs: compile, bind, launch, read back.
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -17,26 +19,39 @@ int cu_count(int dev) {
 
 void free_workspace(rf_program* p) {
   if (p->d_part) hipFree(p->d_part);
-  if (p->d_part_bad) hipFree(p->d_part_bad);
   if (p->d_ticket) hipFree(p->d_ticket);
   if (p->d_out) hipFree(p->d_out);
   if (p->h_out) hipHostFree(p->h_out);
   if (p->d_aux) hipFree(p->d_aux);
   p->d_part = nullptr;
-  p->d_part_bad = nullptr;
   p->d_ticket = nullptr;
   p->d_out = nullptr;
   p->h_out = nullptr;
+  p->d_hout = nullptr;
   p->d_aux = nullptr;
 }
 
 int out_len(const rf_program* p) { return p->L.n_params + 2 + p->L.n_sums; }
 
+// events per lane and step: 16 bytes of a column (4 in FP32, 2 in FP64); one
+// for the convolution leaf, whose per-event loop hides the load latency
+int choose_ept(const Lowered& L) {
+  int ept = L.has_numconv ? 1 : (L.precision == RF_FP32_COMP ? 4 : 2);
+  if (const char* e = getenv("RFGPU_EPT")) {  // tuning override
+    const int v = atoi(e);
+    if (v == 1 || v == 2 || v == 4) ept = v;
+  }
+  return ept;
+}
+
 int choose_blocks(const rf_program* p) {
   if (p->blocks_override > 0) return p->blocks_override;
-  const int64_t per = (int64_t)p->block * 16;
+  // about 16 steps per lane, at most 4 workgroups per CU: enough waves to
+  // hide the load latency while keeping the number of partials (and the last
+  // workgroup's reduction) small
+  const int64_t per = (int64_t)p->block * p->ept * 16;
   int64_t b = (p->n + per - 1) / per;
-  const int64_t cap = (int64_t)cu_count(p->device) * 8;
+  const int64_t cap = (int64_t)cu_count(p->device) * 4;
   if (b > cap) b = cap;
   if (b < 1) b = 1;
   return (int)b;
@@ -47,12 +62,16 @@ void fill_args(const rf_program* p, const double* theta, RfArgs& a) {
   for (int c = 0; c < RF_MAX_COLS; ++c) a.col[c] = p->cols[c];
   a.n = p->n;
   a.part = p->d_part;
-  a.part_bad = p->d_part_bad;
   a.ticket = p->d_ticket;
   a.out = p->d_out;
   a.aux = p->d_aux;
   a.weights = p->d_weights;
   a.nblk_max = p->nblk_max;
+  a.hout = nullptr;
+  // 16-byte vector loads need 16-byte aligned columns
+  a.vec = 1;
+  for (int c = 0; c < p->L.n_cols; ++c)
+    if ((uintptr_t)p->cols[c] % 16) a.vec = 0;
   for (int k = 0; k < p->L.n_params; ++k) a.theta[k] = theta[k];
 }
 
@@ -98,12 +117,27 @@ int ready(rf_program* p, const double* theta) {
 int run_sync(rf_program* p, hipFunction_t f, const double* theta, void* stream) {
   RfArgs a;
   fill_args(p, theta, a);
+  // the last workgroup also writes the result into the mapped host buffer,
+  // then the completion word: poll it (a short call returns as soon as the
+  // kernel's last workgroup is done), falling back to a stream
+  // synchronisation after 20 ms (long calls, and errors)
+  a.hout = p->d_hout;
+  a.seq = ++p->seq;
+  volatile uint64_t* done = (volatile uint64_t*)(p->h_out + out_len(p));
   int rc = launch(p, f, a, stream);
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(p->h_out, p->d_out, sizeof(double) * out_len(p), hipMemcpyDeviceToHost, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-  e = hipStreamSynchronize((hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  const auto t0 = std::chrono::steady_clock::now();
+  p->n_sync++;
+  while (*done != a.seq) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+      p->n_slow++;
+      hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      if (*done != a.seq) return fail(RF_E_DEVICE, "kernel completed without writing its result");
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   return RF_OK;
 }
 
@@ -119,11 +153,12 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
   rf_program* p = new rf_program();
   int rc = lower(g->nodes, top, precision, p->L);
   if (rc) { delete p; return rc; }
-  if (const char* e = getenv("RFGPU_PF")) {  // tuning override of the prefetch distance
+  if (const char* e = getenv("RFGPU_BS")) {  // tuning override of the workgroup size
     const int v = atoi(e);
-    if (v >= 1 && v <= 16) p->unroll = v;
+    if (v >= 64 && v <= 1024 && v % 64 == 0) p->block = v;
   }
-  p->source = generate_source(p->L, p->block, p->unroll);
+  p->ept = choose_ept(p->L);
+  p->source = generate_source(p->L, p->block, p->ept);
   rc = build_code_object(p->source, p->co_path);
   if (rc) { delete p; return rc; }
   if (!(flags & RF_COMPILE_NO_LOAD)) {
@@ -153,6 +188,13 @@ int rf_program_info(const rf_program* p, int32_t* n_params, int32_t* n_columns, 
 }
 
 const char* rf_program_source(const rf_program* p) { return p ? p->source.c_str() : ""; }
+
+int rf_program_stats(const rf_program* p, int64_t* sync_calls, int64_t* slow_waits) {
+  if (!p) return fail(RF_E_INVALID, "program is NULL");
+  if (sync_calls) *sync_calls = p->n_sync;
+  if (slow_waits) *slow_waits = p->n_slow;
+  return RF_OK;
+}
 
 int rf_set_launch(rf_program* p, int32_t blocks, int32_t threads) {
   if (!p) return fail(RF_E_INVALID, "program is NULL");
@@ -188,13 +230,17 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
   if (!p->d_out || nmax > p->nblk_max) {
     free_workspace(p);
     hipError_t e;
-    const size_t np = (size_t)p->L.n_sums * 2 * nmax;
+    const size_t np = (size_t)(p->L.n_sums + 1) * 2 * nmax;  // sums + bad-event count
     if ((e = hipMalloc(&p->d_part, sizeof(double) * np)) != hipSuccess) return hip_fail(e, "hipMalloc partials");
-    if ((e = hipMalloc(&p->d_part_bad, sizeof(unsigned) * nmax)) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMalloc(&p->d_out, sizeof(double) * out_len(p))) != hipSuccess) return hip_fail(e, "hipMalloc");
-    if ((e = hipHostMalloc(&p->h_out, sizeof(double) * out_len(p), hipHostMallocDefault)) != hipSuccess)
+    // result copy + completion word
+    if ((e = hipHostMalloc(&p->h_out, sizeof(double) * (out_len(p) + 1), hipHostMallocMapped | hipHostMallocCoherent)) !=
+        hipSuccess)
       return hip_fail(e, "hipHostMalloc");
+    memset(p->h_out, 0, sizeof(double) * (out_len(p) + 1));
+    if ((e = hipHostGetDevicePointer((void**)&p->d_hout, p->h_out, 0)) != hipSuccess)
+      return hip_fail(e, "hipHostGetDevicePointer");
     if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMemset");
     if (!p->L.aux.empty()) {
       if ((e = hipMalloc(&p->d_aux, sizeof(double) * p->L.aux.size())) != hipSuccess) return hip_fail(e, "hipMalloc aux");
@@ -226,6 +272,7 @@ int rf_eval_values(rf_program* p, const double* theta, void* dev_out, void* stre
   RfArgs a;
   fill_args(p, theta, a);
   a.values = dev_out;
+  if ((uintptr_t)dev_out % 16) a.vec = 0;
   return launch(p, p->m.k_values, a, stream);
 }
 

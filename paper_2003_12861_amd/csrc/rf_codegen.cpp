@@ -6,19 +6,23 @@
 // instead of one array pass per node), then -log p and -- for the gradient
 // entry point -- a reverse sweep over the same program.
 //
-// Gradient decomposition.  For a PDF leaf l with normalised value
-// v_l = u_l / N_l, d p / d(theta) through l equals
-//     (dp/dv_l) v_l [ d log u_l / d(theta) - d log N_l / d(theta) ].
-// With w_l = (d log p / d v_l) v_l (the reverse sweep's adjoint times v_l) the
-// gradient of NLL = -sum log p is
-//     g = -sum_i sum_l w_l,i d log u_l,i / d(theta)  +  sum_l W_l d log N_l / d(theta),
-//     W_l = sum_i w_l,i.
-// So the event loop only accumulates D_slot = sum_i w_l,i d log u_l,i / d(input)
-// per theta-dependent shape input and W_l per leaf (plus the fraction terms of
-// sums of PDFs); the FP64 epilogue contracts them with the prologue's
-// d log N / d(input) and with d(input)/d(theta).  Normalisation derivatives
-// never enter the event loop.
+// Gradient decomposition.  In the event loop a PDF node c has the value u_c
+// (a leaf: its unnormalised shape; a product: the product of its factors; a
+// sum: sum_j a_j s_j u_j with the component scales s_j = 1/N folded into the
+// coefficients), and p = s_top u_top.  The adjoint b_c = (dp/du_c)/p factors
+// as P_c beta_c: P_c collects the parameter-only factors along the path from
+// the top (coefficients a_j s_j), beta_c the per-event ones (1/p, the other
+// factors of a product).  With d_j the leaf's event part of d log u/d(input j)
+// (or du/d(input j) for leaves in linear form) and f_j its parameter-only
+// factor, the gradient of NLL = -sum log p through input j of leaf l is
+//     -P_l [ f_j sum_i beta_l u_l d_j  -  Y_l d log N_l / d(input j) ],
+// Y_l = sum_i beta_l u_l (one sum shared by the factors of a product), and
+// through fraction a_j of a sum n it is -P_n (s_j Y_j - s_last Y_last).  So
+// the event loop accumulates only sum log p, one D sum per theta-dependent
+// leaf input and the Y sums; every parameter-only factor and every
+// normalisation derivative enters once, in the FP64 epilogue.
 #include <cstdio>
+#include <cstdlib>
 #include <functional>
 #include <sstream>
 
@@ -64,6 +68,20 @@ static std::string eval_call(const Node& n, int id, const std::string& x) {
     case RF_OP_MLP: return "mlp_leaf_eval<T, RF_NSPLIT, MODE == 2>(" + x + ", " + k + ", " + d + ")";
   }
   return "";
+}
+
+// leaves whose derivative outputs are du/d(input) (linear form)
+static bool dlin(const Node& n) { return n.op == RF_OP_CHEB; }
+
+// parameter-only factor f_j of a leaf's derivative output j (FP64 expression)
+static std::string dscale(const Node& n, int off, int j) {
+  auto c = [&](int k) { return "cst[" + std::to_string(off + k) + "]"; };
+  switch (n.op) {
+    case RF_OP_GAUSS: return c(4);
+    case RF_OP_EXP: return n.attrs[0] == 0.0 ? c(4) : "1.0";
+    case RF_OP_BW: return j == 0 ? "2.0" : c(5);
+  }
+  return "1.0";
 }
 
 static bool blockwide(const Node& n) { return n.op == RF_OP_NUMCONV_BW_CB || n.op == RF_OP_MLP; }
@@ -123,7 +141,7 @@ static void emit_jac(std::ostringstream& o, const Lowered& L, int id, const std:
   }
 }
 
-std::string generate_source(const Lowered& L, int BS, int U) {
+std::string generate_source(const Lowered& L, int BS, int ept) {
   const auto& g = L.nodes;
   const int N = (int)g.size();
   const bool f32 = L.precision == RF_FP32_COMP;
@@ -137,7 +155,7 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   o << "#define RF_NSUM " << L.n_sums << "\n";
   o << "#define RF_P " << L.n_params << "\n";
   o << "#define RF_BS " << BS << "\n";
-  o << "#define RF_PF " << U << "\n";
+  o << "#define RF_EPT " << ept << "\n";
   // programs with an MLP leaf run the event loop in whole wavefronts (the MLP
   // is wave-cooperative) and evaluate in FP32 only (no FP64 re-evaluation)
   o << "#define RF_WAVE_UNIFORM " << (L.has_mlp ? 1 : 0) << "\n";
@@ -158,12 +176,36 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   if (any_tab) o << "__shared__ double rf_scr[RF_BS / 64 * 6];\n\n";
 
   // ---- per-event constants ----
+  // scale s_c of a PDF node and path constant P_c, as FP64 expressions over
+  // the constant block X
+  std::function<std::string(int, const std::string&)> scale = [&](int id, const std::string& X) -> std::string {
+    const Node& n = g[id];
+    if (is_leaf(n.op)) return X + "[" + std::to_string(L.cst_off[id]) + "]";
+    if (n.op == RF_OP_PROD_PDF) {
+      std::string r = "1.0";
+      for (int i : n.in) r += " * " + scale(i, X);
+      return r;
+    }
+    return "1.0";
+  };
+  std::function<std::string(int, const std::string&)> pathc = [&](int id, const std::string& X) -> std::string {
+    const int par = L.parent[id];
+    if (par < 0) return "(" + scale(id, X) + ")";
+    const Node& pn = g[par];
+    if (pn.op == RF_OP_PROD_PDF) return pathc(par, X);
+    const int nc = ((int)pn.in.size() + 1) / 2;
+    int j = 0;
+    while (j < nc && pn.in[j] != id) ++j;
+    return "(" + pathc(par, X) + " * " + X + "[" + std::to_string(L.cst_off[par] + j) + "] * " + scale(id, X) + ")";
+  };
+  const bool top_add = g[L.top].op == RF_OP_ADD_PDF;
   o << "template <typename T> struct KS {\n";
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
     if (is_leaf(g[id].op)) o << "  " << ktype(g[id]) << " l" << id << ";\n";
     if (g[id].op == RF_OP_ADD_PDF) o << "  T a" << id << "[" << (g[id].in.size() + 1) / 2 << "];\n";
   }
+  if (!top_add) o << "  T stop;\n";
   o << "  int unused_;\n";
   o << "  RF_DEV KS load(const double* C) {\n    KS k;\n";
   for (int id = 0; id < N; ++id) {
@@ -175,10 +217,13 @@ std::string generate_source(const Lowered& L, int BS, int U) {
     else if (is_leaf(g[id].op))
       o << "    k.l" << id << " = " << ktype(g[id]) << "::load(C + " << L.cst_off[id] << ");\n";
     if (g[id].op == RF_OP_ADD_PDF) {
+      // coefficient a_j times the component's scale s_j
       const int nc = ((int)g[id].in.size() + 1) / 2;
-      for (int j = 0; j < nc; ++j) o << "    k.a" << id << "[" << j << "] = (T)C[" << L.cst_off[id] + j << "];\n";
+      for (int j = 0; j < nc; ++j)
+        o << "    k.a" << id << "[" << j << "] = (T)(C[" << L.cst_off[id] + j << "] * " << scale(g[id].in[j], "C") << ");\n";
     }
   }
+  if (!top_add) o << "    k.stop = (T)(" << scale(L.top, "C") << ");\n";
   o << "    k.unused_ = 0;\n    return k;\n  }\n};\n\n";
 
   // ---- prologue ----
@@ -232,16 +277,18 @@ std::string generate_source(const Lowered& L, int BS, int U) {
   o << "  (void)a; (void)tid; (void)cst;\n}\n\n";
 
   // ---- per-event program ----
+  // returns false when p is not a usable probability (FP32: below 1e-30 or
+  // not finite; FP64: not positive or not finite); such an event adds
+  // nothing to the sums.  acc[0] += log p (FP32: log2 p), acc[D], acc[Y].
   o << "template <typename T, int MODE>\n";
-  o << "RF_DEV bool rf_eval(const T* x, const KS<T>& k, double* acc, T* pout, bool valid) {\n";
+  o << "RF_DEV bool rf_eval(const T* x, const KS<T>& k, T* acc, T* pout) {\n";
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
     const Node& n = g[id];
     const std::string v = "v" + std::to_string(id);
     if (is_leaf(n.op)) {
       o << "  T d" << id << "[" << leaf_n_shape(n) << "];\n";
-      o << "  const T " << v << " = " << eval_call(n, id, "x[" + std::to_string(g[n.in[0]].index) + "]")
-        << " * k.l" << id << ".invN;\n";
+      o << "  const T " << v << " = " << eval_call(n, id, "x[" + std::to_string(g[n.in[0]].index) + "]") << ";\n";
     } else if (n.op == RF_OP_PROD_PDF) {
       o << "  const T " << v << " = ";
       for (size_t j = 0; j < n.in.size(); ++j) o << (j ? " * " : "") << "v" << n.in[j];
@@ -253,70 +300,78 @@ std::string generate_source(const Lowered& L, int BS, int U) {
       o << ";\n";
     }
   }
-  o << "  const T p = v" << L.top << ";\n";
+  o << "  const T p = " << (top_add ? "" : "k.stop * ") << "v" << L.top << ";\n";
   o << "  *pout = p;\n";
-  o << "  if (!valid) return true;\n";
-  o << "  if (!(p > RM<T>::tiny()) || !RM<T>::finite(p)) return false;\n";
-  o << "  if (MODE == 0) return true;\n";
-  o << "  acc[0] -= (double)RM<T>::log(p);\n";
+  o << "  const bool ok = p > RM<T>::tiny() && p < (T)INFINITY;\n";
+  o << "  if (MODE == 0) return ok;\n";
+  o << "  acc[0] += ok ? RM<T>::log_acc(p) : (T)0;\n";
   o << "  if (MODE == 2) {\n";
-  for (int id = 0; id < N; ++id)
-    if (L.reach[id] && is_pdf(g[id].op) && id != L.top) o << "    T b" << id << " = (T)0;\n";
-  o << "    const T b" << L.top << " = RM<T>::rcp(p);\n";
-  // slot lookup
-  auto slot_sum = [&](int node, int j) {
-    for (const Slot& s : L.slots)
-      if (s.node == node && s.j == j) return s.sum;
-    return -1;
+  o << "    const T r = ok ? RM<T>::rcp(p) : (T)0;\n";
+  std::vector<char> declared(N, 0), wdecl(N, 0);
+  // beta_c: name of the variable holding it, declared on first use
+  std::function<std::string(int)> beta = [&](int id) -> std::string {
+    const int par = L.parent[id];
+    if (par < 0) return "r";
+    if (g[par].op == RF_OP_ADD_PDF) return beta(par);
+    const std::string b = "bt" + std::to_string(id);
+    if (!declared[id]) {
+      const std::string bp = beta(par);
+      o << "    const T " << b << " = " << bp;
+      for (int i : g[par].in)
+        if (i != id) o << " * v" << i;
+      o << ";\n";
+      declared[id] = 1;
+    }
+    return b;
+  };
+  auto wvar = [&](int c) -> std::string {
+    const std::string w = "w" + std::to_string(c);
+    if (!wdecl[c]) {
+      const std::string b = beta(c);
+      o << "    const T " << w << " = " << b << " * v" << c << ";\n";
+      wdecl[c] = 1;
+    }
+    return w;
   };
   for (int id = N - 1; id >= 0; --id) {
-    if (!L.reach[id]) continue;
-    const Node& n = g[id];
-    const std::string b = "b" + std::to_string(id);
-    if (n.op == RF_OP_ADD_PDF) {
-      const int nc = ((int)n.in.size() + 1) / 2;
-      for (int j = 0; j < nc; ++j) o << "    b" << n.in[j] << " += " << b << " * k.a" << id << "[" << j << "];\n";
-      for (int j = 0; j < nc - 1; ++j) {
-        const int s = slot_sum(id, j);
-        if (s >= 0) o << "    acc[" << s << "] += (double)(" << b << " * (v" << n.in[j] << " - v" << n.in[nc - 1] << "));\n";
-      }
-    } else if (n.op == RF_OP_PROD_PDF) {
-      for (size_t j = 0; j < n.in.size(); ++j) {
-        o << "    b" << n.in[j] << " += " << b;
-        for (size_t i = 0; i < n.in.size(); ++i)
-          if (i != j) o << " * v" << n.in[i];
-        o << ";\n";
-      }
-    } else if (is_leaf(n.op) && L.wsum[id] >= 0) {
-      o << "    {\n      const T w = " << b << " * v" << id << ";\n";
-      for (int j = 0; j < leaf_n_shape(n); ++j) {
-        const int s = slot_sum(id, j);
-        if (s >= 0) o << "      acc[" << s << "] += (double)(w * d" << id << "[" << j << "]);\n";
-      }
-      o << "      acc[" << L.wsum[id] << "] += (double)w;\n    }\n";
+    if (!L.reach[id] || !is_pdf(g[id].op)) continue;
+    if (L.ysum[id] >= 0) {
+      const std::string w = wvar(id);
+      o << "    acc[" << L.ysum[id] << "] += " << w << ";\n";
+    }
+    if (!is_leaf(g[id].op)) continue;
+    for (const Slot& sl : L.slots) {
+      if (sl.node != id || sl.sum < 0) continue;
+      const std::string f = dlin(g[id]) ? beta(id) : wvar(L.canon[id]);
+      o << "    acc[" << sl.sum << "] += " << f << " * d" << id << "[" << sl.j << "];\n";
     }
   }
-  o << "  }\n  return true;\n}\n\n";
+  o << "  }\n  return ok;\n}\n\n";
 
   // ---- epilogue ----
   o << "template <int MODE>\n";
   o << "RF_DEV void rf_epilogue(const double* S, const double* cst, const double* th, double* out, unsigned nbad) {\n";
-  o << "  out[0] = S[0];\n";
+  o << "  out[0] = -S[0];\n";
   o << "  out[" << L.n_params + 1 << "] = (double)nbad;\n";
   o << "  if (MODE != 2) return;\n";
   emit_paramlike(o, L, "  ");
   o << "  double g[" << (L.n_params > 0 ? L.n_params : 1) << "];\n";
   o << "  for (int k2 = 0; k2 < " << L.n_params << "; ++k2) g[k2] = 0.0;\n";
-  for (const Slot& s : L.slots) {
-    const Node& n = g[s.node];
+  for (const Slot& sl : L.slots) {
+    const Node& n = g[sl.node];
     std::string gs;
-    if (is_leaf(n.op))
-      gs = "-S[" + std::to_string(s.sum) + "] + S[" + std::to_string(L.wsum[s.node]) + "] * cst[" +
-           std::to_string(L.cst_off[s.node] + 1 + s.j) + "]";
-    else
-      gs = "-S[" + std::to_string(s.sum) + "]";
+    if (is_leaf(n.op)) {
+      const int off = L.cst_off[sl.node];
+      gs = "-" + pathc(sl.node, "cst") + " * (" + dscale(n, off, sl.j) + " * S[" + std::to_string(sl.sum) + "] - S[" +
+           std::to_string(L.ysum[L.canon[sl.node]]) + "] * cst[" + std::to_string(off + 1 + sl.j) + "])";
+    } else {
+      const int nc = ((int)n.in.size() + 1) / 2;
+      const int cj = n.in[sl.j], cl = n.in[nc - 1];
+      gs = "-" + pathc(sl.node, "cst") + " * (" + scale(cj, "cst") + " * S[" + std::to_string(L.ysum[cj]) + "] - " +
+           scale(cl, "cst") + " * S[" + std::to_string(L.ysum[cl]) + "])";
+    }
     o << "  {\n    const double gs = " << gs << ";\n";
-    emit_jac(o, L, s.pl, "gs");
+    emit_jac(o, L, sl.pl, "gs");
     o << "  }\n";
   }
   o << "  for (int k2 = 0; k2 < " << L.n_params << "; ++k2) out[1 + k2] = g[k2];\n";

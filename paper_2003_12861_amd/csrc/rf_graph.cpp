@@ -42,7 +42,7 @@ static int leaf_ncst(const Node& n) {
     case RF_OP_EXP: return 5;
     case RF_OP_DECAY_GAUSS: return 12;
     case RF_OP_ARGUS: return 6;
-    case RF_OP_BW: return 5;
+    case RF_OP_BW: return 6;
     case RF_OP_NUMCONV_BW_CB: return 8;
     case RF_OP_MLP: return 8;
   }
@@ -206,26 +206,55 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
   if (L.has_mlp && precision != RF_FP32_COMP)
     return fail(RF_E_INVALID, "the MLP leaf runs in FP32 (BF16 weights): compile with RF_FP32_COMP");
 
-  // event sums: 0 = NLL, then one per theta-dependent input slot, then W per leaf
+  // PDF tree: a PDF node may feed one sum or product only
+  L.parent.assign(N, -1);
+  std::vector<int> users(N, 0);
+  for (int id = 0; id < N; ++id) {
+    if (!L.reach[id] || (g[id].op != RF_OP_ADD_PDF && g[id].op != RF_OP_PROD_PDF)) continue;
+    const Node& n = g[id];
+    const int np = n.op == RF_OP_ADD_PDF ? ((int)n.in.size() + 1) / 2 : (int)n.in.size();
+    for (int j = 0; j < np; ++j) {
+      users[n.in[j]]++;
+      L.parent[n.in[j]] = id;
+    }
+  }
+  for (int id = 0; id < N; ++id)
+    if (L.reach[id] && users[id] > 1)
+      return fail(RF_E_INVALID, "PDF node '" + g[id].name + "' feeds more than one sum or product: give each use its own node");
+  // canonical nodes (inputs have smaller ids than their users)
+  L.canon.assign(N, -1);
+  for (int id = N - 1; id >= 0; --id) {
+    if (!L.reach[id] || !is_pdf(g[id].op)) continue;
+    const int par = L.parent[id];
+    L.canon[id] = (par < 0 || g[par].op == RF_OP_ADD_PDF) ? id : L.canon[par];
+  }
+
+  // event sums: 0 = sum log p, then D per theta-dependent leaf input, then Y
+  std::vector<char> needy(N, 0);
   int s = 1;
-  L.wsum.assign(N, -1);
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
     const Node& n = g[id];
     if (is_leaf(n.op)) {
-      bool any = false;
       for (int j = 1; j < (int)n.in.size(); ++j)
-        if (dep[n.in[j]]) { L.slots.push_back({id, j - 1, n.in[j], s++}); any = true; }
-      if (any) L.wsum[id] = -2;  // assigned below
+        if (dep[n.in[j]]) {
+          L.slots.push_back({id, j - 1, n.in[j], s++});
+          needy[L.canon[id]] = 1;
+        }
     }
     if (n.op == RF_OP_ADD_PDF) {
       const int nc = ((int)n.in.size() + 1) / 2;
       for (int j = 0; j < nc - 1; ++j)
-        if (dep[n.in[nc + j]]) L.slots.push_back({id, j, n.in[nc + j], s++});
+        if (dep[n.in[nc + j]]) {
+          L.slots.push_back({id, j, n.in[nc + j], -1});
+          needy[n.in[j]] = 1;
+          needy[n.in[nc - 1]] = 1;
+        }
     }
   }
+  L.ysum.assign(N, -1);
   for (int id = 0; id < N; ++id)
-    if (L.wsum[id] == -2) L.wsum[id] = s++;
+    if (needy[id]) L.ysum[id] = s++;
   L.n_sums = s;
   return RF_OK;
 }

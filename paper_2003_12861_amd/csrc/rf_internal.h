@@ -38,7 +38,7 @@ struct Slot {          // a shape/fraction input whose value depends on theta
   int node;            // leaf or ADD node
   int j;               // input position among its shape inputs (ADD: fraction j)
   int pl;              // parameter-like node feeding it
-  int sum;             // index of its event sum D_slot
+  int sum;             // leaf: index of its event sum D; ADD: -1 (uses Y sums)
 };
 
 struct Lowered {
@@ -50,7 +50,13 @@ struct Lowered {
   std::vector<char> reach;
   std::vector<int> cst_off;        // per node: offset of its FP64 constant block
   int n_cst = 0;
-  std::vector<int> wsum;           // per leaf: index of its W sum (or -1)
+  // PDF tree (every PDF node feeds one sum or product).  For each PDF node
+  // c, beta_c is its per-event adjoint without parameter-only factors;
+  // Y_c = sum_i beta_c u_c is accumulated for "canonical" nodes (the top and
+  // the components of sums); a factor of a product shares the product's.
+  std::vector<int> parent;         // per PDF node: its user (-1 for the top)
+  std::vector<int> canon;          // per PDF node: node whose Y sum it uses
+  std::vector<int> ysum;           // per canonical node: index of Y_c (or -1)
   std::vector<Slot> slots;
   int n_sums = 0;                  // including sum 0 (= NLL)
   bool has_numconv = false, has_mlp = false;
@@ -60,7 +66,7 @@ struct Lowered {
 };
 
 int lower(const std::vector<Node>& g, int top, int precision, Lowered& out);
-std::string generate_source(const Lowered& L, int block_size, int unroll);
+std::string generate_source(const Lowered& L, int block_size, int ept);
 
 // code-object cache + compiler driver
 struct Module {
@@ -96,17 +102,20 @@ struct rf_program {
   std::string co_path;
   rf::Module m;
   bool loaded = false;
-  int block = 256, unroll = 4;  // unroll = prefetch distance (events in flight per thread)
+  int block = 256;  // threads per workgroup (compile-time constant of the kernel)
+  int ept = 4;      // events per lane and step of the event loop (compile-time)
+  uint64_t seq = 0; // completion sequence number of synchronous calls
+  int64_t n_sync = 0, n_slow = 0;  // synchronous calls; those whose wait fell back to a stream sync
   int blocks_override = 0;
   // binding
   const void* cols[RF_MAX_COLS] = {};
   int64_t n = -1;
   int nblk = 0, nblk_max = 0;
   double* d_part = nullptr;
-  unsigned* d_part_bad = nullptr;
   unsigned* d_ticket = nullptr;
   double* d_out = nullptr;
-  double* h_out = nullptr;   // pinned
+  double* h_out = nullptr;   // pinned, mapped: the kernel writes the result here too
+  double* d_hout = nullptr;  // device address of h_out
   double* d_aux = nullptr;   // auxiliary FP64 block (surrogate normalisation, ...)
   const void* d_weights = nullptr;
   int device = -1;
