@@ -14,11 +14,16 @@ path is timed beside it, and both results are checked against the oracle
 Prints ONE JSON line.  Extra fields:
   roofline      the fused kernel against the VALU issue rate: algorithmic
                 lane-slots per event times events, over the kernel's average
-                launch duration (HIP events on the launch stream, around each
-                launch of the timed region);
+                launch duration (HIP events on the launch stream around K
+                back-to-back launches -- the duration a profiler reports per
+                launch);
   cpu_baseline  the oracle's throughput on the host, on a bounded sample.
+The Python garbage collector is paused inside the timed regions (a full
+collection of this process takes tens of milliseconds).
 """
 import argparse
+import gc
+import hashlib
 import json
 import os
 import platform
@@ -49,6 +54,23 @@ SLOTS = {
 BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "decay_argus_5e7": {"fp32": 8, "fp64": 16}}
 
 
+def measured_traffic(workload, kernel, source):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on this exact kernel (same generated source); else None.  The summary
+    holds lines 'traffic kernel=K workload=W source_sha1=H bytes_per_launch=B'."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha1(source.encode()).hexdigest()
+    for line in open(path):
+        if not line.startswith("traffic "):
+            continue
+        kv = dict(f.split("=", 1) for f in line.split()[1:] if "=" in f)
+        if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha1") == sha:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
 def make(workload):
     from paper_2003_12861_amd import synth, workloads
     w = WORKLOADS[workload]
@@ -67,29 +89,55 @@ def make(workload):
 
 def timed_steps(prog, thetas, steps, torch, stream):
     """K synchronous NLL+gradient evaluations; returns (seconds per step,
-    mean kernel seconds from an event pair around each launch)."""
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        evs[i][0].record(stream)
-        prog.nll_grad(thetas[i % len(thetas)], stream=stream)
-        evs[i][1].record(stream)
-    torch.cuda.synchronize()
-    step_s = (time.perf_counter() - t0) / steps
-    kern_s = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
-    return step_s, kern_s
+    median seconds of one step)."""
+    per = np.zeros(steps)
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ti = time.perf_counter()
+            prog.nll_grad(thetas[i % len(thetas)], stream=stream)
+            per[i] = time.perf_counter() - ti
+        torch.cuda.synchronize()
+        step_s = (time.perf_counter() - t0) / steps
+    finally:
+        gc.enable()
+    return step_s, float(np.median(per))
+
+
+def isolated_kernel(prog, thetas, reps, torch, stream):
+    """Median duration of single launches (an event pair around each launch,
+    the GPU idle before it): includes the dispatch of a launch from idle."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    gc.collect()
+    gc.disable()
+    try:
+        for i in range(reps):
+            evs[i][0].record(stream)
+            prog.nll_grad_async(thetas[i % len(thetas)], stream=stream)
+            evs[i][1].record(stream)
+            torch.cuda.synchronize()
+    finally:
+        gc.enable()
+    return float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e-3
 
 
 def pipelined_kernel(prog, thetas, reps, torch, stream):
     """Average duration of back-to-back launches (no host round trip between
     them): the kernel's own time as a profiler reports it."""
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for i in range(reps):
-        prog.nll_grad_async(thetas[i % len(thetas)], stream=stream)
-    b.record(stream)
-    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    try:
+        a.record(stream)
+        for i in range(reps):
+            prog.nll_grad_async(thetas[i % len(thetas)], stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+    finally:
+        gc.enable()
     return a.elapsed_time(b) * 1e-3 / reps
 
 
@@ -134,9 +182,10 @@ def main():
     for key, p in progs.items():
         for i in range(args.warmup):
             p.nll_grad(thetas[i % len(thetas)], stream=stream)
-        step_s, kern_s = timed_steps(p, thetas, args.steps, torch, stream)
-        pipe_s = pipelined_kernel(p, thetas, max(20, min(args.steps, 200)), torch, stream)
-        res[key] = dict(step_s=step_s, kernel_s=kern_s, pipelined_s=pipe_s)
+        step_s, med_s = timed_steps(p, thetas, args.steps, torch, stream)
+        kern_s = pipelined_kernel(p, thetas, max(20, min(args.steps, 200)), torch, stream)
+        iso_s = isolated_kernel(p, thetas, 20, torch, stream)
+        res[key] = dict(step_s=step_s, median_step_s=med_s, kernel_s=kern_s, isolated_s=iso_s)
 
     # validity of both paths against the oracle at the truth point
     cpu = None
@@ -183,13 +232,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "events": n, "precision": "fp32+adjoint, fp64 reductions",
                    "step": "one synchronous NLL+gradient evaluation (result in host memory)"},
-        "fp32": {"kernel_ms": k32 * 1e3, "pipelined_kernel_ms": res["fp32"]["pipelined_s"] * 1e3,
+        "fp32": {"kernel_ms": k32 * 1e3, "isolated_kernel_ms": res["fp32"]["isolated_s"] * 1e3,
+                 "median_step_ms": res["fp32"]["median_step_s"] * 1e3,
                  "kernel_events_per_s": n / k32,
                  "nll_rel_err": res["fp32"].get("nll_rel_err"),
                  "grad_scaled_err": res["fp32"].get("grad_scaled_err"),
                  "valid": res["fp32"].get("valid")},
-        "roofline": {"bound": "alu", "kernel": "rf_k_grad (fp32)", "achieved": achieved, "peak": peak,
-                     "unit": "Tslot/s", "frac": achieved / peak, "traffic": None,
+        "roofline": {"bound": "alu", "kernel": "rf_k_grad_f32", "achieved": achieved, "peak": peak,
+                     "unit": "Tslot/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(args.workload, "rf_k_grad_f32", progs["fp32"].source),
                      "slots_per_event": slots, "events_per_launch": n,
                      "bytes_per_event": BYTES_PER_EVENT[args.workload]["fp32"],
                      "hbm_GBps": n * BYTES_PER_EVENT[args.workload]["fp32"] / k32 / 1e9},
@@ -198,8 +249,9 @@ def main():
     if "fp64" in res:
         line["fp64_plain"] = {"value": n / res["fp64"]["step_s"], "unit": "events/s",
                               "ms_per_step": res["fp64"]["step_s"] * 1e3,
+                              "median_step_ms": res["fp64"]["median_step_s"] * 1e3,
                               "kernel_ms": res["fp64"]["kernel_s"] * 1e3,
-                              "pipelined_kernel_ms": res["fp64"]["pipelined_s"] * 1e3,
+                              "isolated_kernel_ms": res["fp64"]["isolated_s"] * 1e3,
                               "kernel_events_per_s": n / res["fp64"]["kernel_s"],
                               "roofline_frac": n * SLOTS[args.workload]["fp64"] / res["fp64"]["kernel_s"] / VALU_SLOTS_PER_S,
                               "nll_rel_err": res["fp64"].get("nll_rel_err"),

@@ -206,6 +206,11 @@ class Program:
         self._cols = []
         self._weights = None
         self.n_events = None
+        # result buffers reused by every call (no allocation per evaluation)
+        self._v, self._nb = ctypes.c_double(), ctypes.c_int64()
+        self._vref, self._nbref = ctypes.byref(self._v), ctypes.byref(self._nb)
+        self._g = np.zeros(max(1, self.n_params))
+        self._gptr = _dptr(self._g)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -251,7 +256,10 @@ class Program:
         check(rf_set_launch(self.h, blocks, threads))
 
     def _theta(self, theta):
-        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if type(theta) is np.ndarray and theta.dtype == np.float64 and theta.ndim == 1 and theta.flags.c_contiguous:
+            th = theta
+        else:
+            th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
         if th.size != self.n_params:
             raise RfError(-1, "theta has %d values, the program %d parameters" % (th.size, self.n_params))
         return th
@@ -265,21 +273,18 @@ class Program:
 
     def nll(self, theta, stream=None):
         th = self._theta(theta)
-        v, nb = ctypes.c_double(), ctypes.c_int64()
-        rc = rf_nll(self.h, _dptr(th), ctypes.byref(v), ctypes.byref(nb), _stream(stream))
+        rc = rf_nll(self.h, _dptr(th), self._vref, self._nbref, _stream(stream))
         if rc != -3:
             check(rc)
-        return v.value, nb.value
+        return self._v.value, self._nb.value
 
     def nll_grad(self, theta, stream=None):
         """Returns (nll, grad, n_bad); nll = inf and grad = nan when n_bad > 0."""
         th = self._theta(theta)
-        v, nb = ctypes.c_double(), ctypes.c_int64()
-        g = np.zeros(max(1, self.n_params))
-        rc = rf_nll_grad(self.h, _dptr(th), ctypes.byref(v), _dptr(g), ctypes.byref(nb), _stream(stream))
+        rc = rf_nll_grad(self.h, _dptr(th), self._vref, self._gptr, self._nbref, _stream(stream))
         if rc != -3:
             check(rc)
-        return v.value, g[: self.n_params].copy(), nb.value
+        return self._v.value, self._g[: self.n_params].copy(), self._nb.value
 
     def nll_grad_async(self, theta, stream=None):
         th = self._theta(theta)

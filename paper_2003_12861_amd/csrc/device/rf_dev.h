@@ -508,28 +508,51 @@ RF_DEV void dd_add(double& hi, double& lo, double bh, double bl) {
   lo = e - (hi - s);
 }
 
+// Wavefront sums with DPP lane moves (VALU, no LDS round trip).  Within each
+// row of 16 lanes: partner xor 1, xor 2 (quad permutes), then the mirrored
+// lane of the half row and of the row; IEEE addition is commutative, so both
+// partners of every step hold bitwise equal values and each lane ends with
+// its row's sum.  The four row sums (lanes 0, 16, 32, 48) are read into
+// scalar registers and added in a fixed order.  Needs all 64 lanes active.
+template <int CTRL> RF_DEV int dpp_i(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false); }
+template <int CTRL> RF_DEV double dpp_d(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)u);
+  const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+RF_DEV double lane_d(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+RF_DEV double row_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
 RF_DEV double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = row_sum(v);
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
-RF_DEV unsigned wave_sum_u(unsigned v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+RF_DEV unsigned wave_sum_u(unsigned x) {
+  int v = (int)x;
+  v += dpp_i<0xB1>(v);
+  v += dpp_i<0x4E>(v);
+  v += dpp_i<0x141>(v);
+  v += dpp_i<0x140>(v);
+  return (unsigned)(__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+                    __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
+// double-double wavefront sum: plain FP64 wavefront sums of the high and of
+// the low parts (the per-lane values are already compensated sums), then
+// renormalised; compensation happens where the wavefronts are combined
 RF_DEV void wave_dd_sum(double& hi, double& lo) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const double h2 = __shfl_xor(hi, o, 64), l2 = __shfl_xor(lo, o, 64);
-    // combine in a fixed (lane-order independent) way: smaller lane first
-    const bool first = ((int)(threadIdx.x & 63) & o) == 0;
-    double ah = first ? hi : h2, al = first ? lo : l2;
-    double bh = first ? h2 : hi, bl = first ? l2 : lo;
-    dd_add(ah, al, bh, bl);
-    hi = ah;
-    lo = al;
-  }
+  const double h = wave_sum(hi), l = wave_sum(lo);
+  two_sum(h, l, hi, lo);
 }
 
 // ================================= Breit-Wigner (x) Crystal Ball, K-point ==

@@ -10,8 +10,9 @@
 struct RfArgs {
   const void* col[RF_MAX_COLS];  // observable columns (float or double)
   int64_t n;                     // number of events
-  double* part;                  // block partials: [nsum + 1][2 (hi, lo)][nblk_max] (last: bad-event count)
-  unsigned* ticket;              // last-block ticket (0 between launches)
+  double* part;                  // block partials: [nsum + 1][nblk_max] (last: bad-event count)
+  unsigned* ticket;              // last-block tickets (0 between launches): [0] global,
+                                 // [64 (1 + g)] group g
   double* out;                   // result: [nll, grad[P], n_bad, sums...]
   void* values;                  // per-event output of the values kernel
   const double* aux;             // auxiliary FP64 inputs (e.g. surrogate normalisation)
@@ -20,6 +21,6 @@ struct RfArgs {
                                  // followed by a 64-bit completion word set to seq
   uint64_t seq;
   int32_t nblk_max;              // stride of part (>= gridDim.x)
-  int32_t vec;                   // 1: columns (and values) are 16-byte aligned
+  int32_t pad_;
   double theta[RF_MAX_PARAMS];   // parameter point
 };

@@ -44,12 +44,25 @@ int choose_ept(const Lowered& L) {
   return ept;
 }
 
+// load ring depth: three groups in flight when a group is one 16-byte load;
+// two for several columns (more registers per group); none beyond the
+// current event for the convolution leaf
+int choose_pfd(const Lowered& L, int ept) {
+  int d = L.has_numconv ? 1 : (L.n_cols <= 1 ? 3 : 2);
+  (void)ept;
+  if (const char* e = getenv("RFGPU_PFD")) {  // tuning override
+    const int v = atoi(e);
+    if (v >= 1 && v <= 4) d = v;
+  }
+  return d;
+}
+
 int choose_blocks(const rf_program* p) {
   if (p->blocks_override > 0) return p->blocks_override;
-  // about 16 steps per lane, at most 4 workgroups per CU: enough waves to
+  // about 8 steps per lane, at most 4 workgroups per CU: enough waves to
   // hide the load latency while keeping the number of partials (and the last
   // workgroup's reduction) small
-  const int64_t per = (int64_t)p->block * p->ept * 16;
+  const int64_t per = (int64_t)p->block * p->ept * 8;
   int64_t b = (p->n + per - 1) / per;
   const int64_t cap = (int64_t)cu_count(p->device) * 4;
   if (b > cap) b = cap;
@@ -68,10 +81,6 @@ void fill_args(const rf_program* p, const double* theta, RfArgs& a) {
   a.weights = p->d_weights;
   a.nblk_max = p->nblk_max;
   a.hout = nullptr;
-  // 16-byte vector loads need 16-byte aligned columns
-  a.vec = 1;
-  for (int c = 0; c < p->L.n_cols; ++c)
-    if ((uintptr_t)p->cols[c] % 16) a.vec = 0;
   for (int k = 0; k < p->L.n_params; ++k) a.theta[k] = theta[k];
 }
 
@@ -158,13 +167,18 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
     if (v >= 64 && v <= 1024 && v % 64 == 0) p->block = v;
   }
   p->ept = choose_ept(p->L);
-  p->source = generate_source(p->L, p->block, p->ept);
+  p->pfd = choose_pfd(p->L, p->ept);
+  if (const char* e = getenv("RFGPU_TG")) {  // tuning override
+    const int v = atoi(e);
+    if (v >= 1 && v <= 32) p->tg = v;
+  }
+  p->source = generate_source(p->L, p->block, p->ept, p->pfd, p->tg);
   rc = build_code_object(p->source, p->co_path);
   if (rc) { delete p; return rc; }
   if (!(flags & RF_COMPILE_NO_LOAD)) {
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
-    rc = load_module(p->co_path, p->m);
+    rc = load_module(p->co_path, p->L.precision == RF_FP32_COMP, p->m);
     if (rc) { delete p; return rc; }
     p->loaded = true;
   }
@@ -230,9 +244,9 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
   if (!p->d_out || nmax > p->nblk_max) {
     free_workspace(p);
     hipError_t e;
-    const size_t np = (size_t)(p->L.n_sums + 1) * 2 * nmax;  // sums + bad-event count
+    const size_t np = (size_t)(p->L.n_sums + 1) * nmax;  // sums + bad-event count
     if ((e = hipMalloc(&p->d_part, sizeof(double) * np)) != hipSuccess) return hip_fail(e, "hipMalloc partials");
-    if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned) * 64 * 33)) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMalloc(&p->d_out, sizeof(double) * out_len(p))) != hipSuccess) return hip_fail(e, "hipMalloc");
     // result copy + completion word
     if ((e = hipHostMalloc(&p->h_out, sizeof(double) * (out_len(p) + 1), hipHostMallocMapped | hipHostMallocCoherent)) !=
@@ -241,7 +255,7 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
     memset(p->h_out, 0, sizeof(double) * (out_len(p) + 1));
     if ((e = hipHostGetDevicePointer((void**)&p->d_hout, p->h_out, 0)) != hipSuccess)
       return hip_fail(e, "hipHostGetDevicePointer");
-    if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMemset");
+    if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned) * 64 * 33)) != hipSuccess) return hip_fail(e, "hipMemset");
     if (!p->L.aux.empty()) {
       if ((e = hipMalloc(&p->d_aux, sizeof(double) * p->L.aux.size())) != hipSuccess) return hip_fail(e, "hipMalloc aux");
       if ((e = hipMemcpy(p->d_aux, p->L.aux.data(), sizeof(double) * p->L.aux.size(), hipMemcpyHostToDevice)) != hipSuccess)
@@ -272,7 +286,6 @@ int rf_eval_values(rf_program* p, const double* theta, void* dev_out, void* stre
   RfArgs a;
   fill_args(p, theta, a);
   a.values = dev_out;
-  if ((uintptr_t)dev_out % 16) a.vec = 0;
   return launch(p, p->m.k_values, a, stream);
 }
 

@@ -141,7 +141,7 @@ static void emit_jac(std::ostringstream& o, const Lowered& L, int id, const std:
   }
 }
 
-std::string generate_source(const Lowered& L, int BS, int ept) {
+std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg) {
   const auto& g = L.nodes;
   const int N = (int)g.size();
   const bool f32 = L.precision == RF_FP32_COMP;
@@ -150,12 +150,15 @@ std::string generate_source(const Lowered& L, int BS, int ept) {
   o << RF_DEV_SRC_KABI << "\n" << RF_DEV_SRC_OPS << "\n";
   if (L.has_mlp) o << RF_DEV_SRC_MLP << "\n#define RF_NSPLIT 3\n";
   o << "#define RF_T " << (f32 ? "float" : "double") << "\n";
+  o << "#define RF_PREC " << (f32 ? "f32" : "f64") << "\n";
   o << "#define RF_NCOL " << L.n_cols << "\n";
   o << "#define RF_NCST " << L.n_cst << "\n";
   o << "#define RF_NSUM " << L.n_sums << "\n";
   o << "#define RF_P " << L.n_params << "\n";
   o << "#define RF_BS " << BS << "\n";
   o << "#define RF_EPT " << ept << "\n";
+  o << "#define RF_PFD " << pfd << "\n";
+  o << "#define RF_TG " << tg << "\n";
   // programs with an MLP leaf run the event loop in whole wavefronts (the MLP
   // is wave-cooperative) and evaluate in FP32 only (no FP64 re-evaluation)
   o << "#define RF_WAVE_UNIFORM " << (L.has_mlp ? 1 : 0) << "\n";

@@ -66,7 +66,7 @@ struct Lowered {
 };
 
 int lower(const std::vector<Node>& g, int top, int precision, Lowered& out);
-std::string generate_source(const Lowered& L, int block_size, int ept);
+std::string generate_source(const Lowered& L, int block_size, int ept, int pfd, int tg);
 
 // code-object cache + compiler driver
 struct Module {
@@ -74,7 +74,7 @@ struct Module {
   hipFunction_t k_values = nullptr, k_nll = nullptr, k_grad = nullptr;
 };
 int build_code_object(const std::string& src, std::string& path_out);
-int load_module(const std::string& path, Module& m);
+int load_module(const std::string& path, bool f32, Module& m);  // f32: FP32 form entry names
 uint64_t fnv1a(const std::string& s);
 std::string cache_dir();
 
@@ -104,6 +104,8 @@ struct rf_program {
   bool loaded = false;
   int block = 256;  // threads per workgroup (compile-time constant of the kernel)
   int ept = 4;      // events per lane and step of the event loop (compile-time)
+  int pfd = 3;      // groups in flight per lane (load ring depth, compile-time)
+  int tg = 8;       // ticket groups of the end-of-kernel hand-off (compile-time)
   uint64_t seq = 0; // completion sequence number of synchronous calls
   int64_t n_sync = 0, n_slow = 0;  // synchronous calls; those whose wait fell back to a stream sync
   int blocks_override = 0;

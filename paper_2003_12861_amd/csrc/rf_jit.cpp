@@ -118,15 +118,17 @@ int build_code_object(const std::string& src, std::string& path) {
   return RF_OK;
 }
 
-int load_module(const std::string& path, Module& m) {
+int load_module(const std::string& path, bool f32, Module& m) {
   std::ifstream f(path, std::ios::binary);
   std::vector<char> bytes((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
   if (bytes.empty()) return fail(RF_E_DEVICE, "empty code object " + path);
   hipError_t e = hipModuleLoadData(&m.mod, bytes.data());
   if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData");
-  if ((e = hipModuleGetFunction(&m.k_values, m.mod, "rf_k_values")) != hipSuccess) return hip_fail(e, "rf_k_values");
-  if ((e = hipModuleGetFunction(&m.k_nll, m.mod, "rf_k_nll")) != hipSuccess) return hip_fail(e, "rf_k_nll");
-  if ((e = hipModuleGetFunction(&m.k_grad, m.mod, "rf_k_grad")) != hipSuccess) return hip_fail(e, "rf_k_grad");
+  const std::string sfx = f32 ? "_f32" : "_f64";
+  const std::string kv = "rf_k_values" + sfx, kn = "rf_k_nll" + sfx, kg = "rf_k_grad" + sfx;
+  if ((e = hipModuleGetFunction(&m.k_values, m.mod, kv.c_str())) != hipSuccess) return hip_fail(e, kv.c_str());
+  if ((e = hipModuleGetFunction(&m.k_nll, m.mod, kn.c_str())) != hipSuccess) return hip_fail(e, kn.c_str());
+  if ((e = hipModuleGetFunction(&m.k_grad, m.mod, kg.c_str())) != hipSuccess) return hip_fail(e, kg.c_str());
   return RF_OK;
 }
 
