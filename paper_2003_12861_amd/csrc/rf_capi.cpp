@@ -59,12 +59,13 @@ int choose_pfd(const Lowered& L, int ept) {
 
 int choose_blocks(const rf_program* p) {
   if (p->blocks_override > 0) return p->blocks_override;
-  // about 8 steps per lane, at most 4 workgroups per CU: enough waves to
-  // hide the load latency while keeping the number of partials (and the last
-  // workgroup's reduction) small
+  // about 8 steps per lane, at most as many workgroups as the CUs hold at
+  // once (and at most 4 per CU): enough waves to hide the load latency, no
+  // second round of workgroups behind the first, and few partials for the
+  // last workgroup to add
   const int64_t per = (int64_t)p->block * p->ept * 8;
   int64_t b = (p->n + per - 1) / per;
-  const int64_t cap = (int64_t)cu_count(p->device) * 4;
+  const int64_t cap = (int64_t)cu_count(p->device) * (p->resident < 4 ? p->resident : 4);
   if (b > cap) b = cap;
   if (b < 1) b = 1;
   return (int)b;
@@ -180,6 +181,9 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
     if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
     rc = load_module(p->co_path, p->L.precision == RF_FP32_COMP, p->m);
     if (rc) { delete p; return rc; }
+    int nb = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, p->m.k_grad, p->block, 0) == hipSuccess && nb > 0)
+      p->resident = nb;
     p->loaded = true;
   }
   *out = p;

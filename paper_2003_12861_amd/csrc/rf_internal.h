@@ -106,6 +106,7 @@ struct rf_program {
   int ept = 4;      // events per lane and step of the event loop (compile-time)
   int pfd = 3;      // groups in flight per lane (load ring depth, compile-time)
   int tg = 8;       // ticket groups of the end-of-kernel hand-off (compile-time)
+  int resident = 4; // workgroups of the gradient kernel one CU holds at once (occupancy query)
   uint64_t seq = 0; // completion sequence number of synchronous calls
   int64_t n_sync = 0, n_slow = 0;  // synchronous calls; those whose wait fell back to a stream sync
   int blocks_override = 0;
