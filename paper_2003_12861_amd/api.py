@@ -358,13 +358,17 @@ class Binned:
                 pass
 
     def nll_grad(self, theta, stream=None):
-        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if type(theta) is np.ndarray and theta.dtype == np.float64 and theta.ndim == 1 and theta.flags.c_contiguous:
+            th = theta
+        else:
+            th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
         if th.size != self.n_params:
             raise RfError(-1, "theta needs %d values" % self.n_params)
-        v = ctypes.c_double()
-        g = np.zeros(self.n_params)
-        check(rf_binned_nll_grad(self.h, _dptr(th), ctypes.byref(v), _dptr(g), _stream(stream)))
-        return v.value, g
+        if not hasattr(self, "_g"):  # result buffers reused by every call
+            self._v, self._g = ctypes.c_double(), np.zeros(self.n_params)
+            self._vref, self._gptr = ctypes.byref(self._v), _dptr(self._g)
+        check(rf_binned_nll_grad(self.h, _dptr(th), self._vref, self._gptr, _stream(stream)))
+        return self._v.value, self._g.copy()
 
     def nll_grad_async(self, theta, stream=None):
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))

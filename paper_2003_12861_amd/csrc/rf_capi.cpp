@@ -136,22 +136,28 @@ int run_sync(rf_program* p, hipFunction_t f, const double* theta, void* stream) 
   volatile uint64_t* done = (volatile uint64_t*)(p->h_out + out_len(p));
   int rc = launch(p, f, a, stream);
   if (rc) return rc;
-  const auto t0 = std::chrono::steady_clock::now();
   p->n_sync++;
-  while (*done != a.seq) {
+  return wait_result(done, a.seq, stream, &p->n_slow);
+}
+
+}  // namespace
+
+namespace rf {
+int wait_result(volatile uint64_t* done, uint64_t seq, void* stream, int64_t* slow) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (*done != seq) {
     if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
-      p->n_slow++;
+      if (slow) ++*slow;
       hipError_t e = hipStreamSynchronize((hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-      if (*done != a.seq) return fail(RF_E_DEVICE, "kernel completed without writing its result");
+      if (*done != seq) return fail(RF_E_DEVICE, "kernel completed without writing its result");
       break;
     }
   }
   std::atomic_thread_fence(std::memory_order_acquire);
   return RF_OK;
 }
-
-}  // namespace
+}  // namespace rf
 
 extern "C" {
 

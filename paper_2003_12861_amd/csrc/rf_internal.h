@@ -78,6 +78,10 @@ int load_module(const std::string& path, bool f32, Module& m);  // f32: FP32 for
 uint64_t fnv1a(const std::string& s);
 std::string cache_dir();
 
+// wait for a result whose last writer sets *done = seq (mapped host memory):
+// poll, then fall back to a stream synchronisation after 20 ms
+int wait_result(volatile uint64_t* done, uint64_t seq, void* stream, int64_t* slow);
+
 // host-side domain checks of a parameter point
 int check_theta(const Lowered& L, const double* theta);
 void eval_paramlike(const Lowered& L, const double* theta, std::vector<double>& pv);
