@@ -268,10 +268,74 @@ int rfo_mlp_backward(const double* w, const double* in, int64_t n,
   return 0;
 }
 
+/* ---- analytic base of the surrogate ----------------------------------------
+   The surrogate's log density is s = MLP(u) + log b, with the analytic base
+   b(d = x - M; Gamma, sigma, alpha, n) a pseudo-Voigt (Thompson, Cox &
+   Hastings, J. Appl. Cryst. 20 (1987) 79: a Lorentzian and a Gaussian of
+   common full width f, mixed with weight eta; f_G = 2 sigma sqrt(2 ln 2),
+   f_L = Gamma) whose Gaussian part carries the Crystal Ball tail below
+   z = -alpha, z in units of that component's width f / (2 sqrt(2 ln 2)).
+   Evaluated here with forward-mode dual numbers (value and the derivatives
+   with respect to (d, Gamma, sigma, alpha, n)), straight from the
+   definition. */
+static const double SQRT2PI_ = 2.50662827463100050242;
+typedef struct { double v, g[5]; } dual;
+static dual dl_c(double v) { dual r = {v, {0, 0, 0, 0, 0}}; return r; }
+static dual dl_var(double v, int i) { dual r = dl_c(v); r.g[i] = 1.0; return r; }
+static dual dl_add(dual a, dual b) { for (int i = 0; i < 5; ++i) a.g[i] += b.g[i]; a.v += b.v; return a; }
+static dual dl_sub(dual a, dual b) { for (int i = 0; i < 5; ++i) a.g[i] -= b.g[i]; a.v -= b.v; return a; }
+static dual dl_mul(dual a, dual b) {
+  dual r; r.v = a.v * b.v;
+  for (int i = 0; i < 5; ++i) r.g[i] = a.g[i] * b.v + a.v * b.g[i];
+  return r;
+}
+static dual dl_div(dual a, dual b) {
+  dual r; r.v = a.v / b.v;
+  for (int i = 0; i < 5; ++i) r.g[i] = (a.g[i] * b.v - a.v * b.g[i]) / (b.v * b.v);
+  return r;
+}
+static dual dl_scale(dual a, double c) { a.v *= c; for (int i = 0; i < 5; ++i) a.g[i] *= c; return a; }
+static dual dl_exp(dual a) { dual r; r.v = exp(a.v); for (int i = 0; i < 5; ++i) r.g[i] = r.v * a.g[i]; return r; }
+static dual dl_log(dual a) { dual r; r.v = log(a.v); for (int i = 0; i < 5; ++i) r.g[i] = a.g[i] / a.v; return r; }
+static dual dl_powi(dual a, int k) { dual r = dl_c(1.0); for (int i = 0; i < k; ++i) r = dl_mul(r, a); return r; }
+
+/* log b and its derivatives with respect to (d, Gamma, sigma, alpha, n) */
+static dual mlp_base_log(double dx, double G, double sg, double al, double n) {
+  const double c0 = 2.0 * sqrt(2.0 * log(2.0));
+  const double PI = 3.14159265358979323846;
+  dual d = dl_var(dx, 0), fl = dl_var(G, 1), s = dl_var(sg, 2), a = dl_var(al, 3), nn = dl_var(n, 4);
+  dual fg = dl_scale(s, c0);
+  dual P = dl_powi(fg, 5);
+  P = dl_add(P, dl_scale(dl_mul(dl_powi(fg, 4), fl), 2.69269));
+  P = dl_add(P, dl_scale(dl_mul(dl_powi(fg, 3), dl_powi(fl, 2)), 2.42843));
+  P = dl_add(P, dl_scale(dl_mul(dl_powi(fg, 2), dl_powi(fl, 3)), 4.47163));
+  P = dl_add(P, dl_scale(dl_mul(fg, dl_powi(fl, 4)), 0.07842));
+  P = dl_add(P, dl_powi(fl, 5));
+  dual f = dl_exp(dl_scale(dl_log(P), 0.2));
+  dual r = dl_div(fl, f);
+  dual eta = dl_add(dl_sub(dl_scale(r, 1.36603), dl_scale(dl_powi(r, 2), 0.47719)), dl_scale(dl_powi(r, 3), 0.11116));
+  dual h = dl_scale(f, 0.5);
+  dual L = dl_div(dl_scale(h, 1.0 / PI), dl_add(dl_mul(d, d), dl_mul(h, h)));
+  dual se = dl_scale(f, 1.0 / c0);
+  dual z = dl_div(d, se);
+  dual C;
+  if (z.v > -al) {
+    C = dl_exp(dl_scale(dl_mul(z, z), -0.5));
+  } else {
+    /* A (B - z)^-n, A = (n/alpha)^n exp(-alpha^2/2), B = n/alpha - alpha */
+    dual logA = dl_sub(dl_mul(nn, dl_log(dl_div(nn, a))), dl_scale(dl_mul(a, a), 0.5));
+    dual B = dl_sub(dl_div(nn, a), a);
+    C = dl_exp(dl_sub(logA, dl_mul(nn, dl_log(dl_sub(B, z)))));
+  }
+  dual Gn = dl_div(C, dl_scale(se, SQRT2PI_));
+  dual pv = dl_add(dl_mul(eta, L), dl_mul(dl_sub(dl_c(1.0), eta), Gn));
+  return dl_log(pv);
+}
+
 /* MLP surrogate.  Inputs: u0 = affine map of (x - q1) onto [-1, 1] (the
    position relative to the first shape parameter, the Breit-Wigner mass),
-   u_j = affine map of q_j (j = 1..5), each with its (lo, hi) box.  Returns s
-   and d s / d(raw input j), raw = (x, q1..q5). */
+   u_j = affine map of q_j (j = 1..5), each with its (lo, hi) box.  Returns
+   s = MLP(u) + log b and d s / d(raw input j), raw = (x, q1..q5). */
 static double mlp_leaf(const node* d, const double* raw, double* ds /*6*/) {
   double u[6], du[6], sc[6];
   for (int j = 0; j < 6; ++j) {
@@ -282,12 +346,16 @@ static double mlp_leaf(const node* d, const double* raw, double* ds /*6*/) {
   }
   mlp_act a;
   mlp_fwd1(d->mw, u, &a);
+  const dual lb = mlp_base_log(raw[0] - raw[1], raw[2], raw[3], raw[4], raw[5]);
   if (ds) {
     mlp_bwd1(d->mw, u, &a, 1.0, NULL, du);
     for (int j = 0; j < 6; ++j) ds[j] = du[j] * sc[j];
     ds[1] -= du[0] * sc[0];
+    ds[0] += lb.g[0];
+    ds[1] -= lb.g[0];
+    for (int j = 1; j < 5; ++j) ds[j + 1] += lb.g[j];
   }
-  return a.s;
+  return a.s + lb.v;
 }
 
 /* ---- shapes ---------------------------------------------------------------- */

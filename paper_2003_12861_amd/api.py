@@ -107,11 +107,12 @@ def _dptr(a):
 
 
 def _stream(stream=None):
+    """hipStream_t as an integer: torch's current stream, a torch stream, or a raw handle."""
     if stream is None:
-        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return torch.cuda.current_stream().cuda_stream
     if isinstance(stream, torch.cuda.Stream):
-        return ctypes.c_void_p(stream.cuda_stream)
-    return ctypes.c_void_p(stream)
+        return stream.cuda_stream
+    return int(stream) if stream else 0
 
 
 def gauss_legendre(K, lo, hi):
@@ -206,11 +207,14 @@ class Program:
         self._cols = []
         self._weights = None
         self.n_events = None
-        # result buffers reused by every call (no allocation per evaluation)
+        # argument and result buffers reused by every call (no allocation or
+        # pointer conversion per evaluation)
         self._v, self._nb = ctypes.c_double(), ctypes.c_int64()
         self._vref, self._nbref = ctypes.byref(self._v), ctypes.byref(self._nb)
         self._g = np.zeros(max(1, self.n_params))
         self._gptr = _dptr(self._g)
+        self._th = np.zeros(max(1, self.n_params))
+        self._thptr = _dptr(self._th)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -256,13 +260,17 @@ class Program:
         check(rf_set_launch(self.h, blocks, threads))
 
     def _theta(self, theta):
-        if type(theta) is np.ndarray and theta.dtype == np.float64 and theta.ndim == 1 and theta.flags.c_contiguous:
-            th = theta
-        else:
-            th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
         if th.size != self.n_params:
             raise RfError(-1, "theta has %d values, the program %d parameters" % (th.size, self.n_params))
         return th
+
+    def _theta_ptr(self, theta):
+        """theta copied into the program's argument buffer; returns its pointer"""
+        if len(theta) != self.n_params:
+            raise RfError(-1, "theta has %d values, the program %d parameters" % (len(theta), self.n_params))
+        self._th[: self.n_params] = theta
+        return self._thptr
 
     def values(self, theta, out=None, stream=None):
         th = self._theta(theta)
@@ -272,23 +280,20 @@ class Program:
         return out
 
     def nll(self, theta, stream=None):
-        th = self._theta(theta)
-        rc = rf_nll(self.h, _dptr(th), self._vref, self._nbref, _stream(stream))
+        rc = rf_nll(self.h, self._theta_ptr(theta), self._vref, self._nbref, _stream(stream))
         if rc != -3:
             check(rc)
         return self._v.value, self._nb.value
 
     def nll_grad(self, theta, stream=None):
         """Returns (nll, grad, n_bad); nll = inf and grad = nan when n_bad > 0."""
-        th = self._theta(theta)
-        rc = rf_nll_grad(self.h, _dptr(th), self._vref, self._gptr, self._nbref, _stream(stream))
+        rc = rf_nll_grad(self.h, self._theta_ptr(theta), self._vref, self._gptr, self._nbref, _stream(stream))
         if rc != -3:
             check(rc)
         return self._v.value, self._g[: self.n_params].copy(), self._nb.value
 
     def nll_grad_async(self, theta, stream=None):
-        th = self._theta(theta)
-        check(rf_nll_grad_async(self.h, _dptr(th), _stream(stream)))
+        check(rf_nll_grad_async(self.h, self._theta_ptr(theta), _stream(stream)))
 
     def stats(self):
         """(synchronous calls, calls whose wait fell back to a stream sync)"""

@@ -145,6 +145,7 @@ template <> struct ExpScl<double> {
   __device__ __forceinline__ double exp(double x, double extra = 0.0) const { return ::exp(fma(hi, x, extra)); }
 };
 
+static constexpr double RF_PI = 3.14159265358979323846;
 static constexpr double RF_SQRT2 = 1.41421356237309504880;
 static constexpr double RF_SQRTPI = 1.77245385090551602730;
 static constexpr double RF_SQRT2PI = 2.50662827463100050242;

@@ -358,6 +358,105 @@ __device__ void mlp_setup(const double* q, const double* box, const unsigned sho
   }
 }
 
+// ---- analytic base of the surrogate --------------------------------------
+// The network learns the residual r = log p_sig - log b over an analytic
+// base b(d = x - M; Gamma, sigma, alpha, n): a pseudo-Voigt -- the mixture of
+// a Lorentzian and a Gaussian of common full width f with weight eta, by
+// Thompson, Cox & Hastings (J. Appl. Cryst. 20 (1987) 79), f_G = 2 sigma
+// sqrt(2 ln 2), f_L = Gamma -- whose Gaussian part carries the Crystal Ball's
+// power-law tail below z = -alpha (z in units of the component's width
+// s_e = f / (2 sqrt(2 ln 2))):
+//   b = eta L(d) + (1 - eta) C(d / s_e) / (s_e sqrt(2 pi)),
+//   L(d) = (h / pi) / (d^2 + h^2), h = f / 2,
+//   C(z) = exp(-z^2/2) (z > -alpha), exp(log A - n log(B - z)) otherwise,
+//   A = (n/alpha)^n exp(-alpha^2/2), B = n/alpha - alpha.
+// The base carries most of log p_sig's variation (the residual's spread is
+// ~20x smaller), so the same network is far more accurate.  Parameter-only
+// constants, FP64, layout MB_* below (offsets inside the leaf's block).
+enum { MB_H = 8, MB_CL, MB_ISE, MB_CG, MB_ETA, MB_AL, MB_N, MB_LOGA, MB_B, MB_DFG, MB_DFS, MB_DEG, MB_DES, MB_INVC0,
+       MB_M, MB_END };
+RF_DEV void mlp_base_constants(const double* q, double* C) {
+  const double G = q[1], sg = q[2], al = q[3], n = q[4];
+  const double c0 = 2.0 * ::sqrt(2.0 * ::log(2.0));
+  const double fg = c0 * sg, fl = G;
+  const double P = fg * fg * fg * fg * fg + 2.69269 * fg * fg * fg * fg * fl + 2.42843 * fg * fg * fg * fl * fl +
+                   4.47163 * fg * fg * fl * fl * fl + 0.07842 * fg * fl * fl * fl * fl + fl * fl * fl * fl * fl;
+  const double dPg = 5 * fg * fg * fg * fg + 4 * 2.69269 * fg * fg * fg * fl + 3 * 2.42843 * fg * fg * fl * fl +
+                     2 * 4.47163 * fg * fl * fl * fl + 0.07842 * fl * fl * fl * fl;
+  const double dPl = 2.69269 * fg * fg * fg * fg + 2 * 2.42843 * fg * fg * fg * fl + 3 * 4.47163 * fg * fg * fl * fl +
+                     4 * 0.07842 * fg * fl * fl * fl + 5 * fl * fl * fl * fl;
+  const double f = ::pow(P, 0.2);
+  const double df_dP = 0.2 * f / P;
+  const double dfG = df_dP * dPl, dfS = df_dP * dPg * c0;  // df/dGamma, df/dsigma
+  const double r = fl / f;
+  const double eta = 1.36603 * r - 0.47719 * r * r + 0.11116 * r * r * r;
+  const double deta_dr = 1.36603 - 2 * 0.47719 * r + 3 * 0.11116 * r * r;
+  const double se = f / c0;
+  C[MB_H] = 0.5 * f;
+  C[MB_CL] = 0.5 * f / RF_PI;
+  C[MB_ISE] = 1.0 / se;
+  C[MB_CG] = 1.0 / (se * RF_SQRT2PI);
+  C[MB_ETA] = eta;
+  C[MB_AL] = al;
+  C[MB_N] = n;
+  C[MB_LOGA] = n * ::log(n / al) - 0.5 * al * al;
+  C[MB_B] = n / al - al;
+  C[MB_DFG] = dfG;
+  C[MB_DFS] = dfS;
+  C[MB_DEG] = deta_dr * (1.0 / f - fl * dfG / (f * f));
+  C[MB_DES] = deta_dr * (-fl * dfS / (f * f));
+  C[MB_INVC0] = 1.0 / c0;
+  C[MB_M] = q[0];
+}
+struct MlpBase {
+  Loc<float> M;
+  float h, cl, ise, cg, eta, al, n, logA, B, dfG, dfS, deG, deS, ic0;
+  RF_DEV MlpBase make(const double* C) {
+    MlpBase b;
+    b.M = Loc<float>::make(C[MB_M]);
+    b.h = (float)C[MB_H]; b.cl = (float)C[MB_CL]; b.ise = (float)C[MB_ISE]; b.cg = (float)C[MB_CG];
+    b.eta = (float)C[MB_ETA]; b.al = (float)C[MB_AL]; b.n = (float)C[MB_N]; b.logA = (float)C[MB_LOGA];
+    b.B = (float)C[MB_B]; b.dfG = (float)C[MB_DFG]; b.dfS = (float)C[MB_DFS]; b.deG = (float)C[MB_DEG];
+    b.deS = (float)C[MB_DES]; b.ic0 = (float)C[MB_INVC0];
+    return b;
+  }
+};
+// base value b at x; with GRAD, db[j] = d log b / d q_{j+1}, q = (M, Gamma, sigma, alpha, n)
+template <bool GRAD> RF_DEV float mlp_base(float x, const MlpBase& B, float* db) {
+  const float d = B.M.sub(x);
+  const float iD = __builtin_amdgcn_rcpf(fmaf(d, d, B.h * B.h));
+  const float L = B.cl * iD;
+  const float z = d * B.ise;
+  const bool core = z > -B.al;
+  float g, C, ga = 0.f, gn = 0.f;  // g = d log C / dz; ga, gn = d log C / d(alpha, n)
+  if (core) {
+    C = __expf(-0.5f * z * z);
+    g = -z;
+  } else {
+    const float t = B.B - z, it = __builtin_amdgcn_rcpf(t), lt = __logf(t);
+    C = __expf(B.logA - B.n * lt);
+    g = B.n * it;
+    ga = (-B.n / B.al - B.al) + B.n * (B.n / (B.al * B.al) + 1.f) * it;
+    gn = (__logf(B.n / B.al) + 1.f) - lt - (B.n / B.al) * it;
+  }
+  const float Gn = B.cg * C;
+  const float pv = fmaf(B.eta, L - Gn, Gn);
+  if (GRAD) {
+    const float ip = __builtin_amdgcn_rcpf(pv);
+    const float omE = 1.f - B.eta;
+    const float dLd = -2.f * d * L * iD, dGd = Gn * g * B.ise;
+    const float dLf = 0.5f * L * (1.f / B.h - 2.f * B.h * iD);
+    const float dGf = -Gn * (1.f + g * z) * B.ise * B.ic0;
+    const float dpf = fmaf(B.eta, dLf, omE * dGf), dpe = L - Gn;
+    db[0] = -ip * fmaf(B.eta, dLd, omE * dGd);
+    db[1] = ip * fmaf(dpf, B.dfG, dpe * B.deG);
+    db[2] = ip * fmaf(dpf, B.dfS, dpe * B.deS);
+    db[3] = ip * omE * Gn * ga;
+    db[4] = ip * omE * Gn * gn;
+  }
+  return pv;
+}
+
 template <int BS>
 __device__ void mlp_prologue(const double* q, const double* box, const double* nh,
                              const unsigned short* w, double* C, MlpLds& s, float* qs) {
@@ -367,6 +466,7 @@ __device__ void mlp_prologue(const double* q, const double* box, const double* n
     for (int j = 0; j < 5; ++j) C[1 + j] = nh[1 + j] / nh[0];
     C[6] = 2.0 / (box[1] - box[0]);               // du0/dx
     C[7] = -(q[0] + box[0]) * C[6] - 1.0;          // u0 = x C[6] + C[7]
+    mlp_base_constants(q, C);
   }
 }
 
@@ -375,6 +475,7 @@ template <typename T> struct MlpK {
   float xs, xo;
   const MlpLds* s;
   float* sav;  // this wavefront's LDS tile for (1 - h1^2) of a half tile
+  MlpBase base;
   RF_DEV MlpK make(const double* C, const MlpLds* s, float* sav_base) {
     MlpK k;
     k.invN = (T)C[0];
@@ -382,19 +483,21 @@ template <typename T> struct MlpK {
     k.xo = (float)C[7];
     k.s = s;
     k.sav = sav_base + (threadIdx.x >> 6) * 32 * 64;
+    k.base = MlpBase::make(C);
     return k;
   }
 };
 
 // wave-cooperative: every lane of the wavefront must call it together.
-// Returns exp(s) for the lane's event; with GRAD, d[j] = ds/dq_{j+1}.
+// Returns exp(s) b(x) for the lane's event; with GRAD, d[j] = d(s + log b)/dq_{j+1}.
 template <typename T, int NS, bool GRAD>
 RF_DEV T mlp_leaf_eval(T x, const MlpK<T>& k, T* d) {
   const float u0 = fmaf((float)x, k.xs, k.xo);
-  float dq[5];
+  float dq[5], db[5];
   const float sv = mlp_eval_u0<NS, GRAD>(*k.s, u0, k.sav, dq);
+  const float bv = mlp_base<GRAD>((float)x, k.base, db);
   if (GRAD)
 #pragma unroll
-    for (int j = 0; j < 5; ++j) d[j] = (T)dq[j];
-  return (T)expf(sv);
+    for (int j = 0; j < 5; ++j) d[j] = (T)(dq[j] + db[j]);
+  return (T)(expf(sv) * bv);
 }

@@ -148,7 +148,17 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg) 
   std::ostringstream o;
   o << "// generated by rfgpu: one fused likelihood kernel\n";
   o << RF_DEV_SRC_KABI << "\n" << RF_DEV_SRC_OPS << "\n";
-  if (L.has_mlp) o << RF_DEV_SRC_MLP << "\n#define RF_NSPLIT 3\n";
+  if (L.has_mlp) {
+    // BF16 parts per FP32 activation in the surrogate's MFMA products: two
+    // keep a 16-bit mantissa (relative 2^-17), far below the network's own
+    // error, at two thirds of the MFMA work of three
+    int nsplit = 2;
+    if (const char* e = getenv("RFGPU_NSPLIT")) {  // tuning override
+      const int v = atoi(e);
+      if (v == 2 || v == 3) nsplit = v;
+    }
+    o << RF_DEV_SRC_MLP << "\n#define RF_NSPLIT " << nsplit << "\n";
+  }
   o << "#define RF_T " << (f32 ? "float" : "double") << "\n";
   o << "#define RF_PREC " << (f32 ? "f32" : "f64") << "\n";
   o << "#define RF_NCOL " << L.n_cols << "\n";

@@ -44,7 +44,7 @@ static int leaf_ncst(const Node& n) {
     case RF_OP_ARGUS: return 6;
     case RF_OP_BW: return 6;
     case RF_OP_NUMCONV_BW_CB: return 8;
-    case RF_OP_MLP: return 8;
+    case RF_OP_MLP: return 23;  // 8 + the analytic base's constants
   }
   return 0;
 }

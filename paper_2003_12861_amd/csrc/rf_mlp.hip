@@ -44,8 +44,11 @@ __global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
   __shared__ float qs[5];
   __shared__ double red[4][6];
   __shared__ float sav[4 * 32 * 64];
+  __shared__ double bc[MB_END];
   mlp_setup<256>(a.q, a.box, a.w, s, qs);
+  if (threadIdx.x == 0) mlp_base_constants(a.q, bc);
   __syncthreads();
+  const MlpBase B = MlpBase::make(bc);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const double xsd = 2.0 / (a.box[1] - a.box[0]);
@@ -58,12 +61,13 @@ __global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
     const double xg = a.grid[valid ? g : 0];
     const double wg = valid ? a.grid[a.K + g] : 0.0;
     const float u0 = fmaf((float)xg, xs, xo);
-    float dq[5];
+    float dq[5], db[5];
     const float sv = mlp_eval_u0<MLP_SPLIT, true>(s, u0, sav + wid * 32 * 64, dq);
-    const double e = wg * exp((double)sv);
+    const float bv = mlp_base<true>((float)xg, B, db);
+    const double e = wg * exp((double)sv) * (double)bv;
     acc[0] += e;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) acc[1 + j] += e * (double)dq[j];
+    for (int j = 0; j < 5; ++j) acc[1 + j] += e * (double)(dq[j] + db[j]);
   }
 #pragma unroll
   for (int j = 0; j < 6; ++j) {

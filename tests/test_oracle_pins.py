@@ -299,20 +299,71 @@ def test_mlp_forward_backward_vs_torch():
     np.testing.assert_allclose(din, U.grad.numpy(), rtol=1e-11, atol=1e-13)
 
 
+def _base_value(d, G, sg, al, n):
+    """The surrogate's analytic base, written out: pseudo-Voigt of Thompson, Cox
+    & Hastings (1987) with the Crystal Ball tail in its Gaussian part."""
+    c0 = 2 * math.sqrt(2 * math.log(2))
+    fg, fl = c0 * sg, G
+    f = (fg**5 + 2.69269 * fg**4 * fl + 2.42843 * fg**3 * fl**2 + 4.47163 * fg**2 * fl**3
+         + 0.07842 * fg * fl**4 + fl**5) ** 0.2
+    r = fl / f
+    eta = 1.36603 * r - 0.47719 * r**2 + 0.11116 * r**3
+    h = f / 2
+    L = (h / math.pi) / (d * d + h * h)
+    se = f / c0
+    z = d / se
+    if z > -al:
+        C = math.exp(-0.5 * z * z)
+    else:
+        C = (n / al) ** n * math.exp(-0.5 * al * al) * (n / al - al - z) ** (-n)
+    return eta * L + (1 - eta) * C / (se * math.sqrt(2 * math.pi))
+
+
 def test_mlp_leaf_normalisation_vs_quadrature():
+    """The leaf's K-point Gauss-Legendre normalisation against adaptive
+    quadrature of exp(MLP) x base: the base's tail junction (continuous value
+    and slope) limits the rule to ~1e-9 at K = 1024, and the error must shrink
+    at K = 4096."""
     rng = np.random.default_rng(1)
     w = rng.normal(0, 0.2, 8833)
-    spec = workloads.spec_bwcb(surrogate=True)
-    m, top, ids = rfo.from_spec(spec)
-    m.set_mlp_weights(ids["sig"], w)
     th = [91.0, 2.4, 1.2, 1.3, 4.0]
     box = synth.BWCB_MLP_BOX
     def s_of_x(x):
         raw = np.array([[x - th[0]] + th])  # first input: position relative to M
         u = 2 * (raw - [b[0] for b in box]) / np.array([b[1] - b[0] for b in box]) - 1
-        return math.exp(_torch_mlp(w, u)[2].item())
-    N, _ = m.norm(ids["sig"], th + [-0.02, 0.8])
-    assert N == pytest.approx(quad(s_of_x, 60.0, 120.0), rel=1e-11)
+        return math.exp(_torch_mlp(w, u)[2].item()) * _base_value(x - th[0], *th[1:])
+    c0 = 2 * math.sqrt(2 * math.log(2))
+    fg, fl = c0 * th[2], th[1]
+    f = (fg**5 + 2.69269 * fg**4 * fl + 2.42843 * fg**3 * fl**2 + 4.47163 * fg**2 * fl**3
+         + 0.07842 * fg * fl**4 + fl**5) ** 0.2
+    junction = th[0] - th[3] * f / c0
+    from scipy import integrate
+    ref = integrate.quad(s_of_x, 60.0, 120.0, points=[th[0], junction], epsabs=0, epsrel=1e-13, limit=500)[0]
+    errs = []
+    for K in (1024, 4096):
+        m, top, ids = rfo.from_spec(workloads.spec_bwcb(surrogate=True, K=K))
+        m.set_mlp_weights(ids["sig"], w)
+        N, _ = m.norm(ids["sig"], th + [-0.02, 0.8])
+        errs.append(abs(N - ref) / ref)
+    assert errs[0] < 3e-9 and errs[1] < 3e-10 and errs[1] < errs[0] / 5, errs
+
+
+def test_mlp_base_is_pseudo_voigt_without_tail():
+    """With a zero network and the tail moved out of reach (alpha = 30) the
+    surrogate leaf is the Thompson-Cox-Hastings pseudo-Voigt, which
+    approximates the exact Voigt profile (Lorentzian of width Gamma convolved
+    with a Gaussian of width sigma) to about 1% of the peak height."""
+    from scipy.special import voigt_profile
+    spec = workloads.spec_bwcb(surrogate=True)
+    m, top, ids = rfo.from_spec(spec)
+    m.set_mlp_weights(ids["sig"], np.zeros(8833))
+    for M, G, sg in ((91.19, 2.5, 1.5), (90.0, 1.6, 2.8), (92.5, 3.4, 0.6), (91.0, 0.5, 3.0), (91.0, 6.0, 0.5)):
+        th = [M, G, sg, 30.0, 3.0, -0.02, 1.0]  # f = 1 isolates the signal
+        x = np.linspace(M - 8, M + 8, 161)
+        p = m.values(top, th, [x])
+        v = voigt_profile(x - M, sg, G / 2)
+        v /= quad(lambda t: voigt_profile(t - M, sg, G / 2), 60.0, 120.0, points=[M])
+        assert np.abs(p - v).max() <= 0.012 * v.max(), (M, G, sg, np.abs(p - v).max() / v.max())
 
 
 # ------------------------------------------------------------ binned model
