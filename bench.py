@@ -241,6 +241,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "rf_k_grad_f32", "achieved": achieved, "peak": peak,
                      "unit": "Tslot/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.workload, "rf_k_grad_f32", progs["fp32"].source),
+                     "source_sha1": hashlib.sha1(progs["fp32"].source.encode()).hexdigest(),
                      "slots_per_event": slots, "events_per_launch": n,
                      "bytes_per_event": BYTES_PER_EVENT[args.workload]["fp32"],
                      "hbm_GBps": n * BYTES_PER_EVENT[args.workload]["fp32"] / k32 / 1e9},
