@@ -27,9 +27,9 @@
 //
 // Reduction (deterministic, no floating-point atomics): per-thread FP64 sums
 // -> wavefront butterfly (plain FP64) -> across wavefronts in fixed order
-// with TwoSum into (hi, lo) -> one (hi, lo) partial per workgroup -> the last
-// workgroup to finish (atomic ticket) adds all partials in a fixed order with
-// double-double arithmetic and runs the epilogue.
+// with TwoSum, rounded once -> one FP64 partial per workgroup -> the last
+// workgroup to finish (atomic ticket) adds all partials in a fixed order and
+// runs the epilogue.
 #pragma once
 
 #define RF_NCOL1 (RF_NCOL > 0 ? RF_NCOL : 1)
@@ -117,6 +117,30 @@ RF_DEV void rf_group(const RF_T (&x)[RF_NCOL1][E], const KS<RF_T>& k, double* ac
   if (MODE == 0) rf_stv<RF_T, E>((RF_T*)a.values, i0, p);
 }
 
+// Issue priority of the wavefronts by the work left.  The arbiter of a SIMD
+// issues from the wave of highest priority first, and among equals from the
+// oldest: without this, the workgroups that reach a CU first run ahead and
+// the last ones finish their share alone, with too few waves to hide
+// latency.  Lowering the priority of waves that are near the end of their
+// share (fixed share; the summation order does not change) lets the others
+// catch up, so that the workgroups of a CU finish together.
+RF_DEV void rf_prio_remaining(int64_t r, int64_t total) {
+#if RF_PRIO == 1
+  // by positions left: the last three are graded
+  if (r >= 4) __builtin_amdgcn_s_setprio(3);
+  else if (r == 3) __builtin_amdgcn_s_setprio(2);
+  else if (r == 2) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+#else
+  // by quarters of the share done
+  const int64_t q = (4 * (total - r)) / (total > 0 ? total : 1);
+  if (q <= 0) __builtin_amdgcn_s_setprio(3);
+  else if (q == 1) __builtin_amdgcn_s_setprio(2);
+  else if (q == 2) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+#endif
+}
+
 template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   constexpr int NSUM = (MODE == 2) ? RF_NSUM : 1;
   constexpr int NW = RF_BS / 64;
@@ -165,39 +189,63 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   }
 #else
   {
-    const int64_t ng = n / RF_EPT;  // whole groups; the last n % 4 events follow
-    const int64_t gstep = (int64_t)gridDim.x * RF_BS;
-    const int64_t gid = (int64_t)blockIdx.x * RF_BS + threadIdx.x;
+    const int64_t ng = n / RF_EPT;  // whole groups; the last n % RF_EPT events follow
+    const int64_t G = gridDim.x;
+    const int64_t T = (ng + RF_BS - 1) / RF_BS;  // tiles of RF_BS groups (the last may be partial)
     constexpr int D = RF_PFD;
+    // A tile is one group per thread of the workgroup (consecutive threads,
+    // consecutive groups); workgroup b takes tiles b, b + G, b + 2G, ...
+    // (its positions 0, 1, 2, ...), a fixed assignment that keeps the
+    // summation order, and so the result, identical from call to call.
     // group indices past the end are clamped to the last group: every load
     // address is valid (only used when ng > 0)
     auto clampg = [ng](int64_t g) { return g < ng ? g : ng - 1; };
-    // the ring's first loads are issued before the prologue so that their
-    // latency overlaps the FP64 normalisation work
+    // the ring's first loads (positions 0 .. D-1, all fixed) are issued
+    // before the prologue so that their latency overlaps the FP64
+    // normalisation work
     RF_T xb[D][RF_NCOL1][RF_EPT];
+    int64_t ts[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) ts[u] = (int64_t)u * G + blockIdx.x;
     if (ng > 0) {
 #pragma unroll
       for (int u = 0; u < D; ++u)
 #pragma unroll
         for (int c = 0; c < RF_NCOL; ++c)
-          rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(gid + u * gstep) * RF_EPT, xb[u][c]);
+          rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(ts[u] * RF_BS + threadIdx.x) * RF_EPT, xb[u][c]);
     }
     rf_prologue(a.theta, cst, a);
     __syncthreads();
     const KS<RF_T> k = KS<RF_T>::load(cst);
-    for (int64_t g = gid; g < ng; g += D * gstep) {
+    bool more = ts[0] < T;
+    // positions of this workgroup's fixed sequence
+    const int64_t PB = T > (int64_t)blockIdx.x ? (T - blockIdx.x + G - 1) / G : 0;
+    for (int64_t m0 = 0; more; m0 += D) {
 #pragma unroll
       for (int u = 0; u < D; ++u) {
-        const int64_t gu = g + u * gstep;
+        if (!more) break;
+        const int64_t m = m0 + u;
+#if RF_PRIO
+        rf_prio_remaining(PB - m, PB);
+#endif
+        const int64_t gu = ts[u] * RF_BS + threadIdx.x;
         if (gu < ng) rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, gu * RF_EPT, cst);
-        if (D > 1 || gu + gstep < ng) {
+        // the tile of position m + D refills this slot
+        const int64_t tn = (m + D) * G + blockIdx.x;
+        ts[u] = tn;
+        if (tn < T) {
 #pragma unroll
           for (int c = 0; c < RF_NCOL; ++c)
-            rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(gu + D * gstep) * RF_EPT, xb[u][c]);
+            rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(tn * RF_BS + threadIdx.x) * RF_EPT, xb[u][c]);
         }
+        more = ts[(u + 1) % D] < T;
       }
     }
+#if RF_PRIO
+    __builtin_amdgcn_s_setprio(3);  // the hand-off that follows is on the critical path
+#endif
     const int64_t tail0 = ng * RF_EPT;
+    const int64_t gid = (int64_t)blockIdx.x * RF_BS + threadIdx.x;
     if (gid < n - tail0) {
       RF_T x1[RF_NCOL1][1];
 #pragma unroll
@@ -250,60 +298,61 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   __syncthreads();
   if (!last) return;
 
-  // ---- last workgroup: fixed-order double-double sum of all partials ----
-  // Every thread owns the blocks b = tid, tid + RF_BS, ...; eight sums of
-  // two blocks per step, 16 independent loads in flight (one memory round
-  // trip per step and 2 RF_BS workgroups; more would raise the register
-  // count of the whole kernel).  The combination order (thread-local, then the wavefront
-  // sums, then the wavefronts in index order) does not depend on timing:
-  // repeated calls give bitwise identical results.
-  __shared__ double rh[NW][8], rl[NW][8];
+  // ---- last workgroup: sum of all partials in a fixed order ----
+  // Wavefront w adds sums w, w + NW, ... two at a time: each lane reads the
+  // partials of workgroups lane, lane + 64, ... (sixteen per sum and pass,
+  // all loads of a pass in flight together; consecutive lanes read
+  // consecutive words), adds them pairwise, and a wavefront sum completes
+  // the total.  The order depends only on the workgroup count, so repeated
+  // calls give bitwise identical results; the rounding error is a few units
+  // of 2^-53 times the sum of magnitudes of the partials.
   const int nb = (int)gridDim.x;
-  for (int j0 = 0; j0 < NS2; j0 += 8) {
-    double h[8], l[8];
+  for (int j0 = wid; j0 < NS2; j0 += 2 * NW) {
+    const int j1 = j0 + NW < NS2 ? j0 + NW : j0;  // second sum (a repeat of the first if none)
+    double h0 = 0.0, h1 = 0.0;
+    for (int b0 = 0; b0 < nb; b0 += 16 * 64) {
+      double v0[16], v1[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) { h[u] = 0.0; l[u] = 0.0; }
-    for (int b = threadIdx.x; b < nb; b += 2 * RF_BS) {
-      // loads past the last workgroup are clamped to a valid one and skipped
-      int bq[2];
+      for (int q = 0; q < 16; ++q) {
+        const int b = b0 + q * 64 + lane;
+        const int bc = b < nb ? b : nb - 1;  // a valid address; the value is dropped
+        v0[q] = __hip_atomic_load(&a.part[j0 * (int64_t)nblk + bc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v1[q] = __hip_atomic_load(&a.part[j1 * (int64_t)nblk + bc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) bq[q] = b + q * RF_BS < nb ? b + q * RF_BS : b;
-      double pv[2][8];
+      for (int q = 0; q < 16; ++q)
+        if (b0 + q * 64 + lane >= nb) { v0[q] = 0.0; v1[q] = 0.0; }
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int w = 8; w >= 1; w >>= 1)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int j = j0 + u < NS2 ? j0 + u : NS2 - 1;
-          pv[q][u] = __hip_atomic_load(&a.part[j * (int64_t)nblk + bq[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-        if (b + q * RF_BS < nb) {
-#pragma unroll
-          for (int u = 0; u < 8; ++u) dd_add(h[u], l[u], pv[q][u], 0.0);
-        }
+        for (int q = 0; q < w; ++q) { v0[q] += v0[q + w]; v1[q] += v1[q + w]; }
+      h0 += v0[0];
+      h1 += v1[0];
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      wave_dd_sum(h[u], l[u]);
-      if (lane == 0) { rh[wid][u] = h[u]; rl[wid][u] = l[u]; }
-    }
-    __syncthreads();
-    if (threadIdx.x < 8 && j0 + (int)threadIdx.x < NS2) {
-      double H = 0.0, Lo = 0.0;
-      for (int w = 0; w < NW; ++w) dd_add(H, Lo, rh[w][threadIdx.x], rl[w][threadIdx.x]);
-      fin[j0 + threadIdx.x] = H + Lo;
-    }
-    __syncthreads();
+    h0 = wave_sum(h0);
+    h1 = wave_sum(h1);
+    if (lane == 0) { fin[j0] = h0; fin[j1] = h1; }
   }
-  if (threadIdx.x == 0) {
-    rf_epilogue<MODE>(fin, cst, a.theta, a.out, (unsigned)fin[NSUM]);
-    rf_reset_ticket(a.ticket);
-    if (a.hout) {
-      // host copy, then the completion word the host polls for
-      for (int j = 0; j < RF_P + 2 + NSUM; ++j) a.hout[j] = a.out[j];
-      __threadfence_system();
-      __hip_atomic_store((uint64_t*)(a.hout + RF_P + 2 + RF_NSUM), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __syncthreads();
+  if (wid == 0) {
+    // the epilogue (one lane) writes the result into LDS; the wavefront
+    // copies it to the output and to the host's mapped copy
+    constexpr int NOUT = RF_P + 2 + RF_NSUM;
+    __shared__ double res[NOUT];
+    for (int j = lane; j < NOUT; j += 64) res[j] = 0.0;
+    if (lane == 0) rf_epilogue<MODE>(fin, cst, a.theta, res, (unsigned)fin[NSUM]);
+    for (int j = lane; j < NOUT; j += 64) {
+      const double v = res[j];
+      a.out[j] = v;
+      if (a.hout) a.hout[j] = v;
+    }
+    if (lane == 0) {
+      rf_reset_ticket(a.ticket);
+      if (a.hout) {
+        // the result is in host memory before the completion word the host polls for
+        __threadfence_system();
+        __hip_atomic_store((uint64_t*)(a.hout + NOUT), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
   }
 }

@@ -177,9 +177,13 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
   p->pfd = choose_pfd(p->L, p->ept);
   if (const char* e = getenv("RFGPU_TG")) {  // tuning override
     const int v = atoi(e);
-    if (v >= 1 && v <= 32) p->tg = v;
+    if (v >= 1 && v <= RF_TGMAX) p->tg = v;
   }
-  p->source = generate_source(p->L, p->block, p->ept, p->pfd, p->tg);
+  if (const char* e = getenv("RFGPU_PRIO")) {  // tuning override of the issue-priority policy
+    const int v = atoi(e);
+    if (v >= 0 && v <= 2) p->prio = v;
+  }
+  p->source = generate_source(p->L, p->block, p->ept, p->pfd, p->tg, p->prio);
   rc = build_code_object(p->source, p->co_path);
   if (rc) { delete p; return rc; }
   if (!(flags & RF_COMPILE_NO_LOAD)) {
@@ -256,7 +260,7 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
     hipError_t e;
     const size_t np = (size_t)(p->L.n_sums + 1) * nmax;  // sums + bad-event count
     if ((e = hipMalloc(&p->d_part, sizeof(double) * np)) != hipSuccess) return hip_fail(e, "hipMalloc partials");
-    if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned) * 64 * 33)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMalloc(&p->d_out, sizeof(double) * out_len(p))) != hipSuccess) return hip_fail(e, "hipMalloc");
     // result copy + completion word
     if ((e = hipHostMalloc(&p->h_out, sizeof(double) * (out_len(p) + 1), hipHostMallocMapped | hipHostMallocCoherent)) !=
@@ -265,7 +269,7 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
     memset(p->h_out, 0, sizeof(double) * (out_len(p) + 1));
     if ((e = hipHostGetDevicePointer((void**)&p->d_hout, p->h_out, 0)) != hipSuccess)
       return hip_fail(e, "hipHostGetDevicePointer");
-    if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned) * 64 * 33)) != hipSuccess) return hip_fail(e, "hipMemset");
+    if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return hip_fail(e, "hipMemset");
     if (!p->L.aux.empty()) {
       if ((e = hipMalloc(&p->d_aux, sizeof(double) * p->L.aux.size())) != hipSuccess) return hip_fail(e, "hipMalloc aux");
       if ((e = hipMemcpy(p->d_aux, p->L.aux.data(), sizeof(double) * p->L.aux.size(), hipMemcpyHostToDevice)) != hipSuccess)

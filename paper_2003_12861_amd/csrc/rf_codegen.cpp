@@ -141,7 +141,7 @@ static void emit_jac(std::ostringstream& o, const Lowered& L, int id, const std:
   }
 }
 
-std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg) {
+std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, int prio) {
   const auto& g = L.nodes;
   const int N = (int)g.size();
   const bool f32 = L.precision == RF_FP32_COMP;
@@ -169,6 +169,7 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg) 
   o << "#define RF_EPT " << ept << "\n";
   o << "#define RF_PFD " << pfd << "\n";
   o << "#define RF_TG " << tg << "\n";
+  o << "#define RF_PRIO " << prio << "\n";
   // programs with an MLP leaf run the event loop in whole wavefronts (the MLP
   // is wave-cooperative) and evaluate in FP32 only (no FP64 re-evaluation)
   o << "#define RF_WAVE_UNIFORM " << (L.has_mlp ? 1 : 0) << "\n";

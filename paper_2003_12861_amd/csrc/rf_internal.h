@@ -66,7 +66,7 @@ struct Lowered {
 };
 
 int lower(const std::vector<Node>& g, int top, int precision, Lowered& out);
-std::string generate_source(const Lowered& L, int block_size, int ept, int pfd, int tg);
+std::string generate_source(const Lowered& L, int block_size, int ept, int pfd, int tg, int prio);
 
 // code-object cache + compiler driver
 struct Module {
@@ -110,6 +110,7 @@ struct rf_program {
   int ept = 4;      // events per lane and step of the event loop (compile-time)
   int pfd = 3;      // groups in flight per lane (load ring depth, compile-time)
   int tg = 8;       // ticket groups of the end-of-kernel hand-off (compile-time)
+  int prio = 1;     // wavefront issue-priority policy of the event loop (compile-time)
   int resident = 4; // workgroups of the gradient kernel one CU holds at once (occupancy query)
   uint64_t seq = 0; // completion sequence number of synchronous calls
   int64_t n_sync = 0, n_slow = 0;  // synchronous calls; those whose wait fell back to a stream sync
