@@ -146,7 +146,9 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   constexpr int NW = RF_BS / 64;
   __shared__ double cst[RF_NCST > 0 ? RF_NCST : 1];
   constexpr int NS2 = NSUM + 1;
+#if !RF_LDSRED
   __shared__ double red[NW][NS2];
+#endif
   __shared__ double fin[NS2];
   __shared__ int last;
 
@@ -190,62 +192,57 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
 #else
   {
     const int64_t ng = n / RF_EPT;  // whole groups; the last n % RF_EPT events follow
-    const int64_t G = gridDim.x;
-    const int64_t T = (ng + RF_BS - 1) / RF_BS;  // tiles of RF_BS groups (the last may be partial)
+    const int64_t gstep = (int64_t)gridDim.x * RF_BS;
+    const int64_t gid = (int64_t)blockIdx.x * RF_BS + threadIdx.x;
     constexpr int D = RF_PFD;
-    // A tile is one group per thread of the workgroup (consecutive threads,
-    // consecutive groups); workgroup b takes tiles b, b + G, b + 2G, ...
-    // (its positions 0, 1, 2, ...), a fixed assignment that keeps the
-    // summation order, and so the result, identical from call to call.
-    // group indices past the end are clamped to the last group: every load
-    // address is valid (only used when ng > 0)
+    // Fixed assignment: thread gid takes groups gid, gid + gstep, ... (its
+    // positions 0, 1, 2, ...), which keeps the summation order, and so the
+    // result, identical from call to call.  Group indices past the end are
+    // clamped to the last group: every load address is valid (only used
+    // when ng > 0), and the refills stay unconditional, so the compiler
+    // waits for one ring slot at a time.
     auto clampg = [ng](int64_t g) { return g < ng ? g : ng - 1; };
-    // the ring's first loads (positions 0 .. D-1, all fixed) are issued
-    // before the prologue so that their latency overlaps the FP64
-    // normalisation work
+    // the ring's first loads are issued before the prologue so that their
+    // latency overlaps the FP64 normalisation work
     RF_T xb[D][RF_NCOL1][RF_EPT];
-    int64_t ts[D];
-#pragma unroll
-    for (int u = 0; u < D; ++u) ts[u] = (int64_t)u * G + blockIdx.x;
     if (ng > 0) {
 #pragma unroll
       for (int u = 0; u < D; ++u)
 #pragma unroll
         for (int c = 0; c < RF_NCOL; ++c)
-          rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(ts[u] * RF_BS + threadIdx.x) * RF_EPT, xb[u][c]);
+          rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(gid + u * gstep) * RF_EPT, xb[u][c]);
     }
     rf_prologue(a.theta, cst, a);
     __syncthreads();
     const KS<RF_T> k = KS<RF_T>::load(cst);
-    bool more = ts[0] < T;
-    // positions of this workgroup's fixed sequence
-    const int64_t PB = T > (int64_t)blockIdx.x ? (T - blockIdx.x + G - 1) / G : 0;
-    for (int64_t m0 = 0; more; m0 += D) {
+#if RF_PRIO
+    // positions of this workgroup (its first thread's count; uniform)
+    const int64_t g0 = (int64_t)blockIdx.x * RF_BS;
+    const int64_t PB = ng > g0 ? (ng - g0 + gstep - 1) / gstep : 0;
+    int64_t m0 = 0;
+#endif
+    for (int64_t g = gid; g < ng; g += D * gstep) {
 #pragma unroll
       for (int u = 0; u < D; ++u) {
-        if (!more) break;
-        const int64_t m = m0 + u;
 #if RF_PRIO
-        rf_prio_remaining(PB - m, PB);
+        rf_prio_remaining(PB - (m0 + u), PB);
 #endif
-        const int64_t gu = ts[u] * RF_BS + threadIdx.x;
+        const int64_t gu = g + u * gstep;
         if (gu < ng) rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, gu * RF_EPT, cst);
-        // the tile of position m + D refills this slot
-        const int64_t tn = (m + D) * G + blockIdx.x;
-        ts[u] = tn;
-        if (tn < T) {
+        if (D > 1 || gu + gstep < ng) {
 #pragma unroll
           for (int c = 0; c < RF_NCOL; ++c)
-            rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(tn * RF_BS + threadIdx.x) * RF_EPT, xb[u][c]);
+            rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(gu + D * gstep) * RF_EPT, xb[u][c]);
         }
-        more = ts[(u + 1) % D] < T;
       }
+#if RF_PRIO
+      m0 += D;
+#endif
     }
 #if RF_PRIO
     __builtin_amdgcn_s_setprio(3);  // the hand-off that follows is on the critical path
 #endif
     const int64_t tail0 = ng * RF_EPT;
-    const int64_t gid = (int64_t)blockIdx.x * RF_BS + threadIdx.x;
     if (gid < n - tail0) {
       RF_T x1[RF_NCOL1][1];
 #pragma unroll
@@ -258,6 +255,50 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
 
   // ---- workgroup reduction ----
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nblk = a.nblk_max;
+#if RF_LDSRED
+  // Through LDS: every thread writes its sums (and its bad-event count, as
+  // the last sum: exact in FP64); in round r, the RF_BS / 8 threads of sum
+  // 8 r + t / (RF_BS / 8) each add eight consecutive values pairwise, the
+  // sixteen lanes of a row by DPP and the rows by readlane -- a fixed order,
+  // and a few VALU instructions per sum instead of a butterfly per sum and
+  // wavefront.
+  static_assert(RF_BS == 256 || RF_BS == 512, "the LDS reduction takes RF_BS / 8 lanes per sum");
+  constexpr int TPS = RF_BS / 8;
+  __shared__ double sred[NS2][RF_BS];
+#pragma unroll
+  for (int j = 0; j < NSUM; ++j) sred[j][threadIdx.x] = acc[j];
+  sred[NSUM][threadIdx.x] = (double)nbad;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < (NS2 + 7) / 8; ++r) {
+    const int j = r * 8 + (int)threadIdx.x / TPS;
+    const double* row = &sred[j < NS2 ? j : NS2 - 1][((int)threadIdx.x % TPS) * 8];
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = row[q];
+#pragma unroll
+    for (int w = 4; w >= 1; w >>= 1)
+#pragma unroll
+      for (int q = 0; q < w; ++q) v[q] += v[q + w];
+    const double rs = row_sum(v[0]);
+    const double h0 = lane_d(rs, 0) + lane_d(rs, 16);
+    const double h1 = lane_d(rs, 32) + lane_d(rs, 48);
+    if (lane == 0) {
+      if constexpr (TPS == 32) {  // a sum per half-wavefront
+        const int ja = r * 8 + 2 * wid;
+        if (ja < NS2)
+          __hip_atomic_store(&a.part[ja * (int64_t)nblk + blockIdx.x], h0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ja + 1 < NS2)
+          __hip_atomic_store(&a.part[(ja + 1) * (int64_t)nblk + blockIdx.x], h1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {  // a sum per wavefront
+        const int ja = r * 8 + wid;
+        if (ja < NS2)
+          __hip_atomic_store(&a.part[ja * (int64_t)nblk + blockIdx.x], h0 + h1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+#else
 #pragma unroll
   for (int j = 0; j < NSUM; ++j) {
     const double v = wave_sum(acc[j]);
@@ -267,7 +308,6 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   const unsigned wb = wave_sum_u(nbad);
   if (lane == 0) red[wid][NSUM] = (double)wb;
   __syncthreads();
-  const int nblk = a.nblk_max;
   // one compensated value per sum: the wavefront sums added with TwoSum,
   // rounded once
   for (int j = threadIdx.x; j < NS2; j += RF_BS) {
@@ -275,6 +315,7 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
     for (int w = 0; w < NW; ++w) dd_add(hi, lo, red[w][j], 0.0);
     __hip_atomic_store(&a.part[j * (int64_t)nblk + blockIdx.x], hi + lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+#endif
   // publish this workgroup's partials, then take a ticket
   rf_wait_stores();
   __syncthreads();

@@ -170,6 +170,19 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
   o << "#define RF_PFD " << pfd << "\n";
   o << "#define RF_TG " << tg << "\n";
   o << "#define RF_PRIO " << prio << "\n";
+  {
+    // workgroup reduction through LDS (a table of sums x threads, FP64) in
+    // kernels that hold no LDS tables of their own, where it costs no
+    // occupancy; there the per-workgroup VALU work it saves matters most
+    bool has_tab = L.has_mlp;
+    for (int id = 0; id < N; ++id)
+      if (L.reach[id] && blockwide(g[id])) has_tab = true;
+    int ldsred = ((BS == 256 || BS == 512) && !has_tab && (L.n_sums + 1) * BS * 8 <= 48 * 1024) ? 1 : 0;
+    if (const char* e = getenv("RFGPU_LDSRED")) {  // tuning override
+      if (atoi(e) == 0) ldsred = 0;
+    }
+    o << "#define RF_LDSRED " << ldsred << "\n";
+  }
   // programs with an MLP leaf run the event loop in whole wavefronts (the MLP
   // is wave-cooperative) and evaluate in FP32 only (no FP64 re-evaluation)
   o << "#define RF_WAVE_UNIFORM " << (L.has_mlp ? 1 : 0) << "\n";
