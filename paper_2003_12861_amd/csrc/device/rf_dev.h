@@ -171,28 +171,42 @@ RF_DEV void gauss_prologue(const double* in, double lo, double hi, double* C) {
   C[3] = mu;
   C[4] = 1.0 / s;
 }
-// Log form; d log u/d mu = z/sigma, d log u/d sigma = z^2/sigma with
-// z = (x - mu)/sigma: the event part is (z, z^2), the factor 1/sigma (C[4])
-// is applied to the sums.
+// With w = s (x - mu)/sigma, s = 1/sqrt(2 ln 2), the kernel is u = 2^(-w^2).
+// In FP32 programs w and q = w^2 are formed in FP64 (one FP64 operation costs
+// one FP32 issue slot here) and q is split into an FP32 pair qh + ql: the
+// exponent is then exact to far below an FP32 unit, for any mu and sigma
+// (an FP32 w would carry a relative error of 2^-24, which 2 q ln2 amplifies
+// to several 1e-6 in u at |z| ~ 10).  Log form: d log u/d mu = z/sigma and
+// d log u/d sigma = z^2/sigma with z = w/s; the event part is (w, w^2), the
+// factors 1/(s sigma) and 1/(s^2 sigma) are applied to the sums.
+static constexpr double RF_GW = 0.849321800288019042721502834103;      // 1/sqrt(2 ln 2)
+static constexpr double RF_GW_INV = 1.17741002251547469101156932646;   // sqrt(2 ln 2)
+static constexpr double RF_GW_INV2 = 1.38629436111989061883446424292;  // 2 ln 2
 template <typename T> struct GaussK {
-  Loc<T> mu;
-  Scl<T> isig;
-  ExpScl<T> e;
+  double mu, is;  // mu and s / sigma
   RF_DEV GaussK load(const double* C) {
     GaussK k;
-    k.mu = Loc<T>::make(C[3]);
-    k.isig = Scl<T>::make(C[4]);
-    k.e = ExpScl<T>::make(-0.5);
+    k.mu = C[3];
+    k.is = C[4] * RF_GW;
     return k;
   }
 };
 template <typename T> RF_DEV T gauss_eval(T x, const GaussK<T>& k, T* d) {
-  const T z = k.isig.mul(k.mu.sub(x));
-  const T q = z * z;
-  d[0] = z;
-  d[1] = q;
-  // z^2 = q + fma(z, z, -q) exactly; the low part enters the exponent
-  return k.e.exp(q, (T)-0.5 * fma(z, z, -q));
+  const double w = ((double)x - k.mu) * k.is;
+  const double q = w * w;
+  if constexpr (sizeof(T) == 4) {
+    const float qh = (float)q;
+    const float ql = (float)fma(w, w, -(double)qh);  // w^2 - qh
+    d[0] = (float)w;
+    d[1] = qh;
+    const float E = __builtin_amdgcn_exp2f(-qh);
+    return fma(E * ql, -(float)RF_LN2, E);  // 2^(-qh - ql) to first order in ql
+  } else {
+    d[0] = w;
+    d[1] = q;
+    const double E = ::exp2(-q);
+    return fma(E * fma(w, w, -q), -RF_LN2, E);
+  }
 }
 
 // ============================================================= Chebyshev ==

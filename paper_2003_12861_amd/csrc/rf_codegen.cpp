@@ -77,7 +77,7 @@ static bool dlin(const Node& n) { return n.op == RF_OP_CHEB; }
 static std::string dscale(const Node& n, int off, int j) {
   auto c = [&](int k) { return "cst[" + std::to_string(off + k) + "]"; };
   switch (n.op) {
-    case RF_OP_GAUSS: return c(4);
+    case RF_OP_GAUSS: return "(" + c(4) + (j == 0 ? " * RF_GW_INV)" : " * RF_GW_INV2)");
     case RF_OP_EXP: return n.attrs[0] == 0.0 ? c(4) : "1.0";
     case RF_OP_BW: return j == 0 ? "2.0" : c(5);
   }

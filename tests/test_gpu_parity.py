@@ -45,6 +45,51 @@ def test_gauss_cheb_sizes(prec, n):
 
 
 @pytest.mark.parametrize("prec", [api.FP64, api.FP32])
+@pytest.mark.parametrize("mu,sigma", [(0.37, 0.7), (-1.1, 1.3), (2.05, 0.45), (0.0, 1.0)])
+def test_single_tail_events(prec, mu, sigma):
+    """One event at a time, deep in the Gaussian's tails (|z| from 6 to 13):
+    the mu and sigma gradients come from the Gaussian component alone, so
+    they need the component's relative accuracy, not just the mixture's."""
+    f, c1, c2 = 0.3, 0.2, -0.1
+    th = [mu, sigma, f, c1, c2]
+    prog, (om, otop, _) = build_pair(workloads.spec_gauss_cheb(), prec, api)
+    tn, tg = TOL[prec]
+    for z in (-13.0, -9.5, -6.0, 6.5, 8.75, 11.0):
+        x = np.float32(mu + z * sigma)
+        if not -10.0 <= x <= 10.0:
+            continue
+        print("case tail prec=%d mu=%g sigma=%g z=%g" % (prec, mu, sigma, z), flush=True)
+        col = np.array([x], dtype=np.float64)
+        prog.bind(to_dev([col], prec, api))
+        nll, g, nb = prog.nll_grad(th)
+        onll, og, oga, onb = om.nll_ex(otop, th, [col])
+        assert nb == onb == 0
+        assert rel(nll, onll) <= tn, (z, nll, onll)
+        err = scaled_grad_err(g, og, oga)
+        # mu, sigma: the Gaussian component's own accuracy
+        assert err[:2].max() <= tg, (z, err, g, og)
+        # f, c1, c2: within one event, each derivative is a difference of two
+        # terms (component shape and normalisation, or the two components);
+        # rounding of the FP32 arguments is relative to the terms, so the bar
+        # is scaled by the event's cancellation factor (closed forms, FP64)
+        xp = float(x) / 10.0
+        T = (xp, 2.0 * xp * xp - 1.0)
+        u = 1.0 + c1 * T[0] + c2 * T[1]
+        sN = 1.0 + c2 / (1.0 - 4.0)
+        dlogN = (0.0, 1.0 / ((1.0 - 4.0) * sN))
+        kappa = [1.0, 1.0, 1.0]
+        for kk in range(2):
+            a_, b_ = T[kk] / u, dlogN[kk]
+            kappa[1 + kk] = (abs(a_) + abs(b_)) / max(abs(a_ - b_), 1e-300)
+        zz = (float(x) - mu) / sigma
+        from scipy.special import erf
+        Ng = sigma * math.sqrt(math.pi / 2) * (erf((10 - mu) / (math.sqrt(2) * sigma)) - erf((-10 - mu) / (math.sqrt(2) * sigma)))
+        gs, gb = math.exp(-0.5 * zz * zz) / Ng, u / (20.0 * sN)
+        kappa[0] = (gs + gb) / max(abs(gs - gb), 1e-300)
+        assert np.all(err[2:] <= tg * np.array(kappa)), (z, err, kappa, g, og)
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.FP32])
 def test_empty_dataset(prec):
     prog, _ = build_pair(workloads.spec_gauss_cheb(), prec, api)
     prog.bind(to_dev([np.zeros(0)], prec, api))
