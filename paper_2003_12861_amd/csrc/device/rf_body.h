@@ -193,56 +193,64 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   {
     const int64_t ng = n / RF_EPT;  // whole groups; the last n % RF_EPT events follow
     const int64_t gstep = (int64_t)gridDim.x * RF_BS;
-    const int64_t gid = (int64_t)blockIdx.x * RF_BS + threadIdx.x;
+    const int64_t base0 = (int64_t)blockIdx.x * RF_BS;  // thread 0's group at position 0
     constexpr int D = RF_PFD;
-    // Fixed assignment: thread gid takes groups gid, gid + gstep, ... (its
-    // positions 0, 1, 2, ...), which keeps the summation order, and so the
-    // result, identical from call to call.  Group indices past the end are
-    // clamped to the last group: every load address is valid (only used
-    // when ng > 0), and the refills stay unconditional, so the compiler
-    // waits for one ring slot at a time.
-    auto clampg = [ng](int64_t g) { return g < ng ? g : ng - 1; };
+    // Fixed assignment: at position m the workgroup takes the tile of groups
+    // base0 + m gstep + [0, RF_BS), one per thread (consecutive threads,
+    // consecutive groups), which keeps the summation order, and so the
+    // result, identical from call to call.  The main loop runs the MB full
+    // tiles, where every lane is in range: no lane checks, and a refill
+    // past the last full tile re-reads that tile (its base is clamped in
+    // scalar registers) -- so every ring slot is refilled unconditionally
+    // and the compiler waits for one slot at a time.  The one partial tile
+    // and the last n % RF_EPT events follow with lane checks.
+    const int64_t MB = ng >= base0 + RF_BS ? (ng - base0 - RF_BS) / gstep + 1 : 0;
+    auto tile = [&](int64_t m) { return base0 + (m < MB ? m : MB - 1) * gstep; };  // uniform
+    RF_T xb[D][RF_NCOL1][RF_EPT];
     // the ring's first loads are issued before the prologue so that their
     // latency overlaps the FP64 normalisation work
-    RF_T xb[D][RF_NCOL1][RF_EPT];
-    if (ng > 0) {
+    if (MB > 0) {
 #pragma unroll
       for (int u = 0; u < D; ++u)
 #pragma unroll
         for (int c = 0; c < RF_NCOL; ++c)
-          rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(gid + u * gstep) * RF_EPT, xb[u][c]);
+          rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], (tile(u) + threadIdx.x) * RF_EPT, xb[u][c]);
     }
     rf_prologue(a.theta, cst, a);
     __syncthreads();
     const KS<RF_T> k = KS<RF_T>::load(cst);
-#if RF_PRIO
-    // positions of this workgroup (its first thread's count; uniform)
-    const int64_t g0 = (int64_t)blockIdx.x * RF_BS;
-    const int64_t PB = ng > g0 ? (ng - g0 + gstep - 1) / gstep : 0;
     int64_t m0 = 0;
-#endif
-    for (int64_t g = gid; g < ng; g += D * gstep) {
+    for (; m0 + D <= MB; m0 += D) {
 #pragma unroll
       for (int u = 0; u < D; ++u) {
 #if RF_PRIO
-        rf_prio_remaining(PB - (m0 + u), PB);
+        rf_prio_remaining(MB - (m0 + u), MB);
 #endif
-        const int64_t gu = g + u * gstep;
-        if (gu < ng) rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, gu * RF_EPT, cst);
-        if (D > 1 || gu + gstep < ng) {
+        rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, (base0 + (m0 + u) * gstep + threadIdx.x) * RF_EPT, cst);
 #pragma unroll
-          for (int c = 0; c < RF_NCOL; ++c)
-            rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], clampg(gu + D * gstep) * RF_EPT, xb[u][c]);
-        }
+        for (int c = 0; c < RF_NCOL; ++c)
+          rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], (tile(m0 + u + D) + threadIdx.x) * RF_EPT, xb[u][c]);
       }
-#if RF_PRIO
-      m0 += D;
-#endif
+    }
+    // the last MB mod D full tiles are already in the ring
+#pragma unroll
+    for (int u = 0; u < D - 1; ++u)
+      if (m0 + u < MB) rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, (base0 + (m0 + u) * gstep + threadIdx.x) * RF_EPT, cst);
+    // the partial tile (at most one per workgroup: the next one starts past ng)
+    {
+      const int64_t gp = base0 + MB * gstep + threadIdx.x;
+      if (gp < ng) {
+        RF_T xp[RF_NCOL1][RF_EPT];
+#pragma unroll
+        for (int c = 0; c < RF_NCOL; ++c) rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], gp * RF_EPT, xp[c]);
+        rf_group<MODE, RF_EPT>(xp, k, acc, nbad, a, gp * RF_EPT, cst);
+      }
     }
 #if RF_PRIO
     __builtin_amdgcn_s_setprio(3);  // the hand-off that follows is on the critical path
 #endif
     const int64_t tail0 = ng * RF_EPT;
+    const int64_t gid = base0 + threadIdx.x;
     if (gid < n - tail0) {
       RF_T x1[RF_NCOL1][1];
 #pragma unroll

@@ -223,26 +223,30 @@ template <int NC> RF_DEV void cheb_prologue(const double* in, double lo, double 
   C[NC + 2] = -(hi + lo) / (hi - lo);
   for (int k = 1; k <= NC; ++k) C[NC + 2 + k] = in[k - 1];
 }
-// Linear form: d[j] = du/dc_j = T_j(x').
+// Evaluated with y = 2x' and the doubled basis T'_k = 2 T_k, which obey
+// T'_{k+1} = y T'_k - T'_{k-1} (T'_0 = 2, T'_1 = y): no separate doubling per
+// step; y is exactly twice the FP32 x' (scaling by 2 is exact), and
+// u = 1 + sum (c_k / 2) T'_k.  Linear form: d[j] = T'_{j+1} = 2 du/dc_{j+1};
+// the factor 1/2 is applied to the sums.
 template <typename T, int NC> struct ChebK {
-  T a, b;
-  T c[NC];
+  T a, b;      // 2 x (the affine map to [-1, 1])
+  T c[NC];     // c_k / 2
   RF_DEV ChebK load(const double* C) {
     ChebK k;
-    k.a = (T)C[NC + 1];
-    k.b = (T)C[NC + 2];
-    for (int j = 0; j < NC; ++j) k.c[j] = (T)C[NC + 3 + j];
+    k.a = (T)(2.0 * C[NC + 1]);
+    k.b = (T)(2.0 * C[NC + 2]);
+    for (int j = 0; j < NC; ++j) k.c[j] = (T)(0.5 * C[NC + 3 + j]);
     return k;
   }
 };
 template <typename T, int NC> RF_DEV T cheb_eval(T x, const ChebK<T, NC>& k, T* d) {
-  const T xp = fma(x, k.a, k.b);
-  T tkm = (T)1, tk = xp, u = (T)1;
+  const T y = fma(x, k.a, k.b);
+  T tkm = (T)2, tk = y, u = (T)1;
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     u = fma(k.c[j], tk, u);
     d[j] = tk;
-    const T tn = (T)2 * xp * tk - tkm;
+    const T tn = fma(y, tk, -tkm);
     tkm = tk;
     tk = tn;
   }

@@ -80,6 +80,7 @@ static std::string dscale(const Node& n, int off, int j) {
     case RF_OP_GAUSS: return "(" + c(4) + (j == 0 ? " * RF_GW_INV)" : " * RF_GW_INV2)");
     case RF_OP_EXP: return n.attrs[0] == 0.0 ? c(4) : "1.0";
     case RF_OP_BW: return j == 0 ? "2.0" : c(5);
+    case RF_OP_CHEB: return "0.5";
   }
   return "1.0";
 }
