@@ -219,23 +219,20 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
     rf_prologue(a.theta, cst, a);
     __syncthreads();
     const KS<RF_T> k = KS<RF_T>::load(cst);
-    int64_t m0 = 0;
-    for (; m0 + D <= MB; m0 += D) {
+    for (int64_t m0 = 0; m0 < MB; m0 += D) {
 #pragma unroll
       for (int u = 0; u < D; ++u) {
 #if RF_PRIO
         rf_prio_remaining(MB - (m0 + u), MB);
 #endif
-        rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, (base0 + (m0 + u) * gstep + threadIdx.x) * RF_EPT, cst);
+        // the last ring round may hold fewer than D full tiles (uniform test)
+        if (m0 + u < MB)
+          rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, (base0 + (m0 + u) * gstep + threadIdx.x) * RF_EPT, cst);
 #pragma unroll
         for (int c = 0; c < RF_NCOL; ++c)
           rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], (tile(m0 + u + D) + threadIdx.x) * RF_EPT, xb[u][c]);
       }
     }
-    // the last MB mod D full tiles are already in the ring
-#pragma unroll
-    for (int u = 0; u < D - 1; ++u)
-      if (m0 + u < MB) rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, (base0 + (m0 + u) * gstep + threadIdx.x) * RF_EPT, cst);
     // the partial tile (at most one per workgroup: the next one starts past ng)
     {
       const int64_t gp = base0 + MB * gstep + threadIdx.x;
@@ -409,6 +406,13 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
 // entry points, named by precision form: rf_k_{values,nll,grad}_{f32,f64}
 #define RF_CAT2(x, y) x##y
 #define RF_CAT(x, y) RF_CAT2(x, y)
-extern "C" __global__ __launch_bounds__(RF_BS) void RF_CAT(rf_k_values_, RF_PREC)(const RfArgs a) { rf_body<0>(a); }
-extern "C" __global__ __launch_bounds__(RF_BS) void RF_CAT(rf_k_nll_, RF_PREC)(const RfArgs a) { rf_body<1>(a); }
-extern "C" __global__ __launch_bounds__(RF_BS) void RF_CAT(rf_k_grad_, RF_PREC)(const RfArgs a) { rf_body<2>(a); }
+// RF_WPE: wavefronts per SIMD the register allocation must allow (0: the
+// compiler's choice)
+#if RF_WPE > 0
+#define RF_LB __launch_bounds__(RF_BS, RF_WPE)
+#else
+#define RF_LB __launch_bounds__(RF_BS)
+#endif
+extern "C" __global__ RF_LB void RF_CAT(rf_k_values_, RF_PREC)(const RfArgs a) { rf_body<0>(a); }
+extern "C" __global__ RF_LB void RF_CAT(rf_k_nll_, RF_PREC)(const RfArgs a) { rf_body<1>(a); }
+extern "C" __global__ RF_LB void RF_CAT(rf_k_grad_, RF_PREC)(const RfArgs a) { rf_body<2>(a); }

@@ -65,7 +65,12 @@ int choose_blocks(const rf_program* p) {
   // last workgroup to add
   const int64_t per = (int64_t)p->block * p->ept * 8;
   int64_t b = (p->n + per - 1) / per;
-  const int64_t cap = (int64_t)cu_count(p->device) * (p->resident < 4 ? p->resident : 4);
+  int bpc = 4;
+  if (const char* e = getenv("RFGPU_BPC")) {  // tuning override of the per-CU cap
+    const int v = atoi(e);
+    if (v >= 1 && v <= 32) bpc = v;
+  }
+  const int64_t cap = (int64_t)cu_count(p->device) * (p->resident < bpc ? p->resident : bpc);
   if (b > cap) b = cap;
   if (b < 1) b = 1;
   return (int)b;

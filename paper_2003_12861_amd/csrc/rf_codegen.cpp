@@ -184,6 +184,14 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     }
     o << "#define RF_LDSRED " << ldsred << "\n";
   }
+  {
+    int wpe = 0;
+    if (const char* e = getenv("RFGPU_WPE")) {  // tuning override
+      const int v = atoi(e);
+      if (v >= 1 && v <= 8) wpe = v;
+    }
+    o << "#define RF_WPE " << wpe << "\n";
+  }
   // programs with an MLP leaf run the event loop in whole wavefronts (the MLP
   // is wave-cooperative) and evaluate in FP32 only (no FP64 re-evaluation)
   o << "#define RF_WAVE_UNIFORM " << (L.has_mlp ? 1 : 0) << "\n";
