@@ -20,9 +20,9 @@
 // FP32 exponent (error ~5e-7) would be amplified ~50x in the gradient.  The
 // per-bin adjoint terms are FP32; each bin's Poisson term and every reduction
 // are FP64.  Cross-workgroup reduction (deterministic, in fixed order): one
-// compensated partial per workgroup and sum; the last workgroup of each
-// group of BN_G adds its group's partials (one thread per sum, all loads in
-// flight), and the last group to finish adds the group partials -- a few
+// FP64 partial per workgroup and sum; the last workgroup of each group of
+// BN_G adds its group's partials (one thread per sum, all loads in flight,
+// pairwise), and the last group to finish adds the group partials -- a few
 // memory round trips for the 62 sums of a 200-channel model.
 #include <hip/hip_runtime.h>
 
@@ -44,8 +44,8 @@ struct BinnedArgs {
   const float* Lp;     // [C][J][B][S]
   const float* Lm;     // [C][J][B][S]
   const float* nobs;   // [C][B]
-  double* part;        // [NS][nblk]
-  double* gpart;       // [NS][ngrp]
+  double* part;        // [nblk][NS]
+  double* gpart;       // [ngrp][NS]
   unsigned* ticket;    // [0] global, [64 (1 + g)] group g
   double* out;         // [nll, grad[1+J]]
   double* hout;        // optional copy in mapped host memory + completion word (or null)
@@ -60,7 +60,10 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   constexpr int NS = 2 + J;  // NLL, mu, alpha_1..J
   constexpr int NW = BN_BS / 64;
   constexpr int RS = ((J + 1) & 1) ? J + 1 : J + 2;  // odd row stride: conflict-free column reads
-  __shared__ float term[BN_BS][RS];  // column 0: d/dmu, column 1 + j: d/dalpha_j
+  // column 0: d/dmu, column 1 + j: d/dalpha_j; later reused as the staging
+  // buffer of the hand-off (BN_G x NS doubles fit: 512 (J + 1) >= 256 (J + 2) bytes)
+  __shared__ __align__(16) float term[BN_BS][RS];
+  __shared__ double bsum[NS];
   __shared__ double nu_s[BN_BS];
   __shared__ double r_s[BN_BS];
   __shared__ double nll_w[NW];
@@ -74,21 +77,34 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   const int64_t cb = live ? t / S : 0;  // c * B + b
   const int c = (int)(cb / B), b = (int)(cb % B);
 
+  // every load of the thread is issued before any arithmetic, without a
+  // branch (lanes past the end read cell 0 and drop the values): the
+  // compiler then keeps all of them in flight -- one memory round trip
+  const int64_t strideJ = (int64_t)B * S;
+  const int64_t base = ((int64_t)c * J) * strideJ + (int64_t)b * S + s;
+  float Tf = a.T[live ? t : 0];  // T laid out [C][B][S] == thread order
+  float nf = a.nobs[cb];
   // exponent E = sum_j |alpha_j| L^{sgn}_j; keep the 60 table values for the adjoint
   float Lv[J > 0 ? J : 1];
   double E = 0.0;
-  const int64_t strideJ = (int64_t)B * S;
-  const int64_t base = ((int64_t)c * J) * strideJ + (int64_t)b * S + s;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const double al = a.theta[1 + j];
-    const float* L = al >= 0.0 ? a.Lp : a.Lm;
-    Lv[j] = live ? L[base + j * strideJ] : 0.f;
+    const float* L = a.theta[1 + j] >= 0.0 ? a.Lp : a.Lm;
+    Lv[j] = L[base + j * strideJ];
   }
+  Tf = live ? Tf : 0.f;
+  nf = (live && s == 0) ? nf : 0.f;
 #pragma unroll
-  for (int j = 0; j < J; ++j) E = fma(fabs(a.theta[1 + j]), (double)Lv[j], E);
+  for (int j = 0; j < J; ++j) Lv[j] = live ? Lv[j] : 0.f;
+  {
+    // four independent chains: a quarter of the dependent FMA latency
+    double e4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < J; ++j) e4[j & 3] = fma(fabs(a.theta[1 + j]), (double)Lv[j], e4[j & 3]);
+    E = (e4[0] + e4[1]) + (e4[2] + e4[3]);
+  }
   const double mu = a.theta[0];
-  const double Tn = live ? (double)a.T[t] : 0.0;  // T laid out [C][B][S] == thread order
+  const double Tn = (double)Tf;
   const double base_nu = Tn * exp(E);             // nu without the signal strength
   const double nu = (s == 0) ? mu * base_nu : base_nu;
   nu_s[threadIdx.x] = live ? nu : 0.0;
@@ -99,7 +115,7 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   if (live && s == 0) {
     double tot = 0.0;
     for (int q = 0; q < S; ++q) tot += nu_s[threadIdx.x + q];
-    const double n = (double)a.nobs[cb];
+    const double n = (double)nf;
     nllt = tot - n * log(tot);
     const double r = 1.0 - n / tot;
     for (int q = 0; q < S; ++q) r_s[threadIdx.x + q] = r;
@@ -117,37 +133,88 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   const double wn = wave_sum(nllt);
   if ((threadIdx.x & 63) == 0) nll_w[threadIdx.x >> 6] = wn;
   __syncthreads();
-  // workgroup partials: column sums in FP64, fixed order
-  for (int k = threadIdx.x; k < NS; k += BN_BS) {
+  // workgroup partials in FP64, fixed order.  Sum 0 (the Poisson terms)
+  // from the wavefront sums; the term columns by rows of sixteen lanes: lane
+  // l of a row adds rows l, l + 16, ..., l + 112 of its column, and a DPP
+  // row sum completes it (eight columns per pass, every thread busy).
+  // Partials are stored workgroup-major (part[blk][NS], gpart[grp][NS]):
+  // one coalesced store per workgroup, and a group's partials are one
+  // contiguous block that the next level reads with coalesced loads.
+  static_assert(BN_BS == 128, "eight rows of sixteen lanes per pass");
+  static_assert(NS <= BN_BS, "one thread per sum");
+  static_assert(BN_G * NS * 8 <= BN_BS * RS * 4, "the staging buffer fits in the term table");
+  if (threadIdx.x == 0) {
     double hi = 0.0, lo = 0.0;
-    if (k == 0) {
-      for (int w = 0; w < NW; ++w) dd_add(hi, lo, nll_w[w], 0.0);
-    } else {
-      double sum = 0.0;
-      for (int row = 0; row < BN_BS; ++row) sum += (double)term[row][k - 1];
-      hi = sum;
-    }
-    __hip_atomic_store(&a.part[k * (int64_t)a.nblk + blockIdx.x], hi + lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int w = 0; w < NW; ++w) dd_add(hi, lo, nll_w[w], 0.0);
+    bsum[0] = hi + lo;
   }
+  {
+    const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
+#pragma unroll
+    for (int p = 0; p < (NS - 1 + 7) / 8; ++p) {
+      const int col = p * 8 + row;
+      const int cc = col < NS - 1 ? col : NS - 2;
+      double v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (double)term[l16 + 16 * i][cc];
+#pragma unroll
+      for (int w = 4; w >= 1; w >>= 1)
+#pragma unroll
+        for (int i = 0; i < w; ++i) v[i] += v[i + w];
+      const double rs = row_sum(v[0]);
+      if (l16 == 0 && col < NS - 1) bsum[1 + col] = rs;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NS; k += BN_BS)
+    __hip_atomic_store(&a.part[(int64_t)blockIdx.x * NS + k], bsum[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   rf_wait_stores();
   __syncthreads();
+  double* const stage = reinterpret_cast<double*>(&term[0][0]);  // BN_G x NS
+  // the sums of n partials (rows of NS, contiguous from src) into h[k] for
+  // k = threadIdx.x: coalesced loads into LDS (all in flight), then one
+  // thread per sum adds its column pairwise, BN_G rows per pass
+  auto column_sums = [&](const double* src, int n, double& h) {
+    h = 0.0;
+    for (int r0 = 0; r0 < n; r0 += BN_G) {
+      const int rn = n - r0 < BN_G ? n - r0 : BN_G;
+      const int m = rn * NS;
+      constexpr int PER = (BN_G * NS + BN_BS - 1) / BN_BS;
+      double v[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * BN_BS;
+        v[q] = __hip_atomic_load(&src[(int64_t)r0 * NS + (e < m ? e : m - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * BN_BS;
+        if (e < m) stage[e] = v[q];
+      }
+      __syncthreads();
+      if (threadIdx.x < NS) {
+        double c[BN_G];
+#pragma unroll
+        for (int q = 0; q < BN_G; ++q) c[q] = q < rn ? stage[q * NS + threadIdx.x] : 0.0;
+#pragma unroll
+        for (int w = BN_G / 2; w >= 1; w >>= 1)
+#pragma unroll
+          for (int q = 0; q < w; ++q) c[q] += c[q + w];
+        h += c[0];
+      }
+      __syncthreads();
+    }
+  };
   // level 1: the last workgroup of this group adds the group's partials
   const int g = (int)blockIdx.x / BN_G, g0 = g * BN_G;
   const int gn = a.nblk - g0 < BN_G ? a.nblk - g0 : BN_G;
   if (threadIdx.x == 0) last = (rf_take_ticket(a.ticket + 64 * (1 + g)) == (unsigned)(gn - 1));
   __syncthreads();
   if (!last) return;
-  for (int k = threadIdx.x; k < NS; k += BN_BS) {
-    double v[BN_G];
-#pragma unroll
-    for (int q = 0; q < BN_G; ++q)  // past the group's end: clamped to its last workgroup, skipped
-      v[q] = __hip_atomic_load(&a.part[k * (int64_t)a.nblk + g0 + (q < gn ? q : gn - 1)], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    double hi = 0.0, lo = 0.0;
-#pragma unroll
-    for (int q = 0; q < BN_G; ++q)
-      if (q < gn) dd_add(hi, lo, v[q], 0.0);
-    __hip_atomic_store(&a.gpart[k * (int64_t)a.ngrp + g], hi + lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  {
+    double h;
+    column_sums(a.part + (int64_t)g0 * NS, gn, h);
+    if (threadIdx.x < NS) __hip_atomic_store(&a.gpart[(int64_t)g * NS + threadIdx.x], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   rf_wait_stores();
   __syncthreads();
@@ -157,34 +224,35 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   }
   __syncthreads();
   if (!last) return;
-  // level 2: the group partials, 16 loads in flight per thread
-  for (int k = threadIdx.x; k < NS; k += BN_BS) {
-    double hi = 0.0, lo = 0.0;
-    for (int q0 = 0; q0 < a.ngrp; q0 += 16) {
-      double v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        v[u] = __hip_atomic_load(&a.gpart[k * (int64_t)a.ngrp + (q0 + u < a.ngrp ? q0 + u : a.ngrp - 1)],
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (q0 + u < a.ngrp) dd_add(hi, lo, v[u], 0.0);
-    }
-    fin[k] = hi + lo;
+  // level 2: the group partials
+  {
+    double h;
+    column_sums(a.gpart, a.ngrp, h);
+    if (threadIdx.x < NS) fin[threadIdx.x] = h;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double c2 = 0.0;
-    for (int j = 0; j < J; ++j) c2 += 0.5 * a.theta[1 + j] * a.theta[1 + j];
-    a.out[0] = fin[0] + c2;
-    a.out[1] = fin[1];
-    for (int j = 0; j < J; ++j) a.out[2 + j] = fin[2 + j] + a.theta[1 + j];
-    rf_reset_ticket(a.ticket);
-    if (a.hout) {
-      // host copy, then the completion word the host polls for
-      for (int j = 0; j < 2 + J; ++j) a.hout[j] = a.out[j];
-      __threadfence_system();
-      __hip_atomic_store((uint64_t*)(a.hout + 2 + BN_MAXJ), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (threadIdx.x < 64) {
+    // the result into LDS (one lane), then copied by the wavefront to the
+    // output and the host's mapped copy, then the completion word
+    __shared__ double res[2 + J];
+    if (threadIdx.x == 0) {
+      double c2 = 0.0;
+      for (int j = 0; j < J; ++j) c2 += 0.5 * a.theta[1 + j] * a.theta[1 + j];
+      res[0] = fin[0] + c2;
+      res[1] = fin[1];
+      for (int j = 0; j < J; ++j) res[2 + j] = fin[2 + j] + a.theta[1 + j];
+    }
+    for (int j = threadIdx.x; j < 2 + J; j += 64) {
+      const double v = res[j];
+      a.out[j] = v;
+      if (a.hout) a.hout[j] = v;
+    }
+    if (threadIdx.x == 0) {
+      rf_reset_ticket(a.ticket);
+      if (a.hout) {
+        __threadfence_system();
+        __hip_atomic_store((uint64_t*)(a.hout + 2 + BN_MAXJ), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
   }
 }

@@ -109,7 +109,7 @@ struct rf_program {
   int block = 256;  // threads per workgroup (compile-time constant of the kernel)
   int ept = 4;      // events per lane and step of the event loop (compile-time)
   int pfd = 3;      // groups in flight per lane (load ring depth, compile-time)
-  int tg = 8;       // ticket groups of the end-of-kernel hand-off (compile-time)
+  int tg = 16;      // ticket groups of the end-of-kernel hand-off (compile-time)
   int prio = 1;     // wavefront issue-priority policy of the event loop (compile-time)
   int resident = 4; // workgroups of the gradient kernel one CU holds at once (occupancy query)
   uint64_t seq = 0; // completion sequence number of synchronous calls
