@@ -134,6 +134,41 @@ struct BwdLds {
   float G[64];
 };
 
+// dW[o][i] += sum over the tile's 64 rows r of D[o][r] H[i][r] on MFMA:
+// M = o, N = i, K = r.  The operands come from the staged [row][feature]
+// tiles: lane l of K-step s provides D[32 mo + l%32][8 s + 4 (l/32) + 0..3]
+// (A) and H[32 ni + l%32][same rows] (B).  Both are FP32 and enter as three
+// bf16 parts each; the six products of parts whose orders add up to at most
+// two are accumulated (small ones first), which matches an FP32 product to
+// about 2^-24.  acc[mo][ni][v] = dW[mlp_feat(mo, v, l/32)][32 ni + l%32].
+RF_DEV void mlp_dw_mfma(const float* D, const float* H, rf_f32x16 (&acc)[2][2]) {
+  const int l = threadIdx.x & 63, hl = l >> 5, lr = l & 31;
+#pragma unroll 1  // one K-step at a time: unrolling spills
+  for (int s = 0; s < 8; ++s) {
+    rf_bf16x4 Ap[2][3], Bp[2][3];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float a4[4], b4[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a4[j] = D[(8 * s + 4 * hl + j) * TS + 32 * m + lr];
+        b4[j] = H[(8 * s + 4 * hl + j) * TS + 32 * m + lr];
+      }
+      mlp_split4<3>(a4, Ap[m]);
+      mlp_split4<3>(b4, Bp[m]);
+    }
+#pragma unroll
+    for (int ord = 2; ord >= 0; --ord)
+#pragma unroll
+      for (int qa = 0; qa <= ord; ++qa)
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+            acc[mo][ni] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(Ap[mo][qa], Bp[ni][ord - qa], acc[mo][ni], 0, 0, 0);
+  }
+}
+
 __global__ __launch_bounds__(64) void mlp_bwd_kernel(const unsigned short* w, const float* in, const float* dout,
                                                      int64_t n, float* part, float* din) {
   __shared__ MlpLds s;
@@ -141,7 +176,6 @@ __global__ __launch_bounds__(64) void mlp_bwd_kernel(const unsigned short* w, co
   mlp_load(w, s);
   const int lane = threadIdx.x, hl = lane >> 5, lr = lane & 31;
   float* P = part + (size_t)blockIdx.x * MLP_NW;
-  for (int k = lane; k < MLP_NW; k += 64) P[k] = 0.0f;
   __syncthreads();
   const int64_t ntile = (n + 63) / 64;
   for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
@@ -183,62 +217,85 @@ __global__ __launch_bounds__(64) void mlp_bwd_kernel(const unsigned short* w, co
       }
     }
     __syncthreads();
-    // weight gradients: lane = output unit o; sums over the 64 rows of the tile
+    // weight gradients, summed over the 64 rows of the tile; the block's
+    // first tile writes its partial, later ones add to it
+    const bool first = t == (int64_t)blockIdx.x;
+    auto put = [&](int k, float v) { P[k] = first ? v : P[k] + v; };
+    // layers 3 (d3 x h2) and 2 (d2 x h1) on MFMA (one layer at a time)
+#pragma unroll 1
+    for (int L = 2; L >= 1; --L) {
+      rf_f32x16 acc[2][2];
+#pragma unroll
+      for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[mo][ni][v] = 0.0f;
+      mlp_dw_mfma(b.DT[L], b.HT[L - 1], acc);
+      const int ow = L == 2 ? MLP_OW3 : MLP_OW2;
+#pragma unroll
+      for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) put(ow + mlp_feat(mo, v, hl) * 64 + 32 * ni + lr, acc[mo][ni][v]);
+    }
+    // biases of layers 2 and 3, layer 1 (d1 x u) and the output layer (g x
+    // h3): lane = unit o
     {
       const int o = lane;
-      // layers 3 (d3 x h2) and 2 (d2 x h1)
+      float bb2 = 0.0f, bb3 = 0.0f, acc1[6] = {0, 0, 0, 0, 0, 0}, bb1 = 0.0f, acc4 = 0.0f, accg = 0.0f;
+      for (int e = 0; e < 64; ++e) {
+        bb3 += b.DT[2][e * TS + o];
+        bb2 += b.DT[1][e * TS + o];
+        const float d = b.DT[0][e * TS + o];
+        bb1 += d;
 #pragma unroll
-      for (int L = 2; L >= 1; --L) {
-        const float* D = b.DT[L];
-        const float* H = b.HT[L - 1];
-        float accw[64], accb = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 64; ++i) accw[i] = 0.0f;
-        for (int e = 0; e < 64; ++e) {
-          const float d = D[e * TS + o];
-          accb += d;
-#pragma unroll
-          for (int i = 0; i < 64; ++i) accw[i] = fmaf(d, H[e * TS + i], accw[i]);
-        }
-        const int ow = L == 2 ? MLP_OW3 : MLP_OW2, ob = L == 2 ? MLP_OB3 : MLP_OB2;
-#pragma unroll
-        for (int i = 0; i < 64; ++i) P[ow + o * 64 + i] += accw[i];
-        P[ob + o] += accb;
+        for (int j = 0; j < 6; ++j) acc1[j] = fmaf(d, b.UT[e * 6 + j], acc1[j]);
+        acc4 = fmaf(b.G[e], b.HT[2][e * TS + o], acc4);
+        accg += b.G[e];
       }
-      // layer 1 (d1 x u)
-      {
-        float acc1[6] = {0, 0, 0, 0, 0, 0}, accb = 0.0f;
-        for (int e = 0; e < 64; ++e) {
-          const float d = b.DT[0][e * TS + o];
-          accb += d;
+      put(MLP_OB3 + o, bb3);
+      put(MLP_OB2 + o, bb2);
 #pragma unroll
-          for (int j = 0; j < 6; ++j) acc1[j] = fmaf(d, b.UT[e * 6 + j], acc1[j]);
-        }
-#pragma unroll
-        for (int j = 0; j < 6; ++j) P[MLP_OW1 + o * 6 + j] += acc1[j];
-        P[MLP_OB1 + o] += accb;
-      }
-      // output layer (g x h3): lane = input unit i
-      {
-        float acc4 = 0.0f, accg = 0.0f;
-        for (int e = 0; e < 64; ++e) {
-          acc4 = fmaf(b.G[e], b.HT[2][e * TS + o], acc4);
-          accg += b.G[e];
-        }
-        P[MLP_OW4 + o] += acc4;
-        if (o == 0) P[MLP_OB4] += accg;
-      }
+      for (int j = 0; j < 6; ++j) put(MLP_OW1 + o * 6 + j, acc1[j]);
+      put(MLP_OB1 + o, bb1);
+      put(MLP_OW4 + o, acc4);
+      if (o == 0) put(MLP_OB4, accg);
     }
     __syncthreads();
   }
 }
 
-__global__ void mlp_dw_reduce_kernel(const float* part, int nblk, float* dw) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= MLP_NW) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += (double)part[(size_t)b * MLP_NW + k];
-  dw[k] = (float)s;
+// dw[k] = sum over the blocks' partials, in a fixed order: wavefront w of a
+// 256-thread block adds partial rows w, w + 4, ... for 64 consecutive k (16
+// loads in flight per lane, pairwise), the four wavefront sums are added in
+// order
+__global__ __launch_bounds__(256) void mlp_dw_reduce_kernel(const float* part, int nblk, float* dw) {
+  __shared__ double ws[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  const int kc = k < MLP_NW ? k : MLP_NW - 1;
+  double h = 0.0;
+  for (int b0 = w; b0 < nblk; b0 += 4 * 16) {
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int b = b0 + 4 * q;
+      v[q] = part[(size_t)(b < nblk ? b : w) * MLP_NW + kc];
+    }
+    double d[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) d[q] = b0 + 4 * q < nblk ? (double)v[q] : 0.0;
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1)
+#pragma unroll
+      for (int q = 0; q < m; ++q) d[q] += d[q + m];
+    h += d[0];
+  }
+  ws[w][lane] = h;
+  __syncthreads();
+  if (w == 0 && k < MLP_NW) dw[k] = (float)((ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]));
 }
 
 __global__ void adam_kernel(float* w32, unsigned short* wbf, float* m, float* v, const float* g, int64_t n,
@@ -337,7 +394,7 @@ int rf_mlp_backward(const void* w, const float* in, const float* act, const floa
   (void)act;  // activations are recomputed from the inputs (cheaper than reading them back)
   if (!w || !dw || n < 0 || (n > 0 && (!in || !dout))) return fail(RF_E_INVALID, "bad arguments");
   const int64_t ntile = (n + 63) / 64;
-  int nblk = (int)(ntile < 512 ? (ntile > 0 ? ntile : 1) : 512);
+  int nblk = (int)(ntile < 512 ? ntile : 512);
   std::lock_guard<std::mutex> lk(g_ws_mu);
   if (g_part_n < (size_t)nblk * MLP_NW) {
     if (g_part) (void)hipFree(g_part);
@@ -347,11 +404,17 @@ int rf_mlp_backward(const void* w, const float* in, const float* act, const floa
     if (e != hipSuccess) return hip_fail(e, "hipMalloc mlp partials");
     g_part_n = (size_t)nblk * MLP_NW;
   }
-  hipLaunchKernelGGL(mlp_bwd_kernel, dim3(nblk), dim3(64), 0, (hipStream_t)stream, (const unsigned short*)w, in, dout,
-                     n, g_part, din);
-  int rc = launch_err("mlp_backward");
-  if (rc) return rc;
-  hipLaunchKernelGGL(mlp_dw_reduce_kernel, dim3((MLP_NW + 255) / 256), dim3(256), 0, (hipStream_t)stream, g_part, nblk,
+  if (ntile == 0) {
+    nblk = 0;  // no partials: the reduction writes zeros
+  } else {
+    // every block takes at least one tile (nblk <= ntile): its first tile
+    // writes the block's partial
+    hipLaunchKernelGGL(mlp_bwd_kernel, dim3(nblk), dim3(64), 0, (hipStream_t)stream, (const unsigned short*)w, in, dout,
+                       n, g_part, din);
+    int rc = launch_err("mlp_backward");
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(mlp_dw_reduce_kernel, dim3((MLP_NW + 63) / 64), dim3(256), 0, (hipStream_t)stream, g_part, nblk,
                      dw);
   return launch_err("mlp_dw_reduce");
 }
