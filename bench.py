@@ -8,15 +8,27 @@ per-event program and its adjoint, the deterministic reduction and the
 epilogue, and the result in host memory -- what a minimiser waits for on
 every iteration (synchronous call).  Events are seeded synthetic data already
 resident in HBM.  The headline value is the FP32+adjoint path; the plain FP64
-path is timed beside it, and both results are checked against the oracle
-(FP32: NLL relative error <= 1e-6, FP64: <= 1e-9).
+path is timed beside it where the model has one, and both results are checked
+against the oracle (FP32: NLL relative error <= 1e-6, FP64: <= 1e-9).
+
+Workloads (the default is the headline one):
+  gauss_cheb_1e7        1-D Gaussian + Chebyshev mixture, 1e7 events
+  decay_argus_5e7       2-D decay (x) resolution with mass peak, 5e7 events
+  bwcb_exact_1e7        Breit-Wigner (x) Crystal Ball by the exact 1024-point
+                        rule + exponential background, 1e7 events
+  bwcb_surrogate_1e7    the same model with the MLP surrogate of the signal
+                        (FP32; random-init weights: the cost does not depend
+                        on their values), 1e7 events
+  binned_200x4x100x60   binned templates: 200 channels x 4 samples x 100
+                        bins, 60 nuisance parameters (a step is one
+                        evaluation; the unit is evaluations/s)
 
 Prints ONE JSON line.  Extra fields:
-  roofline      the fused kernel against the VALU issue rate: algorithmic
-                lane-slots per event times events, over the kernel's average
-                launch duration (HIP events on the launch stream around K
-                back-to-back launches -- the duration a profiler reports per
-                launch);
+  roofline      the dominant kernel against its bound: VALU issue rate
+                (lane-slots), MFMA rate or HBM bandwidth; algorithmic work per
+                launch over the kernel's average launch duration (HIP events
+                on the launch stream around K back-to-back launches -- the
+                duration a profiler reports per launch);
   cpu_baseline  the oracle's throughput on the host, on a bounded sample.
 The Python garbage collector is paused inside the timed regions (a full
 collection of this process takes tens of milliseconds).
@@ -39,19 +51,20 @@ sys.path.insert(0, ROOT)
 # one full-rate (non-packed) VALU lane operation
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9  # 3.93e13
 HBM_PEAK_GBS = 8000.0
-
-WORKLOADS = {
-    "gauss_cheb_1e7": dict(n=10_000_000, seed=2),
-    "decay_argus_5e7": dict(n=50_000_000, seed=3),
-}
+MFMA_BF16_TFLOPS = 2500.0  # dense
 
 # Algorithmic VALU lane-slots per event of an NLL+gradient evaluation (a
 # transcendental counts 4: the quarter-rate unit), and bytes read per event.
 SLOTS = {
     "gauss_cheb_1e7": {"fp32": 48, "fp64": 90},
     "decay_argus_5e7": {"fp32": 165, "fp64": 400},
+    "bwcb_exact_1e7": {"fp32": 16400, "fp64": 16400},
 }
-BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "decay_argus_5e7": {"fp32": 8, "fp64": 16}}
+BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "decay_argus_5e7": {"fp32": 8, "fp64": 16},
+                   "bwcb_exact_1e7": {"fp32": 4, "fp64": 8}, "bwcb_surrogate_1e7": {"fp32": 4}}
+# surrogate: network multiply-adds per event (forward and input gradient)
+SURROGATE_MAC_PER_EVENT = 17300
+WORKLOADS = ("gauss_cheb_1e7", "decay_argus_5e7", "bwcb_exact_1e7", "bwcb_surrogate_1e7", "binned_200x4x100x60")
 
 
 def measured_traffic(workload, kernel, source):
@@ -72,24 +85,29 @@ def measured_traffic(workload, kernel, source):
 
 
 def make(workload):
+    """(spec, columns, truth theta, list of theta points, precisions, FP32 MLP weights or None)"""
     from paper_2003_12861_amd import synth, workloads
-    w = WORKLOADS[workload]
-    if workload.startswith("gauss_cheb"):
-        spec = workloads.spec_gauss_cheb()
-        cols = [synth.sample_gauss_cheb(w["n"], w["seed"])]
-        theta = workloads.truth_vector(synth.GAUSS_CHEB_TRUTH)
-        thetas = [synth.jitter_gauss_cheb(k) for k in range(100)]
-    else:
-        spec = workloads.spec_decay_argus()
-        cols = list(synth.sample_decay_argus(w["n"], w["seed"]))
-        theta = workloads.truth_vector(synth.DECAY_TRUTH)
-        thetas = [synth.jitter_decay(k) for k in range(10)]
-    return spec, cols, np.asarray(theta), thetas
+    if workload == "gauss_cheb_1e7":
+        return (workloads.spec_gauss_cheb(), [synth.sample_gauss_cheb(10_000_000, 2)],
+                np.asarray(workloads.truth_vector(synth.GAUSS_CHEB_TRUTH)),
+                [synth.jitter_gauss_cheb(k) for k in range(100)], ("fp32", "fp64"), None)
+    if workload == "decay_argus_5e7":
+        return (workloads.spec_decay_argus(), list(synth.sample_decay_argus(50_000_000, 3)),
+                np.asarray(workloads.truth_vector(synth.DECAY_TRUTH)),
+                [synth.jitter_decay(k) for k in range(10)], ("fp32", "fp64"), None)
+    truth = np.asarray(workloads.truth_vector(synth.BWCB_TRUTH))
+    rng = np.random.default_rng(11)
+    thetas = [truth * (1.0 + 0.002 * rng.uniform(-1, 1, truth.size)) for _ in range(10)]
+    x = synth.sample_bw_cb(10_000_000, 4)
+    if workload == "bwcb_exact_1e7":
+        return workloads.spec_bwcb(), [x], truth, thetas, ("fp32", "fp64"), None
+    from paper_2003_12861_amd import surrogate
+    return workloads.spec_bwcb(surrogate=True), [x], truth, thetas, ("fp32",), surrogate.init_weights(0)
 
 
-def timed_steps(prog, thetas, steps, torch, stream):
-    """K synchronous NLL+gradient evaluations; returns (seconds per step,
-    median seconds of one step)."""
+def timed_steps(call, thetas, steps, torch):
+    """K synchronous evaluations; returns (seconds per step, median seconds of
+    one step)."""
     per = np.zeros(steps)
     gc.collect()
     gc.disable()
@@ -98,7 +116,7 @@ def timed_steps(prog, thetas, steps, torch, stream):
         t0 = time.perf_counter()
         for i in range(steps):
             ti = time.perf_counter()
-            prog.nll_grad(thetas[i % len(thetas)], stream=stream)
+            call(thetas[i % len(thetas)])
             per[i] = time.perf_counter() - ti
         torch.cuda.synchronize()
         step_s = (time.perf_counter() - t0) / steps
@@ -107,7 +125,7 @@ def timed_steps(prog, thetas, steps, torch, stream):
     return step_s, float(np.median(per))
 
 
-def isolated_kernel(prog, thetas, reps, torch, stream):
+def isolated_kernel(call_async, thetas, reps, torch, stream):
     """Median duration of single launches (an event pair around each launch,
     the GPU idle before it): includes the dispatch of a launch from idle."""
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -116,7 +134,7 @@ def isolated_kernel(prog, thetas, reps, torch, stream):
     try:
         for i in range(reps):
             evs[i][0].record(stream)
-            prog.nll_grad_async(thetas[i % len(thetas)], stream=stream)
+            call_async(thetas[i % len(thetas)])
             evs[i][1].record(stream)
             torch.cuda.synchronize()
     finally:
@@ -124,7 +142,7 @@ def isolated_kernel(prog, thetas, reps, torch, stream):
     return float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e-3
 
 
-def pipelined_kernel(prog, thetas, reps, torch, stream):
+def pipelined_kernel(call_async, thetas, reps, torch, stream):
     """Average duration of back-to-back launches (no host round trip between
     them): the kernel's own time as a profiler reports it."""
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -133,7 +151,7 @@ def pipelined_kernel(prog, thetas, reps, torch, stream):
     try:
         a.record(stream)
         for i in range(reps):
-            prog.nll_grad_async(thetas[i % len(thetas)], stream=stream)
+            call_async(thetas[i % len(thetas)])
         b.record(stream)
         torch.cuda.synchronize()
     finally:
@@ -141,12 +159,77 @@ def pipelined_kernel(prog, thetas, reps, torch, stream):
     return a.elapsed_time(b) * 1e-3 / reps
 
 
+def time_path(call, call_async, thetas, args, torch, stream):
+    for i in range(args.warmup):
+        call(thetas[i % len(thetas)])
+    step_s, med_s = timed_steps(call, thetas, args.steps, torch)
+    kern_s = pipelined_kernel(call_async, thetas, max(20, min(args.steps, 200)), torch, stream)
+    iso_s = isolated_kernel(call_async, thetas, 20, torch, stream)
+    return dict(step_s=step_s, median_step_s=med_s, kernel_s=kern_s, isolated_s=iso_s)
+
+
+def oracle_rate(fn, n_per_call, budget_s):
+    """Units per second of fn() (n_per_call units each) over about budget_s seconds."""
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        fn()
+        reps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return n_per_call / dt, reps
+
+
+def run_binned(args, torch, stream):
+    from paper_2003_12861_amd import api, synth
+    C, S, B, J = 200, 4, 100, 60
+    d = synth.make_binned(5, C, S, B, J)
+    bn = api.Binned(d["T"], d["Tp"], d["Tm"], d["nobs"], stream=stream)
+    rng = np.random.default_rng(3)
+    thetas = [np.concatenate([[1.0 + 0.05 * rng.uniform(-1, 1)], rng.uniform(-0.5, 0.5, J)]) for _ in range(10)]
+    r = time_path(lambda th: bn.nll_grad(th, stream=stream), lambda th: bn.nll_grad_async(th, stream=stream),
+                  thetas, args, torch, stream)
+    nll, _ = bn.nll_grad(thetas[0], stream=stream)
+    cpu = None
+    check = {}
+    if not args.no_cpu_baseline:
+        from oracle import rfo
+        Lp = np.log(d["Tp"] / d["T"][:, :, None, :])
+        Lm = np.log(d["Tm"] / d["T"][:, :, None, :])
+        onll, _ = rfo.binned_nll(d["T"], Lp, Lm, d["nobs"], thetas[0])
+        rate, reps = oracle_rate(lambda: rfo.binned_nll(d["T"], Lp, Lm, d["nobs"], thetas[0]), 1, 5.0)
+        cpu = dict(value=rate, unit="evaluations/s", cores=1, kind="oracle",
+                   sample="%d full NLL+gradient evaluations (single-threaded C, -O2)" % reps,
+                   host=platform.processor() or platform.machine(), nproc=os.cpu_count())
+        check = dict(nll_rel_err=abs(nll - onll) / abs(onll), valid=bool(abs(nll - onll) <= 1e-6 * abs(onll)))
+    # bytes per evaluation: T, one of the two variation tables per (j, cell), n
+    nbytes = C * S * B * (1 + J) * 4 + C * B * 4
+    k = r["kernel_s"]
+    line = {
+        "metric": "NLL+gradient evaluations/s of the binned template model",
+        "value": 1.0 / r["step_s"], "unit": "evaluations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["step_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "channels": C, "samples": S, "bins": B, "nuisance": J,
+                   "precision": "fp32 terms, fp64 exponent and sums",
+                   "step": "one synchronous NLL+gradient evaluation (result in host memory)"},
+        "binned": {"kernel_ms": k * 1e3, "isolated_kernel_ms": r["isolated_s"] * 1e3,
+                   "median_step_ms": r["median_step_s"] * 1e3, **check},
+        "roofline": {"bound": "hbm", "kernel": "rf_binned_kernel<60>", "achieved": nbytes / k / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nbytes / k / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": nbytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="gauss_cheb_1e7", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="gauss_cheb_1e7", choices=WORKLOADS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 path (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -161,15 +244,24 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    spec, cols, theta, thetas = make(args.workload)
+    if args.workload.startswith("binned"):
+        run_binned(args, torch, stream)
+        return
+    spec, cols, theta, thetas, precs_avail, w32 = make(args.workload)
     n = cols[0].size
-    precs = (("fp32", api.FP32, torch.float32),) if args.fp32_only else (
-        ("fp32", api.FP32, torch.float32), ("fp64", api.FP64, torch.float64))
-    progs = {}
-    for key, prec, dt in precs:
+    precs = [p for p in precs_avail if not (args.fp32_only and p == "fp64")]
+    pmap = {"fp32": (api.FP32, torch.float32), "fp64": (api.FP64, torch.float64)}
+    wbf = torch.tensor(w32, device="cuda").to(torch.bfloat16) if w32 is not None else None
+
+    def program(key, columns):
+        prec, dt = pmap[key]
         p = api.Program(api.Graph.from_spec(spec), precision=prec)
-        p.bind([torch.tensor(c, dtype=dt, device="cuda") for c in cols])
-        progs[key] = p
+        p.bind([torch.tensor(c, dtype=dt, device="cuda") for c in columns])
+        if wbf is not None:
+            p.bind_weights("sig", wbf)
+        return p
+
+    progs = {key: program(key, cols) for key in precs}
 
     if args.calib_copy:
         a = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -180,43 +272,54 @@ def main():
 
     res = {}
     for key, p in progs.items():
-        for i in range(args.warmup):
-            p.nll_grad(thetas[i % len(thetas)], stream=stream)
-        step_s, med_s = timed_steps(p, thetas, args.steps, torch, stream)
-        kern_s = pipelined_kernel(p, thetas, max(20, min(args.steps, 200)), torch, stream)
-        iso_s = isolated_kernel(p, thetas, 20, torch, stream)
-        res[key] = dict(step_s=step_s, median_step_s=med_s, kernel_s=kern_s, isolated_s=iso_s)
+        res[key] = time_path(lambda th, p=p: p.nll_grad(th, stream=stream),
+                             lambda th, p=p: p.nll_grad_async(th, stream=stream), thetas, args, torch, stream)
 
-    # validity of both paths against the oracle at the truth point
+    # validity of each path against the oracle at the truth point
     cpu = None
-    check = {key: p.nll_grad(theta) for key, p in progs.items()}
+    heavy = args.workload.startswith("bwcb")  # the convolution models: checked on a prefix
     if not args.no_cpu_baseline:
         from oracle import rfo
-        om, otop, _ = rfo.from_spec(spec)
-        # bounded sample: full-size oracle NLL+gradient evaluations for ~10 s
-        t0 = time.perf_counter()
-        reps = 0
-        while True:
-            onll, og, oga, _ = om.nll_ex(otop, theta, cols)
-            reps += 1
-            if time.perf_counter() - t0 > 10.0:
-                break
-        cpu_s = (time.perf_counter() - t0) / reps
-        cpu = dict(value=n / cpu_s, unit="events/s", cores=1, kind="oracle",
-                   sample="%d full NLL+gradient evaluations of the %d-event workload (single-threaded C, -O2)" % (reps, n),
+        om, otop, oids = rfo.from_spec(spec)
+        if wbf is not None:
+            om.set_mlp_weights(oids["sig"], wbf.float().double().cpu().numpy())
+        # bounded sample: oracle evaluations for ~10 s (whole workload, or a
+        # 20000-event prefix of the convolution models, scaled to events/s)
+        sample = [c[:20000] for c in cols] if heavy else cols
+        onll, og, oga, _ = om.nll_ex(otop, theta, sample)
+        rate, reps = oracle_rate(lambda: om.nll_ex(otop, theta, sample), sample[0].size, 10.0)
+        what = ("%d NLL+gradient evaluations of a %d-event prefix" % (reps, sample[0].size) if heavy
+                else "%d full NLL+gradient evaluations of the %d-event workload" % (reps, n))
+        cpu = dict(value=rate, unit="events/s", cores=1, kind="oracle",
+                   sample=what + " (single-threaded C, -O2)",
                    host=platform.processor() or platform.machine(), nproc=os.cpu_count())
-        for key, tol in (("fp32", 1e-6), ("fp64", 1e-9)):
-            if key not in check:
-                continue
-            nll, g, _ = check[key]
+        tol = {"fp32": 2e-6 if wbf is not None else 1e-6, "fp64": 1e-9}
+        for key, p in progs.items():
+            q = program(key, sample) if heavy else p
+            nll, g, _ = q.nll_grad(theta)
             res[key]["nll_rel_err"] = abs(nll - onll) / abs(onll)
             res[key]["grad_scaled_err"] = float(np.max(np.abs(g - og) / oga))
-            res[key]["valid"] = bool(res[key]["nll_rel_err"] <= tol)
+            res[key]["valid"] = bool(res[key]["nll_rel_err"] <= tol[key])
+            res[key]["checked_on"] = ("a %d-event prefix" % sample[0].size) if heavy else "all events"
 
     k32 = res["fp32"]["kernel_s"]
-    slots = SLOTS[args.workload]["fp32"]
-    achieved = n * slots / k32 / 1e12
-    peak = VALU_SLOTS_PER_S / 1e12
+    if wbf is not None:
+        achieved = n * 2 * SURROGATE_MAC_PER_EVENT / k32 / 1e12
+        roof = {"bound": "mfma", "kernel": "rf_k_grad_f32 (MLP leaf) with its normalisation kernel",
+                "achieved": achieved, "peak": MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / MFMA_BF16_TFLOPS, "traffic": None,
+                "flop_per_event": 2 * SURROGATE_MAC_PER_EVENT, "events_per_launch": n}
+    else:
+        slots = SLOTS[args.workload]["fp32"]
+        achieved = n * slots / k32 / 1e12
+        peak = VALU_SLOTS_PER_S / 1e12
+        roof = {"bound": "alu", "kernel": "rf_k_grad_f32", "achieved": achieved, "peak": peak,
+                "unit": "Tslot/s", "frac": achieved / peak,
+                "traffic": measured_traffic(args.workload, "rf_k_grad_f32", progs["fp32"].source),
+                "source_sha1": hashlib.sha1(progs["fp32"].source.encode()).hexdigest(),
+                "slots_per_event": slots, "events_per_launch": n}
+    roof["bytes_per_event"] = BYTES_PER_EVENT[args.workload]["fp32"]
+    roof["hbm_GBps"] = n * BYTES_PER_EVENT[args.workload]["fp32"] / k32 / 1e9
     line = {
         "metric": "events/s for NLL+gradient (FP32+adjoint vs FP64 plain) at <=1e-6 rel NLL error",
         "value": n / res["fp32"]["step_s"],
@@ -229,7 +332,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic",
+        "data": "synthetic" + ("; random-init surrogate weights" if wbf is not None else ""),
         "config": {"workload": args.workload, "events": n, "precision": "fp32+adjoint, fp64 reductions",
                    "step": "one synchronous NLL+gradient evaluation (result in host memory)"},
         "fp32": {"kernel_ms": k32 * 1e3, "isolated_kernel_ms": res["fp32"]["isolated_s"] * 1e3,
@@ -237,24 +340,21 @@ def main():
                  "kernel_events_per_s": n / k32,
                  "nll_rel_err": res["fp32"].get("nll_rel_err"),
                  "grad_scaled_err": res["fp32"].get("grad_scaled_err"),
-                 "valid": res["fp32"].get("valid")},
-        "roofline": {"bound": "alu", "kernel": "rf_k_grad_f32", "achieved": achieved, "peak": peak,
-                     "unit": "Tslot/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(args.workload, "rf_k_grad_f32", progs["fp32"].source),
-                     "source_sha1": hashlib.sha1(progs["fp32"].source.encode()).hexdigest(),
-                     "slots_per_event": slots, "events_per_launch": n,
-                     "bytes_per_event": BYTES_PER_EVENT[args.workload]["fp32"],
-                     "hbm_GBps": n * BYTES_PER_EVENT[args.workload]["fp32"] / k32 / 1e9},
+                 "valid": res["fp32"].get("valid"),
+                 "checked_on": res["fp32"].get("checked_on")},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     if "fp64" in res:
+        slots64 = SLOTS.get(args.workload, {}).get("fp64")
         line["fp64_plain"] = {"value": n / res["fp64"]["step_s"], "unit": "events/s",
                               "ms_per_step": res["fp64"]["step_s"] * 1e3,
                               "median_step_ms": res["fp64"]["median_step_s"] * 1e3,
                               "kernel_ms": res["fp64"]["kernel_s"] * 1e3,
                               "isolated_kernel_ms": res["fp64"]["isolated_s"] * 1e3,
                               "kernel_events_per_s": n / res["fp64"]["kernel_s"],
-                              "roofline_frac": n * SLOTS[args.workload]["fp64"] / res["fp64"]["kernel_s"] / VALU_SLOTS_PER_S,
+                              "roofline_frac": (n * slots64 / res["fp64"]["kernel_s"] / VALU_SLOTS_PER_S
+                                                if slots64 else None),
                               "nll_rel_err": res["fp64"].get("nll_rel_err"),
                               "grad_scaled_err": res["fp64"].get("grad_scaled_err"),
                               "valid": res["fp64"].get("valid")}
