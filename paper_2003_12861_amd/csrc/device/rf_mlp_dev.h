@@ -458,12 +458,17 @@ template <bool GRAD> RF_DEV float mlp_base(float x, const MlpBase& B, float* db)
 }
 
 template <int BS>
-__device__ void mlp_prologue(const double* q, const double* box, const double* nh,
+__device__ void mlp_prologue(const double* q, const double* box, const double* nh, int nrow,
                              const unsigned short* w, double* C, MlpLds& s, float* qs) {
   mlp_setup<BS>(q, box, w, s, qs);
   if (threadIdx.x == 0) {
-    C[0] = 1.0 / nh[0];
-    for (int j = 0; j < 5; ++j) C[1 + j] = nh[1 + j] / nh[0];
+    // nh: nrow rows [Nhat, dNhat/dq1..5], one per workgroup of the
+    // normalisation kernel, added in row order
+    double t[6] = {0, 0, 0, 0, 0, 0};
+    for (int r = 0; r < nrow; ++r)
+      for (int j = 0; j < 6; ++j) t[j] += nh[r * 6 + j];
+    C[0] = 1.0 / t[0];
+    for (int j = 0; j < 5; ++j) C[1 + j] = t[1 + j] / t[0];
     C[6] = 2.0 / (box[1] - box[0]);               // du0/dx
     C[7] = -(q[0] + box[0]) * C[6] - 1.0;          // u0 = x C[6] + C[7]
     mlp_base_constants(q, C);

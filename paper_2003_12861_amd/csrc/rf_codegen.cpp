@@ -305,9 +305,9 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     if (n.op == RF_OP_MLP) {
       o << "    const double box[12] = {";
       for (int j = 0; j < 12; ++j) o << (j ? ", " : "") << dstr(n.attrs[j]);
-      o << "};\n    mlp_prologue<RF_BS>(in, box, a.aux + " << L.aux_off[id] + 2 * (int)n.attrs[12]
-        << ", (const unsigned short*)a.weights, cst + " << L.cst_off[id] << ", rf_mlp_" << id << ", rf_mlpqs_" << id
-        << ");\n  }\n";
+      o << "};\n    mlp_prologue<RF_BS>(in, box, a.aux + " << L.aux_off[id] + 2 * (int)n.attrs[12] << ", "
+        << mlp_renorm_blocks((int)n.attrs[12]) << ", (const unsigned short*)a.weights, cst + " << L.cst_off[id]
+        << ", rf_mlp_" << id << ", rf_mlpqs_" << id << ");\n  }\n";
       continue;
     }
     o << "    numconv_prologue<RF_BS, RF_TABT>(in, " << dstr(ob.lo) << ", " << dstr(ob.hi) << ", "

@@ -186,7 +186,8 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
 
   // auxiliary FP64 inputs: the Gauss-Legendre rule of every convolution leaf
   // (on its window); for an MLP leaf the rule on x's range followed by the
-  // six normalisation values [Nhat, dNhat/dq1..5] written before each launch
+  // normalisation values [Nhat, dNhat/dq1..5] of every workgroup of the
+  // normalisation kernel, written before each launch
   L.aux_off.assign(N, -1);
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
@@ -199,7 +200,7 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
       const int K = (int)g[id].attrs[12];
       const Node& ob = g[g[id].in[0]];
       L.aux_off[id] = (int)L.aux.size();
-      L.aux.resize(L.aux.size() + 2 * K + 6, 0.0);
+      L.aux.resize(L.aux.size() + 2 * K + 6 * mlp_renorm_blocks(K), 0.0);
       gauss_legendre(K, ob.lo, ob.hi, &L.aux[L.aux_off[id]], &L.aux[L.aux_off[id] + K]);
     }
   }

@@ -89,6 +89,9 @@ void eval_paramlike(const Lowered& L, const double* theta, std::vector<double>& 
 // surrogate normalisation kernel (rf_mlp.hip)
 int mlp_renorm_launch(const void* w, const double* q5, const double* box12, const double* grid, int K, double* out,
                       void* stream);
+// workgroups of the normalisation kernel for a K-point rule (256 points each);
+// its partial sums take 6 doubles per workgroup
+inline int mlp_renorm_blocks(int K) { return (K + 255) / 256; }
 
 // Gauss-Legendre rule (host)
 void gauss_legendre(int K, double lo, double hi, double* x, double* w);

@@ -32,20 +32,24 @@ namespace {
 struct RenormArgs {
   const unsigned short* w;
   const double* grid;  // [x_0..x_{K-1}, w_0..w_{K-1}] on x's range
-  double* out;         // [Nhat, dNhat/dq1..5]
+  double* out;         // per workgroup: [Nhat, dNhat/dq1..5] of its tiles
   int K;
   int pad_;
   double q[5];
   double box[12];
 };
 
-__global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
+// workgroups of four wavefronts, one 64-point tile of the rule per
+// wavefront (MLP_RN_TILES tiles per workgroup); each workgroup writes its six
+// sums, which the fused kernel's prologue adds in workgroup order
+#define RN_W 4
+__global__ __launch_bounds__(64 * RN_W) void mlp_renorm_kernel(const RenormArgs a) {
   __shared__ MlpLds s;
   __shared__ float qs[5];
-  __shared__ double red[4][6];
-  __shared__ float sav[4 * 32 * 64];
+  __shared__ double red[RN_W][6];
+  __shared__ float sav[RN_W * 32 * 64];
   __shared__ double bc[MB_END];
-  mlp_setup<256>(a.q, a.box, a.w, s, qs);
+  mlp_setup<64 * RN_W>(a.q, a.box, a.w, s, qs);
   if (threadIdx.x == 0) mlp_base_constants(a.q, bc);
   __syncthreads();
   const MlpBase B = MlpBase::make(bc);
@@ -54,7 +58,7 @@ __global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
   const double xsd = 2.0 / (a.box[1] - a.box[0]);
   const float xs = (float)xsd;
   const float xo = (float)(-(a.q[0] + a.box[0]) * xsd - 1.0);  // u0 = map of (x - q1)
-  for (int t = wid; t * 64 < a.K; t += 4) {  // wave-uniform loop
+  for (int t = blockIdx.x * RN_W + wid; t * 64 < a.K; t += gridDim.x * RN_W) {  // wave-uniform loop
     MLP_TILE_BARRIER();
     const int g = t * 64 + lane;
     const bool valid = g < a.K;
@@ -77,8 +81,8 @@ __global__ __launch_bounds__(256) void mlp_renorm_kernel(const RenormArgs a) {
   __syncthreads();
   if (threadIdx.x < 6) {
     double h = 0.0, l = 0.0;
-    for (int w = 0; w < 4; ++w) dd_add(h, l, red[w][threadIdx.x], 0.0);
-    a.out[threadIdx.x] = h + l;
+    for (int w = 0; w < RN_W; ++w) dd_add(h, l, red[w][threadIdx.x], 0.0);
+    a.out[blockIdx.x * 6 + threadIdx.x] = h + l;
   }
 }
 
@@ -365,7 +369,7 @@ int mlp_renorm_launch(const void* w, const double* q5, const double* box12, cons
   a.K = K;
   for (int j = 0; j < 5; ++j) a.q[j] = q5[j];
   for (int j = 0; j < 12; ++j) a.box[j] = box12[j];
-  hipLaunchKernelGGL(mlp_renorm_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL(mlp_renorm_kernel, dim3(mlp_renorm_blocks(K)), dim3(64 * RN_W), 0, (hipStream_t)stream, a);
   return launch_err("mlp_renorm");
 }
 }  // namespace rf
