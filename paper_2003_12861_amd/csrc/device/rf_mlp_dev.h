@@ -8,10 +8,14 @@
 // v_mfma_f32_32x32x8bf16_1k: element v of lane l in block (mb, eb) holds
 //     feature 32 mb + 8 (v/4) + 4 (l/32) + v%4,   row 32 eb + l%32,
 // stored at h[(2 mb + eb) * 16 + v].  For out = W h the A operand is a
-// fragment of W (lane l: W[32 mo + l%32][8 s + 4 (l/32) + 0..3]) read from
-// LDS, and the B operand of K-step s is exactly h[(2 (s/4) + eb) * 16 +
-// 4 (s%4) + 0..3] -- the layer output is already the next layer's input
-// layout, so nothing moves between layers.
+// fragment of W read from LDS and the B operand is a run of 8 registers of h.
+// The 64x64 products use v_mfma_f32_32x32x16_bf16 (K = 16 per instruction).
+// The sum over K does not depend on how the 16 features of a K-step are
+// ordered, as long as A and B order them alike; K-step t takes, in lane half
+// hl = l/32, the eight features 16 t + 4 hl + {0..3} and 16 t + 8 + 4 hl +
+// {0..3}, which are exactly h[(2 (t/2) + eb) * 16 + 8 (t%2) + 0..7] -- the
+// layer output is already the next layer's input layout, so nothing moves
+// between layers.
 //
 // Precision.  Weights are exact in bf16.  FP32 activations enter the MFMA
 // as NSPLIT bf16 parts h = h1 + h2 (+ h3) (each part the round-to-nearest
@@ -21,6 +25,8 @@
 #pragma once
 
 typedef short rf_bf16x4 __attribute__((ext_vector_type(4)));
+typedef short rf_bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 rf_bf16v8 __attribute__((ext_vector_type(8)));  // MFMA operand type
 typedef float rf_f32x16 __attribute__((ext_vector_type(16)));
 
 // Compiler barrier (memory clobber) between the engine's phases and at the top
@@ -34,10 +40,13 @@ typedef float rf_f32x16 __attribute__((ext_vector_type(16)));
 enum { MLP_OW1 = 0, MLP_OB1 = 384, MLP_OW2 = 448, MLP_OB2 = 4544, MLP_OW3 = 4608,
        MLP_OB3 = 8704, MLP_OW4 = 8768, MLP_OB4 = 8832 };
 
-struct MlpLds {
+// Per-feature float arrays start on 16-byte boundaries: a lane reads the
+// coefficients of its four consecutive features (mlp_c4) in one LDS access.
+struct __attribute__((aligned(16))) MlpLds {
   unsigned short W2[64 * MLP_RS], W3[64 * MLP_RS];    // [out][in]
   unsigned short W2T[64 * MLP_RS], W3T[64 * MLP_RS];  // [in][out]
   float W1[64 * 6], b1[64], b2[64], b3[64], W4[64];
+  float w10[64];    // column 0 of W1 (the per-row input of the surrogate leaf)
   float c1[64];     // layer-1 pre-activation of the row-independent inputs
   float gq[5][64];  // d(layer-1 pre-activation o)/d q_j of the surrogate leaf
   float b4;
@@ -66,6 +75,12 @@ RF_DEV void mlp_load(const unsigned short* __restrict__ w, MlpLds& s) {
 }
 
 RF_DEV int mlp_feat(int mb, int v, int hl) { return 32 * mb + 8 * (v >> 2) + 4 * hl + (v & 3); }
+
+// c[mlp_feat(mb, 4 vq + 0..3, hl)] of a 16-byte aligned per-feature LDS array
+RF_DEV float4 mlp_c4(const float* c, int mb, int vq, int hl) {
+  return *(const float4*)&c[32 * mb + 8 * vq + 4 * hl];
+}
+RF_DEV float f4at(const float4& f, int i) { return i == 0 ? f.x : i == 1 ? f.y : i == 2 ? f.z : f.w; }
 
 RF_DEV float mlp_tanh(float x) {
   // tanh(x) = sign(x) (1 - t) / (1 + t), t = exp(-2|x|) = 2^(-2 log2(e) |x|)
@@ -102,6 +117,19 @@ RF_DEV void mlp_split4(const float* h, rf_bf16x4* part) {
   }
 }
 
+// the same for 8 activations; parts as whole 16-byte MFMA operands
+template <int NS>
+RF_DEV void mlp_split8(const float* h, rf_bf16v8* part) {
+  rf_bf16x4 lo[NS], hi[NS];
+  mlp_split4<NS>(h, lo);
+  mlp_split4<NS>(h + 4, hi);
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const rf_bf16x8 p = __builtin_shufflevector(lo[q], hi[q], 0, 1, 2, 3, 4, 5, 6, 7);
+    part[q] = __builtin_bit_cast(rf_bf16v8, p);
+  }
+}
+
 // Event blocks.  A call processes NEB blocks of 32 rows starting at block
 // eb0 (NEB = 2, eb0 = 0: the whole 64-row tile; NEB = 1: one half, which
 // halves the registers holding activations).  Tile storage of a layer:
@@ -119,24 +147,29 @@ RF_DEV void mlp_layer(const unsigned short* W, const float* b, const float* in, 
 #pragma unroll
   for (int mo = 0; mo < 2; ++mo)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float bv = MODE == 0 ? b[mlp_feat(mo, v, hl)] : 0.0f;
+    for (int vq = 0; vq < 4; ++vq) {
+      const float4 b4 = MODE == 0 ? mlp_c4(b, mo, vq, hl) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-      for (int e = 0; e < NEB; ++e) acc[mo][e][v] = bv;
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < NEB; ++e) acc[mo][e][4 * vq + i] = f4at(b4, i);
     }
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    rf_bf16x4 Bq[NEB][NS];
+  for (int t = 0; t < 4; ++t) {
+    rf_bf16v8 Bq[NEB][NS];
 #pragma unroll
-    for (int e = 0; e < NEB; ++e) mlp_split4<NS>(in + (NEB * (s >> 2) + e) * 16 + 4 * (s & 3), Bq[e]);
+    for (int e = 0; e < NEB; ++e) mlp_split8<NS>(in + (NEB * (t >> 1) + e) * 16 + 8 * (t & 1), Bq[e]);
 #pragma unroll
     for (int mo = 0; mo < 2; ++mo) {
-      const rf_bf16x4 A = *(const rf_bf16x4*)&W[(32 * mo + lr) * MLP_RS + 8 * s + 4 * hl];
+      const unsigned short* wr = &W[(32 * mo + lr) * MLP_RS + 16 * t + 4 * hl];
+      const rf_bf16x8 a8 = __builtin_shufflevector(*(const rf_bf16x4*)wr, *(const rf_bf16x4*)(wr + 8), 0, 1, 2, 3,
+                                                   4, 5, 6, 7);
+      const rf_bf16v8 A = __builtin_bit_cast(rf_bf16v8, a8);
 #pragma unroll
       for (int q = NS - 1; q >= 0; --q)  // small parts first
 #pragma unroll
         for (int e = 0; e < NEB; ++e)
-          acc[mo][e] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, Bq[e][q], acc[mo][e], 0, 0, 0);
+          acc[mo][e] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bq[e][q], acc[mo][e], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -172,11 +205,13 @@ RF_DEV void mlp_layer1_u0(const MlpLds& s, float u0, float* h1, int eb0) {
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int o = mlp_feat(mb, v, hl);
-      const float w = s.W1[o * 6], c = s.c1[o];
+    for (int vq = 0; vq < 4; ++vq) {
+      const float4 w4 = mlp_c4(s.w10, mb, vq, hl), c4 = mlp_c4(s.c1, mb, vq, hl);
 #pragma unroll
-      for (int e = 0; e < NEB; ++e) h1[(NEB * mb + e) * 16 + v] = mlp_tanh(fmaf(w, ue[e], c));
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < NEB; ++e)
+          h1[(NEB * mb + e) * 16 + 4 * vq + i] = mlp_tanh(fmaf(f4at(w4, i), ue[e], f4at(c4, i)));
     }
 }
 
@@ -235,13 +270,60 @@ RF_DEV float mlp_rowdot(const float* coef, int stride, const float* t, int eb0) 
   return mine + recv;
 }
 
+// NJ row sums in one pass over the tile: out[j] = sum over features f of
+// coef[j * jstride + f] * t[f][row] for this lane's own row (valid on the
+// same lanes as mlp_rowdot); each coefficient array is contiguous in f and
+// 16-byte aligned, so four features' coefficients come in one LDS access
+template <int NEB, int NJ>
+RF_DEV void mlp_rowdots(const float* coef, int jstride, const float* t, int eb0, float* out) {
+  MLP_TILE_BARRIER();
+  const int hl = (threadIdx.x & 63) >> 5;
+  float p[NJ][NEB];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int e = 0; e < NEB; ++e) p[j][e] = 0.f;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int vq = 0; vq < 4; ++vq) {
+      float4 c[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) c[j] = mlp_c4(coef + j * jstride, mb, vq, hl);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+          for (int e = 0; e < NEB; ++e)
+            p[j][e] = fmaf(f4at(c[j], i), t[(NEB * mb + e) * 16 + 4 * vq + i], p[j][e]);
+    }
+  const int ep = 1 - hl - eb0, eo = hl - eb0;
+  float send[NJ], mine[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    send[j] = 0.f;
+    mine[j] = 0.f;
+#pragma unroll
+    for (int e = 0; e < NEB; ++e) {
+      if (e == ep) send[j] = p[j][e];
+      if (e == eo) mine[j] = p[j][e];
+    }
+  }
+  MLP_TILE_BARRIER();
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) out[j] = mine[j] + __shfl_xor(send[j], 32, 64);
+}
+
 // forward of a row tile; keeps the hidden activations for a backward pass
 template <int NS>
 RF_DEV float mlp_forward_full(const MlpLds& s, const float* u, float* h1, float* h2, float* h3) {
   mlp_layer1_full(s, u, h1);
   mlp_layer<NS, 0, 2>(s.W2, s.b2, h1, h2);
   mlp_layer<NS, 0, 2>(s.W3, s.b3, h2, h3);
-  return mlp_rowdot<2>(s.W4, 1, h3, 0) + s.b4;
+  float o;
+  mlp_rowdots<2, 1>(s.W4, 0, h3, 0, &o);
+  return o + s.b4;
 }
 
 // backward from the per-row cotangent g of the output (whole tile): leaves
@@ -253,13 +335,15 @@ RF_DEV void mlp_backward(const MlpLds& s, float g, float* h1, float* h2, float* 
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float w = s.W4[mlp_feat(mb, v, hl)];
+    for (int vq = 0; vq < 4; ++vq) {
+      const float4 w4 = mlp_c4(s.W4, mb, vq, hl);
 #pragma unroll
-      for (int eb = 0; eb < 2; ++eb) {
-        float& t = h3[(2 * mb + eb) * 16 + v];
-        t = ge[eb] * w * (1.0f - t * t);
-      }
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int eb = 0; eb < 2; ++eb) {
+          float& t = h3[(2 * mb + eb) * 16 + 4 * vq + i];
+          t = ge[eb] * f4at(w4, i) * (1.0f - t * t);
+        }
     }
   mlp_layer<NS, 1, 2>(s.W3T, nullptr, h3, h2);
   mlp_layer<NS, 1, 2>(s.W2T, nullptr, h2, h1);
@@ -280,7 +364,9 @@ RF_DEV float mlp_forward_half(const MlpLds& s, float u0, int eb0, float* sav, fl
 #pragma unroll
   for (int i = 0; i < 32; ++i) sav[i * 64 + l] = 1.0f - h1[i] * h1[i];
   mlp_layer<NS, 0, 1>(s.W3, s.b3, h2, h3);
-  return mlp_rowdot<1>(s.W4, 1, h3, eb0) + s.b4;
+  float o;
+  mlp_rowdots<1, 1>(s.W4, 0, h3, eb0, &o);
+  return o + s.b4;
 }
 template <int NS>
 RF_DEV void mlp_backward_half(const MlpLds& s, int eb0, const float* sav, float* d1, float* h2, float* h3) {
@@ -288,10 +374,13 @@ RF_DEV void mlp_backward_half(const MlpLds& s, int eb0, const float* sav, float*
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float w = s.W4[mlp_feat(mb, v, hl)];
-      float& t = h3[mb * 16 + v];
-      t = w * (1.0f - t * t);  // cotangent 1 per row
+    for (int vq = 0; vq < 4; ++vq) {
+      const float4 w4 = mlp_c4(s.W4, mb, vq, hl);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float& t = h3[mb * 16 + 4 * vq + i];
+        t = f4at(w4, i) * (1.0f - t * t);  // cotangent 1 per row
+      }
     }
   mlp_layer<NS, 1, 1>(s.W3T, nullptr, h3, h2);
   mlp_layer<NS, 2, 1>(s.W2T, sav, h2, d1);
@@ -313,11 +402,11 @@ RF_DEV float mlp_eval_u0(const MlpLds& s, float u0, float* sav, float* dq) {
     if (GRAD) {
       float d1[32];
       mlp_backward_half<NS>(s, eb0, sav, d1, h2, h3);
+      float gj[5];
+      mlp_rowdots<1, 5>(&s.gq[0][0], 64, d1, eb0, gj);
 #pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        const float gj = mlp_rowdot<1>(s.gq[j], 1, d1, eb0);
-        if (hl == eb0) dq[j] = gj;
-      }
+      for (int j = 0; j < 5; ++j)
+        if (hl == eb0) dq[j] = gj[j];
     }
   }
   return out;
@@ -346,6 +435,7 @@ __device__ void mlp_setup(const double* q, const double* box, const unsigned sho
       c = fmaf(s.W1[o * 6 + j], (float)u, c);
     }
     s.c1[o] = c;
+    s.w10[o] = s.W1[o * 6];
   }
   if (threadIdx.x < 5) qs[threadIdx.x] = (float)(2.0 / (box[2 * threadIdx.x + 3] - box[2 * threadIdx.x + 2]));
   // u0 = map of (x - q1): q1 enters layer 1 through u0 as well

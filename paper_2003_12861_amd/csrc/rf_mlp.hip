@@ -124,7 +124,9 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const unsigned short* w, c
     if (ACT) mlp_store_act(act, t, n, 1, hb);
     mlp_layer<MLP_SPLIT, 0, 2>(s.W3, s.b3, hb, ha);
     if (ACT) mlp_store_act(act, t, n, 2, ha);
-    const float sv = mlp_rowdot<2>(s.W4, 1, ha, 0) + s.b4;
+    float sv;
+    mlp_rowdots<2, 1>(s.W4, 0, ha, 0, &sv);
+    sv += s.b4;
     if (valid) out[row] = sv;
   }
 }
