@@ -46,8 +46,10 @@ struct __attribute__((aligned(16))) MlpLds {
   unsigned short W2[64 * MLP_RS], W3[64 * MLP_RS];    // [out][in]
   unsigned short W2T[64 * MLP_RS], W3T[64 * MLP_RS];  // [in][out]
   float W1[64 * 6], b1[64], b2[64], b3[64], W4[64];
-  float w10[64];    // column 0 of W1 (the per-row input of the surrogate leaf)
-  float c1[64];     // layer-1 pre-activation of the row-independent inputs
+  // the surrogate leaf's layer 1, scaled by MLP_TANH_K: pre-activation
+  // = (w10 u0 + c1) / MLP_TANH_K
+  float w10[64];    // column 0 of W1 (the per-row input u0)
+  float c1[64];     // the part from the row-independent inputs and the bias
   float gq[5][64];  // d(layer-1 pre-activation o)/d q_j of the surrogate leaf
   float b4;
 };
@@ -82,52 +84,59 @@ RF_DEV float4 mlp_c4(const float* c, int mb, int vq, int hl) {
 }
 RF_DEV float f4at(const float4& f, int i) { return i == 0 ? f.x : i == 1 ? f.y : i == 2 ? f.z : f.w; }
 
-RF_DEV float mlp_tanh(float x) {
-  // tanh(x) = sign(x) (1 - t) / (1 + t), t = exp(-2|x|) = 2^(-2 log2(e) |x|)
-  const float t = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(x));
-  const float r = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
-  return copysignf(r, x);
+// tanh(x) = sign(x) (1 - t) / (1 + t), t = exp(-2|x|) = 2^(-|y|), y = 2 log2(e) x;
+// with q = 1/(1 + t) the quotient is q - t q, one fused multiply-add.
+// mlp_tanh_y takes y (inputs already scaled by 2 log2(e)).
+#define MLP_TANH_K 2.8853900817779268f
+RF_DEV float mlp_tanh_y(float y) {
+  const float t = __builtin_amdgcn_exp2f(-fabsf(y));
+  const float q = __builtin_amdgcn_rcpf(1.0f + t);
+  return copysignf(fmaf(-t, q, q), y);
 }
+RF_DEV float mlp_tanh(float x) { return mlp_tanh_y(MLP_TANH_K * x); }
 
-// split 4 consecutive activations into NS bf16 parts (packed as MFMA B
-// operands).  Scalar __bf16 values only: element access into vectors of
-// __bf16 combined with a bit cast returned the wrong element.
-RF_DEV short bf16_rne_bits(float x) {
-  const __bf16 h = (__bf16)x;  // round to nearest even (v_cvt_pk_bf16_f32)
-  return __builtin_bit_cast(short, h);
+// Split 2 K consecutive activations into NS bf16 parts, packed as MFMA
+// operands.  Pairs are converted together (one v_cvt_pk_bf16_f32, round to
+// nearest even) and only whole packed words are reinterpreted: element 2 k of
+// an operand is the low half of word k.
+typedef float rf_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 rf_bf16v2 __attribute__((ext_vector_type(2)));
+typedef unsigned rf_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned rf_u32x4 __attribute__((ext_vector_type(4)));
+RF_DEV unsigned bf16_pack2(float a, float b) {
+  const rf_f32x2 f = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f, rf_bf16v2));
 }
-RF_DEV float bf16_bits_f32(short b) { return __uint_as_float(((unsigned)(unsigned short)b) << 16); }
-
+template <int NS, int K>
+RF_DEV void mlp_split_words(const float* h, unsigned (&w)[NS][K]) {
+  float r[2 * K];
+#pragma unroll
+  for (int i = 0; i < 2 * K; ++i) r[i] = h[i];
+#pragma unroll
+  for (int q = 0; q < NS; ++q)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      w[q][k] = bf16_pack2(r[2 * k], r[2 * k + 1]);
+      if (q + 1 < NS) {  // residuals: exact in FP32
+        r[2 * k] -= __uint_as_float(w[q][k] << 16);
+        r[2 * k + 1] -= __uint_as_float(w[q][k] & 0xffff0000u);
+      }
+    }
+}
 template <int NS>
 RF_DEV void mlp_split4(const float* h, rf_bf16x4* part) {
-  float r0 = h[0], r1 = h[1], r2 = h[2], r3 = h[3];
+  unsigned w[NS][2];
+  mlp_split_words<NS, 2>(h, w);
 #pragma unroll
-  for (int q = 0; q < NS; ++q) {
-    const short p0 = bf16_rne_bits(r0), p1 = bf16_rne_bits(r1);
-    const short p2 = bf16_rne_bits(r2), p3 = bf16_rne_bits(r3);
-    if (q + 1 < NS) {
-      r0 -= bf16_bits_f32(p0);
-      r1 -= bf16_bits_f32(p1);
-      r2 -= bf16_bits_f32(p2);
-      r3 -= bf16_bits_f32(p3);
-    }
-    rf_bf16x4 p;
-    p[0] = p0; p[1] = p1; p[2] = p2; p[3] = p3;
-    part[q] = p;
-  }
+  for (int q = 0; q < NS; ++q) part[q] = __builtin_bit_cast(rf_bf16x4, (rf_u32x2){w[q][0], w[q][1]});
 }
-
-// the same for 8 activations; parts as whole 16-byte MFMA operands
 template <int NS>
 RF_DEV void mlp_split8(const float* h, rf_bf16v8* part) {
-  rf_bf16x4 lo[NS], hi[NS];
-  mlp_split4<NS>(h, lo);
-  mlp_split4<NS>(h + 4, hi);
+  unsigned w[NS][4];
+  mlp_split_words<NS, 4>(h, w);
 #pragma unroll
-  for (int q = 0; q < NS; ++q) {
-    const rf_bf16x8 p = __builtin_shufflevector(lo[q], hi[q], 0, 1, 2, 3, 4, 5, 6, 7);
-    part[q] = __builtin_bit_cast(rf_bf16v8, p);
-  }
+  for (int q = 0; q < NS; ++q)
+    part[q] = __builtin_bit_cast(rf_bf16v8, (rf_u32x4){w[q][0], w[q][1], w[q][2], w[q][3]});
 }
 
 // Event blocks.  A call processes NEB blocks of 32 rows starting at block
@@ -194,7 +203,8 @@ RF_DEV float mlp_rowval(float own, int eb) {
   return eb == hl ? own : other;
 }
 
-// layer 1 when only input 0 varies per row: a = W1[:,0] u0 + c1
+// layer 1 when only input 0 varies per row: a = W1[:,0] u0 + c (w10, c1 hold
+// MLP_TANH_K times these coefficients)
 template <int NEB>
 RF_DEV void mlp_layer1_u0(const MlpLds& s, float u0, float* h1, int eb0) {
   MLP_TILE_BARRIER();
@@ -211,7 +221,7 @@ RF_DEV void mlp_layer1_u0(const MlpLds& s, float u0, float* h1, int eb0) {
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int e = 0; e < NEB; ++e)
-          h1[(NEB * mb + e) * 16 + 4 * vq + i] = mlp_tanh(fmaf(f4at(w4, i), ue[e], f4at(c4, i)));
+          h1[(NEB * mb + e) * 16 + 4 * vq + i] = mlp_tanh_y(fmaf(f4at(w4, i), ue[e], f4at(c4, i)));
     }
 }
 
@@ -434,8 +444,8 @@ __device__ void mlp_setup(const double* q, const double* box, const unsigned sho
       const double u = 2.0 * (q[j - 1] - box[2 * j]) / (box[2 * j + 1] - box[2 * j]) - 1.0;
       c = fmaf(s.W1[o * 6 + j], (float)u, c);
     }
-    s.c1[o] = c;
-    s.w10[o] = s.W1[o * 6];
+    s.c1[o] = MLP_TANH_K * c;
+    s.w10[o] = MLP_TANH_K * s.W1[o * 6];
   }
   if (threadIdx.x < 5) qs[threadIdx.x] = (float)(2.0 / (box[2 * threadIdx.x + 3] - box[2 * threadIdx.x + 2]));
   // u0 = map of (x - q1): q1 enters layer 1 through u0 as well
