@@ -210,6 +210,17 @@ int rf_adam_step(float* dev_w32, void* dev_w_bf16, float* dev_m, float* dev_v,
 /* dout[i] = scale * (out[i] - target[i])  (gradient of a mean-squared error) */
 int rf_mse_grad(const float* dev_out, const float* dev_target, int64_t n, float scale, float* dev_dout,
                 void* stream);
+/* One optimiser step of the surrogate's training, as rf_mlp_forward +
+ * rf_mse_grad (scale 2/batch) + rf_mlp_backward + rf_adam_step on a batch of
+ * rows, in two kernel launches.  Batch row r is row dev_idx[r] of dev_in
+ * (n x 6) and dev_target (dev_idx NULL: rows 0..batch-1); the indices must lie
+ * in the arrays (not checked).  The loss is the mean of (s - target)^2 over
+ * the batch.  dev_w_bf16 (read by the step, then refreshed), dev_w32, dev_m,
+ * dev_v are updated in place; dev_dw (8833 FP32, may be NULL) receives the
+ * summed gradient.  Asynchronous on the stream. */
+int rf_mlp_train_step(void* dev_w_bf16, float* dev_w32, float* dev_m, float* dev_v, const float* dev_in,
+                      const float* dev_target, const int64_t* dev_idx, int64_t batch, float lr,
+                      float beta1, float beta2, float eps, int32_t step, float* dev_dw, void* stream);
 /* Exact log p_sig of the Breit-Wigner (x) Crystal Ball signal at per-sample
  * parameters: dev_xq[n][6] = (x, M, Gamma, sigma, alpha, n) FP64; the same
  * K-point Gauss-Legendre rule on [ylo, yhi] and normalisation over [lo, hi]

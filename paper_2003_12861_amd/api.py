@@ -70,6 +70,7 @@ _OPTIONAL = {
     "rf_mlp_backward": ([_P, _P, _P, _P, _I64, _P, _P, _P], _I32),
     "rf_adam_step": ([_P, _P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P], _I32),
     "rf_mse_grad": ([_P, _P, _I64, _F, _P, _P], _I32),
+    "rf_mlp_train_step": ([_P, _P, _P, _P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P, _P], _I32),
     "rf_bwcb_logpdf": ([_P, _I64, _I32, _D, _D, _D, _D, _P, _P], _I32),
 }
 
@@ -410,6 +411,15 @@ def adam_step(w32, w_bf16, m, v, g, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, 
 
 def mse_grad(out, target, scale, dout, stream=None):
     check(rf_mse_grad(_vp(out), _vp(target), out.numel(), scale, _vp(dout), _stream(stream)))
+
+
+def mlp_train_step(w_bf16, w32, m, v, u, target, idx, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, dw=None,
+                   stream=None):
+    """One Adam step on the mean-squared error of MLP(u[idx]) against target[idx]
+    (idx: int64 indices of the batch rows, or None for all rows of u)."""
+    batch = idx.numel() if idx is not None else u.shape[0]
+    check(rf_mlp_train_step(_vp(w_bf16), _vp(w32), _vp(m), _vp(v), _vp(u), _vp(target), _vp(idx), batch, lr, beta1,
+                            beta2, eps, step, _vp(dw), _stream(stream)))
 
 
 def bwcb_logpdf(xq, K, window, x_range, out=None, stream=None):

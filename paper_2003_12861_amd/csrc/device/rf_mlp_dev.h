@@ -101,7 +101,6 @@ RF_DEV float mlp_tanh(float x) { return mlp_tanh_y(MLP_TANH_K * x); }
 // an operand is the low half of word k.
 typedef float rf_f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 rf_bf16v2 __attribute__((ext_vector_type(2)));
-typedef unsigned rf_u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned rf_u32x4 __attribute__((ext_vector_type(4)));
 RF_DEV unsigned bf16_pack2(float a, float b) {
   const rf_f32x2 f = {a, b};
@@ -122,13 +121,6 @@ RF_DEV void mlp_split_words(const float* h, unsigned (&w)[NS][K]) {
         r[2 * k + 1] -= __uint_as_float(w[q][k] & 0xffff0000u);
       }
     }
-}
-template <int NS>
-RF_DEV void mlp_split4(const float* h, rf_bf16x4* part) {
-  unsigned w[NS][2];
-  mlp_split_words<NS, 2>(h, w);
-#pragma unroll
-  for (int q = 0; q < NS; ++q) part[q] = __builtin_bit_cast(rf_bf16x4, (rf_u32x2){w[q][0], w[q][1]});
 }
 template <int NS>
 RF_DEV void mlp_split8(const float* h, rf_bf16v8* part) {
@@ -249,41 +241,11 @@ RF_DEV void mlp_layer1_full(const MlpLds& s, const float* u, float* h1) {
     }
 }
 
-// sum over features of coef[f] * t[f][row] for this lane's own row; valid on
-// lanes whose row lies in the call's blocks (l/32 in [eb0, eb0 + NEB))
-template <int NEB>
-RF_DEV float mlp_rowdot(const float* coef, int stride, const float* t, int eb0) {
-  MLP_TILE_BARRIER();
-  const int hl = (threadIdx.x & 63) >> 5;
-  float p[NEB];
-#pragma unroll
-  for (int e = 0; e < NEB; ++e) p[e] = 0.f;
-#pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float c = coef[mlp_feat(mb, v, hl) * stride];
-#pragma unroll
-      for (int e = 0; e < NEB; ++e) p[e] = fmaf(c, t[(NEB * mb + e) * 16 + v], p[e]);
-    }
-  // the partner lane (l ^ 32) holds the other half of the features of the
-  // same rows; it needs the block of its own row, 1 - hl
-  const int ep = 1 - hl - eb0, eo = hl - eb0;
-  float send = 0.f, mine = 0.f;
-#pragma unroll
-  for (int e = 0; e < NEB; ++e) {
-    if (e == ep) send = p[e];
-    if (e == eo) mine = p[e];
-  }
-  MLP_TILE_BARRIER();
-  const float recv = __shfl_xor(send, 32, 64);
-  return mine + recv;
-}
-
 // NJ row sums in one pass over the tile: out[j] = sum over features f of
-// coef[j * jstride + f] * t[f][row] for this lane's own row (valid on the
-// same lanes as mlp_rowdot); each coefficient array is contiguous in f and
-// 16-byte aligned, so four features' coefficients come in one LDS access
+// coef[j * jstride + f] * t[f][row] for this lane's own row, valid on lanes
+// whose row lies in the call's blocks (l/32 in [eb0, eb0 + NEB)); each
+// coefficient array is contiguous in f and 16-byte aligned, so four
+// features' coefficients come in one LDS access
 template <int NEB, int NJ>
 RF_DEV void mlp_rowdots(const float* coef, int jstride, const float* t, int eb0, float* out) {
   MLP_TILE_BARRIER();
@@ -308,6 +270,8 @@ RF_DEV void mlp_rowdots(const float* coef, int jstride, const float* t, int eb0,
           for (int e = 0; e < NEB; ++e)
             p[j][e] = fmaf(f4at(c[j], i), t[(NEB * mb + e) * 16 + 4 * vq + i], p[j][e]);
     }
+  // the partner lane (l ^ 32) holds the other half of the features of the
+  // same rows; it needs the block of its own row, 1 - hl
   const int ep = 1 - hl - eb0, eo = hl - eb0;
   float send[NJ], mine[NJ];
 #pragma unroll
@@ -325,42 +289,78 @@ RF_DEV void mlp_rowdots(const float* coef, int jstride, const float* t, int eb0,
   for (int j = 0; j < NJ; ++j) out[j] = mine[j] + __shfl_xor(send[j], 32, 64);
 }
 
-// forward of a row tile; keeps the hidden activations for a backward pass
-template <int NS>
-RF_DEV float mlp_forward_full(const MlpLds& s, const float* u, float* h1, float* h2, float* h3) {
-  mlp_layer1_full(s, u, h1);
-  mlp_layer<NS, 0, 2>(s.W2, s.b2, h1, h2);
-  mlp_layer<NS, 0, 2>(s.W3, s.b3, h2, h3);
-  float o;
-  mlp_rowdots<2, 1>(s.W4, 0, h3, 0, &o);
-  return o + s.b4;
+// ---- 32-row tiles for training: one wavefront per 32 rows, lanes l and
+// l + 32 hold the two halves of the features of the same row l % 32 (the
+// NEB = 1 tile layout).  Per element the arithmetic is that of the 64-row
+// functions above, in the same order.
+
+// sum over features of coef[f * stride] * t[f] for the lane's row, on both
+// lanes of the row
+template <int STRIDE>
+RF_DEV float mlp_rowdot_pair(const float* coef, const float* t) {
+  MLP_TILE_BARRIER();
+  const int hl = (threadIdx.x & 63) >> 5;
+  float p = 0.f;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int vq = 0; vq < 4; ++vq) {
+      float c[4];
+      if (STRIDE == 1) {
+        const float4 c4 = mlp_c4(coef, mb, vq, hl);
+        c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = coef[mlp_feat(mb, 4 * vq + i, hl) * STRIDE];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) p = fmaf(c[i], t[mb * 16 + 4 * vq + i], p);
+    }
+  MLP_TILE_BARRIER();
+  return p + __shfl_xor(p, 32, 64);
 }
 
-// backward from the per-row cotangent g of the output (whole tile): leaves
-// d1 = dL/d(pre-activation 1), d2, d3 in place of h1, h2, h3
-template <int NS>
-RF_DEV void mlp_backward(const MlpLds& s, float g, float* h1, float* h2, float* h3) {
+// layer 1 with all six inputs of the lane's own row
+RF_DEV void mlp_layer1_pair(const MlpLds& s, const float* u, float* h1) {
   const int hl = (threadIdx.x & 63) >> 5;
-  const float ge[2] = {mlp_rowval(g, 0), mlp_rowval(g, 1)};
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int o = mlp_feat(mb, v, hl);
+      float a = s.b1[o];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) a = fmaf(s.W1[o * 6 + j], u[j], a);
+      h1[mb * 16 + v] = mlp_tanh(a);
+    }
+}
+
+template <int NS>
+RF_DEV float mlp_forward_pair(const MlpLds& s, const float* u, float* h1, float* h2, float* h3) {
+  mlp_layer1_pair(s, u, h1);
+  mlp_layer<NS, 0, 1>(s.W2, s.b2, h1, h2);
+  mlp_layer<NS, 0, 1>(s.W3, s.b3, h2, h3);
+  return mlp_rowdot_pair<1>(s.W4, h3) + s.b4;
+}
+
+// backward from the row's output cotangent g: d1, d2, d3 replace h1, h2, h3
+template <int NS>
+RF_DEV void mlp_backward_pair(const MlpLds& s, float g, float* h1, float* h2, float* h3) {
+  const int hl = (threadIdx.x & 63) >> 5;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int vq = 0; vq < 4; ++vq) {
       const float4 w4 = mlp_c4(s.W4, mb, vq, hl);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int eb = 0; eb < 2; ++eb) {
-          float& t = h3[(2 * mb + eb) * 16 + 4 * vq + i];
-          t = ge[eb] * f4at(w4, i) * (1.0f - t * t);
-        }
+      for (int i = 0; i < 4; ++i) {
+        float& t = h3[mb * 16 + 4 * vq + i];
+        t = g * f4at(w4, i) * (1.0f - t * t);
+      }
     }
-  mlp_layer<NS, 1, 2>(s.W3T, nullptr, h3, h2);
-  mlp_layer<NS, 1, 2>(s.W2T, nullptr, h2, h1);
+  mlp_layer<NS, 1, 1>(s.W3T, nullptr, h3, h2);
+  mlp_layer<NS, 1, 1>(s.W2T, nullptr, h2, h1);
 }
-
-// d(output)/d(input j) of the own row from d1 = dL/d(pre-activation 1)
-RF_DEV float mlp_input_grad(const MlpLds& s, const float* d1, int j) { return mlp_rowdot<2>(s.W1 + j, 6, d1, 0); }
 
 // Half-tile forward/backward for the surrogate leaf (NEB = 1, block eb0):
 // layer 1's derivative factor (1 - h1^2) is parked in the wavefront's LDS

@@ -14,6 +14,11 @@
 //                             gradients from LDS-staged tiles, one private
 //                             partial per workgroup, summed in a fixed order
 //   update   rf_adam_step     Adam on FP32 master weights, BF16 copy (RNE)
+//   step     rf_mlp_train_step  one optimiser step in two launches: the
+//                             backward kernel gathers its batch rows by index
+//                             and forms the loss cotangent from the forward
+//                             pass it runs anyway; Adam runs inside the
+//                             reduction of the weight gradients
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -140,86 +145,112 @@ struct BwdLds {
   float G[64];
 };
 
-// dW[o][i] += sum over the tile's 64 rows r of D[o][r] H[i][r] on MFMA:
-// M = o, N = i, K = r.  The operands come from the staged [row][feature]
-// tiles: lane l of K-step s provides D[32 mo + l%32][8 s + 4 (l/32) + 0..3]
-// (A) and H[32 ni + l%32][same rows] (B).  Both are FP32 and enter as three
-// bf16 parts each; the six products of parts whose orders add up to at most
-// two are accumulated (small ones first), which matches an FP32 product to
-// about 2^-24.  acc[mo][ni][v] = dW[mlp_feat(mo, v, l/32)][32 ni + l%32].
-RF_DEV void mlp_dw_mfma(const float* D, const float* H, rf_f32x16 (&acc)[2][2]) {
+// dW[o][i] += sum over the tile's 64 rows r of D[o][r] H[i][r] on MFMA
+// (v_mfma_f32_32x32x16_bf16): M = o, N = i, K = r.  The operands come from
+// the staged [row][feature] tiles: in K-step t, lane l provides rows 16 t +
+// 8 (l/32) + 0..7 of D[32 mo + l%32][.] (A) and of H[32 ni + l%32][.] (B);
+// both operands order the 16 rows of a step alike.  Both are FP32 and enter
+// as three bf16 parts each; the six products of parts whose orders add up to
+// at most two are accumulated (small ones first), which matches an FP32
+// product to about 2^-24.  acc[m][ni][v] = dW[mlp_feat(mo0 + m, v, l/32)][32 ni + l%32]
+// for the NM output row blocks mo0 .. mo0 + NM - 1.
+template <int NM>
+RF_DEV void mlp_dw_mfma(const float* D, const float* H, int mo0, rf_f32x16 (&acc)[NM][2]) {
   const int l = threadIdx.x & 63, hl = l >> 5, lr = l & 31;
 #pragma unroll 1  // one K-step at a time: unrolling spills
-  for (int s = 0; s < 8; ++s) {
-    rf_bf16x4 Ap[2][3], Bp[2][3];
+  for (int t = 0; t < 4; ++t) {
+    rf_bf16v8 Ap[NM][3], Bp[2][3];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      float a8[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a8[j] = D[(16 * t + 8 * hl + j) * TS + 32 * (mo0 + m) + lr];
+      mlp_split8<3>(a8, Ap[m]);
+    }
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      float a4[4], b4[4];
+      float b8[8];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        a4[j] = D[(8 * s + 4 * hl + j) * TS + 32 * m + lr];
-        b4[j] = H[(8 * s + 4 * hl + j) * TS + 32 * m + lr];
-      }
-      mlp_split4<3>(a4, Ap[m]);
-      mlp_split4<3>(b4, Bp[m]);
+      for (int j = 0; j < 8; ++j) b8[j] = H[(16 * t + 8 * hl + j) * TS + 32 * m + lr];
+      mlp_split8<3>(b8, Bp[m]);
     }
 #pragma unroll
     for (int ord = 2; ord >= 0; --ord)
 #pragma unroll
       for (int qa = 0; qa <= ord; ++qa)
 #pragma unroll
-        for (int mo = 0; mo < 2; ++mo)
+        for (int m = 0; m < NM; ++m)
 #pragma unroll
           for (int ni = 0; ni < 2; ++ni)
-            acc[mo][ni] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(Ap[mo][qa], Bp[ni][ord - qa], acc[mo][ni], 0, 0, 0);
+            acc[m][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ap[m][qa], Bp[ni][ord - qa], acc[m][ni], 0, 0, 0);
   }
 }
 
-__global__ __launch_bounds__(64) void mlp_bwd_kernel(const unsigned short* w, const float* in, const float* dout,
-                                                     int64_t n, float* part, float* din) {
+// Cotangent source of the backward kernel: given per row (dout), or the
+// mean-squared-error gradient scale (s - target[src]) of the forward output s
+// (target != nullptr); rows are in[src], src = idx ? idx[row] : row.
+struct BwdRows {
+  const float* dout;
+  const int64_t* idx;
+  const float* target;
+  float scale;
+};
+
+// A workgroup of two wavefronts takes a 64-row tile: wavefront wv runs the
+// forward and backward passes of rows 32 wv .. 32 wv + 31 (32-row tiles),
+// both stage their activations and cotangents in LDS, then wavefront wv
+// forms the weight-gradient rows 32 wv .. 32 wv + 31 of the two hidden
+// layers and one share of the per-unit sums.
+#define BWD_W 2
+template <bool FUSED>
+__global__ __launch_bounds__(64 * BWD_W) void mlp_bwd_kernel(const unsigned short* w, const float* in, const BwdRows r,
+                                                             int64_t n, float* part, float* din) {
   __shared__ MlpLds s;
   __shared__ BwdLds b;
   mlp_load(w, s);
-  const int lane = threadIdx.x, hl = lane >> 5, lr = lane & 31;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, hl = lane >> 5, lr = lane & 31;
+  const int er = 32 * wv + lr;  // the lane's row in the tile
   float* P = part + (size_t)blockIdx.x * MLP_NW;
   __syncthreads();
   const int64_t ntile = (n + 63) / 64;
   for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
     MLP_TILE_BARRIER();
-    const int64_t row = t * 64 + lane;
+    const int64_t row = t * 64 + er;
     const bool valid = row < n;
+    const int64_t src = !valid ? 0 : (FUSED && r.idx) ? r.idx[row] : row;
     float u[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) u[j] = valid ? in[row * 6 + j] : 0.0f;
-    const float g = valid ? dout[row] : 0.0f;
-    float h[3][64];
-    (void)mlp_forward_full<MLP_SPLIT>(s, u, h[0], h[1], h[2]);
+    for (int j = 0; j < 6; ++j) u[j] = valid ? in[src * 6 + j] : 0.0f;
+    // the row's target (or cotangent) is read before the forward pass, so its
+    // latency overlaps the network
+    const float gin = !valid ? 0.0f : FUSED ? r.target[src] : r.dout[row];
+    float h[3][32];
+    const float sv = mlp_forward_pair<MLP_SPLIT>(s, u, h[0], h[1], h[2]);
+    const float g = FUSED && valid ? r.scale * (sv - gin) : gin;
     // stage forward activations, inputs and output cotangents
 #pragma unroll
     for (int L = 0; L < 3; ++L)
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int eb = 0; eb < 2; ++eb)
+        for (int v = 0; v < 16; ++v) b.HT[L][er * TS + mlp_feat(mb, v, hl)] = h[L][mb * 16 + v];
+    if (hl == 0) {
 #pragma unroll
-          for (int v = 0; v < 16; ++v) b.HT[L][(32 * eb + lr) * TS + mlp_feat(mb, v, hl)] = h[L][(2 * mb + eb) * 16 + v];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) b.UT[lane * 6 + j] = u[j];
-    b.G[lane] = g;
-    mlp_backward<MLP_SPLIT>(s, g, h[0], h[1], h[2]);
+      for (int j = 0; j < 6; ++j) b.UT[er * 6 + j] = u[j];
+      b.G[er] = g;
+    }
+    mlp_backward_pair<MLP_SPLIT>(s, g, h[0], h[1], h[2]);
 #pragma unroll
     for (int L = 0; L < 3; ++L)
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int eb = 0; eb < 2; ++eb)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) b.DT[L][(32 * eb + lr) * TS + mlp_feat(mb, v, hl)] = h[L][(2 * mb + eb) * 16 + v];
+        for (int v = 0; v < 16; ++v) b.DT[L][er * TS + mlp_feat(mb, v, hl)] = h[L][mb * 16 + v];
     if (din) {  // uniform: every lane takes part in the cross-lane sums
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        const float gj = mlp_input_grad(s, h[0], j);
-        if (valid) din[row * 6 + j] = gj;
+        const float gj = mlp_rowdot_pair<6>(s.W1 + j, h[0]);
+        if (valid && hl == 0) din[row * 6 + j] = gj;
       }
     }
     __syncthreads();
@@ -227,47 +258,75 @@ __global__ __launch_bounds__(64) void mlp_bwd_kernel(const unsigned short* w, co
     // first tile writes its partial, later ones add to it
     const bool first = t == (int64_t)blockIdx.x;
     auto put = [&](int k, float v) { P[k] = first ? v : P[k] + v; };
-    // layers 3 (d3 x h2) and 2 (d2 x h1) on MFMA (one layer at a time)
+    // layers 3 (d3 x h2) and 2 (d2 x h1) on MFMA (one layer at a time),
+    // output rows 32 wv .. 32 wv + 31
 #pragma unroll 1
     for (int L = 2; L >= 1; --L) {
-      rf_f32x16 acc[2][2];
+      rf_f32x16 acc[1][2];
 #pragma unroll
-      for (int mo = 0; mo < 2; ++mo)
+      for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) acc[mo][ni][v] = 0.0f;
-      mlp_dw_mfma(b.DT[L], b.HT[L - 1], acc);
+        for (int v = 0; v < 16; ++v) acc[0][ni][v] = 0.0f;
+      mlp_dw_mfma<1>(b.DT[L], b.HT[L - 1], wv, acc);
       const int ow = L == 2 ? MLP_OW3 : MLP_OW2;
 #pragma unroll
-      for (int mo = 0; mo < 2; ++mo)
+      for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) put(ow + mlp_feat(mo, v, hl) * 64 + 32 * ni + lr, acc[mo][ni][v]);
+        for (int v = 0; v < 16; ++v) put(ow + mlp_feat(wv, v, hl) * 64 + 32 * ni + lr, acc[0][ni][v]);
     }
-    // biases of layers 2 and 3, layer 1 (d1 x u) and the output layer (g x
-    // h3): lane = unit o
+    // per-unit sums over the rows (lane = unit o): wavefront 0 the biases of
+    // layers 2 and 3 and the output layer (g x h3), wavefront 1 layer 1
+    // (d1 x u) and its bias
     {
       const int o = lane;
-      float bb2 = 0.0f, bb3 = 0.0f, acc1[6] = {0, 0, 0, 0, 0, 0}, bb1 = 0.0f, acc4 = 0.0f, accg = 0.0f;
-      for (int e = 0; e < 64; ++e) {
-        bb3 += b.DT[2][e * TS + o];
-        bb2 += b.DT[1][e * TS + o];
-        const float d = b.DT[0][e * TS + o];
-        bb1 += d;
+      if (wv == 0) {
+        float bb2 = 0.0f, bb3 = 0.0f, acc4 = 0.0f, accg = 0.0f;
+#pragma unroll 1
+        for (int e0 = 0; e0 < 64; e0 += 8) {  // eight rows' LDS reads issued together
+          float d3[8], d2[8], h3[8], gg[8];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) acc1[j] = fmaf(d, b.UT[e * 6 + j], acc1[j]);
-        acc4 = fmaf(b.G[e], b.HT[2][e * TS + o], acc4);
-        accg += b.G[e];
+          for (int q = 0; q < 8; ++q) {
+            const int e = e0 + q;
+            d3[q] = b.DT[2][e * TS + o];
+            d2[q] = b.DT[1][e * TS + o];
+            h3[q] = b.HT[2][e * TS + o];
+            gg[q] = b.G[e];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            bb3 += d3[q];
+            bb2 += d2[q];
+            acc4 = fmaf(gg[q], h3[q], acc4);
+            accg += gg[q];
+          }
+        }
+        put(MLP_OB3 + o, bb3);
+        put(MLP_OB2 + o, bb2);
+        put(MLP_OW4 + o, acc4);
+        if (o == 0) put(MLP_OB4, accg);
+      } else {
+        float acc1[6] = {0, 0, 0, 0, 0, 0}, bb1 = 0.0f;
+#pragma unroll 1
+        for (int e0 = 0; e0 < 64; e0 += 8) {
+          float d1[8], uu[8][6];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int e = e0 + q;
+            d1[q] = b.DT[0][e * TS + o];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) uu[q][j] = b.UT[e * 6 + j];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            bb1 += d1[q];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) acc1[j] = fmaf(d1[q], uu[q][j], acc1[j]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) put(MLP_OW1 + o * 6 + j, acc1[j]);
+        put(MLP_OB1 + o, bb1);
       }
-      put(MLP_OB3 + o, bb3);
-      put(MLP_OB2 + o, bb2);
-#pragma unroll
-      for (int j = 0; j < 6; ++j) put(MLP_OW1 + o * 6 + j, acc1[j]);
-      put(MLP_OB1 + o, bb1);
-      put(MLP_OW4 + o, acc4);
-      if (o == 0) put(MLP_OB4, accg);
     }
     __syncthreads();
   }
@@ -277,11 +336,38 @@ __global__ __launch_bounds__(64) void mlp_bwd_kernel(const unsigned short* w, co
 // 256-thread block adds partial rows w, w + 4, ... for 64 consecutive k (16
 // loads in flight per lane, pairwise), the four wavefront sums are added in
 // order
-__global__ __launch_bounds__(256) void mlp_dw_reduce_kernel(const float* part, int nblk, float* dw) {
+struct AdamArgs {
+  float* w32;
+  unsigned short* wbf;
+  float *m, *v;
+  float lr, b1, b2, eps, c1, c2;
+};
+// Adam update of weight i with gradient gi from its current state (m0, v0,
+// w0); writes the state and refreshes the BF16 copy
+__device__ __forceinline__ void adam_update(const AdamArgs& a, int64_t i, float gi, float m0, float v0, float w0) {
+  const float mi = a.b1 * m0 + (1.0f - a.b1) * gi;
+  const float vi = a.b2 * v0 + (1.0f - a.b2) * gi * gi;
+  a.m[i] = mi;
+  a.v[i] = vi;
+  const float wi = w0 - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+  a.w32[i] = wi;
+  const __bf16 hb = (__bf16)wi;  // round to nearest even
+  a.wbf[i] = __builtin_bit_cast(unsigned short, hb);
+}
+
+template <bool ADAM>
+__global__ __launch_bounds__(256) void mlp_dw_reduce_kernel(const float* part, int nblk, float* dw, const AdamArgs ad) {
   __shared__ double ws[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
   const int kc = k < MLP_NW ? k : MLP_NW - 1;
+  // the optimiser state is read up front, overlapping the partials' loads
+  float m0 = 0.f, v0 = 0.f, w0 = 0.f;
+  if (ADAM && w == 0) {
+    m0 = ad.m[kc];
+    v0 = ad.v[kc];
+    w0 = ad.w32[kc];
+  }
   double h = 0.0;
   for (int b0 = w; b0 < nblk; b0 += 4 * 16) {
     float v[16];
@@ -301,22 +387,16 @@ __global__ __launch_bounds__(256) void mlp_dw_reduce_kernel(const float* part, i
   }
   ws[w][lane] = h;
   __syncthreads();
-  if (w == 0 && k < MLP_NW) dw[k] = (float)((ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]));
+  if (w == 0 && k < MLP_NW) {
+    const float gk = (float)((ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]));
+    if (dw) dw[k] = gk;
+    if (ADAM) adam_update(ad, k, gk, m0, v0, w0);
+  }
 }
 
-__global__ void adam_kernel(float* w32, unsigned short* wbf, float* m, float* v, const float* g, int64_t n,
-                            float lr, float b1, float b2, float eps, float c1, float c2) {
+__global__ void adam_kernel(const AdamArgs a, const float* g, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float wi = w32[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  w32[i] = wi;
-  const __bf16 hb = (__bf16)wi;  // round to nearest even
-  wbf[i] = __builtin_bit_cast(unsigned short, hb);
+  if (i < n) adam_update(a, i, g[i], a.m[i], a.v[i], a.w32[i]);
 }
 
 __global__ void mse_grad_kernel(const float* out, const float* y, int64_t n, float scale, float* dout) {
@@ -376,6 +456,63 @@ int mlp_renorm_launch(const void* w, const double* q5, const double* box12, cons
 }
 }  // namespace rf
 
+namespace {
+using namespace rf;
+AdamArgs adam_args(float* w32, void* wbf, float* m, float* v, float lr, float beta1, float beta2, float eps,
+                   int32_t step) {
+  AdamArgs a;
+  a.w32 = w32;
+  a.wbf = (unsigned short*)wbf;
+  a.m = m;
+  a.v = v;
+  a.lr = lr;
+  a.b1 = beta1;
+  a.b2 = beta2;
+  a.eps = eps;
+  a.c1 = 1.0f - powf(beta1, (float)step);
+  a.c2 = 1.0f - powf(beta2, (float)step);
+  return a;
+}
+
+// backward over n rows + the ordered reduction of the per-workgroup partials
+// (with Adam applied to the summed gradient when ad is given)
+int backward_launch(const void* w, const float* in, const BwdRows& r, int64_t n, float* dw, float* din,
+                    const AdamArgs* ad, void* stream) {
+  const int64_t ntile = (n + 63) / 64;
+  int nblk = (int)(ntile < 512 ? ntile : 512);
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (g_part_n < (size_t)nblk * MLP_NW) {
+    if (g_part) (void)hipFree(g_part);
+    g_part = nullptr;
+    g_part_n = 0;
+    hipError_t e = hipMalloc(&g_part, sizeof(float) * (size_t)nblk * MLP_NW);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc mlp partials");
+    g_part_n = (size_t)nblk * MLP_NW;
+  }
+  if (ntile == 0) {
+    nblk = 0;  // no partials: the reduction writes zeros
+  } else {
+    // every block takes at least one tile (nblk <= ntile): its first tile
+    // writes the block's partial
+    if (r.target)
+      hipLaunchKernelGGL(mlp_bwd_kernel<true>, dim3(nblk), dim3(64 * BWD_W), 0, (hipStream_t)stream, (const unsigned short*)w,
+                         in, r, n, g_part, din);
+    else
+      hipLaunchKernelGGL(mlp_bwd_kernel<false>, dim3(nblk), dim3(64 * BWD_W), 0, (hipStream_t)stream, (const unsigned short*)w,
+                         in, r, n, g_part, din);
+    int rc = launch_err("mlp_backward");
+    if (rc) return rc;
+  }
+  if (ad)
+    hipLaunchKernelGGL(mlp_dw_reduce_kernel<true>, dim3((MLP_NW + 63) / 64), dim3(256), 0, (hipStream_t)stream, g_part,
+                       nblk, dw, *ad);
+  else
+    hipLaunchKernelGGL(mlp_dw_reduce_kernel<false>, dim3((MLP_NW + 63) / 64), dim3(256), 0, (hipStream_t)stream,
+                       g_part, nblk, dw, AdamArgs{});
+  return launch_err("mlp_dw_reduce");
+}
+}  // namespace
+
 using namespace rf;
 
 extern "C" {
@@ -395,42 +532,31 @@ int rf_mlp_forward(const void* w, const float* in, int64_t n, float* out, float*
   return launch_err("mlp_forward");
 }
 
+
 int rf_mlp_backward(const void* w, const float* in, const float* act, const float* dout, int64_t n, float* dw,
                     float* din, void* stream) {
   (void)act;  // activations are recomputed from the inputs (cheaper than reading them back)
   if (!w || !dw || n < 0 || (n > 0 && (!in || !dout))) return fail(RF_E_INVALID, "bad arguments");
-  const int64_t ntile = (n + 63) / 64;
-  int nblk = (int)(ntile < 512 ? ntile : 512);
-  std::lock_guard<std::mutex> lk(g_ws_mu);
-  if (g_part_n < (size_t)nblk * MLP_NW) {
-    if (g_part) (void)hipFree(g_part);
-    g_part = nullptr;
-    g_part_n = 0;
-    hipError_t e = hipMalloc(&g_part, sizeof(float) * (size_t)nblk * MLP_NW);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc mlp partials");
-    g_part_n = (size_t)nblk * MLP_NW;
-  }
-  if (ntile == 0) {
-    nblk = 0;  // no partials: the reduction writes zeros
-  } else {
-    // every block takes at least one tile (nblk <= ntile): its first tile
-    // writes the block's partial
-    hipLaunchKernelGGL(mlp_bwd_kernel, dim3(nblk), dim3(64), 0, (hipStream_t)stream, (const unsigned short*)w, in, dout,
-                       n, g_part, din);
-    int rc = launch_err("mlp_backward");
-    if (rc) return rc;
-  }
-  hipLaunchKernelGGL(mlp_dw_reduce_kernel, dim3((MLP_NW + 63) / 64), dim3(256), 0, (hipStream_t)stream, g_part, nblk,
-                     dw);
-  return launch_err("mlp_dw_reduce");
+  BwdRows r{dout, nullptr, nullptr, 0.0f};
+  return backward_launch(w, in, r, n, dw, din, nullptr, stream);
+}
+
+int rf_mlp_train_step(void* w, float* w32, float* m, float* v, const float* in, const float* target,
+                      const int64_t* idx, int64_t batch, float lr, float beta1, float beta2, float eps, int32_t step,
+                      float* dw, void* stream) {
+  if (!w || !w32 || !m || !v || !in || !target || batch < 1 || step < 1)
+    return fail(RF_E_INVALID, "bad arguments");
+  BwdRows r{nullptr, idx, target, 2.0f / (float)batch};
+  const AdamArgs ad = adam_args(w32, w, m, v, lr, beta1, beta2, eps, step);
+  return backward_launch(w, in, r, batch, dw, nullptr, &ad, stream);
 }
 
 int rf_adam_step(float* w32, void* wbf, float* m, float* v, const float* g, int64_t n, float lr, float beta1,
                  float beta2, float eps, int32_t step, void* stream) {
   if (!w32 || !wbf || !m || !v || !g || n < 0 || step < 1) return fail(RF_E_INVALID, "bad arguments");
-  const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w32,
-                     (unsigned short*)wbf, m, v, g, n, lr, beta1, beta2, eps, c1, c2);
+  if (n == 0) return RF_OK;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     adam_args(w32, wbf, m, v, lr, beta1, beta2, eps, step), g, n);
   return launch_err("adam");
 }
 

@@ -107,9 +107,6 @@ def train_surrogate(n_train=2_000_000, epochs=60, batch=8192, lr=2e-3, lr_min=1e
     wbf = to_bf16(w32)
     m = torch.zeros_like(w32)
     v = torch.zeros_like(w32)
-    g = torch.empty_like(w32)
-    out = torch.empty(batch, dtype=torch.float32, device=device)
-    dout = torch.empty(batch, dtype=torch.float32, device=device)
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     steps_per_epoch = n // batch
@@ -122,15 +119,11 @@ def train_surrogate(n_train=2_000_000, epochs=60, batch=8192, lr=2e-3, lr_min=1e
     for ep in range(epochs):
         perm = torch.randperm(n, device=device, generator=gen)
         for b in range(steps_per_epoch):
+            # one fused step: gather, forward, MSE gradient, backward, Adam
             idx = perm[b * batch:(b + 1) * batch]
-            ub = u_tr[idx].contiguous()
-            yb = y_tr[idx].contiguous()
-            api.mlp_forward(wbf, ub, out)
-            api.mse_grad(out, yb, 2.0 / batch, dout)
-            api.mlp_backward(wbf, ub, dout, g)
             step += 1
             lr_t = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / total))
-            api.adam_step(w32, wbf, m, v, g, lr_t, step)
+            api.mlp_train_step(wbf, w32, m, v, u_tr, y_tr, idx, lr_t, step)
         pred = api.mlp_forward(wbf, u_ho)
         err = (pred - y_ho).double()
         rms = float(err.pow(2).mean().sqrt())

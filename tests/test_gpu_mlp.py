@@ -78,6 +78,51 @@ def test_adam_step_and_bf16_copy():
     assert torch.equal(wbf, w32.to(torch.bfloat16))  # round to nearest even
 
 
+@pytest.mark.parametrize("batch,gather", [(1, True), (200, True), (4096, True), (64, False)])
+def test_train_step_vs_oracle(batch, gather):
+    """The fused step (gathered rows, MSE cotangent from its own forward pass,
+    Adam inside the gradient reduction) against the oracle's batch gradient,
+    the separate kernels, and Adam written out on the host."""
+    print("case train step batch=%d gather=%s" % (batch, gather), flush=True)
+    n = 5000
+    wbf, w64 = _weights(6)
+    rng = np.random.default_rng(batch)
+    u = rng.uniform(-1, 1, (n, 6)).astype(np.float32)
+    y = rng.normal(size=n).astype(np.float32)
+    idx = rng.integers(0, n, batch).astype(np.int64) if gather else np.arange(batch, dtype=np.int64)
+    ud, yd = torch.tensor(u, device="cuda"), torch.tensor(y, device="cuda")
+    idd = torch.tensor(idx, device="cuda") if gather else None
+    if not gather:  # no index: the batch is all rows of the arrays passed
+        ud, yd = ud[:batch], yd[:batch]
+    w0 = wbf.float()
+    w32, m, v = w0.clone(), torch.zeros_like(w0), torch.zeros_like(w0)
+    wbf_s = wbf.clone()
+    dw = torch.empty(8833, dtype=torch.float32, device="cuda")
+    lr = 1e-3
+    api.mlp_train_step(wbf_s, w32, m, v, ud, yd, idd, lr, 1, dw=dw)
+    torch.cuda.synchronize()
+    # oracle: gradient of mean (s - y)^2 over the batch rows
+    ub, yb = u[idx].astype(np.float64), y[idx].astype(np.float64)
+    s_ref = rfo.mlp_forward(w64, ub)
+    dw_ref, _ = rfo.mlp_backward(w64, ub, 2.0 / batch * (s_ref - yb))
+    g = dw.double().cpu().numpy()
+    scale = np.abs(dw_ref).max()
+    np.testing.assert_allclose(g, dw_ref, rtol=0, atol=2e-5 * scale)
+    # the separate kernels on the gathered batch give the same gradient
+    ubd = torch.tensor(u[idx], device="cuda")
+    out = api.mlp_forward(wbf, ubd)
+    dout = torch.empty_like(out)
+    api.mse_grad(out, torch.tensor(y[idx], device="cuda"), 2.0 / batch, dout)
+    g2, _ = api.mlp_backward(wbf, ubd, dout)
+    np.testing.assert_allclose(g, g2.double().cpu().numpy(), rtol=0, atol=1e-6 * scale)
+    # Adam (first step) on the fused gradient
+    gm, gv = 0.1 * g, 0.001 * g * g
+    ww = w0.double().cpu().numpy() - lr * (gm / 0.1) / (np.sqrt(gv / 0.001) + 1e-8)
+    np.testing.assert_allclose(w32.double().cpu().numpy(), ww, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(m.double().cpu().numpy(), gm, rtol=1e-6, atol=1e-12)
+    assert torch.equal(wbf_s, w32.to(torch.bfloat16))
+
+
 def test_exact_targets_vs_oracle():
     raw = synth.sobol_design(200, seed=11)
     xq = torch.tensor(raw, dtype=torch.float64, device="cuda")
