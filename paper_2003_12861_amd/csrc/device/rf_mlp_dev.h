@@ -4,8 +4,8 @@
 //
 // Tiles.  A wavefront handles 64 rows (events or training samples) at once;
 // row r belongs to lane r.  A hidden activation tile (64 features x 64 rows)
-// lives in registers in the MFMA accumulator layout of
-// v_mfma_f32_32x32x8bf16_1k: element v of lane l in block (mb, eb) holds
+// lives in registers in the 32x32 MFMA accumulator layout (the same for the
+// K = 8 and K = 16 bf16 forms): element v of lane l in block (mb, eb) holds
 //     feature 32 mb + 8 (v/4) + 4 (l/32) + v%4,   row 32 eb + l%32,
 // stored at h[(2 mb + eb) * 16 + v].  For out = W h the A operand is a
 // fragment of W read from LDS and the B operand is a run of 8 registers of h.
