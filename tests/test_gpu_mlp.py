@@ -157,6 +157,28 @@ def test_surrogate_leaf_vs_oracle(n):
         np.testing.assert_allclose(v, om.values(otop, th, [x]), rtol=5e-6)
 
 
+def test_surrogate_leaf_full_size_sampled():
+    """1e7 events in the benchmark's launch shape: per-event values on a
+    sample of events against the oracle, and the NLL against -sum log p of
+    the values."""
+    n = 10_000_000
+    wbf, w64 = _weights(4, scale=0.7)
+    x = synth.sample_bw_cb(n, 4)
+    spec = workloads.spec_bwcb(surrogate=True)
+    prog, (om, otop, oids) = build_pair(spec, api.FP32, api)
+    prog.bind(to_dev([x], api.FP32, api))
+    prog.bind_weights("sig", wbf)
+    om.set_mlp_weights(oids["sig"], w64)
+    th = [91.19, 2.5, 1.5, 1.5, 3.0, -0.02, 0.8]
+    v = prog.values(th).double().cpu().numpy()
+    rng = np.random.default_rng(0)
+    idx = rng.choice(n, 2000, replace=False)
+    np.testing.assert_allclose(v[idx], om.values(otop, th, [x[idx]]), rtol=5e-6)
+    nll, g, nb = prog.nll_grad(th)
+    assert nb == 0
+    assert rel(nll, -np.log(v).sum()) <= 2e-6
+
+
 def test_training_reduces_error():
     res = surrogate.train_surrogate(n_train=131072, epochs=8, batch=4096, lr=3e-3, log=print)
     h = res["history"]

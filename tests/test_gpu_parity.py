@@ -147,6 +147,52 @@ def test_decay_argus_parity(prec):
         _check(prog, orc, [t, m], th, prec, "k=%d" % k)
 
 
+def test_decay_argus_full_size_sampled():
+    """5e7 events in the benchmark's launch shape.  Per-event values on a
+    sample against the oracle and the NLL against -sum log p of the values
+    (both paths); the FP64 gradient against central differences of the FP64
+    NLL and the FP32 gradient against the FP64 one.  Gradient bars are
+    relative to the scale sum_i |d(-log p_i)/d theta|, estimated from the
+    oracle on a random 20000-event subset times n / 20000 (the scale is a sum
+    over events)."""
+    n = 50_000_000
+    t, m = synth.sample_decay_argus(n, 3)
+    spec = workloads.spec_decay_argus()
+    p64, (om, otop, _) = build_pair(spec, api.FP64, api)
+    p32, _ = build_pair(spec, api.FP32, api)
+    p64.bind(to_dev([t, m], api.FP64, api))
+    p32.bind(to_dev([t, m], api.FP32, api))
+    th = np.array(workloads.truth_vector(synth.DECAY_TRUTH))
+    rng = np.random.default_rng(0)
+    idx = rng.choice(n, 2000, replace=False)
+    ref = om.values(otop, th, [t[idx], m[idx]])
+    for prog, prec in ((p64, api.FP64), (p32, api.FP32)):
+        print("case decay full size prec=%d" % prec, flush=True)
+        v = prog.values(th).double().cpu().numpy()
+        np.testing.assert_allclose(v[idx], ref, rtol=1e-12 if prec == api.FP64 else 2e-6)
+        nll = prog.nll(th)[0]
+        assert rel(nll, -np.log(v).sum()) <= TOL[prec][0]
+    sub = rng.choice(n, 20_000, replace=False)
+    _, _, oga, _ = om.nll_ex(otop, th, [t[sub], m[sub]])
+    scale = np.asarray(oga) * (n / sub.size)
+    nll64, g64, nb = p64.nll_grad(th)
+    assert nb == 0
+    # central differences, steps 1e-4 of each parameter's natural width
+    h = np.array([1.5e-4, 5e-6, 5e-6, 3e-7, 3e-7, 4e-5, 2e-3, 2e-5])
+    assert h.size == th.size
+    fd = np.empty(th.size)
+    for k in range(th.size):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h[k]
+        tm[k] -= h[k]
+        fd[k] = (p64.nll(tp)[0] - p64.nll(tm)[0]) / (2 * h[k])
+    assert (np.abs(g64 - fd) / scale).max() <= 1e-7, (g64, fd, scale)
+    nll32, g32, nb = p32.nll_grad(th)
+    assert nb == 0
+    assert rel(nll32, nll64) <= 1e-6
+    assert (np.abs(g32 - g64) / scale).max() <= 1e-6, (g32, g64, scale)
+
+
 def test_determinism_and_invariants():
     x = synth.sample_gauss_cheb(300_001, 5)
     for prec in (api.FP64, api.FP32):
