@@ -38,3 +38,40 @@ def test_gauss_cheb_fit_uncertainty_is_hessian_based():
     # at the minimum the analytic gradient vanishes
     _, g, _ = prog.nll_grad(th)
     assert np.all(np.abs(g * sig) < 1e-2)
+
+
+def test_fit_matches_oracle_minimiser():
+    """The fit loop against an independent minimiser of the oracle's NLL:
+    scipy's BFGS on the FP64 oracle NLL and gradient, then sigma from the
+    inverse of a central-difference Hessian of the oracle's gradient.  Both
+    minima locate the same point to a small fraction of sigma (the GPU fit
+    stops at EDM < 1e-9, i.e. within about sqrt(2e-9) sigma)."""
+    from scipy.optimize import minimize
+    x = synth.sample_gauss_cheb(200_000, 31)
+    prog, (om, otop, _) = build_pair(workloads.spec_gauss_cheb(), api.FP64, api)
+    prog.bind(to_dev([x], api.FP64, api))
+    start = np.array([0.1, 1.1, 0.25, 0.15, -0.05])
+    th, sig, info = prog.fit(start, edm_tol=1e-9, max_iter=500)
+    assert info["converged"], info
+
+    def f(t):
+        nll, g, _ = om.nll(otop, list(t), [x])
+        return nll, np.asarray(g)
+
+    r = minimize(f, start, jac=True, method="BFGS", options={"gtol": 1e-6, "maxiter": 500})
+    assert r.success, r.message
+    th_o = r.x
+    # oracle Hessian by central differences of its gradient
+    P = th_o.size
+    H = np.empty((P, P))
+    for k in range(P):
+        h = 1e-5 * max(1.0, abs(th_o[k]))
+        tp, tm = th_o.copy(), th_o.copy()
+        tp[k] += h
+        tm[k] -= h
+        H[k] = (f(tp)[1] - f(tm)[1]) / (2 * h)
+    H = 0.5 * (H + H.T)
+    sig_o = np.sqrt(np.diag(np.linalg.inv(H)))
+    print("gpu", th, sig, "oracle", th_o, sig_o, flush=True)
+    assert np.all(np.abs(th - th_o) / sig_o < 1e-3), (th - th_o) / sig_o
+    np.testing.assert_allclose(sig, sig_o, rtol=1e-3)
