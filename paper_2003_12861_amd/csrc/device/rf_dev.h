@@ -52,11 +52,10 @@ template <> struct RM<double> {
   RF_DEV double erfcx(double x) { return ::erfcx(x); }
   RF_DEV double sqrt(double x) { return ::sqrt(x); }
   RF_DEV double rcp(double x) {
-    // hardware estimate + two Newton steps (relative error ~1 ulp)
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return r;
+    // hardware estimate (measured on gfx950: within 2^-25 relative) and one
+    // Newton step: within 11 ulp (a second step would give 0.5 ulp)
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
   }
   RF_DEV double sqrt_fast(double x) { return ::sqrt(x); }
   RF_DEV double log_acc(double x) { return ::log(x); }
