@@ -197,7 +197,10 @@ const double* rf_binned_result(const rf_binned* b);
 int rf_mlp_forward(const void* dev_w_bf16, const float* dev_in, int64_t n, float* dev_out,
                    float* dev_act, void* stream);
 /* dout[n] cotangents -> dw[8833] FP32 (overwritten with the sum over rows),
- * din (n x 6, may be NULL) input gradients. */
+ * din (n x 6, may be NULL) input gradients.  The per-workgroup partial
+ * gradients live in one library-owned workspace (grown on demand, kept until
+ * the process ends) shared by rf_mlp_backward and rf_mlp_train_step: calls
+ * that overlap on different streams race on it. */
 int rf_mlp_backward(const void* dev_w_bf16, const float* dev_in, const float* dev_act,
                     const float* dev_dout, int64_t n, float* dev_dw, float* dev_din,
                     void* stream);
@@ -217,7 +220,8 @@ int rf_mse_grad(const float* dev_out, const float* dev_target, int64_t n, float 
  * in the arrays (not checked).  The loss is the mean of (s - target)^2 over
  * the batch.  dev_w_bf16 (read by the step, then refreshed), dev_w32, dev_m,
  * dev_v are updated in place; dev_dw (8833 FP32, may be NULL) receives the
- * summed gradient.  Asynchronous on the stream. */
+ * summed gradient.  Asynchronous on the stream; shares rf_mlp_backward's
+ * workspace. */
 int rf_mlp_train_step(void* dev_w_bf16, float* dev_w32, float* dev_m, float* dev_v, const float* dev_in,
                       const float* dev_target, const int64_t* dev_idx, int64_t batch, float lr,
                       float beta1, float beta2, float eps, int32_t step, float* dev_dw, void* stream);
