@@ -17,12 +17,12 @@ int cu_count(int dev) {
   return n;
 }
 
-void free_workspace(rf_program* p) {
-  if (p->d_part) hipFree(p->d_part);
-  if (p->d_ticket) hipFree(p->d_ticket);
-  if (p->d_out) hipFree(p->d_out);
-  if (p->h_out) hipHostFree(p->h_out);
-  if (p->d_aux) hipFree(p->d_aux);
+void free_workspace(rf_program* p) {  // release errors are not actionable here
+  if (p->d_part) (void)hipFree(p->d_part);
+  if (p->d_ticket) (void)hipFree(p->d_ticket);
+  if (p->d_out) (void)hipFree(p->d_out);
+  if (p->h_out) (void)hipHostFree(p->h_out);
+  if (p->d_aux) (void)hipFree(p->d_aux);
   p->d_part = nullptr;
   p->d_ticket = nullptr;
   p->d_out = nullptr;
@@ -208,7 +208,7 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
 void rf_program_free(rf_program* p) {
   if (!p) return;
   free_workspace(p);
-  if (p->m.mod) hipModuleUnload(p->m.mod);
+  if (p->m.mod) (void)hipModuleUnload(p->m.mod);
   delete p;
 }
 
@@ -251,7 +251,8 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
     p->cols[c] = dev_cols ? dev_cols[c] : nullptr;
   }
   int dev = 0;
-  hipGetDevice(&dev);
+  hipError_t de = hipGetDevice(&dev);
+  if (de != hipSuccess) return hip_fail(de, "hipGetDevice");
   if (dev != p->device) return fail(RF_E_STATE, "current device differs from the one the program was loaded on");
   p->n = n_events;
   const int saved = p->blocks_override;
@@ -261,24 +262,32 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
   const int cap = cu_count(dev) * 8;
   const int nmax = need > cap ? need : cap;
   if (!p->d_out || nmax > p->nblk_max) {
+    // a failed allocation leaves the program unbound (no evaluation can run
+    // on a partial workspace)
+    auto unbind = [&](int rc) {
+      free_workspace(p);
+      p->n = -1;
+      p->nblk_max = 0;
+      return rc;
+    };
     free_workspace(p);
     hipError_t e;
     const size_t np = (size_t)(p->L.n_sums + 1) * nmax;  // sums + bad-event count
-    if ((e = hipMalloc(&p->d_part, sizeof(double) * np)) != hipSuccess) return hip_fail(e, "hipMalloc partials");
-    if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return hip_fail(e, "hipMalloc");
-    if ((e = hipMalloc(&p->d_out, sizeof(double) * out_len(p))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&p->d_part, sizeof(double) * np)) != hipSuccess) return unbind(hip_fail(e, "hipMalloc partials"));
+    if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return unbind(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&p->d_out, sizeof(double) * out_len(p))) != hipSuccess) return unbind(hip_fail(e, "hipMalloc"));
     // result copy + completion word
     if ((e = hipHostMalloc(&p->h_out, sizeof(double) * (out_len(p) + 1), hipHostMallocMapped | hipHostMallocCoherent)) !=
         hipSuccess)
-      return hip_fail(e, "hipHostMalloc");
+      return unbind(hip_fail(e, "hipHostMalloc"));
     memset(p->h_out, 0, sizeof(double) * (out_len(p) + 1));
     if ((e = hipHostGetDevicePointer((void**)&p->d_hout, p->h_out, 0)) != hipSuccess)
-      return hip_fail(e, "hipHostGetDevicePointer");
-    if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return hip_fail(e, "hipMemset");
+      return unbind(hip_fail(e, "hipHostGetDevicePointer"));
+    if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return unbind(hip_fail(e, "hipMemset"));
     if (!p->L.aux.empty()) {
-      if ((e = hipMalloc(&p->d_aux, sizeof(double) * p->L.aux.size())) != hipSuccess) return hip_fail(e, "hipMalloc aux");
+      if ((e = hipMalloc(&p->d_aux, sizeof(double) * p->L.aux.size())) != hipSuccess) return unbind(hip_fail(e, "hipMalloc aux"));
       if ((e = hipMemcpy(p->d_aux, p->L.aux.data(), sizeof(double) * p->L.aux.size(), hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy aux");
+        return unbind(hip_fail(e, "hipMemcpy aux"));
     }
     p->nblk_max = nmax;
   }
