@@ -261,6 +261,10 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   // ---- workgroup reduction ----
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nblk = a.nblk_max;
+  // a single workgroup keeps its sums in LDS and goes straight to the
+  // epilogue: no partials to publish, no ticket, no second pass (the result
+  // is the one the multi-workgroup path computes, which only adds zeros)
+  const bool solo = gridDim.x == 1;
 #if RF_LDSRED
   // Through LDS: every thread writes its sums (and its bad-event count, as
   // the last sum: exact in FP64); in round r, the RF_BS / 8 threads of sum
@@ -292,14 +296,25 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
     if (lane == 0) {
       if constexpr (TPS == 32) {  // a sum per half-wavefront
         const int ja = r * 8 + 2 * wid;
-        if (ja < NS2)
-          __hip_atomic_store(&a.part[ja * (int64_t)nblk + blockIdx.x], h0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (ja + 1 < NS2)
-          __hip_atomic_store(&a.part[(ja + 1) * (int64_t)nblk + blockIdx.x], h1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (solo) {
+          if (ja < NS2) fin[ja] = h0;
+          if (ja + 1 < NS2) fin[ja + 1] = h1;
+        } else {
+          if (ja < NS2)
+            __hip_atomic_store(&a.part[ja * (int64_t)nblk + blockIdx.x], h0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (ja + 1 < NS2)
+            __hip_atomic_store(&a.part[(ja + 1) * (int64_t)nblk + blockIdx.x], h1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
       } else {  // a sum per wavefront
         const int ja = r * 8 + wid;
-        if (ja < NS2)
-          __hip_atomic_store(&a.part[ja * (int64_t)nblk + blockIdx.x], h0 + h1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ja < NS2) {
+          if (solo)
+            fin[ja] = h0 + h1;
+          else
+            __hip_atomic_store(&a.part[ja * (int64_t)nblk + blockIdx.x], h0 + h1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
     }
   }
@@ -318,67 +333,72 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
   for (int j = threadIdx.x; j < NS2; j += RF_BS) {
     double hi = 0.0, lo = 0.0;
     for (int w = 0; w < NW; ++w) dd_add(hi, lo, red[w][j], 0.0);
-    __hip_atomic_store(&a.part[j * (int64_t)nblk + blockIdx.x], hi + lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (solo)
+      fin[j] = hi + lo;
+    else
+      __hip_atomic_store(&a.part[j * (int64_t)nblk + blockIdx.x], hi + lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 #endif
-  // publish this workgroup's partials, then take a ticket
-  rf_wait_stores();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (RF_TG == 1) {
-      last = (rf_take_ticket(a.ticket) == gridDim.x - 1);
-    } else {
-      // two levels: RF_TG group counters (256 bytes apart), then the global
-      // counter for the last workgroup of each group -- spreads the
-      // end-of-kernel atomics over several addresses
-      const unsigned g = blockIdx.x % RF_TG;
-      const unsigned gsize = gridDim.x / RF_TG + (g < gridDim.x % RF_TG ? 1u : 0u);
-      const unsigned ngroups = gridDim.x < RF_TG ? gridDim.x : RF_TG;
-      last = 0;
-      if (rf_take_ticket(a.ticket + 64 * (1 + g)) == gsize - 1) {
-        rf_reset_ticket(a.ticket + 64 * (1 + g));
-        last = (rf_take_ticket(a.ticket) == ngroups - 1);
+  if (!solo) {
+    // publish this workgroup's partials, then take a ticket
+    rf_wait_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (RF_TG == 1) {
+        last = (rf_take_ticket(a.ticket) == gridDim.x - 1);
+      } else {
+        // two levels: RF_TG group counters (256 bytes apart), then the global
+        // counter for the last workgroup of each group -- spreads the
+        // end-of-kernel atomics over several addresses
+        const unsigned g = blockIdx.x % RF_TG;
+        const unsigned gsize = gridDim.x / RF_TG + (g < gridDim.x % RF_TG ? 1u : 0u);
+        const unsigned ngroups = gridDim.x < RF_TG ? gridDim.x : RF_TG;
+        last = 0;
+        if (rf_take_ticket(a.ticket + 64 * (1 + g)) == gsize - 1) {
+          rf_reset_ticket(a.ticket + 64 * (1 + g));
+          last = (rf_take_ticket(a.ticket) == ngroups - 1);
+        }
       }
     }
-  }
-  __syncthreads();
-  if (!last) return;
+    __syncthreads();
+    if (!last) return;
 
-  // ---- last workgroup: sum of all partials in a fixed order ----
-  // Wavefront w adds sums w, w + NW, ... two at a time: each lane reads the
-  // partials of workgroups lane, lane + 64, ... (sixteen per sum and pass,
-  // all loads of a pass in flight together; consecutive lanes read
-  // consecutive words), adds them pairwise, and a wavefront sum completes
-  // the total.  The order depends only on the workgroup count, so repeated
-  // calls give bitwise identical results; the rounding error is a few units
-  // of 2^-53 times the sum of magnitudes of the partials.
-  const int nb = (int)gridDim.x;
-  for (int j0 = wid; j0 < NS2; j0 += 2 * NW) {
-    const int j1 = j0 + NW < NS2 ? j0 + NW : j0;  // second sum (a repeat of the first if none)
-    double h0 = 0.0, h1 = 0.0;
-    for (int b0 = 0; b0 < nb; b0 += 16 * 64) {
-      double v0[16], v1[16];
+    // ---- last workgroup: sum of all partials in a fixed order ----
+    // Wavefront w adds sums w, w + NW, ... two at a time: each lane reads the
+    // partials of workgroups lane, lane + 64, ... (sixteen per sum and pass,
+    // all loads of a pass in flight together; consecutive lanes read
+    // consecutive words), adds them pairwise, and a wavefront sum completes
+    // the total.  The order depends only on the workgroup count, so repeated
+    // calls give bitwise identical results; the rounding error is a few units
+    // of 2^-53 times the sum of magnitudes of the partials.
+    const int nb = (int)gridDim.x;
+    for (int j0 = wid; j0 < NS2; j0 += 2 * NW) {
+      const int j1 = j0 + NW < NS2 ? j0 + NW : j0;  // second sum (a repeat of the first if none)
+      double h0 = 0.0, h1 = 0.0;
+      for (int b0 = 0; b0 < nb; b0 += 16 * 64) {
+        double v0[16], v1[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int b = b0 + q * 64 + lane;
-        const int bc = b < nb ? b : nb - 1;  // a valid address; the value is dropped
-        v0[q] = __hip_atomic_load(&a.part[j0 * (int64_t)nblk + bc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        v1[q] = __hip_atomic_load(&a.part[j1 * (int64_t)nblk + bc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int q = 0; q < 16; ++q) {
+          const int b = b0 + q * 64 + lane;
+          const int bc = b < nb ? b : nb - 1;  // a valid address; the value is dropped
+          v0[q] = __hip_atomic_load(&a.part[j0 * (int64_t)nblk + bc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          v1[q] = __hip_atomic_load(&a.part[j1 * (int64_t)nblk + bc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (b0 + q * 64 + lane >= nb) { v0[q] = 0.0; v1[q] = 0.0; }
+#pragma unroll
+        for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+          for (int q = 0; q < w; ++q) { v0[q] += v0[q + w]; v1[q] += v1[q + w]; }
+        h0 += v0[0];
+        h1 += v1[0];
       }
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (b0 + q * 64 + lane >= nb) { v0[q] = 0.0; v1[q] = 0.0; }
-#pragma unroll
-      for (int w = 8; w >= 1; w >>= 1)
-#pragma unroll
-        for (int q = 0; q < w; ++q) { v0[q] += v0[q + w]; v1[q] += v1[q + w]; }
-      h0 += v0[0];
-      h1 += v1[0];
+      h0 = wave_sum(h0);
+      h1 = wave_sum(h1);
+      if (lane == 0) { fin[j0] = h0; fin[j1] = h1; }
     }
-    h0 = wave_sum(h0);
-    h1 = wave_sum(h1);
-    if (lane == 0) { fin[j0] = h0; fin[j1] = h1; }
-  }
+  }  // !solo
   __syncthreads();
   if (wid == 0) {
     // the epilogue (one lane) writes the result into LDS; the wavefront
