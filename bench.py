@@ -13,6 +13,8 @@ against the oracle (FP32: NLL relative error <= 1e-6, FP64: <= 1e-9).
 
 Workloads (the default is the headline one):
   gauss_cheb_1e7        1-D Gaussian + Chebyshev mixture, 1e7 events
+  gauss_cheb_weighted_1e7  the same with per-event weights (uniform in
+                        [0.5, 1.5]): NLL = -sum_i w_i log p_i
   decay_argus_5e7       2-D decay (x) resolution with mass peak, 5e7 events
   bwcb_exact_1e7        Breit-Wigner (x) Crystal Ball by the exact 1024-point
                         rule + exponential background, 1e7 events
@@ -57,14 +59,19 @@ MFMA_BF16_TFLOPS = 2500.0  # dense
 # transcendental counts 4: the quarter-rate unit), and bytes read per event.
 SLOTS = {
     "gauss_cheb_1e7": {"fp32": 48, "fp64": 90},
+    # weights: one more multiply on log p and one on 1/p
+    "gauss_cheb_weighted_1e7": {"fp32": 50, "fp64": 92},
     "decay_argus_5e7": {"fp32": 165, "fp64": 400},
     "bwcb_exact_1e7": {"fp32": 16400, "fp64": 16400},
 }
-BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "decay_argus_5e7": {"fp32": 8, "fp64": 16},
+BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "gauss_cheb_weighted_1e7": {"fp32": 8, "fp64": 16},
+                   "decay_argus_5e7": {"fp32": 8, "fp64": 16},
                    "bwcb_exact_1e7": {"fp32": 4, "fp64": 8}, "bwcb_surrogate_1e7": {"fp32": 4}}
 # surrogate: network multiply-adds per event (forward and input gradient)
 SURROGATE_MAC_PER_EVENT = 17300
-WORKLOADS = ("gauss_cheb_1e7", "decay_argus_5e7", "bwcb_exact_1e7", "bwcb_surrogate_1e7", "binned_200x4x100x60")
+WORKLOADS = ("gauss_cheb_1e7", "gauss_cheb_weighted_1e7", "decay_argus_5e7", "bwcb_exact_1e7", "bwcb_surrogate_1e7",
+             "binned_200x4x100x60")
+WEIGHTED = ("gauss_cheb_weighted_1e7",)  # the last column holds the event weights
 
 
 def measured_traffic(workload, kernel, source):
@@ -87,9 +94,12 @@ def measured_traffic(workload, kernel, source):
 def make(workload):
     """(spec, columns, truth theta, list of theta points, precisions, FP32 MLP weights or None)"""
     from paper_2003_12861_amd import synth, workloads
-    if workload == "gauss_cheb_1e7":
-        return (workloads.spec_gauss_cheb(), [synth.sample_gauss_cheb(10_000_000, 2)],
-                np.asarray(workloads.truth_vector(synth.GAUSS_CHEB_TRUTH)),
+    if workload in ("gauss_cheb_1e7", "gauss_cheb_weighted_1e7"):
+        cols = [synth.sample_gauss_cheb(10_000_000, 2)]
+        if workload in WEIGHTED:
+            w = np.random.default_rng(21).uniform(0.5, 1.5, cols[0].size)
+            cols.append(w.astype(np.float32).astype(np.float64))  # exact in both precisions
+        return (workloads.spec_gauss_cheb(), cols, np.asarray(workloads.truth_vector(synth.GAUSS_CHEB_TRUTH)),
                 [synth.jitter_gauss_cheb(k) for k in range(100)], ("fp32", "fp64"), None)
     if workload == "decay_argus_5e7":
         return (workloads.spec_decay_argus(), list(synth.sample_decay_argus(50_000_000, 3)),
@@ -253,9 +263,11 @@ def main():
     pmap = {"fp32": (api.FP32, torch.float32), "fp64": (api.FP64, torch.float64)}
     wbf = torch.tensor(w32, device="cuda").to(torch.bfloat16) if w32 is not None else None
 
+    weighted = args.workload in WEIGHTED
+
     def program(key, columns):
         prec, dt = pmap[key]
-        p = api.Program(api.Graph.from_spec(spec), precision=prec)
+        p = api.Program(api.Graph.from_spec(spec), precision=prec, weighted=weighted)
         p.bind([torch.tensor(c, dtype=dt, device="cuda") for c in columns])
         if wbf is not None:
             p.bind_weights("sig", wbf)
@@ -286,8 +298,9 @@ def main():
         # bounded sample: oracle evaluations for ~10 s (whole workload, or a
         # 20000-event prefix of the convolution models, scaled to events/s)
         sample = [c[:20000] for c in cols] if heavy else cols
-        onll, og, oga, _ = om.nll_ex(otop, theta, sample)
-        rate, reps = oracle_rate(lambda: om.nll_ex(otop, theta, sample), sample[0].size, 10.0)
+        obs, wts = (sample[:-1], sample[-1]) if weighted else (sample, None)
+        onll, og, oga, _ = om.nll_ex(otop, theta, obs, weights=wts)
+        rate, reps = oracle_rate(lambda: om.nll_ex(otop, theta, obs, weights=wts), sample[0].size, 10.0)
         what = ("%d NLL+gradient evaluations of a %d-event prefix" % (reps, sample[0].size) if heavy
                 else "%d full NLL+gradient evaluations of the %d-event workload" % (reps, n))
         cpu = dict(value=rate, unit="events/s", cores=1, kind="oracle",

@@ -62,8 +62,16 @@ enum {
 enum {
   RF_COMPILE_NO_LOAD = 1u << 0, /* generate + build the code object only (no GPU
                                    needed); the program can then only be queried */
-  RF_VALIDATE = 1u << 1         /* rf_bind_columns checks every event lies in its
-                                   observable's range (one device pass) */
+  RF_VALIDATE = 1u << 1,        /* rf_bind_columns checks that every event lies in
+                                   its observables' ranges and every event weight is
+                                   finite (one device pass), RF_E_INVALID otherwise */
+  RF_COMPILE_WEIGHTED = 1u << 2 /* weighted events: one more column after the
+                                   observables holds per-event weights w_i (program
+                                   dtype, any finite real); the NLL is
+                                   -sum_i w_i log p_i and the gradient its derivative
+                                   (uncertainties from its Hessian carry no
+                                   sum-of-squared-weights correction); values p_i are
+                                   unchanged.  At most 7 observables. */
 };
 
 /* ---- graph ops ----------------------------------------------------------- */
@@ -126,7 +134,8 @@ int rf_graph_node(rf_graph* g, int32_t op, const int32_t* inputs, int32_t n_inpu
 int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags,
                rf_program** out);
 void rf_program_free(rf_program* p);
-/* n_sums: number of FP64 event sums the gradient kernel accumulates */
+/* n_columns: observables, plus one for the weights of a RF_COMPILE_WEIGHTED
+ * program; n_sums: number of FP64 event sums the gradient kernel accumulates */
 int rf_program_info(const rf_program* p, int32_t* n_params, int32_t* n_columns,
                     int32_t* n_sums);
 /* generated HIP source (NUL-terminated, owned by the program) */
@@ -138,8 +147,10 @@ int rf_program_stats(const rf_program* p, int64_t* sync_calls, int64_t* slow_wai
 
 /* ---- binding ------------------------------------------------------------- */
 /* dev_cols[j]: contiguous column of observable j (n_events values), float64
- * for RF_FP64 programs, float32 for RF_FP32_COMP.  Allocates the program's
- * workspace (block partials, result block) on the current device. */
+ * for RF_FP64 programs, float32 for RF_FP32_COMP; for a RF_COMPILE_WEIGHTED
+ * program dev_cols[n_observables] holds the event weights.  Allocates the
+ * program's workspace (block partials, result block) on the current device;
+ * with RF_VALIDATE, also checks the columns (synchronising the stream). */
 int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols,
                     int64_t n_events, void* stream);
 /* MLP leaf weights: 8833 bf16 values (layout W1[64][6] b1[64] W2[64][64]

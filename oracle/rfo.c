@@ -764,6 +764,15 @@ int rfo_nll(rfo_model* m, int top, const double* theta,
 int rfo_nll_ex(rfo_model* m, int top, const double* theta,
                const double* const* cols, int64_t n,
                double* nll, double* grad, double* gabs, int64_t* n_bad) {
+  return rfo_nll_w(m, top, theta, cols, NULL, n, nll, grad, gabs, n_bad);
+}
+
+/* Weighted events: NLL = -sum_i w_i log p_i, straight from its definition
+ * (w = NULL: every weight 1, the same arithmetic as unweighted since a
+ * product with 1 is exact). */
+int rfo_nll_w(rfo_model* m, int top, const double* theta,
+              const double* const* cols, const double* w, int64_t n,
+              double* nll, double* grad, double* gabs, int64_t* n_bad) {
   char reach[MAXN];
   int rc = prepare(m, top, theta, reach);
   if (rc) return rc;
@@ -781,11 +790,12 @@ int rfo_nll_ex(rfo_model* m, int top, const double* theta,
     eval_event(m, xs, reach, val, grd, grad != NULL || gabs != NULL);
     double p = val[top];
     if (!(p > 0) || !isfinite(p)) { ++bad; continue; }
-    nadd(&L, -log(p));
+    const double wi = w ? w[i] : 1.0;
+    nadd(&L, -wi * log(p));
     if (grad)
-      for (int k = 0; k < P; ++k) nadd(&G[k], -grd[top][k] / p);
+      for (int k = 0; k < P; ++k) nadd(&G[k], -wi * (grd[top][k] / p));
     if (gabs)
-      for (int k = 0; k < P; ++k) nadd(&A[k], fabs(grd[top][k] / p));
+      for (int k = 0; k < P; ++k) nadd(&A[k], fabs(wi * (grd[top][k] / p)));
   }
   *nll = bad ? INFINITY : nval(&L);
   if (grad) for (int k = 0; k < P; ++k) grad[k] = nval(&G[k]);

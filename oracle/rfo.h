@@ -75,6 +75,11 @@ int rfo_nll(rfo_model* m, int top, const double* theta,
 int rfo_nll_ex(rfo_model* m, int top, const double* theta,
                const double* const* cols, int64_t n,
                double* nll, double* grad, double* gabs, int64_t* n_bad);
+/* as rfo_nll_ex for weighted events: -sum_i w_i log p_i and its gradient,
+   gabs[k] = sum_i |w_i d(log p_i)/d theta_k|; w = NULL means every w_i = 1 */
+int rfo_nll_w(rfo_model* m, int top, const double* theta,
+              const double* const* cols, const double* w, int64_t n,
+              double* nll, double* grad, double* gabs, int64_t* n_bad);
 /* per-event normalised PDF values */
 int rfo_values(rfo_model* m, int top, const double* theta,
                const double* const* cols, int64_t n, double* out);

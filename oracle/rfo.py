@@ -56,6 +56,7 @@ def lib():
         L.rfo_set_mlp_weights.argtypes = [P, I, DP]
         L.rfo_nll.argtypes = [P, I, DP, ctypes.POINTER(DP), I64, DP, DP, ctypes.POINTER(I64)]
         L.rfo_nll_ex.argtypes = [P, I, DP, ctypes.POINTER(DP), I64, DP, DP, DP, ctypes.POINTER(I64)]
+        L.rfo_nll_w.argtypes = [P, I, DP, ctypes.POINTER(DP), DP, I64, DP, DP, DP, ctypes.POINTER(I64)]
         L.rfo_values.argtypes = [P, I, DP, ctypes.POINTER(DP), I64, DP]
         L.rfo_norm.argtypes = [P, I, DP, DP, DP]
         L.rfo_gauss_legendre.argtypes = [I, D, D, DP, DP]
@@ -128,15 +129,23 @@ class Model:
                              _dp(g) if grad else None, ctypes.byref(nb)))
         return out.value, (g[: self.n_params] if grad else None), nb.value
 
-    def nll_ex(self, top, theta, cols):
-        """(nll, grad, gabs, n_bad); gabs[k] = sum_i |d(-log p_i)/d theta_k|."""
+    def nll_ex(self, top, theta, cols, weights=None):
+        """(nll, grad, gabs, n_bad); gabs[k] = sum_i |d(-log p_i)/d theta_k|.
+        weights: per-event w_i (NLL = -sum_i w_i log p_i), or None."""
         th = _f64(theta)
         cs, arr, n = self._cols(cols)
         out = ctypes.c_double()
         g = np.zeros(max(1, self.n_params))
         ga = np.zeros(max(1, self.n_params))
         nb = ctypes.c_int64()
-        _check(lib().rfo_nll_ex(self.h, top, _dp(th), arr, n, ctypes.byref(out), _dp(g), _dp(ga), ctypes.byref(nb)))
+        if weights is None:
+            _check(lib().rfo_nll_ex(self.h, top, _dp(th), arr, n, ctypes.byref(out), _dp(g), _dp(ga),
+                                    ctypes.byref(nb)))
+        else:
+            w = _f64(weights)
+            assert w.size == n
+            _check(lib().rfo_nll_w(self.h, top, _dp(th), arr, _dp(w), n, ctypes.byref(out), _dp(g), _dp(ga),
+                                   ctypes.byref(nb)))
         return out.value, g[: self.n_params], ga[: self.n_params], nb.value
 
     def values(self, top, theta, cols):

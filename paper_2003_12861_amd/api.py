@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librfgpu.so")
 
 FP64, FP32 = 0, 1
-RF_COMPILE_NO_LOAD, RF_VALIDATE = 1, 2
+RF_COMPILE_NO_LOAD, RF_VALIDATE, RF_COMPILE_WEIGHTED = 1, 2, 4
 OPS = {
     "gauss": 1, "cheb": 2, "exp": 3, "decay_gauss": 4, "argus": 5, "bw": 6,
     "numconv_bw_cb": 7, "mlp": 8, "add": 20, "prod": 21, "linear": 40, "product": 41,
@@ -193,10 +193,13 @@ class Graph:
 class Program:
     """A compiled graph: one fused kernel per precision form."""
 
-    def __init__(self, graph, top=None, precision=FP64, load=True, flags=0):
+    def __init__(self, graph, top=None, precision=FP64, load=True, flags=0, weighted=False, validate=False):
+        """weighted: bind() takes one more column, the per-event weights
+        (NLL = -sum w_i log p_i); validate: bind() checks the columns."""
         h = ctypes.c_void_p()
         top = graph.top if top is None else (graph.ids[top] if isinstance(top, str) else top)
-        fl = flags | (0 if load else RF_COMPILE_NO_LOAD)
+        fl = flags | (0 if load else RF_COMPILE_NO_LOAD) | (RF_COMPILE_WEIGHTED if weighted else 0)
+        fl |= RF_VALIDATE if validate else 0
         check(rf_compile(graph.h, top, precision, fl, ctypes.byref(h)))
         self.h = h
         self.precision = precision
@@ -235,7 +238,8 @@ class Program:
         return torch.float32 if self.precision == FP32 else torch.float64
 
     def bind(self, cols, stream=None):
-        """cols: device tensors (one per observable, contiguous, program dtype)."""
+        """cols: device tensors (one per observable, then the event weights for a
+        weighted program; contiguous, program dtype)."""
         cols = [c.contiguous() for c in cols]
         for c in cols:
             if c.dtype != self.dtype or not c.is_cuda:
@@ -315,8 +319,8 @@ class Program:
                               converged=bool(info[3]))
 
 
-def compile_program(graph, top=None, precision=FP64, load=True, flags=0):
-    return Program(graph, top, precision, load, flags)
+def compile_program(graph, top=None, precision=FP64, load=True, flags=0, weighted=False, validate=False):
+    return Program(graph, top, precision, load, flags, weighted, validate)
 
 
 class NLLFunction(torch.autograd.Function):

@@ -48,7 +48,7 @@ int choose_ept(const Lowered& L) {
 // two for several columns (more registers per group); none beyond the
 // current event for the convolution leaf
 int choose_pfd(const Lowered& L, int ept) {
-  int d = L.has_numconv ? 1 : (L.n_cols <= 1 ? 3 : 2);
+  int d = L.has_numconv ? 1 : (L.n_cols + L.weighted <= 1 ? 3 : 2);
   (void)ept;
   if (const char* e = getenv("RFGPU_PFD")) {  // tuning override
     const int v = atoi(e);
@@ -174,6 +174,12 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
   rf_program* p = new rf_program();
   int rc = lower(g->nodes, top, precision, p->L);
   if (rc) { delete p; return rc; }
+  p->flags = flags;
+  p->L.weighted = (flags & RF_COMPILE_WEIGHTED) ? 1 : 0;
+  if (p->L.n_cols + p->L.weighted > RF_MAX_COLS) {
+    delete p;
+    return fail(RF_E_INVALID, "a weighted program takes at most 7 observables");
+  }
   if (const char* e = getenv("RFGPU_BS")) {  // tuning override of the workgroup size
     const int v = atoi(e);
     if (v >= 64 && v <= 1024 && v % 64 == 0) p->block = v;
@@ -215,7 +221,7 @@ void rf_program_free(rf_program* p) {
 int rf_program_info(const rf_program* p, int32_t* n_params, int32_t* n_columns, int32_t* n_sums) {
   if (!p) return fail(RF_E_INVALID, "program is NULL");
   if (n_params) *n_params = p->L.n_params;
-  if (n_columns) *n_columns = p->L.n_cols;
+  if (n_columns) *n_columns = p->L.n_cols + p->L.weighted;
   if (n_sums) *n_sums = p->L.n_sums;
   return RF_OK;
 }
@@ -243,7 +249,9 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
   (void)stream;
   if (!p) return fail(RF_E_INVALID, "program is NULL");
   if (!p->loaded) return fail(RF_E_STATE, "program was compiled without loading");
-  if (n_cols != p->L.n_cols) return fail(RF_E_INVALID, "number of columns differs from the number of observables");
+  if (n_cols != p->L.n_cols + p->L.weighted)
+    return fail(RF_E_INVALID, p->L.weighted ? "a weighted program takes the observables' columns and one weight column"
+                                            : "number of columns differs from the number of observables");
   if (n_events < 0) return fail(RF_E_INVALID, "n_events < 0");
   if (n_events > 0 && n_cols > 0 && !dev_cols) return fail(RF_E_INVALID, "columns are NULL");
   for (int c = 0; c < n_cols; ++c) {
@@ -293,6 +301,26 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
   }
   p->nblk = choose_blocks(p);
   if (p->nblk > p->nblk_max) p->nblk = p->nblk_max;
+  if (p->flags & RF_VALIDATE) {
+    // observable ranges by column; the weight column (if any) must be finite
+    double lo[RF_MAX_COLS] = {}, hi[RF_MAX_COLS] = {};
+    for (const Node& nd : p->L.nodes)
+      if (nd.op == K_OBS && nd.index >= 0 && nd.index < p->L.n_cols) {
+        lo[nd.index] = nd.lo;
+        hi[nd.index] = nd.hi;
+      }
+    int64_t bad = 0;
+    int rc = validate_columns(p->cols, n_cols, p->L.n_cols, lo, hi, n_events, p->L.precision == RF_FP32_COMP, stream,
+                              &bad);
+    if (rc) {
+      p->n = -1;
+      return rc;
+    }
+    if (bad) {
+      p->n = -1;  // not bound
+      return fail(RF_E_INVALID, std::to_string(bad) + " event values outside their observable's range or not finite");
+    }
+  }
   return RF_OK;
 }
 

@@ -162,7 +162,8 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
   }
   o << "#define RF_T " << (f32 ? "float" : "double") << "\n";
   o << "#define RF_PREC " << (f32 ? "f32" : "f64") << "\n";
-  o << "#define RF_NCOL " << L.n_cols << "\n";
+  // loaded columns: the observables, then the event weights of a weighted program
+  o << "#define RF_NCOL " << L.n_cols + L.weighted << "\n";
   o << "#define RF_NCST " << L.n_cst << "\n";
   o << "#define RF_NSUM " << L.n_sums << "\n";
   o << "#define RF_P " << L.n_params << "\n";
@@ -344,9 +345,18 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
   o << "  *pout = p;\n";
   o << "  const bool ok = p > RM<T>::tiny() && p < (T)INFINITY;\n";
   o << "  if (MODE == 0) return ok;\n";
-  o << "  acc[0] += ok ? RM<T>::log_acc(p) : (T)0;\n";
-  o << "  if (MODE == 2) {\n";
-  o << "    const T r = ok ? RM<T>::rcp(p) : (T)0;\n";
+  if (L.weighted) {
+    // weighted events: every sum of the event carries its weight, through
+    // log p and through r = 1/p, which all adjoint terms share
+    o << "  const T wt = x[" << L.n_cols << "];\n";
+    o << "  acc[0] += ok ? wt * RM<T>::log_acc(p) : (T)0;\n";
+    o << "  if (MODE == 2) {\n";
+    o << "    const T r = ok ? RM<T>::rcp(p) * wt : (T)0;\n";
+  } else {
+    o << "  acc[0] += ok ? RM<T>::log_acc(p) : (T)0;\n";
+    o << "  if (MODE == 2) {\n";
+    o << "    const T r = ok ? RM<T>::rcp(p) : (T)0;\n";
+  }
   std::vector<char> declared(N, 0), wdecl(N, 0);
   // beta_c: name of the variable holding it, declared on first use
   std::function<std::string(int)> beta = [&](int id) -> std::string {

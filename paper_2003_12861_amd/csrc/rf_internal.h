@@ -45,7 +45,8 @@ struct Lowered {
   std::vector<Node> nodes;         // copy of the graph
   int top = -1;
   int precision = RF_FP64;
-  int n_params = 0, n_cols = 0;
+  int n_params = 0, n_cols = 0;    // n_cols: observables
+  int weighted = 0;                // one more column: per-event weights
   std::vector<double> plo, phi;    // parameter bounds
   std::vector<char> reach;
   std::vector<int> cst_off;        // per node: offset of its FP64 constant block
@@ -93,6 +94,13 @@ int mlp_renorm_launch(const void* w, const double* q5, const double* box12, cons
 // its partial sums take 6 doubles per workgroup
 inline int mlp_renorm_blocks(int K) { return (K + 255) / 256; }
 
+// column checks of rf_bind_columns with RF_VALIDATE (rf_validate.hip): the
+// number of events outside [lo[c], hi[c]] (or not finite) in columns
+// c < n_range, plus the number of non-finite values in columns n_range ..
+// n_cols - 1 (event weights); synchronises the stream
+int validate_columns(const void* const* cols, int n_cols, int n_range, const double* lo, const double* hi,
+                     int64_t n, bool f32, void* stream, int64_t* n_bad);
+
 // Gauss-Legendre rule (host)
 void gauss_legendre(int K, double lo, double hi, double* x, double* w);
 
@@ -118,6 +126,7 @@ struct rf_program {
   uint64_t seq = 0; // completion sequence number of synchronous calls
   int64_t n_sync = 0, n_slow = 0;  // synchronous calls; those whose wait fell back to a stream sync
   int blocks_override = 0;
+  uint32_t flags = 0;  // RF_COMPILE_* / RF_VALIDATE given to rf_compile
   // binding
   const void* cols[RF_MAX_COLS] = {};
   int64_t n = -1;

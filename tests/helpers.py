@@ -4,9 +4,9 @@ import numpy as np
 from oracle import rfo
 
 
-def build_pair(spec, precision, api):
+def build_pair(spec, precision, api, **kw):
     g = api.Graph.from_spec(spec)
-    prog = api.Program(g, precision=precision)
+    prog = api.Program(g, precision=precision, **kw)
     om, otop, oids = rfo.from_spec(spec)
     return prog, (om, otop, oids)
 

@@ -509,3 +509,47 @@ def test_bad_events_make_nll_infinite():
     x = np.linspace(-10, 10, 101)
     nll, _, nb = m.nll(top, [0.0, 1.0, 0.0, 1.5, 0.0], [x])  # 1 + 1.5 x' < 0 for x' < -2/3
     assert math.isinf(nll) and nb == np.sum((x / 10.0) * 1.5 + 1 <= 0)
+
+
+# ---- weighted events: NLL = -sum_i w_i log p_i -------------------------------
+def _weighted_cases():
+    g = workloads.spec_gauss_cheb()
+    d = workloads.spec_decay_argus()
+    x = synth.sample_gauss_cheb(300, 41)
+    t, m = synth.sample_decay_argus(300, 42)
+    return [(g, [x], [0.1, 1.2, 0.3, 0.15, -0.05]),
+            (d, [t, m], workloads.truth_vector(synth.DECAY_TRUTH))]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_oracle_unit_weights_equal_unweighted(case):
+    spec, cols, th = _weighted_cases()[case]
+    om, top, _ = rfo.from_spec(spec)
+    a = om.nll_ex(top, th, cols)
+    b = om.nll_ex(top, th, cols, weights=np.ones(cols[0].size))
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]) and a[3] == b[3] == 0
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_oracle_integer_weights_equal_repeated_events(case):
+    """w_i in {0, 1, 2, 3} is the unweighted NLL of the sample with event i
+    repeated w_i times (zero drops it): value, gradient and gradient scale."""
+    spec, cols, th = _weighted_cases()[case]
+    om, top, _ = rfo.from_spec(spec)
+    w = np.random.default_rng(7).integers(0, 4, cols[0].size)
+    rep = [np.repeat(c, w) for c in cols]
+    a = om.nll_ex(top, th, cols, weights=w.astype(np.float64))
+    b = om.nll_ex(top, th, rep)
+    assert abs(a[0] - b[0]) <= 1e-13 * abs(b[0])
+    np.testing.assert_allclose(a[1], b[1], rtol=0, atol=1e-12 * np.abs(b[2]).max())
+    np.testing.assert_allclose(a[2], b[2], rtol=1e-13)
+
+
+def test_oracle_weights_are_linear():
+    spec, cols, th = _weighted_cases()[1]
+    om, top, _ = rfo.from_spec(spec)
+    rng = np.random.default_rng(8)
+    w1, w2 = rng.uniform(-0.5, 2, cols[0].size), rng.uniform(0, 1, cols[0].size)
+    a, b, c = (om.nll_ex(top, th, cols, weights=w) for w in (w1, w2, w1 + w2))
+    assert abs(c[0] - (a[0] + b[0])) <= 1e-13 * (abs(a[0]) + abs(b[0]))
+    np.testing.assert_allclose(c[1], a[1] + b[1], rtol=0, atol=1e-12 * (np.abs(a[2]) + np.abs(b[2])).max())
