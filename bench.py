@@ -25,6 +25,12 @@ Workloads (the default is the headline one):
                         bins, 60 nuisance parameters (a step is one
                         evaluation; the unit is evaluations/s)
 
+--unfused-ablation (gauss_cheb_1e7 or decay_argus_5e7): instead, time the
+NLL-only evaluation of the fused kernel against the paper's unfused per-node
+batch mode (rf_nll_unfused: one kernel per PDF node writing its values to
+device memory, then the NLL) in both precisions, and print one JSON line with
+both step times, the ratio, and the unfused mode's device-memory traffic.
+
 Prints ONE JSON line.  Extra fields:
   roofline      the dominant kernel against its bound: VALU issue rate
                 (lane-slots), MFMA rate or HBM bandwidth; algorithmic work per
@@ -234,6 +240,44 @@ def run_binned(args, torch, stream):
     print(json.dumps(line))
 
 
+def run_unfused_ablation(args, progs, cols, thetas, n, torch, stream):
+    """Synchronous NLL-only steps: the fused kernel against the unfused
+    per-node batch mode, same program, same events, same parameter points."""
+    from paper_2003_12861_amd import api
+    if args.workload not in ("gauss_cheb_1e7", "decay_argus_5e7"):
+        raise SystemExit("--unfused-ablation takes gauss_cheb_1e7 or decay_argus_5e7")
+    out = {}
+    for key, p in progs.items():
+        fused = lambda th, p=p: p.nll(th, stream=stream)
+        unf = lambda th, p=p: p.nll_unfused(th, stream=stream)
+        for f in (fused, unf):
+            for i in range(args.warmup):
+                f(thetas[i % len(thetas)])
+        tf, _ = timed_steps(fused, thetas, args.steps, torch)
+        tu, _ = timed_steps(unf, thetas, args.steps, torch)
+        a, b = p.nll(thetas[0], stream=stream)[0], p.nll_unfused(thetas[0], stream=stream)[0]
+        out[key] = {"fused_nll_ms": tf * 1e3, "unfused_nll_ms": tu * 1e3, "unfused_over_fused": tu / tf,
+                    "nll_rel_diff": abs(a - b) / abs(b)}
+    nodes = {"gauss_cheb_1e7": 3, "decay_argus_5e7": 7}[args.workload]
+    # values moved per event by the unfused mode: each node reads its inputs
+    # (a column or its input nodes' arrays) and writes its array, and the NLL
+    # reads the top's array -- 1-D: 2 leaves x 2 + sum 3 + 1 = 8; 2-D:
+    # 4 leaves x 2 + 2 products x 3 + sum 3 + 1 = 18 (the fused kernel: the
+    # columns only)
+    moved = {"gauss_cheb_1e7": 8, "decay_argus_5e7": 18}[args.workload]
+    line = {
+        "metric": "NLL evaluation time: fused kernel vs the paper's unfused per-node batch mode",
+        "value": out["fp32"]["unfused_over_fused"], "unit": "unfused/fused step time (fp32)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": args.workload, "events": n, "pdf_nodes": nodes,
+                   "step": "one synchronous NLL evaluation (no gradient)"},
+        "unfused_bytes_per_event": {k: moved * (4 if k == "fp32" else 8) for k in out},
+        "fused_bytes_per_event": {k: len(cols) * (4 if k == "fp32" else 8) for k in out},
+        **out,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +286,8 @@ def main():
     ap.add_argument("--workload", default="gauss_cheb_1e7", choices=WORKLOADS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 path (profiling runs)")
+    ap.add_argument("--unfused-ablation", action="store_true",
+                    help="fused vs unfused per-node NLL (gauss_cheb_1e7, decay_argus_5e7)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -274,6 +320,10 @@ def main():
         return p
 
     progs = {key: program(key, cols) for key in precs}
+
+    if args.unfused_ablation:
+        run_unfused_ablation(args, progs, cols, thetas, n, torch, stream)
+        return
 
     if args.calib_copy:
         a = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)

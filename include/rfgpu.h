@@ -167,6 +167,19 @@ int rf_nll(rf_program* p, const double* theta, double* nll, int64_t* n_bad, void
 /* NLL and gradient (n_params); synchronous. */
 int rf_nll_grad(rf_program* p, const double* theta, double* nll, double* grad,
                 int64_t* n_bad, void* stream);
+/* The unfused batch mode of the paper (Section 4.1: one call per node computes
+ * that node's values for all events into an array), kept as an ablation of the
+ * fused kernel: one kernel per PDF node writes the node's value of every event
+ * into its own array in device memory (inputs before users), then the NLL of
+ * the top node's array is summed in a fixed order.  NLL only; unweighted
+ * programs without convolution or MLP leaves (RF_E_INVALID otherwise).  The
+ * first call builds its code object; the node arrays (PDF nodes x n_events
+ * values of the program dtype) are allocated on first use and kept with the
+ * program.  Synchronous; n_bad may be NULL. */
+int rf_nll_unfused(rf_program* p, const double* theta, double* nll, int64_t* n_bad, void* stream);
+/* builds the unfused mode's code object into the cache without loading it (no
+ * GPU needed; also valid for a RF_COMPILE_NO_LOAD program) */
+int rf_unfused_build(const rf_program* p);
 /* enqueue one NLL+gradient evaluation without synchronising; the result
  * block [nll, grad[n_params], n_bad] stays in device memory at
  * rf_program_result(p) until the next evaluation of this program. */

@@ -71,6 +71,8 @@ _OPTIONAL = {
     "rf_adam_step": ([_P, _P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P], _I32),
     "rf_mse_grad": ([_P, _P, _I64, _F, _P, _P], _I32),
     "rf_mlp_train_step": ([_P, _P, _P, _P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P, _P], _I32),
+    "rf_nll_unfused": ([_P, _P, _P, _P, _P], _I32),
+    "rf_unfused_build": ([_P], _I32),
     "rf_bwcb_logpdf": ([_P, _I64, _I32, _D, _D, _D, _D, _P, _P], _I32),
 }
 
@@ -286,6 +288,18 @@ class Program:
 
     def nll(self, theta, stream=None):
         rc = rf_nll(self.h, self._theta_ptr(theta), self._vref, self._nbref, _stream(stream))
+        if rc != -3:
+            check(rc)
+        return self._v.value, self._nb.value
+
+    def build_unfused(self):
+        """Build the unfused mode's code object (no GPU needed)."""
+        check(rf_unfused_build(self.h))
+
+    def nll_unfused(self, theta, stream=None):
+        """The NLL by the unfused per-node batch mode (an ablation of the fused
+        kernel): (nll, n_bad)."""
+        rc = rf_nll_unfused(self.h, self._theta_ptr(theta), self._vref, self._nbref, _stream(stream))
         if rc != -3:
             check(rc)
         return self._v.value, self._nb.value

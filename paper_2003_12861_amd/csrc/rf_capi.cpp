@@ -5,6 +5,9 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <fstream>
+#include <iterator>
+
 #include "rf_internal.h"
 
 using namespace rf;
@@ -214,6 +217,10 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
 void rf_program_free(rf_program* p) {
   if (!p) return;
   free_workspace(p);
+  if (p->unf.vals) (void)hipFree(p->unf.vals);
+  if (p->unf.part) (void)hipFree(p->unf.part);
+  if (p->unf.out) (void)hipFree(p->unf.out);
+  if (p->unf.mod) (void)hipModuleUnload(p->unf.mod);
   if (p->m.mod) (void)hipModuleUnload(p->m.mod);
   delete p;
 }
@@ -382,6 +389,91 @@ int rf_nll_grad_async(rf_program* p, const double* theta, void* stream) {
 }
 
 const double* rf_program_result(const rf_program* p) { return p ? p->d_out : nullptr; }
+
+int rf_unfused_build(const rf_program* p) {
+  if (!p) return fail(RF_E_INVALID, "program is NULL");
+  if (p->L.has_mlp || p->L.has_numconv || p->L.weighted)
+    return fail(RF_E_INVALID, "the unfused mode takes unweighted programs without convolution or MLP leaves");
+  std::string path;
+  return build_code_object(generate_source(p->L, p->block, p->ept, p->pfd, p->tg, p->prio, true), path);
+}
+
+int rf_nll_unfused(rf_program* p, const double* theta, double* nll, int64_t* n_bad, void* stream) {
+  int rc = ready(p, theta);
+  if (rc) return rc;
+  if (!nll) return fail(RF_E_INVALID, "nll is NULL");
+  if (p->L.has_mlp || p->L.has_numconv || p->L.weighted)
+    return fail(RF_E_INVALID, "the unfused mode takes unweighted programs without convolution or MLP leaves");
+  rf_program::Unfused& u = p->unf;
+  hipError_t e;
+  if (!u.mod) {
+    const std::string src = generate_source(p->L, p->block, p->ept, p->pfd, p->tg, p->prio, true);
+    std::string path;
+    if ((rc = build_code_object(src, path))) return rc;
+    std::ifstream f(path, std::ios::binary);
+    std::vector<char> bytes((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    if (bytes.empty()) return fail(RF_E_DEVICE, "empty code object " + path);
+    if ((e = hipModuleLoadData(&u.mod, bytes.data())) != hipSuccess) return hip_fail(e, "hipModuleLoadData");
+    const std::vector<int> slot = unfused_slots(p->L);
+    std::vector<hipFunction_t> fns;
+    for (size_t id = 0; id < slot.size(); ++id) {
+      if (slot[id] < 0) continue;
+      hipFunction_t fn;
+      const std::string name = "rf_u" + std::to_string(id);
+      if ((e = hipModuleGetFunction(&fn, u.mod, name.c_str())) != hipSuccess) return hip_fail(e, name.c_str());
+      fns.push_back(fn);
+    }
+    if ((e = hipModuleGetFunction(&u.k_nll, u.mod, "rf_u_nll")) != hipSuccess) return hip_fail(e, "rf_u_nll");
+    if ((e = hipModuleGetFunction(&u.k_sum, u.mod, "rf_u_sum")) != hipSuccess) return hip_fail(e, "rf_u_sum");
+    u.nodes = fns;
+  }
+  const int64_t n = p->n;
+  const size_t es = p->L.precision == RF_FP32_COMP ? 4 : 8;
+  const size_t need = es * u.nodes.size() * (size_t)(n > 0 ? n : 1);
+  if (need > u.vals_bytes) {
+    if (u.vals) (void)hipFree(u.vals);
+    u.vals = nullptr;
+    u.vals_bytes = 0;
+    if ((e = hipMalloc(&u.vals, need)) != hipSuccess) return hip_fail(e, "hipMalloc (node arrays)");
+    u.vals_bytes = need;
+  }
+  int64_t G = (n + p->block - 1) / p->block;
+  const int64_t gcap = (int64_t)cu_count(p->device) * 8;
+  G = G < 1 ? 1 : (G > gcap ? gcap : G);
+  if (G > u.part_n) {
+    if (u.part) (void)hipFree(u.part);
+    u.part = nullptr;
+    u.part_n = 0;
+    if ((e = hipMalloc(&u.part, sizeof(double) * 2 * G)) != hipSuccess) return hip_fail(e, "hipMalloc (partials)");
+    u.part_n = (int)G;
+  }
+  if (!u.out && (e = hipMalloc(&u.out, sizeof(double) * 2)) != hipSuccess) return hip_fail(e, "hipMalloc");
+  RfArgs a;
+  fill_args(p, theta, a);
+  a.values = u.vals;
+  a.part = u.part;
+  a.nblk_max = u.part_n;
+  a.out = u.out;
+  hipStream_t st = (hipStream_t)stream;
+  void* args1[] = {&a};
+  for (hipFunction_t fn : u.nodes)
+    if ((e = hipModuleLaunchKernel(fn, (unsigned)G, 1, 1, p->block, 1, 1, 0, st, args1, nullptr)) != hipSuccess)
+      return hip_fail(e, "unfused node kernel");
+  if ((e = hipModuleLaunchKernel(u.k_nll, (unsigned)G, 1, 1, p->block, 1, 1, 0, st, args1, nullptr)) != hipSuccess)
+    return hip_fail(e, "rf_u_nll");
+  int nb = (int)G;
+  void* args2[] = {&a, &nb};
+  if ((e = hipModuleLaunchKernel(u.k_sum, 1, 1, 1, p->block, 1, 1, 0, st, args2, nullptr)) != hipSuccess)
+    return hip_fail(e, "rf_u_sum");
+  double h[2] = {0, 0};
+  if ((e = hipMemcpyAsync(h, u.out, sizeof h, hipMemcpyDeviceToHost, st)) != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  const int64_t bad = (int64_t)h[1];
+  if (n_bad) *n_bad = bad;
+  *nll = bad ? INFINITY : h[0];
+  if (bad) return fail(RF_E_NONFINITE, std::to_string(bad) + " events with p <= 0 or non-finite p");
+  return RF_OK;
+}
 
 int rf_gauss_legendre(int32_t K, double lo, double hi, double* x, double* w) {
   if (K < 1 || !x || !w) return fail(RF_E_INVALID, "bad arguments");

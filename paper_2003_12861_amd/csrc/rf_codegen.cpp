@@ -142,7 +142,84 @@ static void emit_jac(std::ostringstream& o, const Lowered& L, int id, const std:
   }
 }
 
-std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, int prio) {
+std::vector<int> unfused_slots(const Lowered& L) {
+  std::vector<int> slot(L.nodes.size(), -1);
+  int ns = 0;
+  for (size_t id = 0; id < L.nodes.size(); ++id)
+    if (L.reach[id] && is_pdf(L.nodes[id].op)) slot[id] = ns++;
+  return slot;
+}
+
+// The paper's batch mode (one call per node computes the node's values for all
+// events into an array, Section 4.1), as an ablation of the fused kernel:
+// kernel rf_u<id> per PDF node in node order (inputs before users) writes
+// node id's value of every event to a.values + slot * n; rf_u_nll sums
+// log p of the top's array per workgroup into a.part (sums, then bad-event
+// counts at a.part + nblk_max), and rf_u_sum adds the partials in a fixed
+// order into a.out = [NLL, bad events].  Same per-node arithmetic as rf_eval.
+static void emit_unfused(std::ostringstream& o, const Lowered& L) {
+  const auto& g = L.nodes;
+  const int N = (int)g.size();
+  const std::vector<int> slot = unfused_slots(L);
+  const bool top_add = g[L.top].op == RF_OP_ADD_PDF;
+  auto arr = [&](int id) { return "((const RF_T*)a.values + (int64_t)" + std::to_string(slot[id]) + " * a.n)"; };
+  const char* head =
+      "  typedef RF_T T;\n"
+      "  __shared__ double cst[RF_NCST > 0 ? RF_NCST : 1];\n"
+      "  rf_prologue(a.theta, cst, a);\n"
+      "  __syncthreads();\n"
+      "  const KS<T> k = KS<T>::load(cst);\n"
+      "  const int64_t step = (int64_t)gridDim.x * RF_BS;\n";
+  for (int id = 0; id < N; ++id) {
+    if (slot[id] < 0) continue;
+    const Node& n = g[id];
+    o << "extern \"C\" __global__ __launch_bounds__(RF_BS) void rf_u" << id << "(const RfArgs a) {\n" << head;
+    o << "  T* const out = (T*)a.values + (int64_t)" << slot[id] << " * a.n;\n";
+    if (is_leaf(n.op)) o << "  const T* const xc = (const T*)a.col[" << g[n.in[0]].index << "];\n";
+    o << "  for (int64_t i = (int64_t)blockIdx.x * RF_BS + threadIdx.x; i < a.n; i += step) {\n";
+    if (is_leaf(n.op)) {
+      o << "    T d" << id << "[" << leaf_n_shape(n) << "];\n";
+      o << "    out[i] = " << eval_call(n, id, "xc[i]") << ";\n";
+    } else if (n.op == RF_OP_PROD_PDF) {
+      o << "    out[i] = ";
+      for (size_t j = 0; j < n.in.size(); ++j) o << (j ? " * " : "") << arr(n.in[j]) << "[i]";
+      o << ";\n";
+    } else {
+      const int nc = ((int)n.in.size() + 1) / 2;
+      o << "    out[i] = ";
+      for (int j = 0; j < nc; ++j) o << (j ? " + " : "") << "k.a" << id << "[" << j << "] * " << arr(n.in[j]) << "[i]";
+      o << ";\n";
+    }
+    o << "  }\n  (void)k;\n}\n\n";
+  }
+  o << "extern \"C\" __global__ __launch_bounds__(RF_BS) void rf_u_nll(const RfArgs a) {\n" << head;
+  o << "  const T* const top = " << arr(L.top) << ";\n";
+  o << "  double s = 0.0;\n  unsigned bad = 0;\n";
+  o << "  for (int64_t i = (int64_t)blockIdx.x * RF_BS + threadIdx.x; i < a.n; i += step) {\n";
+  o << "    const T p = " << (top_add ? "" : "k.stop * ") << "top[i];\n";
+  o << "    if (p > (T)0 && p < (T)INFINITY) s += (sizeof(T) == 4 ? RF_LN2 : 1.0) * (double)RM<T>::log_acc(p);\n";
+  o << "    else ++bad;\n  }\n";
+  o << "  __shared__ double ws[RF_BS / 64][2];\n";
+  o << "  s = wave_sum(s);\n  const unsigned wb = wave_sum_u(bad);\n";
+  o << "  if ((threadIdx.x & 63) == 0) { ws[threadIdx.x >> 6][0] = s; ws[threadIdx.x >> 6][1] = (double)wb; }\n";
+  o << "  __syncthreads();\n";
+  o << "  if (threadIdx.x == 0) {\n    double t = 0.0, b = 0.0;\n";
+  o << "    for (int w = 0; w < RF_BS / 64; ++w) { t += ws[w][0]; b += ws[w][1]; }\n";
+  o << "    a.part[blockIdx.x] = t;\n    a.part[a.nblk_max + blockIdx.x] = b;\n  }\n  (void)k;\n}\n\n";
+  o << "// one workgroup: a.out = [-sum of the partials, bad events], fixed order\n";
+  o << "extern \"C\" __global__ __launch_bounds__(RF_BS) void rf_u_sum(const RfArgs a, int nb) {\n";
+  o << "  __shared__ double ws[RF_BS / 64][2];\n";
+  o << "  double s = 0.0, b = 0.0;\n";
+  o << "  for (int j = threadIdx.x; j < nb; j += RF_BS) { s += a.part[j]; b += a.part[a.nblk_max + j]; }\n";
+  o << "  s = wave_sum(s);\n  b = wave_sum(b);\n";
+  o << "  if ((threadIdx.x & 63) == 0) { ws[threadIdx.x >> 6][0] = s; ws[threadIdx.x >> 6][1] = b; }\n";
+  o << "  __syncthreads();\n";
+  o << "  if (threadIdx.x == 0) {\n    double t = 0.0, c = 0.0;\n";
+  o << "    for (int w = 0; w < RF_BS / 64; ++w) { t += ws[w][0]; c += ws[w][1]; }\n";
+  o << "    a.out[0] = -t;\n    a.out[1] = c;\n  }\n}\n";
+}
+
+std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, int prio, bool unfused) {
   const auto& g = L.nodes;
   const int N = (int)g.size();
   const bool f32 = L.precision == RF_FP32_COMP;
@@ -428,7 +505,10 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
   o << "  for (int j = 0; j < RF_NSUM; ++j) out[" << L.n_params + 2 << " + j] = S[j];\n";
   o << "  (void)cst; (void)th;\n}\n\n";
 
-  o << RF_DEV_SRC_BODY << "\n";
+  if (unfused)
+    emit_unfused(o, L);
+  else
+    o << RF_DEV_SRC_BODY << "\n";
   return o.str();
 }
 

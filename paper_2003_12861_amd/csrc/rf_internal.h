@@ -67,7 +67,12 @@ struct Lowered {
 };
 
 int lower(const std::vector<Node>& g, int top, int precision, Lowered& out);
-std::string generate_source(const Lowered& L, int block_size, int ept, int pfd, int tg, int prio);
+// unfused = false: the fused kernels (values, NLL, NLL+gradient); true: the
+// unfused per-node batch mode (one kernel per PDF node, then the NLL)
+std::string generate_source(const Lowered& L, int block_size, int ept, int pfd, int tg, int prio,
+                            bool unfused = false);
+// unfused mode: slot of each PDF node's value array (-1: not a reachable PDF node)
+std::vector<int> unfused_slots(const Lowered& L);
 
 // code-object cache + compiler driver
 struct Module {
@@ -139,4 +144,15 @@ struct rf_program {
   double* d_aux = nullptr;   // auxiliary FP64 block (surrogate normalisation, ...)
   const void* d_weights = nullptr;
   int device = -1;
+  // unfused per-node batch mode (rf_nll_unfused): built and allocated on first use
+  struct Unfused {
+    hipModule_t mod = nullptr;
+    std::vector<hipFunction_t> nodes;  // kernels of the PDF nodes, inputs before users
+    hipFunction_t k_nll = nullptr, k_sum = nullptr;
+    void* vals = nullptr;  // node value arrays
+    size_t vals_bytes = 0;
+    double* part = nullptr;  // [2][part_n]: partial sums, bad-event counts
+    int part_n = 0;
+    double* out = nullptr;  // [NLL, bad events]
+  } unf;
 };
