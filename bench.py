@@ -15,6 +15,8 @@ Workloads (the default is the headline one):
   gauss_cheb_1e7        1-D Gaussian + Chebyshev mixture, 1e7 events
   gauss_cheb_weighted_1e7  the same with per-event weights (uniform in
                         [0.5, 1.5]): NLL = -sum_i w_i log p_i
+  gauss_cheb_extended_1e7  the same mixture as an extended likelihood with
+                        yields (nu_s, nu_b)
   decay_argus_5e7       2-D decay (x) resolution with mass peak, 5e7 events
   bwcb_exact_1e7        Breit-Wigner (x) Crystal Ball by the exact 1024-point
                         rule + exponential background, 1e7 events
@@ -67,15 +69,18 @@ SLOTS = {
     "gauss_cheb_1e7": {"fp32": 48, "fp64": 90},
     # weights: one more multiply on log p and one on 1/p
     "gauss_cheb_weighted_1e7": {"fp32": 50, "fp64": 92},
+    # extended: the same per-event program (the yield term is parameter-only)
+    "gauss_cheb_extended_1e7": {"fp32": 48, "fp64": 90},
     "decay_argus_5e7": {"fp32": 165, "fp64": 400},
     "bwcb_exact_1e7": {"fp32": 16400, "fp64": 16400},
 }
 BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "gauss_cheb_weighted_1e7": {"fp32": 8, "fp64": 16},
+                   "gauss_cheb_extended_1e7": {"fp32": 4, "fp64": 8},
                    "decay_argus_5e7": {"fp32": 8, "fp64": 16},
                    "bwcb_exact_1e7": {"fp32": 4, "fp64": 8}, "bwcb_surrogate_1e7": {"fp32": 4}}
 # surrogate: network multiply-adds per event (forward and input gradient)
 SURROGATE_MAC_PER_EVENT = 17300
-WORKLOADS = ("gauss_cheb_1e7", "gauss_cheb_weighted_1e7", "decay_argus_5e7", "bwcb_exact_1e7", "bwcb_surrogate_1e7",
+WORKLOADS = ("gauss_cheb_1e7", "gauss_cheb_weighted_1e7", "gauss_cheb_extended_1e7", "decay_argus_5e7", "bwcb_exact_1e7", "bwcb_surrogate_1e7",
              "binned_200x4x100x60")
 WEIGHTED = ("gauss_cheb_weighted_1e7",)  # the last column holds the event weights
 
@@ -107,6 +112,14 @@ def make(workload):
             cols.append(w.astype(np.float32).astype(np.float64))  # exact in both precisions
         return (workloads.spec_gauss_cheb(), cols, np.asarray(workloads.truth_vector(synth.GAUSS_CHEB_TRUTH)),
                 [synth.jitter_gauss_cheb(k) for k in range(100)], ("fp32", "fp64"), None)
+    if workload == "gauss_cheb_extended_1e7":
+        n = 10_000_000
+
+        def ext(t):  # (mu, sigma, f, c1, c2) -> (mu, sigma, nu_s, nu_b, c1, c2), nu = n
+            return np.array([t[0], t[1], t[2] * n, (1.0 - t[2]) * n, t[3], t[4]])
+        return (workloads.spec_gauss_cheb_extended(), [synth.sample_gauss_cheb(n, 2)],
+                ext(workloads.truth_vector(synth.GAUSS_CHEB_TRUTH)),
+                [ext(synth.jitter_gauss_cheb(k)) for k in range(100)], ("fp32", "fp64"), None)
     if workload == "decay_argus_5e7":
         return (workloads.spec_decay_argus(), list(synth.sample_decay_argus(50_000_000, 3)),
                 np.asarray(workloads.truth_vector(synth.DECAY_TRUTH)),

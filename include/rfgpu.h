@@ -99,8 +99,16 @@ enum {
   RF_OP_ADD_PDF = 20,       /* (pdf_1..pdf_n, f_1..f_{n-1}): sum_j f_j pdf_j +
                                (1 - sum f) pdf_n, each pdf normalised            */
   RF_OP_PROD_PDF = 21,      /* (pdf_1..pdf_n) over disjoint observables           */
+  RF_OP_EXTENDED = 22,      /* (pdf, nu param-like > 0), only as the compiled top of
+                               an unweighted program: the extended likelihood.  Event
+                               values are pdf's; the NLL gains nu - N log nu (N the
+                               number of bound events), i.e. it is, up to the
+                               constant log N!, -sum_i log(nu p_i) + nu.  Yields of
+                               a sum: fractions nu_j / nu_tot (RF_OP_FN_RATIO) and
+                               nu = nu_tot (RF_OP_FN_LINEAR of the yields). */
   RF_OP_FN_LINEAR = 40,     /* (a_1..a_n param-like); attrs (c0, c1..cn): c0 + sum c_j a_j */
-  RF_OP_FN_PRODUCT = 41     /* (a_1..a_n param-like): prod a_j                     */
+  RF_OP_FN_PRODUCT = 41,    /* (a_1..a_n param-like): prod a_j                     */
+  RF_OP_FN_RATIO = 42       /* (a, b param-like): a / b (b != 0)                     */
 };
 
 typedef struct rf_graph rf_graph;

@@ -85,9 +85,9 @@ void rfo_model_free(rfo_model* m) {
 int rfo_n_params(const rfo_model* m) { return m->np; }
 int rfo_n_obs(const rfo_model* m) { return m->nobs; }
 
-static int is_pdf(int k) { return k >= RFO_GAUSS; }
+static int is_pdf(int k) { return k >= RFO_GAUSS && k != RFO_EXTENDED; }
 static int is_paramlike(int k) {
-  return k == RFO_PARAM || k == RFO_CONST || k == RFO_FN_LINEAR || k == RFO_FN_PRODUCT;
+  return k == RFO_PARAM || k == RFO_CONST || k == RFO_FN_LINEAR || k == RFO_FN_PRODUCT || k == RFO_FN_RATIO;
 }
 
 /* ---- Gauss-Legendre nodes: Newton iteration on P_K in long double ------ */
@@ -153,6 +153,10 @@ int rfo_node(rfo_model* m, int kind, const int* in, int n_in,
       if (n_attrs != n_in + 1) FAIL(-1, "LINEAR attrs");
       break;
     case RFO_FN_PRODUCT:
+      break;
+    case RFO_FN_RATIO:
+    case RFO_EXTENDED:
+      if (n_in != 2) FAIL(-1, "RATIO and EXTENDED take two inputs");
       break;
     case RFO_NUMCONV_BW_CB: {
       if (n_in != 6 || n_attrs != 3) FAIL(-1, "NUMCONV arity");
@@ -669,6 +673,12 @@ static int prepare(rfo_model* m, int top, const double* theta, char* reach) {
         }
         m->pv[id] = s; break;
       }
+      case RFO_FN_RATIO: {  /* d(a/b) = da/b - a db/b^2 */
+        const double a = m->pv[d->in[0]], b = m->pv[d->in[1]];
+        m->pv[id] = a / b;
+        for (int k = 0; k < P; ++k) g[k] = m->pg[d->in[0]][k] / b - a * m->pg[d->in[1]][k] / (b * b);
+        break;
+      }
       default: break;
     }
   }
@@ -774,6 +784,11 @@ int rfo_nll_w(rfo_model* m, int top, const double* theta,
               const double* const* cols, const double* w, int64_t n,
               double* nll, double* grad, double* gabs, int64_t* n_bad) {
   char reach[MAXN];
+  int ext = -1; /* extended likelihood: node of nu */
+  if (top >= 0 && top < m->n && m->nd[top].kind == RFO_EXTENDED) {
+    ext = m->nd[top].in[1];
+    top = m->nd[top].in[0];
+  }
   int rc = prepare(m, top, theta, reach);
   if (rc) return rc;
   int P = m->np, no = m->nobs;
@@ -797,6 +812,19 @@ int rfo_nll_w(rfo_model* m, int top, const double* theta,
     if (gabs)
       for (int k = 0; k < P; ++k) nadd(&A[k], fabs(wi * (grd[top][k] / p)));
   }
+  if (ext >= 0) {
+    /* + nu - N log nu, N = sum of the weights (the event count unweighted) */
+    nsum Nw = {0, 0};
+    for (int64_t i = 0; i < n; ++i) nadd(&Nw, w ? w[i] : 1.0);
+    const double nu = m->pv[ext], N = nval(&Nw);
+    if (!(nu > 0)) { free(val); free(grd); FAIL(-2, "extended: nu must be > 0"); }
+    nadd(&L, nu - N * log(nu));
+    for (int k = 0; k < P; ++k) {
+      const double t = (1.0 - N / nu) * m->pg[ext][k];
+      nadd(&G[k], t);
+      nadd(&A[k], fabs(t));
+    }
+  }
   *nll = bad ? INFINITY : nval(&L);
   if (grad) for (int k = 0; k < P; ++k) grad[k] = nval(&G[k]);
   if (gabs) for (int k = 0; k < P; ++k) gabs[k] = nval(&A[k]);
@@ -808,6 +836,7 @@ int rfo_nll_w(rfo_model* m, int top, const double* theta,
 int rfo_values(rfo_model* m, int top, const double* theta,
                const double* const* cols, int64_t n, double* out) {
   char reach[MAXN];
+  if (top >= 0 && top < m->n && m->nd[top].kind == RFO_EXTENDED) top = m->nd[top].in[0];
   int rc = prepare(m, top, theta, reach);
   if (rc) return rc;
   double* val = malloc(sizeof(double) * MAXN);

@@ -35,6 +35,7 @@ enum {
   RFO_OBS = 1, RFO_PARAM = 2, RFO_CONST = 3,
   RFO_FN_LINEAR = 4,  /* attrs[0] + sum_j attrs[j+1]*in_j          */
   RFO_FN_PRODUCT = 5, /* prod_j in_j                                */
+  RFO_FN_RATIO = 6,   /* in_0 / in_1                                */
   RFO_GAUSS = 10,     /* in: x, mu, sigma                           */
   RFO_CHEB = 11,      /* in: x, c1..cn  (T0 coefficient fixed to 1) */
   RFO_EXP = 12,       /* in: x, k ; attrs[0]=0: exp(-x/k), 1: exp(k*x) */
@@ -47,7 +48,11 @@ enum {
                          input; the first box is that of x - q1), K (grid
                          points on x's range)                        */
   RFO_ADD = 30,       /* in: pdf_1..pdf_n, f_1..f_{n-1}             */
-  RFO_PROD = 31       /* in: pdf_1..pdf_n (disjoint observables)    */
+  RFO_PROD = 31,      /* in: pdf_1..pdf_n (disjoint observables)    */
+  RFO_EXTENDED = 32   /* in: pdf, nu; only as the top of an NLL: the
+                         extended likelihood -sum_i w_i log p_i + nu - N log nu
+                         with N = sum_i w_i (the event count unweighted);
+                         values are pdf's */
 };
 
 const char* rfo_last_error(void);

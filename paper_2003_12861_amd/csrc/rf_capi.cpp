@@ -91,6 +91,7 @@ void fill_args(const rf_program* p, const double* theta, RfArgs& a) {
   a.nblk_max = p->nblk_max;
   a.hout = nullptr;
   for (int k = 0; k < p->L.n_params; ++k) a.theta[k] = theta[k];
+  if (p->L.ext_nu >= 0) a.theta[p->L.n_params] = (double)p->n;  // N of the extended term
 }
 
 // parameter-dependent pre-pass: the surrogate leaves' normalisation
@@ -179,6 +180,10 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
   if (rc) { delete p; return rc; }
   p->flags = flags;
   p->L.weighted = (flags & RF_COMPILE_WEIGHTED) ? 1 : 0;
+  if (p->L.ext_nu >= 0 && (p->L.weighted || p->L.n_params >= RF_MAX_PARAMS)) {
+    delete p;
+    return fail(RF_E_INVALID, "an extended program is unweighted and has at most 63 parameters");
+  }
   if (p->L.n_cols + p->L.weighted > RF_MAX_COLS) {
     delete p;
     return fail(RF_E_INVALID, "a weighted program takes at most 7 observables");
@@ -392,8 +397,8 @@ const double* rf_program_result(const rf_program* p) { return p ? p->d_out : nul
 
 int rf_unfused_build(const rf_program* p) {
   if (!p) return fail(RF_E_INVALID, "program is NULL");
-  if (p->L.has_mlp || p->L.has_numconv || p->L.weighted)
-    return fail(RF_E_INVALID, "the unfused mode takes unweighted programs without convolution or MLP leaves");
+  if (p->L.has_mlp || p->L.has_numconv || p->L.weighted || p->L.ext_nu >= 0)
+    return fail(RF_E_INVALID, "the unfused mode takes unweighted, non-extended programs without convolution or MLP leaves");
   std::string path;
   return build_code_object(generate_source(p->L, p->block, p->ept, p->pfd, p->tg, p->prio, true), path);
 }
@@ -402,8 +407,8 @@ int rf_nll_unfused(rf_program* p, const double* theta, double* nll, int64_t* n_b
   int rc = ready(p, theta);
   if (rc) return rc;
   if (!nll) return fail(RF_E_INVALID, "nll is NULL");
-  if (p->L.has_mlp || p->L.has_numconv || p->L.weighted)
-    return fail(RF_E_INVALID, "the unfused mode takes unweighted programs without convolution or MLP leaves");
+  if (p->L.has_mlp || p->L.has_numconv || p->L.weighted || p->L.ext_nu >= 0)
+    return fail(RF_E_INVALID, "the unfused mode takes unweighted, non-extended programs without convolution or MLP leaves");
   rf_program::Unfused& u = p->unf;
   hipError_t e;
   if (!u.mod) {

@@ -120,6 +120,8 @@ static void emit_paramlike(std::ostringstream& o, const Lowered& L, const char* 
       o << indent << "const double " << v << " = 1.0";
       for (int i : n.in) o << " * pv" << i;
       o << ";\n";
+    } else if (n.op == RF_OP_FN_RATIO) {
+      o << indent << "const double " << v << " = pv" << n.in[0] << " / pv" << n.in[1] << ";\n";
     }
   }
 }
@@ -139,6 +141,10 @@ static void emit_jac(std::ostringstream& o, const Lowered& L, int id, const std:
         if (i != j) others += " * pv" + std::to_string(n.in[i]);
       emit_jac(o, L, n.in[j], "(" + expr + ") * " + others);
     }
+  } else if (n.op == RF_OP_FN_RATIO) {  // d(a/b) = da / b - (a/b) db / b
+    const std::string a = "pv" + std::to_string(n.in[0]), b = "pv" + std::to_string(n.in[1]);
+    emit_jac(o, L, n.in[0], "(" + expr + ") / " + b);
+    emit_jac(o, L, n.in[1], "-(" + expr + ") * (" + a + " / " + b + ") / " + b);
   }
 }
 
@@ -478,10 +484,20 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
   // ---- epilogue ----
   o << "template <int MODE>\n";
   o << "RF_DEV void rf_epilogue(const double* S, const double* cst, const double* th, double* out, unsigned nbad) {\n";
-  o << "  out[0] = -S[0];\n";
-  o << "  out[" << L.n_params + 1 << "] = (double)nbad;\n";
-  o << "  if (MODE != 2) return;\n";
-  emit_paramlike(o, L, "  ");
+  if (L.ext_nu >= 0) {
+    // extended likelihood: + nu - N log nu, N (the number of events) passed
+    // after the parameters
+    emit_paramlike(o, L, "  ");
+    o << "  const double ext_n = th[" << L.n_params << "], ext_nu = pv" << L.ext_nu << ";\n";
+    o << "  out[0] = -S[0] + (ext_nu - ext_n * ::log(ext_nu));\n";
+    o << "  out[" << L.n_params + 1 << "] = (double)nbad;\n";
+    o << "  if (MODE != 2) return;\n";
+  } else {
+    o << "  out[0] = -S[0];\n";
+    o << "  out[" << L.n_params + 1 << "] = (double)nbad;\n";
+    o << "  if (MODE != 2) return;\n";
+    emit_paramlike(o, L, "  ");
+  }
   o << "  double g[" << (L.n_params > 0 ? L.n_params : 1) << "];\n";
   o << "  for (int k2 = 0; k2 < " << L.n_params << "; ++k2) g[k2] = 0.0;\n";
   for (const Slot& sl : L.slots) {
@@ -499,6 +515,11 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     }
     o << "  {\n    const double gs = " << gs << ";\n";
     emit_jac(o, L, sl.pl, "gs");
+    o << "  }\n";
+  }
+  if (L.ext_nu >= 0) {
+    o << "  {\n";
+    emit_jac(o, L, L.ext_nu, "1.0 - ext_n / ext_nu");
     o << "  }\n";
   }
   o << "  for (int k2 = 0; k2 < " << L.n_params << "; ++k2) out[1 + k2] = g[k2];\n";

@@ -30,7 +30,7 @@ const char* last_error() { return g_err.c_str(); }
 bool is_leaf(int op) { return op >= RF_OP_GAUSS && op <= RF_OP_MLP; }
 bool is_pdf(int op) { return is_leaf(op) || op == RF_OP_ADD_PDF || op == RF_OP_PROD_PDF; }
 bool is_paramlike(int op) {
-  return op == K_PARAM || op == K_CONST || op == RF_OP_FN_LINEAR || op == RF_OP_FN_PRODUCT;
+  return op == K_PARAM || op == K_CONST || op == RF_OP_FN_LINEAR || op == RF_OP_FN_PRODUCT || op == RF_OP_FN_RATIO;
 }
 int leaf_n_shape(const Node& n) { return (int)n.in.size() - 1; }
 
@@ -103,10 +103,21 @@ static int check_leaf(const std::vector<Node>& g, const Node& n) {
 int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
   if (precision != RF_FP64 && precision != RF_FP32_COMP) return fail(RF_E_INVALID, "unknown precision");
   if (top < 0 || top >= (int)g.size()) return fail(RF_E_INVALID, "top id out of range");
+  // the extended-likelihood wrapper: the program's top is the wrapped PDF, and
+  // the epilogue adds nu - N log nu
+  int ext_nu = -1;
+  if (g[top].op == RF_OP_EXTENDED) {
+    const Node& e = g[top];
+    if (e.in.size() != 2 || !is_pdf(g[e.in[0]].op) || !is_paramlike(g[e.in[1]].op))
+      return fail(RF_E_INVALID, "extended: inputs (pdf, nu parameter-like)");
+    ext_nu = e.in[1];
+    top = e.in[0];
+  }
   if (!is_pdf(g[top].op)) return fail(RF_E_INVALID, "top node is not a PDF");
   L = Lowered();
   L.nodes = g;
   L.top = top;
+  L.ext_nu = ext_nu;
   L.precision = precision;
   const int N = (int)g.size();
   for (const Node& n : g) {
@@ -126,6 +137,9 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
     for (int i : g[id].in) mark(i);
   };
   mark(top);
+  if (ext_nu >= 0) mark(ext_nu);
+  for (int id = 0; id < N; ++id)
+    if (L.reach[id] && g[id].op == RF_OP_EXTENDED) return fail(RF_E_INVALID, "extended: only as the compiled top");
 
   // observable sets (bit masks) of PDFs; parameter dependence of param-likes
   std::vector<uint32_t> obs(N, 0);
@@ -134,8 +148,9 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
     const Node& n = g[id];
     if (!L.reach[id]) continue;
     if (n.op == K_PARAM) dep[id] = 1;
-    if (n.op == RF_OP_FN_LINEAR || n.op == RF_OP_FN_PRODUCT) {
+    if (n.op == RF_OP_FN_LINEAR || n.op == RF_OP_FN_PRODUCT || n.op == RF_OP_FN_RATIO) {
       if (n.in.empty()) return fail(RF_E_INVALID, "function without inputs");
+      if (n.op == RF_OP_FN_RATIO && n.in.size() != 2) return fail(RF_E_INVALID, "ratio: inputs (a, b)");
       if (n.op == RF_OP_FN_LINEAR && n.attrs.size() != n.in.size() + 1)
         return fail(RF_E_INVALID, "linear function: attrs = (c0, c1..cn)");
       for (int i : n.in) {
@@ -275,6 +290,8 @@ void eval_paramlike(const Lowered& L, const double* theta, std::vector<double>& 
       double v = 1.0;
       for (int i : n.in) v *= pv[i];
       pv[id] = v;
+    } else if (n.op == RF_OP_FN_RATIO) {
+      pv[id] = pv[n.in[0]] / pv[n.in[1]];
     }
   }
 }
@@ -288,11 +305,15 @@ int check_theta(const Lowered& L, const double* theta) {
   std::vector<double> pv;
   eval_paramlike(L, theta, pv);
   const auto& g = L.nodes;
+  if (L.ext_nu >= 0 && !(pv[L.ext_nu] > 0 && std::isfinite(pv[L.ext_nu])))
+    return fail(RF_E_DOMAIN, "extended: nu must be > 0");
   for (size_t id = 0; id < g.size(); ++id) {
     if (!L.reach[id]) continue;
     const Node& n = g[id];
     auto in = [&](int j) { return pv[n.in[j]]; };
     const double lo = is_leaf(n.op) ? g[n.in[0]].lo : 0.0;
+    if (n.op == RF_OP_FN_RATIO && !(in(1) != 0 && std::isfinite(pv[id])))
+      return fail(RF_E_DOMAIN, n.name + ": ratio with a zero denominator or a non-finite result");
     switch (n.op) {
       case RF_OP_GAUSS:
         if (!(in(2) > 0)) return fail(RF_E_DOMAIN, n.name + ": sigma must be > 0");
@@ -379,7 +400,9 @@ int rf_graph_constant(rf_graph* g, double value, int32_t* id) {
 int rf_graph_node(rf_graph* g, int32_t op, const int32_t* inputs, int32_t n_inputs,
                   const double* attrs, int32_t n_attrs, int32_t* id) {
   if (!g) return fail(RF_E_INVALID, "graph is NULL");
-  if (!(is_pdf(op) || op == RF_OP_FN_LINEAR || op == RF_OP_FN_PRODUCT)) return fail(RF_E_INVALID, "unknown op");
+  if (!(is_pdf(op) || op == RF_OP_EXTENDED || op == RF_OP_FN_LINEAR || op == RF_OP_FN_PRODUCT ||
+        op == RF_OP_FN_RATIO))
+    return fail(RF_E_INVALID, "unknown op");
   if (n_inputs < 0 || n_inputs > 64 || n_attrs < 0 || n_attrs > 64) return fail(RF_E_INVALID, "bad input/attribute count");
   if ((n_inputs && !inputs) || (n_attrs && !attrs)) return fail(RF_E_INVALID, "NULL inputs/attrs");
   Node n;

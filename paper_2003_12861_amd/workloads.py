@@ -25,6 +25,27 @@ def spec_gauss_cheb(lo=-10.0, hi=10.0):
     ]
 
 
+def spec_gauss_cheb_extended(lo=-10.0, hi=10.0):
+    """The extended 1-D mixture with yields: nu_s Gauss(x; mu, sigma) +
+    nu_b Chebyshev2(x; c1, c2), fraction nu_s / (nu_s + nu_b), extended term
+    on nu = nu_s + nu_b; theta = (mu, sigma, nu_s, nu_b, c1, c2)."""
+    return [
+        ("obs", "x", [], [lo, hi]),
+        ("param", "mu", [], [-5.0, 5.0]),
+        ("param", "sigma", [], [0.05, 10.0]),
+        ("param", "nu_s", [], [0.0, 1e12]),
+        ("param", "nu_b", [], [0.0, 1e12]),
+        ("param", "c1", [], [-1.0, 1.0]),
+        ("param", "c2", [], [-1.0, 1.0]),
+        ("gauss", "sig", ["x", "mu", "sigma"], []),
+        ("cheb", "bkg", ["x", "c1", "c2"], []),
+        ("linear", "nu", ["nu_s", "nu_b"], [0.0, 1.0, 1.0]),
+        ("ratio", "f", ["nu_s", "nu"], []),
+        ("add", "mix", ["sig", "bkg", "f"], []),
+        ("extended", "model", ["mix", "nu"], []),
+    ]
+
+
 def spec_decay_argus():
     """Signal: [decay(tau_s) (x) Gauss resolution(sigma_t, bias_t)](t) * Gauss(m; mu_m, sigma_m);
     background: exp(-t/tau_b) * ARGUS(m; m0 = 5.29 constant, c); fraction f.

@@ -553,3 +553,49 @@ def test_oracle_weights_are_linear():
     a, b, c = (om.nll_ex(top, th, cols, weights=w) for w in (w1, w2, w1 + w2))
     assert abs(c[0] - (a[0] + b[0])) <= 1e-13 * (abs(a[0]) + abs(b[0]))
     np.testing.assert_allclose(c[1], a[1] + b[1], rtol=0, atol=1e-12 * (np.abs(a[2]) + np.abs(b[2])).max())
+
+
+# ---- extended likelihood: -sum_i log(sum_k nu_k u_k(x_i)) + sum_k nu_k ------
+def _leaf_values(kind, th, x):
+    spec = [("obs", "x", [], [-10.0, 10.0]), ("param", "a", [], [-5, 5]), ("param", "b", [], [-5, 10]),
+            (kind, "leaf", ["x", "a", "b"], [])]
+    om, top, _ = rfo.from_spec(spec)
+    return om.values(top, th, [x])
+
+
+def test_oracle_extended_is_the_textbook_extended_likelihood():
+    """Yields as fractions nu_s / nu plus the term nu - N log nu equal the
+    textbook form built from the normalised components."""
+    x = synth.sample_gauss_cheb(500, 51)
+    mu, sg, ns, nb, c1, c2 = 0.2, 1.1, 180.0, 290.0, 0.15, -0.05
+    om, top, _ = rfo.from_spec(workloads.spec_gauss_cheb_extended())
+    nll, g, nbad = om.nll(top, [mu, sg, ns, nb, c1, c2], [x])
+    ug, uc = _leaf_values("gauss", [mu, sg], x), _leaf_values("cheb", [c1, c2], x)
+    ref = -np.sum(np.log(ns * ug + nb * uc)) + ns + nb
+    assert nbad == 0 and abs(nll - ref) <= 1e-13 * abs(ref)
+
+
+def test_oracle_extended_gradient_central_differences():
+    x = synth.sample_gauss_cheb(400, 52)
+    th = np.array([0.2, 1.1, 180.0, 290.0, 0.15, -0.05])
+    om, top, _ = rfo.from_spec(workloads.spec_gauss_cheb_extended())
+    _, g, ga, _ = om.nll_ex(top, th, [x])
+    for k in range(th.size):
+        h = 1e-6 * max(1.0, abs(th[k]))
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (om.nll(top, tp, [x], grad=False)[0] - om.nll(top, tm, [x], grad=False)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * ga[k], (k, fd, g[k])
+
+
+def test_oracle_extended_single_component_yield_stationary_at_n():
+    """One component: d NLL / d nu = 1 - N / nu, zero at nu = N."""
+    x = synth.sample_gauss_cheb(250, 53)
+    spec = [("obs", "x", [], [-10.0, 10.0]), ("param", "mu", [], [-5, 5]), ("param", "sigma", [], [0.05, 10]),
+            ("param", "nu", [], [0, 1e9]), ("gauss", "sig", ["x", "mu", "sigma"], []),
+            ("extended", "model", ["sig", "nu"], [])]
+    om, top, _ = rfo.from_spec(spec)
+    for nu in (100.0, 250.0, 400.0):
+        _, g, _ = om.nll(top, [0.1, 1.5, nu], [x])
+        assert abs(g[2] - (1.0 - 250.0 / nu)) <= 1e-14
