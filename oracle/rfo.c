@@ -482,6 +482,12 @@ static double leaf_value(const node* d, double x, const double* v, double* du) {
       du[0] = 2 * q * b * b; du[1] = -0.5 * G * b * b;
       return b;
     }
+    case RFO_POISSON: { /* the probability mass lambda^n e^-lambda / n! */
+      double lam = v[1];
+      double u = exp(x * log(lam) - lam - lgamma(x + 1.0));
+      du[0] = u * (x / lam - 1.0);
+      return u;
+    }
     case RFO_NUMCONV_BW_CB: {
       double M = v[1], G = v[2];
       nsum S = {0, 0}, dM = {0, 0}, dG = {0, 0}, ds = {0, 0}, da = {0, 0}, dn = {0, 0};
@@ -581,6 +587,18 @@ static int leaf_norm(node* d, const double* v, double* dN) {
       dN[0] = 0;
       dN[1] = 0.5 * m0 * m0 * (J3l - J3t);
       return 0;
+    }
+    case RFO_POISSON: { /* sum of the mass over the integers lo..hi */
+      double lam = v[1];
+      if (!(lam > 0)) FAIL(-2, "poisson: lambda <= 0");
+      nsum N = {0, 0}, D = {0, 0};
+      for (double k = ceil(lo); k <= hi; k += 1.0) {
+        double u = exp(k * log(lam) - lam - lgamma(k + 1.0));
+        nadd(&N, u);
+        nadd(&D, u * (k / lam - 1.0));
+      }
+      dN[0] = nval(&D);
+      d->N = nval(&N); return 0;
     }
     case RFO_BW: {
       double M = v[1], G = v[2];

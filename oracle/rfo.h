@@ -47,6 +47,8 @@ enum {
   RFO_MLP = 17,       /* in: x, q1..q5 ; attrs: 12 box bounds (lo,hi per
                          input; the first box is that of x - q1), K (grid
                          points on x's range)                        */
+  RFO_POISSON = 18,   /* in: n, lambda: lambda^n e^-lambda / n! on the integers
+                         of the observable's range [lo, hi] */
   RFO_ADD = 30,       /* in: pdf_1..pdf_n, f_1..f_{n-1}             */
   RFO_PROD = 31,      /* in: pdf_1..pdf_n (disjoint observables)    */
   RFO_EXTENDED = 32   /* in: pdf, nu; only as the top of an NLL: the

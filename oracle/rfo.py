@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "librfo.so")
 KIND = {
     "obs": 1, "param": 2, "const": 3, "linear": 4, "product": 5, "ratio": 6, "extended": 32,
     "gauss": 10, "cheb": 11, "exp": 12, "decay_gauss": 13, "argus": 14,
-    "bw": 15, "numconv_bw_cb": 16, "mlp": 17, "add": 30, "prod": 31,
+    "bw": 15, "numconv_bw_cb": 16, "mlp": 17, "poisson": 18, "add": 30, "prod": 31,
 }
 
 

@@ -90,6 +90,45 @@ def sample_gauss_cheb(n, seed, mu=0.0, sigma=1.0, f=0.3, c1=0.2, c2=-0.1,
     return _mixture(n, seed, f, sig, bkg)
 
 
+# --------------------------------------------------------------------------
+# 2-D with a count: per-event multiplicity n (Poisson) and a mass x;
+# signal Poisson(n; lam_s) Gauss(x; mu, sigma), background Poisson(n; lam_b)
+# times the order-2 Chebyshev polynomial, fraction f of signal
+# --------------------------------------------------------------------------
+POISSON_TRUTH = dict(lam_s=12.0, lam_b=5.0, mu=0.0, sigma=1.0, c1=0.2, c2=-0.1, f=0.3)
+POISSON_N_RANGE = (0.0, 40.0)
+
+
+def sample_poisson_gauss_cheb(n, seed, lam_s=12.0, lam_b=5.0, mu=0.0, sigma=1.0, c1=0.2, c2=-0.1, f=0.3,
+                              nlo=0.0, nhi=40.0, lo=-10.0, hi=10.0):
+    """Returns (counts, x): the component's count by numpy's Poisson draw,
+    rejected outside [nlo, nhi]; x as in sample_gauss_cheb."""
+    cand = [-1.0, 1.0]
+    if c2 != 0.0:
+        v = -c1 / (4.0 * c2)
+        if -1.0 <= v <= 1.0:
+            cand.append(v)
+    hmax = max(1.0 + c1 * t + c2 * (2 * t * t - 1) for t in cand)
+
+    def sig(rng, m):
+        k = rng.poisson(lam_s, m).astype(np.float64)
+        x = _f32(rng.normal(mu, sigma, m))
+        ok = _inside(k, nlo, nhi) & _inside(x, lo, hi)
+        return k[ok], x[ok]
+
+    def bkg(rng, m):
+        k = rng.poisson(lam_b, m).astype(np.float64)
+        t = rng.uniform(-1.0, 1.0, m)
+        acc = rng.random(m) * hmax <= 1.0 + c1 * t + c2 * (2 * t * t - 1)
+        x = _f32(0.5 * (hi - lo) * t + 0.5 * (hi + lo))
+        ok = acc & _inside(k, nlo, nhi) & _inside(x, lo, hi)
+        return k[ok], x[ok]
+
+    if n == 0:
+        return np.zeros(0), np.zeros(0)
+    return _mixture(n, seed, f, sig, bkg)
+
+
 def jitter_gauss_cheb(k, truth=GAUSS_CHEB_TRUTH, base_seed=1000):
     """Parameter point k of the +-10% jitter: theta_j = truth_j + 0.1 s_j U(-1,1),
     s_j = |truth_j| (1 for a zero truth value), one uniform per parameter in the

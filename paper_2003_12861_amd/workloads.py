@@ -46,6 +46,30 @@ def spec_gauss_cheb_extended(lo=-10.0, hi=10.0):
     ]
 
 
+def spec_poisson_gauss_cheb(nlo=0.0, nhi=40.0, lo=-10.0, hi=10.0):
+    """Multiplicity n and mass x: f * Poisson(n; lam_s) Gauss(x; mu, sigma) +
+    (1 - f) * Poisson(n; lam_b) Chebyshev2(x; c1, c2), each Poisson normalised
+    over the integers nlo..nhi; theta = (lam_s, lam_b, mu, sigma, c1, c2, f)."""
+    return [
+        ("obs", "n", [], [nlo, nhi]),
+        ("obs", "x", [], [lo, hi]),
+        ("param", "lam_s", [], [0.1, 40.0]),
+        ("param", "lam_b", [], [0.1, 40.0]),
+        ("param", "mu", [], [-5.0, 5.0]),
+        ("param", "sigma", [], [0.05, 10.0]),
+        ("param", "c1", [], [-1.0, 1.0]),
+        ("param", "c2", [], [-1.0, 1.0]),
+        ("param", "f", [], [0.0, 1.0]),
+        ("poisson", "sig_n", ["n", "lam_s"], []),
+        ("gauss", "sig_x", ["x", "mu", "sigma"], []),
+        ("prod", "sig", ["sig_n", "sig_x"], []),
+        ("poisson", "bkg_n", ["n", "lam_b"], []),
+        ("cheb", "bkg_x", ["x", "c1", "c2"], []),
+        ("prod", "bkg", ["bkg_n", "bkg_x"], []),
+        ("add", "model", ["sig", "bkg", "f"], []),
+    ]
+
+
 def spec_decay_argus():
     """Signal: [decay(tau_s) (x) Gauss resolution(sigma_t, bias_t)](t) * Gauss(m; mu_m, sigma_m);
     background: exp(-t/tau_b) * ARGUS(m; m0 = 5.29 constant, c); fraction f.

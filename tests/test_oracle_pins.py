@@ -599,3 +599,73 @@ def test_oracle_extended_single_component_yield_stationary_at_n():
     for nu in (100.0, 250.0, 400.0):
         _, g, _ = om.nll(top, [0.1, 1.5, nu], [x])
         assert abs(g[2] - (1.0 - 250.0 / nu)) <= 1e-14
+
+
+# ---- unbinned Poisson PDF of an integer observable -------------------------
+def _poisson_leaf(lo, hi):
+    spec = [("obs", "n", [], [lo, hi]), ("param", "lam", [], [0.1, 100.0]), ("poisson", "p", ["n", "lam"], [])]
+    om, top, _ = rfo.from_spec(spec)
+    return om, top
+
+
+@pytest.mark.parametrize("lo,hi,lam", [(0.0, 60.0, 7.3), (3.0, 15.0, 9.0), (20.0, 400.0, 55.5), (0.0, 1.0, 0.4)])
+def test_poisson_leaf_vs_scipy_truncated(lo, hi, lam):
+    """Values are scipy's Poisson mass renormalised over the integers lo..hi."""
+    om, top = _poisson_leaf(lo, hi)
+    n = np.arange(lo, hi + 1.0)
+    v = om.values(top, [lam], [n])
+    z = stats.poisson.cdf(hi, lam) - stats.poisson.cdf(lo - 1, lam)
+    ref = stats.poisson.pmf(n, lam) / z
+    assert np.max(np.abs(v / ref - 1.0)) <= 2e-12
+    assert abs(v.sum() - 1.0) <= 1e-13
+
+
+def test_poisson_mle_is_the_sample_mean():
+    """With a range holding all the mass, d NLL / d lambda = N - sum n / lambda,
+    which vanishes at the sample mean."""
+    rng = np.random.default_rng(61)
+    n = rng.poisson(10.0, 2000).astype(np.float64)
+    om, top = _poisson_leaf(0.0, 300.0)
+    for lam in (6.0, n.mean(), 14.5):
+        _, g, _ = om.nll(top, [lam], [n])
+        ref = n.size - n.sum() / lam
+        assert abs(g[0] - ref) <= 1e-11 * n.sum() / lam
+    nll_at = lambda lam: om.nll(top, [lam], [n], grad=False)[0]
+    assert nll_at(n.mean()) < min(nll_at(n.mean() * 0.99), nll_at(n.mean() * 1.01))
+
+
+def test_poisson_truncation_gradient_central_differences():
+    """A range that cuts the mass on both sides makes d log N / d lambda
+    matter; the analytic gradient must follow the finite differences."""
+    rng = np.random.default_rng(62)
+    n = np.clip(rng.poisson(9.0, 500), 4, 13).astype(np.float64)
+    om, top = _poisson_leaf(4.0, 13.0)
+    _, g, ga, _ = om.nll_ex(top, [8.7], [n])
+    h = 1e-5
+    fd = (om.nll(top, [8.7 + h], [n], grad=False)[0] - om.nll(top, [8.7 - h], [n], grad=False)[0]) / (2 * h)
+    assert abs(fd - g[0]) <= 1e-7 * ga[0]
+    assert abs(g[0] - (n.size - n.sum() / 8.7)) > 1.0  # the truncation term is not negligible here
+
+
+def test_poisson_gauss_cheb_mixture_vs_scipy():
+    """The 2-D count x mass mixture equals the mixture assembled from scipy's
+    Poisson mass (renormalised over the count range) and the normalised
+    Gauss and Chebyshev leaves."""
+    k, x = synth.sample_poisson_gauss_cheb(600, 63)
+    th = [11.0, 5.5, 0.1, 1.2, 0.15, -0.05, 0.35]
+    om, top, _ = rfo.from_spec(workloads.spec_poisson_gauss_cheb())
+    nll, g, ga, nbad = om.nll_ex(top, th, [k, x])
+    z = lambda lam: stats.poisson.cdf(40, lam) - stats.poisson.cdf(-1, lam)
+    ps = stats.poisson.pmf(k, th[0]) / z(th[0])
+    pb = stats.poisson.pmf(k, th[1]) / z(th[1])
+    ug, uc = _leaf_values("gauss", th[2:4], x), _leaf_values("cheb", th[4:6], x)
+    ref = -np.sum(np.log(th[6] * ps * ug + (1 - th[6]) * pb * uc))
+    assert nbad == 0 and abs(nll - ref) <= 1e-12 * abs(ref)
+    th = np.array(th)
+    for j in range(th.size):
+        h = 1e-6 * max(1.0, abs(th[j]))
+        tp, tm = th.copy(), th.copy()
+        tp[j] += h
+        tm[j] -= h
+        fd = (om.nll(top, tp, [k, x], grad=False)[0] - om.nll(top, tm, [k, x], grad=False)[0]) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-6 * ga[j], (j, fd, g[j])
