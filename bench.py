@@ -18,6 +18,8 @@ Workloads (the default is the headline one):
   gauss_cheb_extended_1e7  the same mixture as an extended likelihood with
                         yields (nu_s, nu_b)
   decay_argus_5e7       2-D decay (x) resolution with mass peak, 5e7 events
+  poisson_gauss_cheb_1e7  2-D count x mass: Poisson(n) Gauss(x) signal,
+                        Poisson(n) Chebyshev(x) background, 1e7 events
   bwcb_exact_1e7        Breit-Wigner (x) Crystal Ball by the exact 1024-point
                         rule + exponential background, 1e7 events
   bwcb_surrogate_1e7    the same model with the MLP surrogate of the signal
@@ -72,15 +74,20 @@ SLOTS = {
     # extended: the same per-event program (the yield term is parameter-only)
     "gauss_cheb_extended_1e7": {"fp32": 48, "fp64": 90},
     "decay_argus_5e7": {"fp32": 165, "fp64": 400},
+    # the 1-D mixture's work, two Poisson leaves (an LDS table read each:
+    # index, clamp, conversion) and the two products' adjoint terms
+    "poisson_gauss_cheb_1e7": {"fp32": 68, "fp64": 112},
     "bwcb_exact_1e7": {"fp32": 16400, "fp64": 16400},
 }
 BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "gauss_cheb_weighted_1e7": {"fp32": 8, "fp64": 16},
                    "gauss_cheb_extended_1e7": {"fp32": 4, "fp64": 8},
                    "decay_argus_5e7": {"fp32": 8, "fp64": 16},
+                   "poisson_gauss_cheb_1e7": {"fp32": 8, "fp64": 16},
                    "bwcb_exact_1e7": {"fp32": 4, "fp64": 8}, "bwcb_surrogate_1e7": {"fp32": 4}}
 # surrogate: network multiply-adds per event (forward and input gradient)
 SURROGATE_MAC_PER_EVENT = 17300
-WORKLOADS = ("gauss_cheb_1e7", "gauss_cheb_weighted_1e7", "gauss_cheb_extended_1e7", "decay_argus_5e7", "bwcb_exact_1e7", "bwcb_surrogate_1e7",
+WORKLOADS = ("gauss_cheb_1e7", "gauss_cheb_weighted_1e7", "gauss_cheb_extended_1e7", "decay_argus_5e7",
+             "poisson_gauss_cheb_1e7", "bwcb_exact_1e7", "bwcb_surrogate_1e7",
              "binned_200x4x100x60")
 WEIGHTED = ("gauss_cheb_weighted_1e7",)  # the last column holds the event weights
 
@@ -120,6 +127,12 @@ def make(workload):
         return (workloads.spec_gauss_cheb_extended(), [synth.sample_gauss_cheb(n, 2)],
                 ext(workloads.truth_vector(synth.GAUSS_CHEB_TRUTH)),
                 [ext(synth.jitter_gauss_cheb(k)) for k in range(100)], ("fp32", "fp64"), None)
+    if workload == "poisson_gauss_cheb_1e7":
+        truth = np.asarray(workloads.truth_vector(synth.POISSON_TRUTH))
+        rng = np.random.default_rng(12)
+        thetas = [truth * (1.0 + 0.05 * rng.uniform(-1, 1, truth.size)) for _ in range(10)]
+        return (workloads.spec_poisson_gauss_cheb(), list(synth.sample_poisson_gauss_cheb(10_000_000, 5)), truth,
+                thetas, ("fp32", "fp64"), None)
     if workload == "decay_argus_5e7":
         return (workloads.spec_decay_argus(), list(synth.sample_decay_argus(50_000_000, 3)),
                 np.asarray(workloads.truth_vector(synth.DECAY_TRUTH)),

@@ -96,6 +96,10 @@ enum {
                                onto [-1,1] of (x - q1, q1..q5) with the boxes
                                (the first box is that of x - q1), normalised by a
                                K-point Gauss-Legendre sum over x's range; FP32 only */
+  RF_OP_POISSON = 9,        /* (n, lambda > 0): lambda^n e^-lambda / n!, an unbinned
+                               Poisson PDF; the observable holds integers and its
+                               range [lo, hi] has integer ends, 0 <= lo < hi,
+                               hi - lo < 2048 (normalised over lo..hi) */
   RF_OP_ADD_PDF = 20,       /* (pdf_1..pdf_n, f_1..f_{n-1}): sum_j f_j pdf_j +
                                (1 - sum f) pdf_n, each pdf normalised            */
   RF_OP_PROD_PDF = 21,      /* (pdf_1..pdf_n) over disjoint observables           */

@@ -19,7 +19,7 @@ FP64, FP32 = 0, 1
 RF_COMPILE_NO_LOAD, RF_VALIDATE, RF_COMPILE_WEIGHTED = 1, 2, 4
 OPS = {
     "gauss": 1, "cheb": 2, "exp": 3, "decay_gauss": 4, "argus": 5, "bw": 6,
-    "numconv_bw_cb": 7, "mlp": 8, "add": 20, "prod": 21, "extended": 22, "linear": 40, "product": 41, "ratio": 42,
+    "numconv_bw_cb": 7, "mlp": 8, "poisson": 9, "add": 20, "prod": 21, "extended": 22, "linear": 40, "product": 41, "ratio": 42,
 }
 STATUS = {0: "RF_OK", -1: "RF_E_INVALID", -2: "RF_E_DOMAIN", -3: "RF_E_NONFINITE",
           -4: "RF_E_DEVICE", -5: "RF_E_OOM", -6: "RF_E_STATE"}

@@ -397,8 +397,8 @@ const double* rf_program_result(const rf_program* p) { return p ? p->d_out : nul
 
 int rf_unfused_build(const rf_program* p) {
   if (!p) return fail(RF_E_INVALID, "program is NULL");
-  if (p->L.has_mlp || p->L.has_numconv || p->L.weighted || p->L.ext_nu >= 0)
-    return fail(RF_E_INVALID, "the unfused mode takes unweighted, non-extended programs without convolution or MLP leaves");
+  if (p->L.has_mlp || p->L.has_numconv || p->L.has_poisson || p->L.weighted || p->L.ext_nu >= 0)
+    return fail(RF_E_INVALID, "the unfused mode takes unweighted, non-extended programs without convolution, MLP or Poisson leaves");
   std::string path;
   return build_code_object(generate_source(p->L, p->block, p->ept, p->pfd, p->tg, p->prio, true), path);
 }
@@ -407,8 +407,8 @@ int rf_nll_unfused(rf_program* p, const double* theta, double* nll, int64_t* n_b
   int rc = ready(p, theta);
   if (rc) return rc;
   if (!nll) return fail(RF_E_INVALID, "nll is NULL");
-  if (p->L.has_mlp || p->L.has_numconv || p->L.weighted || p->L.ext_nu >= 0)
-    return fail(RF_E_INVALID, "the unfused mode takes unweighted, non-extended programs without convolution or MLP leaves");
+  if (p->L.has_mlp || p->L.has_numconv || p->L.has_poisson || p->L.weighted || p->L.ext_nu >= 0)
+    return fail(RF_E_INVALID, "the unfused mode takes unweighted, non-extended programs without convolution, MLP or Poisson leaves");
   rf_program::Unfused& u = p->unf;
   hipError_t e;
   if (!u.mod) {

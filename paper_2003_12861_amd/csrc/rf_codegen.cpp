@@ -50,6 +50,7 @@ static std::string ktype(const Node& n) {
     case RF_OP_BW: return "BwK<T>";
     case RF_OP_NUMCONV_BW_CB: return "NumconvK<T, RF_TABT>";
     case RF_OP_MLP: return "MlpK<T>";
+    case RF_OP_POISSON: return "PoissonK<T>";
   }
   return "void";
 }
@@ -66,6 +67,7 @@ static std::string eval_call(const Node& n, int id, const std::string& x) {
     case RF_OP_NUMCONV_BW_CB:
       return "numconv_eval<T, RF_TABT, " + std::to_string((int)n.attrs[2]) + ">(" + x + ", " + k + ", " + d + ")";
     case RF_OP_MLP: return "mlp_leaf_eval<T, RF_NSPLIT, MODE == 2>(" + x + ", " + k + ", " + d + ")";
+    case RF_OP_POISSON: return "poisson_eval<T>(" + x + ", " + k + ", " + d + ")";
   }
   return "";
 }
@@ -81,11 +83,14 @@ static std::string dscale(const Node& n, int off, int j) {
     case RF_OP_EXP: return n.attrs[0] == 0.0 ? c(4) : "1.0";
     case RF_OP_BW: return j == 0 ? "2.0" : c(5);
     case RF_OP_CHEB: return "0.5";
+    case RF_OP_POISSON: return c(4);  // 1/lambda
   }
   return "1.0";
 }
 
-static bool blockwide(const Node& n) { return n.op == RF_OP_NUMCONV_BW_CB || n.op == RF_OP_MLP; }
+static bool blockwide(const Node& n) {
+  return n.op == RF_OP_NUMCONV_BW_CB || n.op == RF_OP_MLP || n.op == RF_OP_POISSON;
+}
 
 static std::string prologue_call(const Node& n, const Lowered& L, const std::string& in) {
   const auto& g = L.nodes;
@@ -243,6 +248,7 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     }
     o << RF_DEV_SRC_MLP << "\n#define RF_NSPLIT " << nsplit << "\n";
   }
+  if (L.has_poisson) o << RF_DEV_SRC_POISSON << "\n";
   o << "#define RF_T " << (f32 ? "float" : "double") << "\n";
   o << "#define RF_PREC " << (f32 ? "f32" : "f64") << "\n";
   // loaded columns: the observables, then the event weights of a weighted program
@@ -294,6 +300,12 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
       o << "__shared__ float rf_mlpsav_" << id << "[RF_BS / 64 * 32 * 64];\n";
       continue;
     }
+    if (g[id].op == RF_OP_POISSON) {
+      const Node& ob = g[g[id].in[0]];
+      o << "__shared__ double rf_ptab_" << id << "[" << (int)(ob.hi - ob.lo) + 1 << "];\n";
+      o << "__shared__ double rf_pscr_" << id << "[RF_BS / 64 * 2];\n";
+      continue;
+    }
     any_tab = true;
     o << "__shared__ RF_TABT rf_tab_" << id << "[" << (int)g[id].attrs[2] << " * NumconvRow<RF_TABT>::stride];\n";
   }
@@ -336,6 +348,9 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     if (!L.reach[id]) continue;
     if (g[id].op == RF_OP_MLP)
       o << "    k.l" << id << " = MlpK<T>::make(C + " << L.cst_off[id] << ", &rf_mlp_" << id << ", rf_mlpsav_" << id << ");\n";
+    else if (g[id].op == RF_OP_POISSON)
+      o << "    k.l" << id << " = PoissonK<T>::make(C + " << L.cst_off[id] << ", rf_ptab_" << id << ", "
+        << (int)g[g[id].in[0]].lo << ", " << (int)(g[g[id].in[0]].hi - g[g[id].in[0]].lo) + 1 << ");\n";
     else if (blockwide(g[id]))
       o << "    k.l" << id << " = " << ktype(g[id]) << "::make(C + " << L.cst_off[id] << ", rf_tab_" << id << ");\n";
     else if (is_leaf(g[id].op))
@@ -386,6 +401,11 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     o << "  {\n    const double in[] = {";
     for (size_t j = 1; j < n.in.size(); ++j) o << (j > 1 ? ", " : "") << "pv" << n.in[j];
     o << "};\n";
+    if (n.op == RF_OP_POISSON) {
+      o << "    poisson_prologue<RF_BS>(in, " << (int)ob.lo << ", " << (int)(ob.hi - ob.lo) + 1 << ", a.aux + "
+        << L.aux_off[id] << ", cst + " << L.cst_off[id] << ", rf_ptab_" << id << ", rf_pscr_" << id << ");\n  }\n";
+      continue;
+    }
     if (n.op == RF_OP_MLP) {
       o << "    const double box[12] = {";
       for (int j = 0; j < 12; ++j) o << (j ? ", " : "") << dstr(n.attrs[j]);

@@ -27,7 +27,7 @@ int hip_fail(hipError_t e, const char* what) {
 }
 const char* last_error() { return g_err.c_str(); }
 
-bool is_leaf(int op) { return op >= RF_OP_GAUSS && op <= RF_OP_MLP; }
+bool is_leaf(int op) { return op >= RF_OP_GAUSS && op <= RF_OP_POISSON; }
 bool is_pdf(int op) { return is_leaf(op) || op == RF_OP_ADD_PDF || op == RF_OP_PROD_PDF; }
 bool is_paramlike(int op) {
   return op == K_PARAM || op == K_CONST || op == RF_OP_FN_LINEAR || op == RF_OP_FN_PRODUCT || op == RF_OP_FN_RATIO;
@@ -44,6 +44,7 @@ static int leaf_ncst(const Node& n) {
     case RF_OP_ARGUS: return 6;
     case RF_OP_BW: return 6;
     case RF_OP_NUMCONV_BW_CB: return 8;
+    case RF_OP_POISSON: return 5;
     case RF_OP_MLP: return 23;  // 8 + the analytic base's constants
   }
   return 0;
@@ -81,6 +82,14 @@ static int check_leaf(const std::vector<Node>& g, const Node& n) {
           return fail(RF_E_INVALID, "numconv: attrs (ylo < yhi, integer K in [2, 1024])");
       }
       break;
+    case RF_OP_POISSON: {
+      rc = want(2, 0);
+      const Node& ob = g[n.in[0]];
+      if (!rc && !(ob.lo >= 0 && ob.lo == std::floor(ob.lo) && ob.hi == std::floor(ob.hi) && ob.lo < ob.hi &&
+                   ob.hi - ob.lo < 2048))
+        return fail(RF_E_INVALID, "poisson: the observable's range needs integer ends, 0 <= lo < hi, hi - lo < 2048");
+      break;
+    }
     case RF_OP_MLP:
       rc = want(6, 13);
       if (!rc) {
@@ -163,6 +172,7 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
       if (rc) return rc;
       obs[id] = 1u << g[n.in[0]].index;
       if (n.op == RF_OP_NUMCONV_BW_CB) L.has_numconv = true;
+      if (n.op == RF_OP_POISSON) L.has_poisson = true;
       if (n.op == RF_OP_MLP) { L.has_mlp = true; L.mlp_nodes.push_back(id); }
     }
     if (n.op == RF_OP_PROD_PDF) {
@@ -211,6 +221,12 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
       L.aux_off[id] = (int)L.aux.size();
       L.aux.resize(L.aux.size() + 2 * K);
       gauss_legendre(K, g[id].attrs[0], g[id].attrs[1], &L.aux[L.aux_off[id]], &L.aux[L.aux_off[id] + K]);
+    } else if (g[id].op == RF_OP_POISSON) {
+      // log k! for the observable's integer range
+      const Node& ob = g[g[id].in[0]];
+      const int lo = (int)ob.lo, K = (int)ob.hi - lo + 1;
+      L.aux_off[id] = (int)L.aux.size();
+      for (int k = lo; k < lo + K; ++k) L.aux.push_back(std::lgamma((double)k + 1.0));
     } else if (g[id].op == RF_OP_MLP) {
       const int K = (int)g[id].attrs[12];
       const Node& ob = g[g[id].in[0]];
@@ -315,6 +331,9 @@ int check_theta(const Lowered& L, const double* theta) {
     if (n.op == RF_OP_FN_RATIO && !(in(1) != 0 && std::isfinite(pv[id])))
       return fail(RF_E_DOMAIN, n.name + ": ratio with a zero denominator or a non-finite result");
     switch (n.op) {
+      case RF_OP_POISSON:
+        if (!(in(1) > 0)) return fail(RF_E_DOMAIN, n.name + ": lambda must be > 0");
+        break;
       case RF_OP_GAUSS:
         if (!(in(2) > 0)) return fail(RF_E_DOMAIN, n.name + ": sigma must be > 0");
         break;

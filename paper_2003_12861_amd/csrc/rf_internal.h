@@ -61,7 +61,7 @@ struct Lowered {
   std::vector<int> ysum;           // per canonical node: index of Y_c (or -1)
   std::vector<Slot> slots;
   int n_sums = 0;                  // including sum 0 (= NLL)
-  bool has_numconv = false, has_mlp = false;
+  bool has_numconv = false, has_mlp = false, has_poisson = false;
   std::vector<double> aux;         // FP64 device inputs (Gauss-Legendre rules, ...)
   std::vector<int> aux_off;        // per node: offset into aux (or -1)
   std::vector<int> mlp_nodes;      // MLP leaves (need bound weights)

@@ -70,6 +70,11 @@ def spec_poisson_gauss_cheb(nlo=0.0, nhi=40.0, lo=-10.0, hi=10.0):
     ]
 
 
+def spec_poisson(lo, hi, lam_lo=0.1, lam_hi=2000.0):
+    """One Poisson leaf of a count n on the integers lo..hi; theta = (lam,)."""
+    return [("obs", "n", [], [lo, hi]), ("param", "lam", [], [lam_lo, lam_hi]), ("poisson", "p", ["n", "lam"], [])]
+
+
 def spec_decay_argus():
     """Signal: [decay(tau_s) (x) Gauss resolution(sigma_t, bias_t)](t) * Gauss(m; mu_m, sigma_m);
     background: exp(-t/tau_b) * ARGUS(m; m0 = 5.29 constant, c); fraction f.

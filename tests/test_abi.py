@@ -189,3 +189,24 @@ def test_host_gauss_legendre(lib):
     # exact for x^8 on [-1, 1]: 2/9
     assert abs(sum(wi * xi ** 8 for xi, wi in zip(x, w)) - 2.0 / 9.0) < 1e-14
     assert lib.rf_gauss_legendre(0, -1.0, 1.0, x, w) == RF_E_INVALID
+
+
+def test_poisson_range_checks(lib):
+    """The Poisson leaf needs an observable range with integer ends,
+    0 <= lo < hi and at most 2048 values; a good one compiles on the host."""
+    op = _consts()
+    for lo, hi, ok in [(0.0, 40.0, True), (0.5, 40.0, False), (-1.0, 40.0, False), (0.0, 2047.0, True),
+                       (0.0, 2048.0, False), (2.0, 7.5, False)]:
+        g = G(lib)
+        n = g.obs("n", lo, hi)
+        lam = g.par("lam", 0.1, 100.0)
+        rc, p = g.node(op["RF_OP_POISSON"], "p", [n, lam])
+        if rc == RF_OK:
+            rc, prog = _compile(lib, g, p, RF_FP64)
+        assert (rc == RF_OK) == ok, (lo, hi, rc, lib.rf_last_error())
+        if rc == RF_OK:
+            assert "poisson_prologue" in lib.rf_program_source(prog).decode()
+            lib.rf_program_free(prog)
+        else:
+            assert b"poisson" in lib.rf_last_error()
+        g.free()
