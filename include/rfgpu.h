@@ -104,9 +104,10 @@ enum {
                                (1 - sum f) pdf_n, each pdf normalised            */
   RF_OP_PROD_PDF = 21,      /* (pdf_1..pdf_n) over disjoint observables           */
   RF_OP_EXTENDED = 22,      /* (pdf, nu param-like > 0), only as the compiled top of
-                               an unweighted program: the extended likelihood.  Event
+                               a program: the extended likelihood.  Event
                                values are pdf's; the NLL gains nu - N log nu (N the
-                               number of bound events), i.e. it is, up to the
+                               number of bound events; in a weighted program the
+                               sum of the weights), i.e. it is, up to the
                                constant log N!, -sum_i log(nu p_i) + nu.  Yields of
                                a sum: fractions nu_j / nu_tot (RF_OP_FN_RATIO) and
                                nu = nu_tot (RF_OP_FN_LINEAR of the yields). */

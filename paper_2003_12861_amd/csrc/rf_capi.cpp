@@ -180,10 +180,13 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
   if (rc) { delete p; return rc; }
   p->flags = flags;
   p->L.weighted = (flags & RF_COMPILE_WEIGHTED) ? 1 : 0;
-  if (p->L.ext_nu >= 0 && (p->L.weighted || p->L.n_params >= RF_MAX_PARAMS)) {
+  if (p->L.ext_nu >= 0 && p->L.n_params >= RF_MAX_PARAMS) {
     delete p;
-    return fail(RF_E_INVALID, "an extended program is unweighted and has at most 63 parameters");
+    return fail(RF_E_INVALID, "an extended program has at most 63 parameters");
   }
+  // weighted extended likelihood: N of the extended term is the sum of the
+  // weights, accumulated by the kernel as one more sum
+  if (p->L.ext_nu >= 0 && p->L.weighted) p->L.wsum = p->L.n_sums++;
   if (p->L.n_cols + p->L.weighted > RF_MAX_COLS) {
     delete p;
     return fail(RF_E_INVALID, "a weighted program takes at most 7 observables");

@@ -453,6 +453,7 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     // log p and through r = 1/p, which all adjoint terms share
     o << "  const T wt = x[" << L.n_cols << "];\n";
     o << "  acc[0] += ok ? wt * RM<T>::log_acc(p) : (T)0;\n";
+    if (L.wsum >= 0) o << "  acc[" << L.wsum << "] += wt;\n";
     o << "  if (MODE == 2) {\n";
     o << "    const T r = ok ? RM<T>::rcp(p) * wt : (T)0;\n";
   } else {
@@ -505,10 +506,12 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
   o << "template <int MODE>\n";
   o << "RF_DEV void rf_epilogue(const double* S, const double* cst, const double* th, double* out, unsigned nbad) {\n";
   if (L.ext_nu >= 0) {
-    // extended likelihood: + nu - N log nu, N (the number of events) passed
-    // after the parameters
+    // extended likelihood: + nu - N log nu, N the number of events (passed
+    // after the parameters) or, with weights, their sum over all events
     emit_paramlike(o, L, "  ");
-    o << "  const double ext_n = th[" << L.n_params << "], ext_nu = pv" << L.ext_nu << ";\n";
+    o << "  const double ext_n = "
+      << (L.wsum >= 0 ? "S[" + std::to_string(L.wsum) + "]" : "th[" + std::to_string(L.n_params) + "]")
+      << ", ext_nu = pv" << L.ext_nu << ";\n";
     o << "  out[0] = -S[0] + (ext_nu - ext_n * ::log(ext_nu));\n";
     o << "  out[" << L.n_params + 1 << "] = (double)nbad;\n";
     o << "  if (MODE != 2) return;\n";

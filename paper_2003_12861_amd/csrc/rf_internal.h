@@ -48,6 +48,7 @@ struct Lowered {
   int n_params = 0, n_cols = 0;    // n_cols: observables
   int weighted = 0;                // one more column: per-event weights
   int ext_nu = -1;                 // extended likelihood: node of nu (-1: not extended)
+  int wsum = -1;                   // weighted extended likelihood: index of the sum of weights
   std::vector<double> plo, phi;    // parameter bounds
   std::vector<char> reach;
   std::vector<int> cst_off;        // per node: offset of its FP64 constant block

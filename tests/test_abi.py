@@ -210,3 +210,26 @@ def test_poisson_range_checks(lib):
         else:
             assert b"poisson" in lib.rf_last_error()
         g.free()
+
+
+def test_weighted_extended_adds_a_sum(lib):
+    """A weighted extended program accumulates the sum of the weights as one
+    more event sum; the extended term reads it in place of the event count."""
+    op = _consts()
+    res = {}
+    for flags in (RF_COMPILE_NO_LOAD, RF_COMPILE_NO_LOAD | 4):  # 4: RF_COMPILE_WEIGHTED
+        g = G(lib)
+        x = g.obs("x", -10.0, 10.0)
+        mu, s, nu = g.par("mu", -5, 5), g.par("sigma", 0.05, 10), g.par("nu", 0, 1e9)
+        _, gs = g.node(op["RF_OP_GAUSS"], "sig", [x, mu, s])
+        _, e = g.node(op["RF_OP_EXTENDED"], "model", [gs, nu])
+        rc, p = _compile(lib, g, e, RF_FP64, flags)
+        assert rc == RF_OK, lib.rf_last_error()
+        npar, ncol, nsum = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert lib.rf_program_info(p, ctypes.byref(npar), ctypes.byref(ncol), ctypes.byref(nsum)) == RF_OK
+        res[flags] = (ncol.value, nsum.value, lib.rf_program_source(p).decode())
+        lib.rf_program_free(p)
+        g.free()
+    (c0, s0, src0), (c1, s1, src1) = res.values()
+    assert (c1, s1) == (c0 + 1, s0 + 1)
+    assert "ext_n = th[3]" in src0 and ("ext_n = S[%d]" % s0) in src1

@@ -43,3 +43,32 @@ def test_extended_fit_total_yield_is_the_event_count():
     assert abs(th[2] + th[3] - n) <= 1e-3 * np.sqrt(n), (th, n)
     # signal fraction near the sample's (0.3), yields' uncertainties ~ sqrt
     assert abs(th[2] / n - 0.3) < 5 * sig[2] / n
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.FP32])
+@pytest.mark.parametrize("n", [1, 100_003])
+def test_weighted_extended_parity(prec, n):
+    """Weighted events in the extended likelihood: N of the term is the sum of
+    the weights, formed on the GPU as one more event sum."""
+    print("case weighted extended n=%d prec=%d" % (n, prec), flush=True)
+    x = synth.sample_gauss_cheb(n, 33)
+    w = np.random.default_rng(34).uniform(-0.5, 2.0, n).astype(np.float32).astype(np.float64)
+    nw = float(np.sum(w))
+    th = [0.2, 1.1, abs(0.3 * nw) + 0.5, abs(0.7 * nw) + 0.25, 0.15, -0.05]
+    prog, (om, otop, _) = build_pair(workloads.spec_gauss_cheb_extended(), prec, api, weighted=True)
+    prog.bind(to_dev([x, w], prec, api))
+    nll, g, nb = prog.nll_grad(th)
+    onll, og, oga, onb = om.nll_ex(otop, th, [x], weights=w)
+    assert nb == onb == 0
+    tn, tg = TOL[prec]
+    nu = th[2] + th[3]
+    v = om.values(otop, th, [x])
+    scale = float(np.sum(np.abs(w * np.log(v)))) + nu + np.sum(np.abs(w)) * abs(np.log(nu))
+    assert abs(nll - onll) <= tn * scale, (nll, onll)
+    assert scaled_grad_err(g, og, oga).max() <= tg
+    # unit weights reproduce the unweighted extended program
+    prog.bind(to_dev([x, np.ones(n)], prec, api))
+    ref, _ = build_pair(workloads.spec_gauss_cheb_extended(), prec, api)
+    ref.bind(to_dev([x], prec, api))
+    a, b = prog.nll_grad(th)[0], ref.nll_grad(th)[0]
+    assert abs(a - b) <= 1e-14 * max(1.0, abs(b)), (a, b)

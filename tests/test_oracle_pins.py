@@ -669,3 +669,17 @@ def test_poisson_gauss_cheb_mixture_vs_scipy():
         tm[j] -= h
         fd = (om.nll(top, tp, [k, x], grad=False)[0] - om.nll(top, tm, [k, x], grad=False)[0]) / (2 * h)
         assert abs(fd - g[j]) <= 1e-6 * ga[j], (j, fd, g[j])
+
+
+def test_oracle_weighted_extended_equals_repeated_events():
+    """Integer weights in the extended likelihood: N becomes the sum of the
+    weights, and the result equals the unweighted extended NLL of the sample
+    with each event repeated w_i times."""
+    x = synth.sample_gauss_cheb(300, 54)
+    w = np.random.default_rng(55).integers(0, 4, x.size).astype(np.float64)
+    th = [0.2, 1.1, 150.0, 320.0, 0.15, -0.05]
+    om, top, _ = rfo.from_spec(workloads.spec_gauss_cheb_extended())
+    a, ga, _, _ = om.nll_ex(top, th, [x], weights=w)
+    b, gb, _, _ = om.nll_ex(top, th, [np.repeat(x, w.astype(int))])
+    assert abs(a - b) <= 1e-12 * abs(b)
+    np.testing.assert_allclose(ga, gb, rtol=1e-11, atol=1e-9)
