@@ -184,8 +184,9 @@ int rf_nll_grad(rf_program* p, const double* theta, double* nll, double* grad,
  * that node's values for all events into an array), kept as an ablation of the
  * fused kernel: one kernel per PDF node writes the node's value of every event
  * into its own array in device memory (inputs before users), then the NLL of
- * the top node's array is summed in a fixed order.  NLL only; unweighted
- * programs without convolution or MLP leaves (RF_E_INVALID otherwise).  The
+ * the top node's array is summed in a fixed order (weighted and extended
+ * programs included).  NLL only; programs without MLP leaves (RF_E_INVALID
+ * otherwise: the surrogate evaluates whole wavefronts on MFMA).  The
  * first call builds its code object; the node arrays (PDF nodes x n_events
  * values of the program dtype) are allocated on first use and kept with the
  * program.  Synchronous; n_bad may be NULL. */

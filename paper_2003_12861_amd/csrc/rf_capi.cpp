@@ -364,7 +364,9 @@ int rf_nll(rf_program* p, const double* theta, double* nll, int64_t* n_bad, void
   int rc = ready(p, theta);
   if (rc) return rc;
   if (!nll) return fail(RF_E_INVALID, "nll is NULL");
-  rc = run_sync(p, p->m.k_nll, theta, stream);
+  // a weighted extended NLL needs the sum of the weights, which only the
+  // gradient kernel accumulates; its result block has the NLL in the same place
+  rc = run_sync(p, p->L.wsum >= 0 ? p->m.k_grad : p->m.k_nll, theta, stream);
   if (rc) return rc;
   const int64_t bad = (int64_t)p->h_out[p->L.n_params + 1];
   if (n_bad) *n_bad = bad;
@@ -400,8 +402,7 @@ const double* rf_program_result(const rf_program* p) { return p ? p->d_out : nul
 
 int rf_unfused_build(const rf_program* p) {
   if (!p) return fail(RF_E_INVALID, "program is NULL");
-  if (p->L.has_mlp || p->L.has_numconv || p->L.has_poisson || p->L.weighted || p->L.ext_nu >= 0)
-    return fail(RF_E_INVALID, "the unfused mode takes unweighted, non-extended programs without convolution, MLP or Poisson leaves");
+  if (p->L.has_mlp) return fail(RF_E_INVALID, "the unfused mode takes programs without MLP leaves");
   std::string path;
   return build_code_object(generate_source(p->L, p->block, p->ept, p->pfd, p->tg, p->prio, true), path);
 }
@@ -410,8 +411,7 @@ int rf_nll_unfused(rf_program* p, const double* theta, double* nll, int64_t* n_b
   int rc = ready(p, theta);
   if (rc) return rc;
   if (!nll) return fail(RF_E_INVALID, "nll is NULL");
-  if (p->L.has_mlp || p->L.has_numconv || p->L.has_poisson || p->L.weighted || p->L.ext_nu >= 0)
-    return fail(RF_E_INVALID, "the unfused mode takes unweighted, non-extended programs without convolution, MLP or Poisson leaves");
+  if (p->L.has_mlp) return fail(RF_E_INVALID, "the unfused mode takes programs without MLP leaves");
   rf_program::Unfused& u = p->unf;
   hipError_t e;
   if (!u.mod) {
@@ -452,7 +452,7 @@ int rf_nll_unfused(rf_program* p, const double* theta, double* nll, int64_t* n_b
     if (u.part) (void)hipFree(u.part);
     u.part = nullptr;
     u.part_n = 0;
-    if ((e = hipMalloc(&u.part, sizeof(double) * 2 * G)) != hipSuccess) return hip_fail(e, "hipMalloc (partials)");
+    if ((e = hipMalloc(&u.part, sizeof(double) * 3 * G)) != hipSuccess) return hip_fail(e, "hipMalloc (partials)");
     u.part_n = (int)G;
   }
   if (!u.out && (e = hipMalloc(&u.out, sizeof(double) * 2)) != hipSuccess) return hip_fail(e, "hipMalloc");

@@ -203,31 +203,50 @@ static void emit_unfused(std::ostringstream& o, const Lowered& L) {
     }
     o << "  }\n  (void)k;\n}\n\n";
   }
+  // NLL kernel: per-workgroup partials of sum w_i log p_i (w_i = 1 without
+  // weights), of the bad events and of sum w_i; rows of a.part, nblk_max apart
   o << "extern \"C\" __global__ __launch_bounds__(RF_BS) void rf_u_nll(const RfArgs a) {\n" << head;
   o << "  const T* const top = " << arr(L.top) << ";\n";
-  o << "  double s = 0.0;\n  unsigned bad = 0;\n";
+  if (L.weighted) o << "  const T* const wc = (const T*)a.col[" << L.n_cols << "];\n";
+  o << "  double s = 0.0, sw = 0.0;\n  unsigned bad = 0;\n";
   o << "  for (int64_t i = (int64_t)blockIdx.x * RF_BS + threadIdx.x; i < a.n; i += step) {\n";
   o << "    const T p = " << (top_add ? "" : "k.stop * ") << "top[i];\n";
-  o << "    if (p > (T)0 && p < (T)INFINITY) s += (sizeof(T) == 4 ? RF_LN2 : 1.0) * (double)RM<T>::log_acc(p);\n";
-  o << "    else ++bad;\n  }\n";
-  o << "  __shared__ double ws[RF_BS / 64][2];\n";
-  o << "  s = wave_sum(s);\n  const unsigned wb = wave_sum_u(bad);\n";
-  o << "  if ((threadIdx.x & 63) == 0) { ws[threadIdx.x >> 6][0] = s; ws[threadIdx.x >> 6][1] = (double)wb; }\n";
+  o << "    const double wt = " << (L.weighted ? "(double)wc[i]" : "1.0") << ";\n";
+  o << "    if (p > (T)0 && p < (T)INFINITY) s += wt * ((sizeof(T) == 4 ? RF_LN2 : 1.0) * (double)RM<T>::log_acc(p));\n";
+  o << "    else ++bad;\n    sw += wt;\n  }\n";
+  o << "  __shared__ double ws[RF_BS / 64][3];\n";
+  o << "  s = wave_sum(s);\n  sw = wave_sum(sw);\n  const unsigned wb = wave_sum_u(bad);\n";
+  o << "  if ((threadIdx.x & 63) == 0) {\n";
+  o << "    ws[threadIdx.x >> 6][0] = s; ws[threadIdx.x >> 6][1] = (double)wb; ws[threadIdx.x >> 6][2] = sw;\n  }\n";
   o << "  __syncthreads();\n";
-  o << "  if (threadIdx.x == 0) {\n    double t = 0.0, b = 0.0;\n";
-  o << "    for (int w = 0; w < RF_BS / 64; ++w) { t += ws[w][0]; b += ws[w][1]; }\n";
-  o << "    a.part[blockIdx.x] = t;\n    a.part[a.nblk_max + blockIdx.x] = b;\n  }\n  (void)k;\n}\n\n";
-  o << "// one workgroup: a.out = [-sum of the partials, bad events], fixed order\n";
+  o << "  if (threadIdx.x == 0) {\n    double t = 0.0, b = 0.0, c = 0.0;\n";
+  o << "    for (int w = 0; w < RF_BS / 64; ++w) { t += ws[w][0]; b += ws[w][1]; c += ws[w][2]; }\n";
+  o << "    a.part[blockIdx.x] = t;\n    a.part[a.nblk_max + blockIdx.x] = b;\n";
+  o << "    a.part[2 * a.nblk_max + blockIdx.x] = c;\n  }\n  (void)k;\n}\n\n";
+  o << "// one workgroup: a.out = [NLL, bad events] from the partials, fixed order;\n";
+  o << "// an extended program adds nu - N log nu (N: the event count or the sum of\n";
+  o << "// the weights)\n";
   o << "extern \"C\" __global__ __launch_bounds__(RF_BS) void rf_u_sum(const RfArgs a, int nb) {\n";
-  o << "  __shared__ double ws[RF_BS / 64][2];\n";
-  o << "  double s = 0.0, b = 0.0;\n";
-  o << "  for (int j = threadIdx.x; j < nb; j += RF_BS) { s += a.part[j]; b += a.part[a.nblk_max + j]; }\n";
-  o << "  s = wave_sum(s);\n  b = wave_sum(b);\n";
-  o << "  if ((threadIdx.x & 63) == 0) { ws[threadIdx.x >> 6][0] = s; ws[threadIdx.x >> 6][1] = b; }\n";
+  o << "  __shared__ double ws[RF_BS / 64][3];\n";
+  o << "  double s = 0.0, b = 0.0, sw = 0.0;\n";
+  o << "  for (int j = threadIdx.x; j < nb; j += RF_BS) {\n";
+  o << "    s += a.part[j]; b += a.part[a.nblk_max + j]; sw += a.part[2 * a.nblk_max + j];\n  }\n";
+  o << "  s = wave_sum(s);\n  b = wave_sum(b);\n  sw = wave_sum(sw);\n";
+  o << "  if ((threadIdx.x & 63) == 0) {\n";
+  o << "    ws[threadIdx.x >> 6][0] = s; ws[threadIdx.x >> 6][1] = b; ws[threadIdx.x >> 6][2] = sw;\n  }\n";
   o << "  __syncthreads();\n";
-  o << "  if (threadIdx.x == 0) {\n    double t = 0.0, c = 0.0;\n";
-  o << "    for (int w = 0; w < RF_BS / 64; ++w) { t += ws[w][0]; c += ws[w][1]; }\n";
-  o << "    a.out[0] = -t;\n    a.out[1] = c;\n  }\n}\n";
+  o << "  if (threadIdx.x == 0) {\n    double t = 0.0, c = 0.0, n_w = 0.0;\n";
+  o << "    for (int w = 0; w < RF_BS / 64; ++w) { t += ws[w][0]; c += ws[w][1]; n_w += ws[w][2]; }\n";
+  if (L.ext_nu >= 0) {
+    o << "    const double* const th = a.theta;\n";
+    emit_paramlike(o, L, "    ");
+    o << "    const double ext_n = " << (L.weighted ? "n_w" : "th[" + std::to_string(L.n_params) + "]")
+      << ", ext_nu = pv" << L.ext_nu << ";\n";
+    o << "    a.out[0] = -t + (ext_nu - ext_n * ::log(ext_nu));\n";
+  } else {
+    o << "    a.out[0] = -t;\n";
+  }
+  o << "    a.out[1] = c;\n    (void)n_w;\n  }\n}\n";
 }
 
 std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, int prio, bool unfused) {
@@ -453,7 +472,9 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     // log p and through r = 1/p, which all adjoint terms share
     o << "  const T wt = x[" << L.n_cols << "];\n";
     o << "  acc[0] += ok ? wt * RM<T>::log_acc(p) : (T)0;\n";
-    if (L.wsum >= 0) o << "  acc[" << L.wsum << "] += wt;\n";
+    // the sum of the weights exists in the gradient mode only (the NLL-only
+    // kernel keeps one sum); rf_nll runs the gradient kernel for such programs
+    if (L.wsum >= 0) o << "  if (MODE == 2) acc[" << L.wsum << "] += wt;\n";
     o << "  if (MODE == 2) {\n";
     o << "    const T r = ok ? RM<T>::rcp(p) * wt : (T)0;\n";
   } else {
@@ -510,7 +531,8 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     // after the parameters) or, with weights, their sum over all events
     emit_paramlike(o, L, "  ");
     o << "  const double ext_n = "
-      << (L.wsum >= 0 ? "S[" + std::to_string(L.wsum) + "]" : "th[" + std::to_string(L.n_params) + "]")
+      << (L.wsum >= 0 ? "(MODE == 2 ? S[" + std::to_string(L.wsum) + "] : 0.0)"
+                      : "th[" + std::to_string(L.n_params) + "]")
       << ", ext_nu = pv" << L.ext_nu << ";\n";
     o << "  out[0] = -S[0] + (ext_nu - ext_n * ::log(ext_nu));\n";
     o << "  out[" << L.n_params + 1 << "] = (double)nbad;\n";

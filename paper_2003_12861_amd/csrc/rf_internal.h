@@ -153,7 +153,7 @@ struct rf_program {
     hipFunction_t k_nll = nullptr, k_sum = nullptr;
     void* vals = nullptr;  // node value arrays
     size_t vals_bytes = 0;
-    double* part = nullptr;  // [2][part_n]: partial sums, bad-event counts
+    double* part = nullptr;  // [3][part_n]: partial sums, bad-event counts, sums of weights
     int part_n = 0;
     double* out = nullptr;  // [NLL, bad events]
   } unf;

@@ -232,4 +232,4 @@ def test_weighted_extended_adds_a_sum(lib):
         g.free()
     (c0, s0, src0), (c1, s1, src1) = res.values()
     assert (c1, s1) == (c0 + 1, s0 + 1)
-    assert "ext_n = th[3]" in src0 and ("ext_n = S[%d]" % s0) in src1
+    assert "ext_n = th[3]" in src0 and ("ext_n = (MODE == 2 ? S[%d]" % s0) in src1

@@ -66,6 +66,7 @@ def test_weighted_extended_parity(prec, n):
     scale = float(np.sum(np.abs(w * np.log(v)))) + nu + np.sum(np.abs(w)) * abs(np.log(nu))
     assert abs(nll - onll) <= tn * scale, (nll, onll)
     assert scaled_grad_err(g, og, oga).max() <= tg
+    assert abs(prog.nll(th)[0] - onll) <= tn * scale  # the NLL-only entry point
     # unit weights reproduce the unweighted extended program
     prog.bind(to_dev([x, np.ones(n)], prec, api))
     ref, _ = build_pair(workloads.spec_gauss_cheb_extended(), prec, api)

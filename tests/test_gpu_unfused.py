@@ -43,9 +43,50 @@ def test_unfused_empty_and_rejected_programs():
     assert prog.nll_unfused(th)[0] == 0.0
     pw, _ = build_pair(spec, api.FP64, api, weighted=True)
     pw.bind(to_dev(cols + [np.zeros(0)], api.FP64, api))
+    assert pw.nll_unfused(th)[0] == 0.0
+    # the surrogate leaf evaluates whole wavefronts on MFMA: not in this mode
+    pm = api.Program(api.Graph.from_spec(workloads.spec_bwcb(surrogate=True)), precision=api.FP32, load=False)
     with pytest.raises(api.RfError):
-        pw.nll_unfused(th)
-    pc, _ = build_pair(workloads.spec_bwcb(K=100), api.FP64, api)
-    pc.bind(to_dev([synth.sample_bw_cb(10, 3)], api.FP64, api))
-    with pytest.raises(api.RfError):
-        pc.nll_unfused(workloads.truth_vector(synth.BWCB_TRUTH))
+        pm.build_unfused()
+
+
+def _more(case, n):
+    """(spec, columns, weights or None, theta) of the programs beyond the plain
+    unweighted ones: table leaves, weights, the extended term."""
+    rng = np.random.default_rng(23)
+    w = rng.uniform(-0.5, 2.0, n).astype(np.float32).astype(np.float64)
+    if case == "poisson":
+        k, x = synth.sample_poisson_gauss_cheb(n, 22)
+        return workloads.spec_poisson_gauss_cheb(), [k, x], None, [11.0, 5.5, 0.1, 1.2, 0.15, -0.05, 0.35]
+    if case == "bwcb_exact":
+        return (workloads.spec_bwcb(), [synth.sample_bw_cb(n, 24)], None,
+                workloads.truth_vector(synth.BWCB_TRUTH))
+    x = synth.sample_gauss_cheb(n, 25)
+    if case == "weighted":
+        return workloads.spec_gauss_cheb(), [x], w, [0.1, 1.2, 0.3, 0.15, -0.05]
+    nw = float(np.sum(w)) if case == "weighted_extended" else float(n)
+    th = [0.2, 1.1, 0.3 * nw + 0.5, 0.7 * nw + 0.25, 0.15, -0.05]
+    return workloads.spec_gauss_cheb_extended(), [x], (w if case == "weighted_extended" else None), th
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.FP32])
+@pytest.mark.parametrize("case,n", [("poisson", 100_003), ("bwcb_exact", 20_000), ("weighted", 100_003),
+                                    ("extended", 100_003), ("weighted_extended", 100_003)])
+def test_unfused_more_programs(prec, case, n):
+    print("case unfused %s n=%d prec=%d" % (case, n, prec), flush=True)
+    spec, cols, w, th = _more(case, n)
+    prog, (om, otop, _) = build_pair(spec, prec, api, weighted=w is not None)
+    prog.bind(to_dev(cols + ([w] if w is not None else []), prec, api))
+    nll, nb = prog.nll_unfused(th)
+    onll, _, _, onb = om.nll_ex(otop, th, cols, weights=w)
+    assert nb == onb == 0
+    # bar relative to the magnitudes of the parts, which partly cancel
+    lp = np.abs(np.log(om.values(otop, th, cols)))
+    ww = np.abs(w) if w is not None else np.ones(n)
+    scale = float(np.sum(ww * lp))
+    if "extended" in case:
+        nu = th[2] + th[3]
+        scale += nu + float(np.sum(ww)) * abs(np.log(nu))
+    assert abs(nll - onll) <= TOL[prec] * scale, (nll, onll)
+    assert abs(nll - prog.nll(th)[0]) <= (1e-12 if prec == api.FP64 else 1e-6) * scale
+    assert prog.nll_unfused(th)[0] == nll  # repeatable
