@@ -63,8 +63,10 @@ enum {
   RF_COMPILE_NO_LOAD = 1u << 0, /* generate + build the code object only (no GPU
                                    needed); the program can then only be queried */
   RF_VALIDATE = 1u << 1,        /* rf_bind_columns checks that every event lies in
-                                   its observables' ranges and every event weight is
-                                   finite (one device pass), RF_E_INVALID otherwise */
+                                   its observables' ranges, that the observables of
+                                   Poisson leaves hold integers and that every event
+                                   weight is finite (one device pass), RF_E_INVALID
+                                   otherwise */
   RF_COMPILE_WEIGHTED = 1u << 2 /* weighted events: one more column after the
                                    observables holds per-event weights w_i (program
                                    dtype, any finite real); the NLL is

@@ -325,15 +325,20 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
         hi[nd.index] = nd.hi;
       }
     int64_t bad = 0;
-    int rc = validate_columns(p->cols, n_cols, p->L.n_cols, lo, hi, n_events, p->L.precision == RF_FP32_COMP, stream,
-                              &bad);
+    unsigned int_mask = 0;  // the observables of Poisson leaves hold counts
+    for (size_t id = 0; id < p->L.nodes.size(); ++id)
+      if (p->L.reach[id] && p->L.nodes[id].op == RF_OP_POISSON)
+        int_mask |= 1u << p->L.nodes[p->L.nodes[id].in[0]].index;
+    int rc = validate_columns(p->cols, n_cols, p->L.n_cols, lo, hi, int_mask, n_events,
+                              p->L.precision == RF_FP32_COMP, stream, &bad);
     if (rc) {
       p->n = -1;
       return rc;
     }
     if (bad) {
       p->n = -1;  // not bound
-      return fail(RF_E_INVALID, std::to_string(bad) + " event values outside their observable's range or not finite");
+      return fail(RF_E_INVALID, std::to_string(bad) +
+                                    " event values outside their observable's range, not finite, or not an integer count");
     }
   }
   return RF_OK;

@@ -102,11 +102,12 @@ int mlp_renorm_launch(const void* w, const double* q5, const double* box12, cons
 inline int mlp_renorm_blocks(int K) { return (K + 255) / 256; }
 
 // column checks of rf_bind_columns with RF_VALIDATE (rf_validate.hip): the
-// number of events outside [lo[c], hi[c]] (or not finite) in columns
-// c < n_range, plus the number of non-finite values in columns n_range ..
-// n_cols - 1 (event weights); synchronises the stream
+// number of events outside [lo[c], hi[c]] (or not finite, or, for the
+// columns in int_mask, not an integer) in columns c < n_range, plus the
+// number of non-finite values in columns n_range .. n_cols - 1 (event
+// weights); synchronises the stream
 int validate_columns(const void* const* cols, int n_cols, int n_range, const double* lo, const double* hi,
-                     int64_t n, bool f32, void* stream, int64_t* n_bad);
+                     unsigned int_mask, int64_t n, bool f32, void* stream, int64_t* n_bad);
 
 // Gauss-Legendre rule (host)
 void gauss_legendre(int K, double lo, double hi, double* x, double* w);

@@ -1,6 +1,7 @@
 // rf_validate.hip -- the RF_VALIDATE pass of rf_bind_columns: one read of
 // every bound column, counting events outside their observable's range (or
-// not finite) and event weights that are not finite.  A count, so the order
+// not finite, or not an integer where the observable is a count) and event
+// weights that are not finite.  A count, so the order
 // of the atomic additions does not matter.
 #include <hip/hip_runtime.h>
 
@@ -15,6 +16,7 @@ struct ValArgs {
   const void* col[VAL_MAXC];
   double lo[VAL_MAXC], hi[VAL_MAXC];
   int n_cols, n_range;
+  unsigned int_mask;  // columns whose values must be integers
   int64_t n;
   unsigned long long* bad;
 };
@@ -27,9 +29,11 @@ __global__ __launch_bounds__(256) void validate_kernel(const ValArgs a) {
     const T* x = (const T*)a.col[c];
     const bool range = c < a.n_range;
     const double lo = a.lo[c], hi = a.hi[c];
+    const bool integer = (a.int_mask >> c) & 1u;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
       const double v = (double)x[i];
-      const bool ok = range ? (v >= lo && v <= hi) : isfinite(v);  // NaN fails both
+      bool ok = range ? (v >= lo && v <= hi) : isfinite(v);  // NaN fails both
+      if (integer) ok = ok && v == floor(v);
       cnt += ok ? 0u : 1u;
     }
   }
@@ -41,8 +45,8 @@ __global__ __launch_bounds__(256) void validate_kernel(const ValArgs a) {
 }  // namespace
 
 namespace rf {
-int validate_columns(const void* const* cols, int n_cols, int n_range, const double* lo, const double* hi, int64_t n,
-                     bool f32, void* stream, int64_t* n_bad) {
+int validate_columns(const void* const* cols, int n_cols, int n_range, const double* lo, const double* hi,
+                     unsigned int_mask, int64_t n, bool f32, void* stream, int64_t* n_bad) {
   *n_bad = 0;
   if (n <= 0 || n_cols <= 0) return RF_OK;
   if (n_cols > VAL_MAXC) return fail(RF_E_INVALID, "too many columns to validate");
@@ -55,6 +59,7 @@ int validate_columns(const void* const* cols, int n_cols, int n_range, const dou
   }
   a.n_cols = n_cols;
   a.n_range = n_range;
+  a.int_mask = int_mask;
   a.n = n;
   hipStream_t st = (hipStream_t)stream;
   unsigned long long* d = nullptr;

@@ -62,3 +62,17 @@ def test_poisson_fit_recovers_the_sample_mean():
     assert info["converged"], info
     assert abs(th[0] - k.mean()) <= 1e-6 * k.mean(), (th[0], k.mean())
     assert abs(sig[0] - np.sqrt(k.mean() / k.size)) <= 1e-3 * sig[0]
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.FP32])
+def test_validate_rejects_non_integer_counts(prec):
+    """RF_VALIDATE: the observable of a Poisson leaf must hold integers; the
+    continuous observable beside it need not."""
+    k, x = synth.sample_poisson_gauss_cheb(1000, 44)
+    prog, _ = build_pair(workloads.spec_poisson_gauss_cheb(), prec, api, validate=True)
+    prog.bind(to_dev([k, x], prec, api))  # integer counts, continuous x: accepted
+    assert prog.nll(TH)[1] == 0
+    kb = k.copy()
+    kb[[3, 500]] += 0.5
+    with pytest.raises(api.RfError, match="integer"):
+        prog.bind(to_dev([kb, x], prec, api))
