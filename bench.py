@@ -382,13 +382,13 @@ def main():
         cpu = dict(value=rate, unit="events/s", cores=1, kind="oracle",
                    sample=what + " (single-threaded C, -O2)",
                    host=platform.processor() or platform.machine(), nproc=os.cpu_count())
-        tol = {"fp32": 2e-6 if wbf is not None else 1e-6, "fp64": 1e-9}
+        tol = {"fp32": 1e-6, "fp64": 1e-9}
         for key, p in progs.items():
             q = program(key, sample) if heavy else p
             nll, g, _ = q.nll_grad(theta)
             res[key]["nll_rel_err"] = abs(nll - onll) / abs(onll)
             res[key]["grad_scaled_err"] = float(np.max(np.abs(g - og) / oga))
-            res[key]["valid"] = bool(res[key]["nll_rel_err"] <= tol[key])
+            res[key]["valid"] = bool(res[key]["nll_rel_err"] <= tol[key] and res[key]["grad_scaled_err"] <= tol[key])
             res[key]["checked_on"] = ("a %d-event prefix" % sample[0].size) if heavy else "all events"
 
     k32 = res["fp32"]["kernel_s"]

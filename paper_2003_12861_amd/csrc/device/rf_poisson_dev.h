@@ -16,7 +16,9 @@
 //   C[0] = 1/N, C[1] = d log N / d lambda + 1 = sum k u(k) / (lambda N),
 //   C[2] = log lambda, C[3] = lambda, C[4] = 1/lambda.
 // The derivative output is the event part n (factor C[4]); the -1 of
-// d log u / d lambda is carried by C[1].
+// d log u / d lambda is carried by C[1].  Without RF_VALIDATE an event off
+// the integer range (or not an integer) reads the entry of its clamped,
+// truncated count, and its derivative part is that same count.
 #pragma once
 
 enum { POISSON_NC = 5, POISSON_KMAX = 2048 };
@@ -70,6 +72,6 @@ template <typename T> struct PoissonK {
 template <typename T> RF_DEV T poisson_eval(T n, const PoissonK<T>& k, T* d) {
   int j = (int)n - k.lo;  // events off the integer range are the caller's error: clamped
   j = j < 0 ? 0 : (j > k.kmax ? k.kmax : j);
-  d[0] = n;
+  d[0] = (T)(j + k.lo);  // the count whose table entry was read, so the gradient matches the value
   return (T)k.tab[j];
 }

@@ -167,7 +167,8 @@ std::vector<int> unfused_slots(const Lowered& L) {
 // node id's value of every event to a.values + slot * n; rf_u_nll sums
 // log p of the top's array per workgroup into a.part (sums, then bad-event
 // counts at a.part + nblk_max), and rf_u_sum adds the partials in a fixed
-// order into a.out = [NLL, bad events].  Same per-node arithmetic as rf_eval.
+// order into a.out = [NLL, bad events].  Same per-node arithmetic as rf_eval,
+// and the same FP64 re-evaluation of FP32 events below the tail threshold.
 static void emit_unfused(std::ostringstream& o, const Lowered& L) {
   const auto& g = L.nodes;
   const int N = (int)g.size();
@@ -206,14 +207,25 @@ static void emit_unfused(std::ostringstream& o, const Lowered& L) {
   // NLL kernel: per-workgroup partials of sum w_i log p_i (w_i = 1 without
   // weights), of the bad events and of sum w_i; rows of a.part, nblk_max apart
   o << "extern \"C\" __global__ __launch_bounds__(RF_BS) void rf_u_nll(const RfArgs a) {\n" << head;
+  o << "#if RF_TAIL64\n  const KS<double> kd = KS<double>::load(cst);\n#endif\n";
   o << "  const T* const top = " << arr(L.top) << ";\n";
   if (L.weighted) o << "  const T* const wc = (const T*)a.col[" << L.n_cols << "];\n";
   o << "  double s = 0.0, sw = 0.0;\n  unsigned bad = 0;\n";
   o << "  for (int64_t i = (int64_t)blockIdx.x * RF_BS + threadIdx.x; i < a.n; i += step) {\n";
   o << "    const T p = " << (top_add ? "" : "k.stop * ") << "top[i];\n";
   o << "    const double wt = " << (L.weighted ? "(double)wc[i]" : "1.0") << ";\n";
-  o << "    if (p > (T)0 && p < (T)INFINITY) s += wt * ((sizeof(T) == 4 ? RF_LN2 : 1.0) * (double)RM<T>::log_acc(p));\n";
-  o << "    else ++bad;\n    sw += wt;\n  }\n";
+  o << "    if (p > RM<T>::tiny() && p < (T)INFINITY) {\n";
+  o << "      s += wt * ((sizeof(T) == 4 ? RF_LN2 : 1.0) * (double)RM<T>::log_acc(p));\n";
+  o << "    } else {\n";
+  // as in the fused kernel: an FP32 probability below the tail threshold (or
+  // not finite) is evaluated again, in FP64, from the event's columns (the
+  // weight included, which the per-event program applies itself)
+  o << "#if RF_TAIL64\n";
+  o << "      double xd[RF_NCOL > 0 ? RF_NCOL : 1], l1 = 0.0, pd;\n";
+  o << "      for (int c = 0; c < RF_NCOL; ++c) xd[c] = (double)((const T*)a.col[c])[i];\n";
+  o << "      if (rf_eval<double, 1>(xd, kd, &l1, &pd)) s += l1; else ++bad;\n";
+  o << "#else\n      ++bad;\n#endif\n";
+  o << "    }\n    sw += wt;\n  }\n";
   o << "  __shared__ double ws[RF_BS / 64][3];\n";
   o << "  s = wave_sum(s);\n  sw = wave_sum(sw);\n  const unsigned wb = wave_sum_u(bad);\n";
   o << "  if ((threadIdx.x & 63) == 0) {\n";
@@ -473,8 +485,12 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     o << "  const T wt = x[" << L.n_cols << "];\n";
     o << "  acc[0] += ok ? wt * RM<T>::log_acc(p) : (T)0;\n";
     // the sum of the weights exists in the gradient mode only (the NLL-only
-    // kernel keeps one sum); rf_nll runs the gradient kernel for such programs
-    if (L.wsum >= 0) o << "  if (MODE == 2) acc[" << L.wsum << "] += wt;\n";
+    // kernel keeps one sum); rf_nll runs the gradient kernel for such programs.
+    // A weight enters it only where its event's terms do: an FP32 event
+    // below the tail threshold adds its weight in the FP64 re-evaluation
+    // instead, so that every weight is counted once (a bad event makes the
+    // NLL infinite whatever N is)
+    if (L.wsum >= 0) o << "  if (MODE == 2) acc[" << L.wsum << "] += ok ? wt : (T)0;\n";
     o << "  if (MODE == 2) {\n";
     o << "    const T r = ok ? RM<T>::rcp(p) * wt : (T)0;\n";
   } else {

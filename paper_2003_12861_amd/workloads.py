@@ -132,5 +132,38 @@ def spec_bwcb(surrogate=False, K=1024):
     return spec
 
 
+def spec_two_gauss_extended(lo=-10.0, hi=10.0):
+    """nu1 Gauss(x; mu1, s1) + nu2 Gauss(x; mu2, s2), extended with
+    nu = nu1 + nu2; theta = (mu1, s1, mu2, s2, nu1, nu2).  Between and beyond
+    two narrow peaks the density falls far below FP32's tail threshold."""
+    return [
+        ("obs", "x", [], [lo, hi]),
+        ("param", "mu1", [], [-5.0, 5.0]),
+        ("param", "s1", [], [0.05, 5.0]),
+        ("param", "mu2", [], [-5.0, 5.0]),
+        ("param", "s2", [], [0.05, 5.0]),
+        ("param", "nu1", [], [0.0, 1e12]),
+        ("param", "nu2", [], [0.0, 1e12]),
+        ("gauss", "g1", ["x", "mu1", "s1"], []),
+        ("gauss", "g2", ["x", "mu2", "s2"], []),
+        ("linear", "nu", ["nu1", "nu2"], [0.0, 1.0, 1.0]),
+        ("ratio", "f", ["nu1", "nu"], []),
+        ("add", "mix", ["g1", "g2", "f"], []),
+        ("extended", "model", ["mix", "nu"], []),
+    ]
+
+
+def spec_decay_leaf():
+    """One decay (x) Gaussian resolution leaf on t in [0, 10]; theta = (tau, s, b)."""
+    tlo, thi = synth.DECAY_T_RANGE
+    return [
+        ("obs", "t", [], [tlo, thi]),
+        ("param", "tau", [], [0.1, 10.0]),
+        ("param", "s", [], [0.005, 1.0]),
+        ("param", "b", [], [-0.5, 0.5]),
+        ("decay_gauss", "d", ["t", "tau", "s", "b"], []),
+    ]
+
+
 def truth_vector(truth):
     return [float(v) for v in truth.values()]

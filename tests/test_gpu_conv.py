@@ -3,7 +3,7 @@ exponential background against the oracle."""
 import numpy as np
 import pytest
 
-from helpers import build_pair, rel, scaled_grad_err, to_dev
+from helpers import build_pair, oracle_nll_threads, rel, scaled_grad_err, to_dev
 from paper_2003_12861_amd import synth, workloads
 
 pytestmark = pytest.mark.gpu
@@ -31,22 +31,40 @@ def test_conv_parity(prec, K):
         assert err.max() <= tg, err
 
 
+_FULL = {}
+
+
+def _full_conv_oracle():
+    """The oracle's NLL and gradient over all 1e7 events (host threads), once."""
+    if not _FULL:
+        n = 10_000_000
+        x = synth.sample_bw_cb(n, 4)
+        print("case conv full size: oracle over all events", flush=True)
+        _FULL["x"] = x
+        _FULL["ref"] = oracle_nll_threads(workloads.spec_bwcb(), TRUTH, [x])
+    return _FULL["x"], _FULL["ref"]
+
+
 @pytest.mark.parametrize("prec", [api.FP64, api.FP32])
-def test_conv_full_size_sampled(prec):
-    """1e7 events in the benchmark's launch shape: per-event values on a sample
-    of events against the oracle, and the NLL against -sum log p of the values."""
-    n = 10_000_000
-    x = synth.sample_bw_cb(n, 4)
+def test_conv_full_size(prec):
+    """1e7 events in the benchmark's launch shape: the NLL and gradient against
+    the oracle over all events, per-event values on a sample of events."""
+    x, (onll, og, oga, onb) = _full_conv_oracle()
+    n = x.size
     prog, (om, otop, _) = build_pair(workloads.spec_bwcb(), prec, api)
     prog.bind(to_dev([x], prec, api))
     th = TRUTH
+    print("case conv full size prec=%d" % prec, flush=True)
+    nll, g, nb = prog.nll_grad(th)
+    assert nb == onb == 0
+    tn, tg = (1e-9, 1e-9) if prec == api.FP64 else (1e-6, 1e-6)
+    assert rel(nll, onll) <= tn, (nll, onll)
+    err = scaled_grad_err(g, og, oga)
+    assert err.max() <= tg, err
     v = prog.values(th).double().cpu().numpy()
     idx = np.random.default_rng(0).choice(n, 2000, replace=False)
     ref = om.values(otop, th, [x[idx]])
     np.testing.assert_allclose(v[idx], ref, rtol=1e-12 if prec == api.FP64 else 2e-6)
-    nll, g, nb = prog.nll_grad(th)
-    assert nb == 0
-    assert rel(nll, -np.log(v).sum()) <= (1e-12 if prec == api.FP64 else 1e-6)
 
 
 def test_conv_gradient_vs_central_differences():

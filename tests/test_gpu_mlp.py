@@ -4,7 +4,7 @@ exact-target kernel, and the surrogate PDF leaf inside a compiled likelihood."""
 import numpy as np
 import pytest
 
-from helpers import build_pair, rel, scaled_grad_err, to_dev
+from helpers import build_pair, oracle_nll_threads, rel, scaled_grad_err, to_dev
 from oracle import rfo
 from paper_2003_12861_amd import synth, workloads
 
@@ -12,6 +12,36 @@ pytestmark = pytest.mark.gpu
 api = pytest.importorskip("paper_2003_12861_amd.api")
 torch = pytest.importorskip("torch")
 from paper_2003_12861_amd import surrogate  # noqa: E402
+
+
+# FP32 per-event values of the surrogate leaf: its exponentials take
+# arguments up to ~25 in the tails (relative rounding 2^-24 times the
+# argument) and the activations enter the MFMA products as two BF16 parts
+# (relative 2^-17 per product); measured within 1.7e-6.  The NLL and the
+# gradient meet the FP32 bar of 1e-6.
+VALUES_RTOL = 3e-6
+
+
+# weight and input gradients: each entry against its own scale, the sum
+# over rows of the magnitudes of its terms (entries far smaller than the
+# largest one are checked to their own accuracy)
+DW_TOL = 1e-5
+
+
+def _dw_scale(w64, u, dout):
+    """sum over rows r of |dout_r d s_r / d w| per weight (the oracle, row by row)"""
+    sc = np.zeros(8833)
+    for r in range(u.shape[0]):
+        dw_r, _ = rfo.mlp_backward(w64, u[r:r + 1], dout[r:r + 1])
+        sc += np.abs(dw_r)
+    return sc
+
+
+def _assert_dw(dw, dw_ref, scale):
+    err = np.abs(dw - dw_ref)
+    ratio = err / np.maximum(scale, 1e-300)
+    print("weight gradient: max error / entry scale %.3g" % ratio.max(), flush=True)
+    assert np.all(err <= DW_TOL * scale + 1e-30), (ratio.max(), int(np.argmax(ratio)))
 
 
 def _weights(seed, scale=1.0):
@@ -39,9 +69,11 @@ def test_mlp_forward_backward_vs_oracle(n):
     dw, _ = api.mlp_backward(wbf, ud, torch.tensor(dout, device="cuda"), din=din)
     dw_ref, din_ref = rfo.mlp_backward(w64, u.astype(np.float64), dout.astype(np.float64))
     dw = dw.double().cpu().numpy()
-    scale = np.abs(dw_ref).max()
-    np.testing.assert_allclose(dw, dw_ref, rtol=0, atol=2e-5 * scale)
-    np.testing.assert_allclose(din.double().cpu().numpy(), din_ref, rtol=0, atol=2e-5 * np.abs(din_ref).max())
+    _assert_dw(dw, dw_ref, _dw_scale(w64, u.astype(np.float64), dout.astype(np.float64)))
+    # input gradients: each row against its own largest component
+    din = din.double().cpu().numpy()
+    row = np.abs(din_ref).max(axis=1, keepdims=True)
+    assert np.all(np.abs(din - din_ref) <= DW_TOL * row), np.max(np.abs(din - din_ref) / row)
 
 
 def test_mlp_activations_layout():
@@ -106,8 +138,8 @@ def test_train_step_vs_oracle(batch, gather):
     s_ref = rfo.mlp_forward(w64, ub)
     dw_ref, _ = rfo.mlp_backward(w64, ub, 2.0 / batch * (s_ref - yb))
     g = dw.double().cpu().numpy()
+    _assert_dw(g, dw_ref, _dw_scale(w64, ub, 2.0 / batch * (s_ref - yb)))
     scale = np.abs(dw_ref).max()
-    np.testing.assert_allclose(g, dw_ref, rtol=0, atol=2e-5 * scale)
     # the separate kernels on the gathered batch give the same gradient
     ubd = torch.tensor(u[idx], device="cuda")
     out = api.mlp_forward(wbf, ubd)
@@ -150,17 +182,17 @@ def test_surrogate_leaf_vs_oracle(n):
         nll, g, nb = prog.nll_grad(th)
         onll, og, oga, onb = om.nll_ex(otop, th, [x])
         assert nb == onb == 0
-        assert rel(nll, onll) <= 2e-6, (nll, onll)
+        assert rel(nll, onll) <= 1e-6, (nll, onll)
         err = scaled_grad_err(g, og, oga)
-        assert err.max() <= 2e-5, err
+        assert err.max() <= 1e-6, err
         v = prog.values(th).double().cpu().numpy()
-        np.testing.assert_allclose(v, om.values(otop, th, [x]), rtol=5e-6)
+        np.testing.assert_allclose(v, om.values(otop, th, [x]), rtol=VALUES_RTOL)
 
 
-def test_surrogate_leaf_full_size_sampled():
-    """1e7 events in the benchmark's launch shape: per-event values on a
-    sample of events against the oracle, and the NLL against -sum log p of
-    the values."""
+def test_surrogate_leaf_full_size():
+    """1e7 events in the benchmark's launch shape: the NLL and gradient
+    against the oracle over all events (host threads), per-event values on a
+    sample of events."""
     n = 10_000_000
     wbf, w64 = _weights(4, scale=0.7)
     x = synth.sample_bw_cb(n, 4)
@@ -170,13 +202,17 @@ def test_surrogate_leaf_full_size_sampled():
     prog.bind_weights("sig", wbf)
     om.set_mlp_weights(oids["sig"], w64)
     th = [91.19, 2.5, 1.5, 1.5, 3.0, -0.02, 0.8]
+    print("case surrogate full size: oracle over all events", flush=True)
+    onll, og, oga, onb = oracle_nll_threads(spec, th, [x], mlp_weights={"sig": w64})
+    nll, g, nb = prog.nll_grad(th)
+    assert nb == onb == 0
+    assert rel(nll, onll) <= 1e-6, (nll, onll)
+    err = scaled_grad_err(g, og, oga)
+    assert err.max() <= 1e-6, err
     v = prog.values(th).double().cpu().numpy()
     rng = np.random.default_rng(0)
     idx = rng.choice(n, 2000, replace=False)
-    np.testing.assert_allclose(v[idx], om.values(otop, th, [x[idx]]), rtol=5e-6)
-    nll, g, nb = prog.nll_grad(th)
-    assert nb == 0
-    assert rel(nll, -np.log(v).sum()) <= 2e-6
+    np.testing.assert_allclose(v[idx], om.values(otop, th, [x[idx]]), rtol=VALUES_RTOL)
 
 
 def test_training_reduces_error():

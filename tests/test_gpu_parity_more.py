@@ -1,0 +1,194 @@
+"""More GPU parity cases against the oracle: FP32 events below the tail
+threshold in weighted extended programs and in the unfused per-node mode, the
+decay leaf's scaled-erfc branch, the full 5e7-event 2-D model, and the
+torch.autograd.Function around the adjoint kernel.
+
+Bars as everywhere: FP64 1e-9, FP32 1e-6 on the NLL (relative) and on the
+gradient (relative to sum_i |d(-log p_i)/d theta|, the cancellation-aware
+scale the oracle returns)."""
+import numpy as np
+import pytest
+
+from helpers import build_pair, rel, scaled_grad_err, to_dev
+from paper_2003_12861_amd import synth, workloads
+
+pytestmark = pytest.mark.gpu
+api = pytest.importorskip("paper_2003_12861_amd.api")
+torch = pytest.importorskip("torch")
+
+TOL = {0: (1e-9, 1e-9), 1: (1e-6, 1e-6)}
+
+
+# events 12 to 22 widths from both peaks: FP32 probabilities from 1e-32 down
+# to values that underflow FP32 entirely
+TAIL_X = [8.0, 8.5, 9.0, -8.0, -8.4, -9.1]
+
+
+def _two_gauss_events(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.where(rng.random(n) < 0.4, rng.normal(-2.0, 0.5, n), rng.normal(2.0, 0.5, n))
+    x = np.clip(x, -9.9, 9.9)
+    x = np.concatenate([x, TAIL_X])
+    return x.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.FP32])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_extended_tail_events(prec, weighted):
+    """FP32 events whose probability is below 1e-30 are evaluated again in
+    FP64; with weights, each event's weight enters the N of the extended term
+    once (in the FP32 pass or in its FP64 re-evaluation, not in both)."""
+    print("case extended tail prec=%d weighted=%d" % (prec, weighted), flush=True)
+    x = _two_gauss_events(2000, 41)
+    n = x.size
+    w = np.random.default_rng(42).uniform(0.5, 2.0, n).astype(np.float32).astype(np.float64) if weighted else None
+    nw = float(np.sum(w)) if weighted else float(n)
+    th = [-2.0, 0.5, 2.0, 0.5, 0.4 * nw, 0.6 * nw + 3.0]
+    spec = workloads.spec_two_gauss_extended()
+    prog, (om, otop, _) = build_pair(spec, prec, api, weighted=weighted)
+    prog.bind(to_dev([x, w] if weighted else [x], prec, api))
+    nll, g, nb = prog.nll_grad(th)
+    onll, og, oga, onb = om.nll_ex(otop, th, [x], weights=w)
+    assert nb == onb == 0
+    wa = np.abs(w) if weighted else np.ones(n)
+    v = om.values(otop, th, [x])
+    assert v[-len(TAIL_X):].max() < 1e-30  # the tail events are below the threshold
+    nu = th[4] + th[5]
+    scale = float(np.sum(wa * np.abs(np.log(v)))) + nu + float(np.sum(wa)) * abs(np.log(nu))
+    tn, tg = TOL[prec]
+    assert abs(nll - onll) <= tn * scale, (nll, onll, abs(nll - onll) / scale)
+    err = scaled_grad_err(g, og, oga)
+    assert err.max() <= tg, (err, g, og)
+    assert abs(prog.nll(th)[0] - onll) <= tn * scale  # the NLL-only entry point
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.FP32])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_unfused_tail_events(prec, weighted):
+    """The unfused mode re-evaluates FP32 events below the tail threshold in
+    FP64 as the fused kernel does: events whose FP32 probability underflows
+    are not counted as bad."""
+    print("case unfused tail prec=%d weighted=%d" % (prec, weighted), flush=True)
+    x = _two_gauss_events(3000, 43)
+    n = x.size
+    w = np.random.default_rng(44).uniform(0.5, 2.0, n).astype(np.float32).astype(np.float64) if weighted else None
+    nw = float(np.sum(w)) if weighted else float(n)
+    th = [-2.0, 0.5, 2.0, 0.5, 0.4 * nw, 0.6 * nw + 3.0]
+    prog, (om, otop, _) = build_pair(workloads.spec_two_gauss_extended(), prec, api, weighted=weighted)
+    prog.bind(to_dev([x, w] if weighted else [x], prec, api))
+    onll, _, _, onb = om.nll_ex(otop, th, [x], weights=w)
+    assert onb == 0
+    nll_u, nb_u = prog.nll_unfused(th)
+    nll_f, nb_f = prog.nll(th)
+    assert nb_u == nb_f == 0
+    wa = np.abs(w) if weighted else np.ones(n)
+    v = om.values(otop, th, [x])
+    nu = th[4] + th[5]
+    scale = float(np.sum(wa * np.abs(np.log(v)))) + nu + float(np.sum(wa)) * abs(np.log(nu))
+    tn = TOL[prec][0]
+    assert abs(nll_u - onll) <= tn * scale, (nll_u, onll)
+    assert abs(nll_u - nll_f) <= tn * scale, (nll_u, nll_f)
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.FP32])
+def test_decay_scaled_erfc_branch(prec):
+    """A resolution bias of 0.4 at width 0.05: events below t = 0.12 have an
+    erfc argument w > 4 and take the scaled (erfcx) branch on the GPU; the
+    oracle evaluates erfc directly (its relative accuracy holds far beyond
+    w = 5.7, the largest argument here)."""
+    print("case decay erfcx prec=%d" % prec, flush=True)
+    tau, s, b = 1.5, 0.05, 0.4
+    t, _ = synth.sample_decay_argus(20_000, 45, bias_t=b, f=1.0)
+    grid = np.linspace(0.0, 0.12, 61)
+    t = np.concatenate([t, grid]).astype(np.float32).astype(np.float64)
+    th = [tau, s, b]
+    prog, (om, otop, _) = build_pair(workloads.spec_decay_leaf(), prec, api)
+    prog.bind(to_dev([t], prec, api))
+    u = t - b
+    wv = (s * s / tau - u) / (np.sqrt(2.0) * s)
+    assert np.sum(wv > 4.0) >= 50  # the branch is taken
+    nll, g, nb = prog.nll_grad(th)
+    onll, og, oga, onb = om.nll_ex(otop, th, [t])
+    assert nb == onb == 0
+    tn, tg = TOL[prec]
+    assert rel(nll, onll) <= tn, (nll, onll)
+    assert scaled_grad_err(g, og, oga).max() <= tg, (g, og)
+    v = prog.values(th).double().cpu().numpy()
+    ref = om.values(otop, th, [t])
+    if prec == api.FP64:
+        np.testing.assert_allclose(v, ref, rtol=1e-12)
+    else:
+        # FP32 exponent arguments carry a relative rounding of a few 2^-24,
+        # which the exponential turns into that much times the argument
+        arg = u * u / (2 * s * s) + np.abs(u) / tau + np.where(wv > 4.0, 0.0, wv * wv)
+        bar = 2e-6 + 4.0 * 2.0 ** -24 * arg
+        assert np.all(np.abs(v - ref) <= bar * ref), np.max(np.abs(v - ref) / (bar * ref))
+
+
+def test_decay_argus_5e7_full_oracle():
+    """The 2-D model at 5e7 events in the benchmark's launch shape against
+    one full oracle evaluation over all events: NLL and gradient in both
+    precision forms at the usual bars."""
+    n = 50_000_000
+    t, m = synth.sample_decay_argus(n, 3)
+    spec = workloads.spec_decay_argus()
+    p64, (om, otop, _) = build_pair(spec, api.FP64, api)
+    th = workloads.truth_vector(synth.DECAY_TRUTH)
+    print("case decay 5e7 oracle", flush=True)
+    onll, og, oga, onb = om.nll_ex(otop, th, [t, m])
+    assert onb == 0
+    p64.bind(to_dev([t, m], api.FP64, api))
+    for prec in (api.FP64, api.FP32):
+        print("case decay 5e7 prec=%d" % prec, flush=True)
+        prog = p64 if prec == api.FP64 else build_pair(spec, api.FP32, api)[0]
+        if prec == api.FP32:
+            del p64
+            torch.cuda.empty_cache()
+            prog.bind(to_dev([t, m], api.FP32, api))
+        nll, g, nb = prog.nll_grad(th)
+        assert nb == 0
+        tn, tg = TOL[prec]
+        assert rel(nll, onll) <= tn, (prec, nll, onll)
+        err = scaled_grad_err(g, og, oga)
+        assert err.max() <= tg, (prec, err, g, og)
+        print("decay 5e7 prec=%d nll rel %.3g grad scaled %.3g" % (prec, rel(nll, onll), err.max()), flush=True)
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.FP32])
+@pytest.mark.parametrize("device", ["cpu", "cuda"])
+def test_nll_function_autograd(prec, device):
+    """NLLFunction: torch.autograd through the adjoint kernel.  The backward
+    multiplies the kernel's gradient by the incoming gradient exactly; the
+    gradient matches the oracle's analytic one and central differences."""
+    print("case NLLFunction prec=%d device=%s" % (prec, device), flush=True)
+    x = synth.sample_gauss_cheb(20_000, 46)
+    prog, (om, otop, _) = build_pair(workloads.spec_gauss_cheb(), prec, api)
+    prog.bind(to_dev([x], prec, api))
+    th0 = [0.05, 0.97, 0.31, 0.21, -0.09]
+    theta = torch.tensor(th0, dtype=torch.float64, device=device, requires_grad=True)
+    nll = api.NLLFunction.apply(theta, prog)
+    assert nll.dtype == torch.float64 and nll.device == theta.device and nll.dim() == 0
+    k_nll, k_g, _ = prog.nll_grad(th0)
+    assert nll.item() == k_nll
+    upstream = 2.5
+    (gt,) = torch.autograd.grad(upstream * nll, theta)
+    assert gt.device == theta.device and gt.dtype == torch.float64
+    assert np.array_equal(gt.detach().cpu().numpy(), upstream * k_g)  # gout * g, exactly
+    # the analytic gradient against the oracle's
+    onll, og, oga, _ = om.nll_ex(otop, th0, [x])
+    tn, tg = TOL[prec]
+    assert rel(nll.item(), onll) <= tn
+    assert scaled_grad_err(k_g, og, oga).max() <= tg
+    # and against central differences (h = 1e-5) of the oracle's NLL
+    h = 1e-5
+    fd = np.empty(5)
+    for k in range(5):
+        tp, tm = list(th0), list(th0)
+        tp[k] += h
+        tm[k] -= h
+        fd[k] = (om.nll(otop, tp, [x], grad=False)[0] - om.nll(otop, tm, [x], grad=False)[0]) / (2 * h)
+    np.testing.assert_allclose(k_g, fd, rtol=1e-5, atol=1e-4)
+    # a second use of the same graph node: gradients accumulate in .grad
+    theta.grad = None
+    (upstream * api.NLLFunction.apply(theta, prog) + api.NLLFunction.apply(theta, prog)).backward()
+    np.testing.assert_allclose(theta.grad.cpu().numpy(), (upstream + 1.0) * k_g, rtol=1e-15, atol=0)

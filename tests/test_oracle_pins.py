@@ -366,6 +366,92 @@ def test_mlp_base_is_pseudo_voigt_without_tail():
         assert np.abs(p - v).max() <= 0.012 * v.max(), (M, G, sg, np.abs(p - v).max() / v.max())
 
 
+def _zero_net_leaf():
+    """The oracle's surrogate leaf with a zero network: its values are the
+    analytic base b(x - M; Gamma, sigma, alpha, n), normalised."""
+    m, top, ids = rfo.from_spec(workloads.spec_bwcb(surrogate=True))
+    m.set_mlp_weights(ids["sig"], np.zeros(8833))
+    return m, top
+
+
+def _base_ratio(m, top, th, x):
+    """b(x - M) / b(0): the normalisation cancels (f = 1 isolates the signal)."""
+    v = m.values(top, list(th[:5]) + [-0.02, 1.0], [np.concatenate([[th[0]], np.atleast_1d(x)])])
+    return v[1:] / v[0]
+
+
+def test_mlp_base_limits_are_gaussian_and_lorentzian():
+    """The pseudo-Voigt base in its two limits, without the tail (alpha =
+    30): at Gamma -> 0 it is the Gaussian of width sigma, at sigma -> 0 the
+    Lorentzian of full width Gamma (the mixing weight becomes exactly 1: its
+    polynomial's coefficients add up to 1)."""
+    m, top = _zero_net_leaf()
+    for M, sg in ((91.19, 1.5), (90.0, 0.6), (92.0, 2.9)):
+        d = np.linspace(-4 * sg, 4 * sg, 33)
+        r = _base_ratio(m, top, [M, 1e-12, sg, 30.0, 3.0], M + d)
+        np.testing.assert_allclose(r, stats.norm.pdf(d, 0, sg) / stats.norm.pdf(0, 0, sg), rtol=1e-7, atol=1e-12)
+    for M, G in ((91.19, 2.5), (89.5, 0.5), (92.5, 6.0)):
+        d = np.linspace(-5 * G, 5 * G, 41)
+        r = _base_ratio(m, top, [M, G, 1e-9, 30.0, 3.0], M + d)
+        np.testing.assert_allclose(r, stats.cauchy.pdf(d, 0, G / 2) / stats.cauchy.pdf(0, 0, G / 2), rtol=1e-7)
+
+
+def _half_max_crossing(d, r):
+    """First d where the ratio r(d) (decreasing from 1) falls to 1/2, by
+    linear interpolation between grid neighbours."""
+    k = int(np.argmax(r < 0.5))
+    return d[k - 1] + (0.5 - r[k - 1]) * (d[k] - d[k - 1]) / (r[k] - r[k - 1])
+
+
+def test_mlp_base_width_is_the_voigt_fwhm():
+    """The full width at half maximum of the base (half-maximum crossings of
+    the oracle's own values on a grid of spacing 5e-4) against that of the
+    exact Voigt profile (scipy.special.voigt_profile, Lorentzian half width
+    Gamma/2, crossing by root-finding) over the surrogate's (Gamma, sigma)
+    box and beyond.  The pseudo-Voigt's width approximates that FWHM:
+    measured within 0.45% over Gamma in [0.5, 6], sigma in [0.5, 3], so the
+    bar is 0.5%; a wrong width coefficient or component width moves it
+    further (a 10x slip in the smallest coefficient moves it 2.5%)."""
+    from scipy.optimize import brentq
+    from scipy.special import voigt_profile
+    m, top = _zero_net_leaf()
+    M = 91.19
+    worst = 0.0
+    for G in (0.5, 2.5, 6.0):
+        for sg in (0.5, 1.5, 3.0):
+            th = [M, G, sg, 30.0, 3.0]
+            d = np.arange(0.0, 12.0, 5e-4)
+            hi = _half_max_crossing(d, _base_ratio(m, top, th, M + d))
+            lo = _half_max_crossing(d, _base_ratio(m, top, th, M - d))
+            pk = voigt_profile(0.0, sg, G / 2)
+            fv = 2 * brentq(lambda t: voigt_profile(t, sg, G / 2) - pk / 2, 1e-6, 50.0, xtol=1e-12)
+            assert abs(hi - lo) <= 1e-6 * fv  # symmetric without the tail
+            worst = max(worst, abs((hi + lo) - fv) / fv)
+    assert worst <= 5e-3, worst
+
+
+@pytest.mark.parametrize("G,sg,al,n", [(2.5, 1.5, 1.5, 3.0), (1.6, 2.8, 0.5, 1.0), (3.4, 0.6, 2.9, 9.5),
+                                       (2.0, 1.0, 1.0, 5.0)])
+def test_mlp_base_is_c1_at_the_tail_junction(G, sg, al, n):
+    """The Crystal Ball tail joins the base's Gaussian part with a continuous
+    value and slope.  Scanned on grids without knowing where the junction
+    is: for a function with continuous value and slope, the change of the
+    difference quotient of log b between neighbours shrinks in proportion to
+    the spacing (it is about the second derivative times the spacing); a
+    jump in the slope would keep it constant, a jump in the value would make
+    it grow."""
+    m, top = _zero_net_leaf()
+    M = 91.19
+    th = [M, G, sg, al, n, -0.02, 1.0]
+    span = 6.0 * sg + 1.0
+    worst = []
+    for step in (2e-3, 2e-4):
+        x = M - span + step * np.arange(int(span / step))
+        q = np.diff(np.log(m.values(top, th, [x]))) / step
+        worst.append(np.abs(np.diff(q)).max())
+    assert worst[1] <= 0.3 * worst[0], worst
+
+
 # ------------------------------------------------------------ binned model
 def _binned_small(seed=3, C=3, S=2, B=5, J=4):
     d = synth.make_binned(seed, C, S, B, J)
