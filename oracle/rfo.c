@@ -927,3 +927,412 @@ int rfo_binned_nll(int C, int S, int B, int J, const double* T,
   free(G); free(nu_s);
   return 0;
 }
+
+/* ===== second derivatives: the Hessian of the NLL ==========================
+ * The paper's fits need uncertainties, which come from the curvature of the
+ * NLL at its minimum.  This section carries, per event and node, the value,
+ * the dense gradient and the dense Hessian in theta (forward mode, second
+ * order), from the second derivatives of every analytic leaf and of its
+ * normalisation written out below, and of the parameter functions.  The
+ * convolution and MLP leaves have no second derivatives here.
+ * H(NLL) = -sum_i w_i [ p_i'' / p_i - p_i' p_i'^T / p_i^2 ], plus, for an
+ * extended likelihood, (N / nu^2) nu' nu'^T + (1 - N / nu) nu''. */
+#define MAXPH 16 /* parameters of a model whose Hessian the oracle forms */
+#define MAXS 8   /* shape inputs of a leaf */
+
+typedef double hmat[MAXPH][MAXPH];
+
+/* decay (x) resolution: F and its first and second derivatives in
+   (tau, s, b); with u = t - b and phi = exp(-u^2 / (2 s^2)) / sqrt(2 pi) */
+static double decay_F2(double t, double tau, double s, double b, double* d, double (*h)[MAXS]) {
+  const double u = t - b;
+  double d1[3];
+  const double F = decay_F(t, tau, s, b, d1);
+  const double phi = exp(-u * u / (2 * s * s)) / SQRT2PI;
+  const double Ft = d1[0], Fs = d1[1], Fb = d1[2];
+  const double at = u / (tau * tau) - s * s / (tau * tau * tau); /* d(log F)/dtau without the phi term */
+  d[0] = Ft; d[1] = Fs; d[2] = Fb;
+  h[0][0] = Ft * at + F * (-2 * u / (tau * tau * tau) + 3 * s * s / (tau * tau * tau * tau)) - 2 * s * phi / (tau * tau * tau);
+  h[0][1] = Fs * at - 2 * s * F / (tau * tau * tau) + phi / (tau * tau) + phi * u * u / (s * s * tau * tau);
+  h[0][2] = Fb * at - F / (tau * tau) + phi * u / (s * tau * tau);
+  h[1][1] = Fs * s / (tau * tau) + F / (tau * tau) - phi * u * u / (s * s * s) * (1 / tau + u / (s * s)) + 2 * phi * u / (s * s * s);
+  h[1][2] = Fb * s / (tau * tau) - phi * u / (s * s) * (1 / tau + u / (s * s)) + phi / (s * s);
+  h[2][2] = Fb / tau - phi * u / (s * s * s);
+  h[1][0] = h[0][1]; h[2][0] = h[0][2]; h[2][1] = h[1][2];
+  return F;
+}
+/* A(t) = tau (Phi(u/s) - F(t)) with first and second derivatives */
+static double decay_A2(double t, double tau, double s, double b, double* d, double (*h)[MAXS]) {
+  const double u = t - b;
+  double dF[3], hF[MAXS][MAXS];
+  const double F = decay_F2(t, tau, s, b, dF, hF);
+  const double Phi = 0.5 * erfc(-u / (SQRT2 * s));
+  const double phi = exp(-u * u / (2 * s * s)) / SQRT2PI;
+  d[0] = Phi - F - tau * dF[0];
+  d[1] = tau * (-u * phi / (s * s) - dF[1]);
+  d[2] = tau * (-phi / s - dF[2]);
+  h[0][0] = -2 * dF[0] - tau * hF[0][0];
+  h[0][1] = -u * phi / (s * s) - dF[1] - tau * hF[0][1];
+  h[0][2] = -phi / s - dF[2] - tau * hF[0][2];
+  h[1][1] = tau * (-u * u * u * phi / (s * s * s * s * s) + 2 * u * phi / (s * s * s) - hF[1][1]);
+  h[1][2] = tau * (phi / (s * s) - u * u * phi / (s * s * s * s) - hF[1][2]);
+  h[2][2] = tau * (-u * phi / (s * s * s) - hF[2][2]);
+  h[1][0] = h[0][1]; h[2][0] = h[0][2]; h[2][1] = h[1][2];
+  return tau * (Phi - F);
+}
+
+/* J5(U) = int_0^U v^(5/2) e^{-k v} dv (the ARGUS normalisation's second
+   derivative in c); power series up to kU = 2, else by parts from J3 */
+static double argus_J5(double U, double k) {
+  if (U <= 0) return 0;
+  if (k * U < 2.0) {
+    double s = 0, term = 1;
+    for (int nn = 0; nn < 60; ++nn) {
+      s += term * pow(U, nn + 3.5) / (nn + 3.5);
+      term *= -k / (nn + 1);
+    }
+    return s;
+  }
+  double J, J3;
+  argus_J(U, k, &J, &J3);
+  return 2.5 / k * J3 - U * U * sqrt(U) * exp(-k * U) / k;
+}
+
+/* u, du/d(input j) and d2u/d(input j)d(input k), inputs j = 1..n_in-1 at j-1 */
+static int leaf_value2(const node* d, double x, const double* v, double* du, double (*h)[MAXS]) {
+  for (int j = 0; j < MAXS; ++j) for (int k = 0; k < MAXS; ++k) h[j][k] = 0;
+  switch (d->kind) {
+    case RFO_GAUSS: {
+      const double mu = v[1], s = v[2], z = (x - mu) / s, g = exp(-0.5 * z * z);
+      du[0] = g * z / s; du[1] = g * z * z / s;
+      h[0][0] = g * (z * z - 1) / (s * s);
+      h[0][1] = h[1][0] = g * (z * z * z - 2 * z) / (s * s);
+      h[1][1] = g * (z * z * z * z - 3 * z * z) / (s * s);
+      return 0;
+    }
+    case RFO_CHEB: case RFO_ARGUS: case RFO_BW: case RFO_POISSON: case RFO_EXP: case RFO_DECAY_GAUSS: break;
+    default: FAIL(-1, "no second derivatives for this leaf");
+  }
+  switch (d->kind) {
+    case RFO_CHEB: leaf_value(d, x, v, du); return 0; /* linear in its coefficients */
+    case RFO_EXP: {
+      const double k = v[1];
+      if ((int)d->attrs[0] == 0) {
+        const double e = exp(-x / k);
+        du[0] = e * x / (k * k);
+        h[0][0] = e * (x * x / (k * k * k * k) - 2 * x / (k * k * k));
+      } else {
+        const double e = exp(k * x);
+        du[0] = e * x; h[0][0] = e * x * x;
+      }
+      return 0;
+    }
+    case RFO_DECAY_GAUSS: decay_F2(x, v[1], v[2], v[3], du, h); return 0;
+    case RFO_ARGUS: {
+      const double m0 = v[1], c = v[2];
+      du[0] = 0; du[1] = 0;
+      if (x >= m0) return 0;
+      const double U = (m0 - x) * (m0 + x) / (m0 * m0);
+      const double a = x * sqrt(U) * exp(c * U);
+      du[1] = a * U; h[1][1] = a * U * U;
+      return 0;
+    }
+    case RFO_BW: {
+      const double M = v[1], G = v[2], q = x - M, b = 1.0 / (q * q + 0.25 * G * G);
+      du[0] = 2 * q * b * b; du[1] = -0.5 * G * b * b;
+      h[0][0] = -2 * b * b + 8 * q * q * b * b * b;
+      h[0][1] = h[1][0] = -2 * q * G * b * b * b;
+      h[1][1] = -0.5 * b * b + 0.5 * G * G * b * b * b;
+      return 0;
+    }
+    case RFO_POISSON: {
+      const double lam = v[1], u = exp(x * log(lam) - lam - lgamma(x + 1.0)), r = x / lam - 1.0;
+      du[0] = u * r; h[0][0] = u * (r * r - x / (lam * lam));
+      return 0;
+    }
+  }
+  FAIL(-1, "no second derivatives for this leaf");
+}
+
+/* second derivatives of the normalisation N over the observable's range in
+   the leaf's inputs (d->N and the first derivatives come from leaf_norm) */
+static int leaf_norm2(const node* d, const double* v, double (*h)[MAXS]) {
+  const double lo = d->lo, hi = d->hi;
+  for (int j = 0; j < MAXS; ++j) for (int k = 0; k < MAXS; ++k) h[j][k] = 0;
+  switch (d->kind) {
+    case RFO_GAUSS: {
+      const double mu = v[1], s = v[2];
+      const double ea = exp(-0.5 * (lo - mu) * (lo - mu) / (s * s)), eb = exp(-0.5 * (hi - mu) * (hi - mu) / (s * s));
+      const double a = lo - mu, b = hi - mu;
+      h[0][0] = (a * ea - b * eb) / (s * s);
+      h[0][1] = h[1][0] = (a * a * ea - b * b * eb) / (s * s * s);
+      h[1][1] = (a * a * a * ea - b * b * b * eb) / (s * s * s * s);
+      return 0;
+    }
+    case RFO_CHEB: return 0;
+    case RFO_EXP: {
+      const double k = v[1];
+      if ((int)d->attrs[0] == 0) {
+        h[0][0] = (lo * lo * exp(-lo / k) - hi * hi * exp(-hi / k)) / (k * k * k);
+        return 0;
+      }
+      if (fabs(k) < 1e-12) { h[0][0] = (hi * hi * hi - lo * lo * lo) / 3.0; return 0; }
+      /* int x^2 e^{k x} dx = e^{k x} (x^2 / k - 2 x / k^2 + 2 / k^3) */
+      const double Fh = exp(k * hi) * (hi * hi / k - 2 * hi / (k * k) + 2 / (k * k * k));
+      const double Fl = exp(k * lo) * (lo * lo / k - 2 * lo / (k * k) + 2 / (k * k * k));
+      h[0][0] = Fh - Fl;
+      return 0;
+    }
+    case RFO_DECAY_GAUSS: {
+      double dA[3], dB[3], hA[MAXS][MAXS], hB[MAXS][MAXS];
+      decay_A2(hi, v[1], v[2], v[3], dA, hA);
+      decay_A2(lo, v[1], v[2], v[3], dB, hB);
+      for (int j = 0; j < 3; ++j) for (int k = 0; k < 3; ++k) h[j][k] = hA[j][k] - hB[j][k];
+      return 0;
+    }
+    case RFO_ARGUS: {
+      const double m0 = v[1], k = -v[2], top = hi < m0 ? hi : m0;
+      const double Ul = (m0 - lo) * (m0 + lo) / (m0 * m0), Ut = (m0 - top) * (m0 + top) / (m0 * m0);
+      h[1][1] = 0.5 * m0 * m0 * (argus_J5(Ul, k) - argus_J5(Ut, k));
+      return 0;
+    }
+    case RFO_BW: {
+      const double M = v[1], G = v[2];
+      const double bl = 1.0 / ((lo - M) * (lo - M) + 0.25 * G * G);
+      const double bh = 1.0 / ((hi - M) * (hi - M) + 0.25 * G * G);
+      const double qh = 2 * (hi - M) / G, ql = 2 * (lo - M) / G;
+      const double N = 2.0 / G * (atan(qh) - atan(ql));
+      const double ph = qh / (1 + qh * qh), pl = ql / (1 + ql * ql);
+      const double dph = (1 - qh * qh) / ((1 + qh * qh) * (1 + qh * qh)), dpl = (1 - ql * ql) / ((1 + ql * ql) * (1 + ql * ql));
+      const double NG = -N / G - 2.0 / (G * G) * (ph - pl);
+      h[0][0] = 2 * (lo - M) * bl * bl - 2 * (hi - M) * bh * bh;
+      h[0][1] = h[1][0] = -0.5 * G * (bl * bl - bh * bh);
+      h[1][1] = -NG / G + N / (G * G) + 4.0 / (G * G * G) * (ph - pl) + 2.0 / (G * G * G) * (qh * dph - ql * dpl);
+      return 0;
+    }
+    case RFO_POISSON: {
+      const double lam = v[1];
+      nsum S = {0, 0};
+      for (double k = ceil(lo); k <= hi; k += 1.0) {
+        const double u = exp(k * log(lam) - lam - lgamma(k + 1.0)), r = k / lam - 1.0;
+        nadd(&S, u * (r * r - k / (lam * lam)));
+      }
+      h[0][0] = nval(&S);
+      return 0;
+    }
+  }
+  FAIL(-1, "no second derivatives for this leaf");
+}
+
+/* second derivatives in theta of the parameter-like nodes */
+static void param_hess(const rfo_model* m, hmat* ph) {
+  const int P = m->np;
+  for (int id = 0; id < m->n; ++id) {
+    const node* d = &m->nd[id];
+    double (*H)[MAXPH] = ph[id];
+    for (int a = 0; a < MAXPH; ++a) for (int b = 0; b < MAXPH; ++b) H[a][b] = 0;
+    switch (d->kind) {
+      case RFO_FN_LINEAR:
+        for (int j = 0; j < d->n_in; ++j)
+          for (int a = 0; a < P; ++a) for (int b = 0; b < P; ++b) H[a][b] += d->attrs[j + 1] * ph[d->in[j]][a][b];
+        break;
+      case RFO_FN_PRODUCT:
+        for (int j = 0; j < d->n_in; ++j) {
+          double o = 1;
+          for (int i = 0; i < d->n_in; ++i) if (i != j) o *= m->pv[d->in[i]];
+          for (int a = 0; a < P; ++a) for (int b = 0; b < P; ++b) H[a][b] += o * ph[d->in[j]][a][b];
+          for (int k = 0; k < d->n_in; ++k) {
+            if (k == j) continue;
+            double o2 = 1;
+            for (int i = 0; i < d->n_in; ++i) if (i != j && i != k) o2 *= m->pv[d->in[i]];
+            for (int a = 0; a < P; ++a)
+              for (int b = 0; b < P; ++b) H[a][b] += o2 * m->pg[d->in[j]][a] * m->pg[d->in[k]][b];
+          }
+        }
+        break;
+      case RFO_FN_RATIO: { /* a/b */
+        const double A = m->pv[d->in[0]], B = m->pv[d->in[1]];
+        const double* ga = m->pg[d->in[0]]; const double* gb = m->pg[d->in[1]];
+        for (int a = 0; a < P; ++a)
+          for (int b = 0; b < P; ++b)
+            H[a][b] = ph[d->in[0]][a][b] / B - (ga[a] * gb[b] + gb[a] * ga[b]) / (B * B) - A * ph[d->in[1]][a][b] / (B * B) +
+                      2 * A * gb[a] * gb[b] / (B * B * B);
+        break;
+      }
+      default: break;
+    }
+  }
+}
+
+int rfo_nll_hess(rfo_model* m, int top, const double* theta, const double* const* cols, const double* w,
+                 int64_t n, double* nll, double* grad, double* hess, int64_t* n_bad) {
+  char reach[MAXN];
+  int ext = -1;
+  if (top >= 0 && top < m->n && m->nd[top].kind == RFO_EXTENDED) {
+    ext = m->nd[top].in[1];
+    top = m->nd[top].in[0];
+  }
+  const int P = m->np, no = m->nobs;
+  if (P > MAXPH) FAIL(-1, "the oracle's Hessian takes at most 16 parameters");
+  int rc = prepare(m, top, theta, reach);
+  if (rc) return rc;
+  hmat* ph = calloc(MAXN, sizeof(hmat));
+  hmat* lN2 = calloc(MAXN, sizeof(hmat)); /* per leaf: d2N/dtheta2 */
+  double* val = malloc(sizeof(double) * MAXN);
+  double (*grd)[MAXPH] = malloc(sizeof(double) * MAXN * MAXPH);
+  hmat* hss = malloc(sizeof(hmat) * MAXN);
+  nsum* HS = calloc(MAXPH * MAXPH, sizeof(nsum));
+  nsum L = {0, 0}, G[MAXPH];
+  memset(G, 0, sizeof(G));
+  param_hess(m, ph);
+  /* theta-space second derivatives of every leaf's normalisation */
+  for (int id = 0; id < m->n && rc == 0; ++id) {
+    node* d = &m->nd[id];
+    if (!reach[id] || !is_pdf(d->kind) || d->kind == RFO_ADD || d->kind == RFO_PROD) continue;
+    double v[MAXIN], h[MAXS][MAXS], dN[MAXIN];
+    for (int j = 1; j < d->n_in; ++j) v[j] = m->pv[d->in[j]];
+    leaf_norm(d, v, dN);
+    rc = leaf_norm2(d, v, h);
+    for (int a = 0; a < P && rc == 0; ++a)
+      for (int b = 0; b < P; ++b) {
+        double s = 0;
+        for (int j = 1; j < d->n_in; ++j) {
+          s += dN[j - 1] * ph[d->in[j]][a][b];
+          for (int k = 1; k < d->n_in; ++k) s += h[j - 1][k - 1] * m->pg[d->in[j]][a] * m->pg[d->in[k]][b];
+        }
+        lN2[id][a][b] = s;
+      }
+  }
+  int64_t bad = 0;
+  double xs[MAXN];
+  for (int64_t i = 0; i < n && rc == 0; ++i) {
+    for (int j = 0; j < no; ++j) xs[j] = cols[j][i];
+    for (int id = 0; id < m->n && rc == 0; ++id) {
+      node* d = &m->nd[id];
+      if (!reach[id] || !is_pdf(d->kind)) continue;
+      double* g = grd[id];
+      double (*H)[MAXPH] = hss[id];
+      if (d->kind == RFO_ADD) {
+        const int nc = (d->n_in + 1) / 2;
+        double fs = 0, c[MAXIN];
+        for (int j = 0; j < nc - 1; ++j) { c[j] = m->pv[d->in[nc + j]]; fs += c[j]; }
+        c[nc - 1] = 1.0 - fs;
+        /* d c_j: the fraction's own derivatives; the last one is minus their sum */
+        double dc[MAXIN][MAXPH];
+        hmat* hc = malloc(sizeof(hmat) * MAXIN);
+        for (int a = 0; a < P; ++a) {
+          double t = 0;
+          for (int j = 0; j < nc - 1; ++j) { dc[j][a] = m->pg[d->in[nc + j]][a]; t += dc[j][a]; }
+          dc[nc - 1][a] = -t;
+        }
+        for (int a = 0; a < P; ++a)
+          for (int b = 0; b < P; ++b) {
+            double t = 0;
+            for (int j = 0; j < nc - 1; ++j) { hc[j][a][b] = ph[d->in[nc + j]][a][b]; t += hc[j][a][b]; }
+            hc[nc - 1][a][b] = -t;
+          }
+        double vv = 0;
+        for (int j = 0; j < nc; ++j) vv += c[j] * val[d->in[j]];
+        val[id] = vv;
+        for (int a = 0; a < P; ++a) {
+          double t = 0;
+          for (int j = 0; j < nc; ++j) t += c[j] * grd[d->in[j]][a] + dc[j][a] * val[d->in[j]];
+          g[a] = t;
+        }
+        for (int a = 0; a < P; ++a)
+          for (int b = 0; b < P; ++b) {
+            double t = 0;
+            for (int j = 0; j < nc; ++j) {
+              const int cj = d->in[j];
+              t += c[j] * hss[cj][a][b] + dc[j][a] * grd[cj][b] + dc[j][b] * grd[cj][a] + hc[j][a][b] * val[cj];
+            }
+            H[a][b] = t;
+          }
+        free(hc);
+      } else if (d->kind == RFO_PROD) {
+        /* fold the factors one at a time: (f g)'' = f'' g + f' g'^T + g' f'^T + f g'' */
+        const int c0 = d->in[0];
+        double vv = val[c0], gg[MAXPH];
+        hmat hh;
+        for (int a = 0; a < P; ++a) gg[a] = grd[c0][a];
+        memcpy(hh, hss[c0], sizeof(hmat));
+        for (int j = 1; j < d->n_in; ++j) {
+          const int cj = d->in[j];
+          hmat nh;
+          for (int a = 0; a < P; ++a)
+            for (int b = 0; b < P; ++b)
+              nh[a][b] = hh[a][b] * val[cj] + gg[a] * grd[cj][b] + grd[cj][a] * gg[b] + vv * hss[cj][a][b];
+          for (int a = 0; a < P; ++a) gg[a] = gg[a] * val[cj] + vv * grd[cj][a];
+          vv *= val[cj];
+          memcpy(hh, nh, sizeof(hmat));
+        }
+        val[id] = vv;
+        for (int a = 0; a < P; ++a) g[a] = gg[a];
+        memcpy(H, hh, sizeof(hmat));
+      } else {
+        double v[MAXIN], du[MAXIN], h2[MAXS][MAXS];
+        for (int j = 1; j < d->n_in; ++j) v[j] = m->pv[d->in[j]];
+        const double x = xs[m->nd[d->in[0]].index];
+        const double u = leaf_value(d, x, v, du);
+        rc = leaf_value2(d, x, v, du, h2);
+        if (rc) break;
+        /* U' and U'' in theta, through the parameter-like inputs */
+        double Ug[MAXPH];
+        hmat Uh;
+        for (int a = 0; a < P; ++a) {
+          double t = 0;
+          for (int j = 1; j < d->n_in; ++j) t += du[j - 1] * m->pg[d->in[j]][a];
+          Ug[a] = t;
+        }
+        for (int a = 0; a < P; ++a)
+          for (int b = 0; b < P; ++b) {
+            double t = 0;
+            for (int j = 1; j < d->n_in; ++j) {
+              t += du[j - 1] * ph[d->in[j]][a][b];
+              for (int k = 1; k < d->n_in; ++k) t += h2[j - 1][k - 1] * m->pg[d->in[j]][a] * m->pg[d->in[k]][b];
+            }
+            Uh[a][b] = t;
+          }
+        /* v = U / N */
+        const double N = d->N;
+        val[id] = u / N;
+        for (int a = 0; a < P; ++a) g[a] = Ug[a] / N - u * d->dN[a] / (N * N);
+        for (int a = 0; a < P; ++a)
+          for (int b = 0; b < P; ++b)
+            H[a][b] = Uh[a][b] / N - (Ug[a] * d->dN[b] + d->dN[a] * Ug[b]) / (N * N) - u * lN2[id][a][b] / (N * N) +
+                      2 * u * d->dN[a] * d->dN[b] / (N * N * N);
+      }
+    }
+    if (rc) break;
+    const double p = val[top];
+    if (!(p > 0) || !isfinite(p)) { ++bad; continue; }
+    const double wi = w ? w[i] : 1.0;
+    nadd(&L, -wi * log(p));
+    for (int a = 0; a < P; ++a) nadd(&G[a], -wi * grd[top][a] / p);
+    for (int a = 0; a < P; ++a)
+      for (int b = 0; b < P; ++b)
+        nadd(&HS[a * MAXPH + b], -wi * (hss[top][a][b] / p - grd[top][a] * grd[top][b] / (p * p)));
+  }
+  if (rc == 0 && ext >= 0) {
+    nsum Nw = {0, 0};
+    for (int64_t i = 0; i < n; ++i) nadd(&Nw, w ? w[i] : 1.0);
+    const double nu = m->pv[ext], N = nval(&Nw);
+    if (!(nu > 0)) rc = -2, g_err = "extended: nu must be > 0";
+    else {
+      nadd(&L, nu - N * log(nu));
+      for (int a = 0; a < P; ++a) nadd(&G[a], (1.0 - N / nu) * m->pg[ext][a]);
+      for (int a = 0; a < P; ++a)
+        for (int b = 0; b < P; ++b)
+          nadd(&HS[a * MAXPH + b], N / (nu * nu) * m->pg[ext][a] * m->pg[ext][b] + (1.0 - N / nu) * ph[ext][a][b]);
+    }
+  }
+  if (rc == 0) {
+    *nll = bad ? INFINITY : nval(&L);
+    if (grad) for (int a = 0; a < P; ++a) grad[a] = nval(&G[a]);
+    if (hess)
+      for (int a = 0; a < P; ++a) for (int b = 0; b < P; ++b) hess[a * P + b] = nval(&HS[a * MAXPH + b]);
+    if (n_bad) *n_bad = bad;
+  }
+  free(ph); free(lN2); free(val); free(grd); free(hss); free(HS);
+  return rc;
+}

@@ -88,6 +88,12 @@ int rfo_nll_w(rfo_model* m, int top, const double* theta,
               const double* const* cols, const double* w, int64_t n,
               double* nll, double* grad, double* gabs, int64_t* n_bad);
 /* per-event normalised PDF values */
+/* The NLL (weights w may be NULL), its gradient and its Hessian
+ * hess[P][P] (row-major) at theta, by second-order forward mode through every
+ * node; analytic leaves only (no convolution or MLP leaf), at most 16
+ * parameters. */
+int rfo_nll_hess(rfo_model* m, int top, const double* theta, const double* const* cols, const double* w,
+                 int64_t n, double* nll, double* grad, double* hess, int64_t* n_bad);
 int rfo_values(rfo_model* m, int top, const double* theta,
                const double* const* cols, int64_t n, double* out);
 /* normalisation integral of a PDF leaf and its d/dtheta (n_params) */

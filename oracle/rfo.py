@@ -58,6 +58,7 @@ def lib():
         L.rfo_nll_ex.argtypes = [P, I, DP, ctypes.POINTER(DP), I64, DP, DP, DP, ctypes.POINTER(I64)]
         L.rfo_nll_w.argtypes = [P, I, DP, ctypes.POINTER(DP), DP, I64, DP, DP, DP, ctypes.POINTER(I64)]
         L.rfo_values.argtypes = [P, I, DP, ctypes.POINTER(DP), I64, DP]
+        L.rfo_nll_hess.argtypes = [P, I, DP, ctypes.POINTER(DP), DP, I64, DP, DP, DP, ctypes.POINTER(I64)]
         L.rfo_norm.argtypes = [P, I, DP, DP, DP]
         L.rfo_gauss_legendre.argtypes = [I, D, D, DP, DP]
         L.rfo_mlp_forward.argtypes = [DP, DP, I64, DP]
@@ -147,6 +148,20 @@ class Model:
             _check(lib().rfo_nll_w(self.h, top, _dp(th), arr, _dp(w), n, ctypes.byref(out), _dp(g), _dp(ga),
                                    ctypes.byref(nb)))
         return out.value, g[: self.n_params], ga[: self.n_params], nb.value
+
+    def nll_hess(self, top, theta, cols, weights=None):
+        """(nll, grad, hess[P, P], n_bad): the NLL with its gradient and Hessian."""
+        th = _f64(theta)
+        cs, arr, n = self._cols(cols)
+        out = ctypes.c_double()
+        P = self.n_params
+        g = np.zeros(max(1, P))
+        h = np.zeros(max(1, P * P))
+        nb = ctypes.c_int64()
+        w = None if weights is None else _f64(weights)
+        _check(lib().rfo_nll_hess(self.h, top, _dp(th), arr, None if w is None else _dp(w), n, ctypes.byref(out),
+                                  _dp(g), _dp(h), ctypes.byref(nb)))
+        return out.value, g[:P], h[: P * P].reshape(P, P), nb.value
 
     def values(self, top, theta, cols):
         th = _f64(theta)

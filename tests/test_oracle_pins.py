@@ -769,3 +769,133 @@ def test_oracle_weighted_extended_equals_repeated_events():
     b, gb, _, _ = om.nll_ex(top, th, [np.repeat(x, w.astype(int))])
     assert abs(a - b) <= 1e-12 * abs(b)
     np.testing.assert_allclose(ga, gb, rtol=1e-11, atol=1e-9)
+
+
+# ------------------------------------------------------ second derivatives
+def _hess_fd(om, otop, th, cols, weights=None, h=None):
+    """Central differences of the oracle's analytic gradient, Richardson-
+    extrapolated, one column per parameter."""
+    th = np.asarray(th, float)
+    P = th.size
+    H = np.empty((P, P))
+    for k in range(P):
+        hk = (h[k] if h is not None else 1e-4 * max(1.0, abs(th[k])))
+
+        def d(hh):
+            tp, tm = th.copy(), th.copy()
+            tp[k] += hh
+            tm[k] -= hh
+            return (om.nll_ex(otop, tp, cols, weights=weights)[1] - om.nll_ex(otop, tm, cols, weights=weights)[1]) / (2 * hh)
+        H[:, k] = (4 * d(hk / 2) - d(hk)) / 3
+    return H
+
+
+def _hess_close(H, Href, tol):
+    s = np.sqrt(np.abs(np.outer(np.diag(Href), np.diag(Href))))
+    err = np.abs(H - Href) / s
+    assert err.max() <= tol, (err.max(), np.unravel_index(np.argmax(err), err.shape), H, Href)
+
+
+def _spec_product_fn():
+    """Two Gaussians whose widths are tied by a product function s2 = k s1 and
+    whose fraction is a ratio of yields (second derivatives of the parameter
+    functions); theta = (mu1, s1, mu2, k, y1, y2)."""
+    return [
+        ("obs", "x", [], [-10.0, 10.0]),
+        ("param", "mu1", [], [-5.0, 5.0]), ("param", "s1", [], [0.05, 5.0]),
+        ("param", "mu2", [], [-5.0, 5.0]), ("param", "k", [], [0.1, 10.0]),
+        ("param", "y1", [], [0.0, 1e9]), ("param", "y2", [], [0.0, 1e9]),
+        ("product", "s2", ["s1", "k"], []),
+        ("gauss", "g1", ["x", "mu1", "s1"], []), ("gauss", "g2", ["x", "mu2", "s2"], []),
+        ("linear", "yt", ["y1", "y2"], [0.0, 1.0, 1.0]), ("ratio", "f", ["y1", "yt"], []),
+        ("add", "model", ["g1", "g2", "f"], []),
+    ]
+
+
+HESS_CASES = {
+    "gauss_cheb": (workloads.spec_gauss_cheb, lambda: [synth.sample_gauss_cheb(3000, 61)], [0.05, 0.97, 0.31, 0.21, -0.09]),
+    "decay_argus": (workloads.spec_decay_argus, lambda: list(synth.sample_decay_argus(3000, 62)),
+                    list(synth.jitter_decay(3)), [1.5e-3, 5e-5, 5e-5, 3e-6, 3e-6, 4e-4, 2e-2, 2e-4]),
+    "poisson_mix": (workloads.spec_poisson_gauss_cheb, lambda: list(synth.sample_poisson_gauss_cheb(3000, 63)),
+                    [11.5, 5.2, 0.03, 1.02, 0.19, -0.11, 0.31]),
+    "two_gauss_ext": (workloads.spec_two_gauss_extended,
+                      lambda: [np.concatenate([np.random.default_rng(64).normal(-2, 0.5, 1200),
+                                               np.random.default_rng(65).normal(2, 0.5, 1800)]).clip(-9.9, 9.9)],
+                      [-1.98, 0.51, 2.01, 0.49, 1190.0, 1815.0]),
+    "product_ratio": (_spec_product_fn,
+                      lambda: [np.concatenate([np.random.default_rng(66).normal(-2, 0.5, 1200),
+                                               np.random.default_rng(67).normal(2, 1.0, 1800)]).clip(-9.9, 9.9)],
+                      [-1.98, 0.51, 2.01, 1.9, 1190.0, 1815.0]),
+    "bw_exp": (lambda: [("obs", "x", [], [60.0, 120.0]), ("param", "M", [], [85.0, 97.0]),
+                        ("param", "G", [], [0.5, 6.0]), ("param", "lam", [], [-0.2, 0.2]), ("param", "f", [], [0.0, 1.0]),
+                        ("bw", "s", ["x", "M", "G"], []), ("exp", "b", ["x", "lam"], [1.0]),
+                        ("add", "model", ["s", "b", "f"], [])],
+               lambda: [np.random.default_rng(68).uniform(60, 120, 3000)], [91.1, 2.6, -0.021, 0.7]),
+    "argus_steep": (lambda: [("obs", "m", [], [5.2, 5.29]), ("param", "c", [], [-200.0, 0.0]),
+                             ("const", "m0", [], [5.29]), ("argus", "a", ["m", "m0", "c"], [])],
+                    lambda: [np.random.default_rng(73).uniform(5.2, 5.2899, 2000)], [-80.0]),
+    "exp_tau": (lambda: [("obs", "t", [], [0.3, 7.0]), ("param", "tau", [], [0.1, 10.0]), ("exp", "e", ["t", "tau"], [0.0])],
+                lambda: [np.random.default_rng(69).uniform(0.3, 7.0, 2000)], [1.3]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(HESS_CASES))
+@pytest.mark.parametrize("weighted", [False, True])
+def test_oracle_hessian_vs_gradient_differences(case, weighted):
+    """The oracle's analytic Hessian against Richardson-extrapolated central
+    differences of its analytic gradient (which is pinned against differences
+    of the NLL itself), relative to sqrt(H_jj H_kk); also symmetric, and its
+    NLL and gradient are the ones rfo_nll_w gives."""
+    make_spec, make_cols, th = HESS_CASES[case][:3]
+    steps = HESS_CASES[case][3] if len(HESS_CASES[case]) > 3 else None
+    om, otop, _ = rfo.from_spec(make_spec())
+    cols = [synth._f32(c) for c in make_cols()]
+    w = np.random.default_rng(70).uniform(0.5, 2.0, cols[0].size) if weighted else None
+    nll, g, H, nb = om.nll_hess(otop, th, cols, weights=w)
+    n2, g2, _, _ = om.nll_ex(otop, th, cols, weights=w)
+    assert nb == 0 and nll == pytest.approx(n2, rel=1e-14) and np.allclose(g, g2, rtol=1e-12, atol=1e-9)
+    assert np.array_equal(H, H.T) or np.abs(H - H.T).max() <= 1e-12 * np.abs(H).max()
+    _hess_close(H, _hess_fd(om, otop, th, cols, weights=w, h=steps), 2e-7)
+
+
+def test_oracle_hessian_closed_forms():
+    """A lone Gaussian on a range wide enough that its normalisation is
+    sigma sqrt(2 pi) to the last bit, and a lone exponential likewise tau:
+    the NLL's Hessian in closed form."""
+    rng = np.random.default_rng(71)
+    x = synth._f32(rng.normal(0.3, 1.7, 5000))
+    m, top = single_leaf("gauss", -1000.0, 1000.0, 2)
+    mu, s = 0.25, 1.65
+    _, _, H, _ = m.nll_hess(top, [mu, s], [x])
+    d = x - mu
+    n = x.size
+    ref = np.array([[n / s**2, 2 * d.sum() / s**3], [2 * d.sum() / s**3, 3 * (d * d).sum() / s**4 - n / s**2]])
+    np.testing.assert_allclose(H, ref, rtol=1e-12)
+    t = synth._f32(rng.exponential(1.4, 5000))
+    m, top = single_leaf("exp", 0.0, 1e4, 1, attrs=[0.0])
+    tau = 1.35
+    _, _, H, _ = m.nll_hess(top, [tau], [t])
+    np.testing.assert_allclose(H[0, 0], 2 * t.sum() / tau**3 - t.size / tau**2, rtol=1e-12)
+
+
+def test_oracle_hessian_fraction_entry_vs_scipy():
+    """For f g + (1 - f) c the fraction-fraction entry is
+    sum_i ((g_i - c_i) / p_i)^2, with the normalised Gaussian from
+    scipy.stats.truncnorm and the normalised Chebyshev polynomial written
+    out."""
+    x = synth.sample_gauss_cheb(4000, 72)
+    th = [0.05, 0.97, 0.31, 0.21, -0.09]
+    om, otop, _ = rfo.from_spec(workloads.spec_gauss_cheb())
+    _, _, H, _ = om.nll_hess(otop, th, [x])
+    mu, s, f, c1, c2 = th
+    gpdf = stats.truncnorm.pdf(x, (-10 - mu) / s, (10 - mu) / s, loc=mu, scale=s)
+    xp = x / 10.0
+    cpdf = (1 + c1 * xp + c2 * (2 * xp * xp - 1)) / (20.0 * (1 - c2 / 3))
+    p = f * gpdf + (1 - f) * cpdf
+    np.testing.assert_allclose(H[2, 2], np.sum(((gpdf - cpdf) / p) ** 2), rtol=1e-11)
+
+
+def test_oracle_hessian_rejects_leaves_without_second_derivatives():
+    om, otop, _ = rfo.from_spec(workloads.spec_bwcb(K=64))
+    with pytest.raises(RuntimeError):
+        om.nll_hess(otop, workloads.truth_vector(synth.BWCB_TRUTH), [synth.sample_bw_cb(10, 4)])
