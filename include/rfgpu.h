@@ -202,11 +202,31 @@ int rf_unfused_build(const rf_program* p);
 int rf_nll_grad_async(rf_program* p, const double* theta, void* stream);
 const double* rf_program_result(const rf_program* p);
 
+/* The NLL, its gradient and its Hessian hess[n_params * n_params] (row-major)
+ * at theta in one fused pass: the curvature from which a fit's uncertainties
+ * come (the paper's fits, Section 3 and Fig. 5; its parameter-only caching,
+ * Section 4, here for second derivatives of the normalisations too).
+ * Per-event arithmetic in FP64 whatever the program's precision form; the
+ * kernel accumulates log p, its gradient and its Hessian in the leaf and
+ * fraction inputs and contracts them with the parameter functions' first and
+ * second derivatives.  Programs whose leaves all have second derivatives
+ * (Gaussian, Chebyshev, exponential, decay (x) resolution, ARGUS,
+ * Breit-Wigner) and at most 16 parameters; RF_E_INVALID otherwise.  The first
+ * call builds and loads its own code object and allocates its workspace
+ * (kept with the program).  Synchronous; n_bad may be NULL; events with
+ * p <= 0 give RF_E_NONFINITE, nll = +inf, grad and hess NaN. */
+int rf_nll_grad_hess(rf_program* p, const double* theta, double* nll, double* grad, double* hess,
+                     int64_t* n_bad, void* stream);
+/* builds the Hessian kernel's code object into the cache without loading it
+ * (no GPU needed; also valid for a RF_COMPILE_NO_LOAD program) */
+int rf_hess_build(const rf_program* p);
+
 /* ---- fit ------------------------------------------------------------------ */
 /* Quasi-Newton (BFGS) minimisation of NLL with backtracking line search that
  * backs off infinite NLL and out-of-bounds points; converged when
- * EDM = g^T H^-1 g / 2 < edm_tol.  sigma_out: sqrt(diag(H^-1)) with H from
- * central differences of the analytic gradient at the minimum (may be NULL).
+ * EDM = g^T H^-1 g / 2 < edm_tol.  sigma_out: sqrt(diag(H^-1)) with H the
+ * Hessian of rf_nll_grad_hess at the minimum, or central differences of the
+ * analytic gradient for programs it does not take (may be NULL).
  * info_out[4] = {n_iterations, n_evaluations, edm, converged(0/1)}. */
 int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, int32_t max_iter,
                 double* theta_out, double* sigma_out, double* info_out, void* stream);

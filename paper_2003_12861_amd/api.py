@@ -74,6 +74,8 @@ _OPTIONAL = {
     "rf_nll_unfused": ([_P, _P, _P, _P, _P], _I32),
     "rf_unfused_build": ([_P], _I32),
     "rf_bwcb_logpdf": ([_P, _I64, _I32, _D, _D, _D, _D, _P, _P], _I32),
+    "rf_nll_grad_hess": ([_P, _DP, _DP, _DP, _DP, _PI64, _P], _I32),
+    "rf_hess_build": ([_P], _I32),
 }
 
 
@@ -313,6 +315,21 @@ class Program:
 
     def nll_grad_async(self, theta, stream=None):
         check(rf_nll_grad_async(self.h, self._theta_ptr(theta), _stream(stream)))
+
+    def nll_grad_hess(self, theta, stream=None):
+        """Returns (nll, grad, hess[P, P], n_bad) from the Hessian kernel."""
+        P = self.n_params
+        h = np.zeros(max(1, P * P))
+        g = np.zeros(max(1, P))
+        rc = rf_nll_grad_hess(self.h, self._theta_ptr(theta), self._vref, _dptr(g), _dptr(h), self._nbref,
+                              _stream(stream))
+        if rc != -3:
+            check(rc)
+        return self._v.value, g[:P].copy(), h[: P * P].reshape(P, P).copy(), self._nb.value
+
+    def build_hess(self):
+        """Build the Hessian kernel's code object (no GPU needed)."""
+        check(rf_hess_build(self.h))
 
     def stats(self):
         """(synchronous calls, calls whose wait fell back to a stream sync)"""

@@ -229,6 +229,11 @@ void rf_program_free(rf_program* p) {
   if (p->unf.part) (void)hipFree(p->unf.part);
   if (p->unf.out) (void)hipFree(p->unf.out);
   if (p->unf.mod) (void)hipModuleUnload(p->unf.mod);
+  if (p->hes.part) (void)hipFree(p->hes.part);
+  if (p->hes.ticket) (void)hipFree(p->hes.ticket);
+  if (p->hes.out) (void)hipFree(p->hes.out);
+  if (p->hes.h_out) (void)hipHostFree(p->hes.h_out);
+  if (p->hes.mod) (void)hipModuleUnload(p->hes.mod);
   if (p->m.mod) (void)hipModuleUnload(p->m.mod);
   delete p;
 }
@@ -403,6 +408,8 @@ int rf_nll_grad_async(rf_program* p, const double* theta, void* stream) {
   return launch(p, p->m.k_grad, a, stream);
 }
 
+
+
 const double* rf_program_result(const rf_program* p) { return p ? p->d_out : nullptr; }
 
 int rf_unfused_build(const rf_program* p) {
@@ -484,6 +491,78 @@ int rf_nll_unfused(rf_program* p, const double* theta, double* nll, int64_t* n_b
   const int64_t bad = (int64_t)h[1];
   if (n_bad) *n_bad = bad;
   *nll = bad ? INFINITY : h[0];
+  if (bad) return fail(RF_E_NONFINITE, std::to_string(bad) + " events with p <= 0 or non-finite p");
+  return RF_OK;
+}
+
+int rf_hess_build(const rf_program* p) {
+  if (!p) return fail(RF_E_INVALID, "program is NULL");
+  std::string why;
+  if (!hess_supported(p->L, &why)) return fail(RF_E_INVALID, why);
+  std::string path;
+  return build_code_object(generate_hess_source(p->L, p->block), path);
+}
+
+int rf_nll_grad_hess(rf_program* p, const double* theta, double* nll, double* grad, double* hess, int64_t* n_bad,
+                     void* stream) {
+  int rc = ready(p, theta);
+  if (rc) return rc;
+  const int P = p->L.n_params;
+  if (!nll || (P && (!grad || !hess))) return fail(RF_E_INVALID, "nll, grad or hess is NULL");
+  std::string why;
+  if (!hess_supported(p->L, &why)) return fail(RF_E_INVALID, why);
+  rf_program::Hess& h = p->hes;
+  hipError_t e;
+  const int nout = P + 2 + P * P;
+  if (!h.mod) {
+    std::string path;
+    if ((rc = build_code_object(generate_hess_source(p->L, p->block), path))) return rc;
+    std::ifstream f(path, std::ios::binary);
+    std::vector<char> bytes((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    if (bytes.empty()) return fail(RF_E_DEVICE, "empty code object " + path);
+    if ((e = hipModuleLoadData(&h.mod, bytes.data())) != hipSuccess) return hip_fail(e, "hipModuleLoadData");
+    if ((e = hipModuleGetFunction(&h.k, h.mod, "rf_k_hess")) != hipSuccess) return hip_fail(e, "rf_k_hess");
+    if ((e = hipMalloc(&h.ticket, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMemset(h.ticket, 0, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return hip_fail(e, "hipMemset");
+    if ((e = hipMalloc(&h.out, sizeof(double) * nout)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipHostMalloc(&h.h_out, sizeof(double) * (nout + 1), hipHostMallocMapped | hipHostMallocCoherent)) !=
+        hipSuccess)
+      return hip_fail(e, "hipHostMalloc");
+    memset(h.h_out, 0, sizeof(double) * (nout + 1));
+    if ((e = hipHostGetDevicePointer((void**)&h.d_hout, h.h_out, 0)) != hipSuccess)
+      return hip_fail(e, "hipHostGetDevicePointer");
+  }
+  // one workgroup per 1024 events (four per lane), at most two per CU
+  int64_t G = (p->n + 4 * (int64_t)p->block - 1) / (4 * (int64_t)p->block);
+  const int64_t gcap = (int64_t)cu_count(p->device) * 2;
+  G = G < 1 ? 1 : (G > gcap ? gcap : G);
+  const int ns1 = hess_nsums(p->L) + 1;
+  if (G > h.part_n) {
+    if (h.part) (void)hipFree(h.part);
+    h.part = nullptr;
+    h.part_n = 0;
+    if ((e = hipMalloc(&h.part, sizeof(double) * ns1 * G)) != hipSuccess) return hip_fail(e, "hipMalloc (partials)");
+    h.part_n = (int)G;
+  }
+  RfArgs a;
+  fill_args(p, theta, a);
+  a.part = h.part;
+  a.nblk_max = h.part_n;
+  a.ticket = h.ticket;
+  a.out = h.out;
+  a.hout = h.d_hout;
+  a.seq = ++h.seq;
+  size_t sz = sizeof(RfArgs);
+  void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &sz, HIP_LAUNCH_PARAM_END};
+  if ((e = hipModuleLaunchKernel(h.k, (unsigned)G, 1, 1, p->block, 1, 1, 0, (hipStream_t)stream, nullptr, cfg)) !=
+      hipSuccess)
+    return hip_fail(e, "rf_k_hess launch");
+  if ((rc = wait_result((volatile uint64_t*)(h.h_out + nout), a.seq, stream, nullptr))) return rc;
+  const int64_t bad = (int64_t)h.h_out[P + 1];
+  if (n_bad) *n_bad = bad;
+  *nll = bad ? INFINITY : h.h_out[0];
+  for (int k = 0; k < P; ++k) grad[k] = bad ? NAN : h.h_out[1 + k];
+  for (int k = 0; k < P * P; ++k) hess[k] = bad ? NAN : h.h_out[P + 2 + k];
   if (bad) return fail(RF_E_NONFINITE, std::to_string(bad) + " events with p <= 0 or non-finite p");
   return RF_OK;
 }

@@ -24,13 +24,14 @@
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
+#include <map>
 #include <sstream>
 
 #include "rf_internal.h"
 
 namespace rf {
 
-#include "_gen/rf_device_src.inc"  // RF_DEV_SRC_KABI, _OPS, _MLP, _BODY
+#include "_gen/rf_device_src.inc"  // RF_DEV_SRC_KABI, _OPS, _MLP, _POISSON, _BODY, _HESS, _HBODY
 
 static std::string dstr(double v) {
   char b[40];
@@ -591,6 +592,385 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     emit_unfused(o, L);
   else
     o << RF_DEV_SRC_BODY << "\n";
+  return o.str();
+}
+
+// ============================================================ Hessian ==
+// The Hessian kernel (its own module, built on first use).  The NLL depends
+// on theta only through the slot values a (the theta-dependent leaf inputs
+// and fractions), so per event it forms, in FP64 and forward mode over the
+// PDF tree, the slot gradient G and slot Hessian H of p (a leaf from its
+// second derivatives and those of its normalisation; a product by the
+// product rule; a sum linearly, its fractions entering at first order), and
+// adds log p, q = G/p and H/p - q q^T to 1 + K + K(K+1)/2 event sums.  The
+// epilogue contracts them with the parameter functions' first and second
+// derivatives:
+//   grad = sum_a g_a J_a,
+//   hess = sum_ab H_ab J_a J_b^T + sum_a g_a d2a/dtheta2,
+// (g, H the slot gradient and Hessian of the NLL, J_a = da/dtheta), and adds
+// the extended term's (N/nu^2) J_nu J_nu^T + (1 - N/nu) d2nu/dtheta2.
+
+bool hess_supported(const Lowered& L, std::string* why) {
+  for (size_t id = 0; id < L.nodes.size(); ++id) {
+    if (!L.reach[id]) continue;
+    const int op = L.nodes[id].op;
+    if (op == RF_OP_NUMCONV_BW_CB || op == RF_OP_MLP || op == RF_OP_POISSON) {
+      if (why) *why = "no second derivatives for the leaf '" + L.nodes[id].name + "' (convolution, MLP and Poisson leaves)";
+      return false;
+    }
+  }
+  if (L.n_params > 16) {
+    if (why) *why = "the Hessian takes at most 16 parameters";
+    return false;
+  }
+  return true;
+}
+
+int hess_nsums(const Lowered& L) {
+  const int K = (int)L.slots.size();
+  return 1 + K + K * (K + 1) / 2 + (L.wsum >= 0 ? 1 : 0);
+}
+
+// theta-sparse Jacobian of a parameter-like node: (theta index, FP64 factor)
+typedef std::vector<std::pair<int, std::string>> SJac;
+static SJac sjac(const Lowered& L, int id) {
+  const Node& n = L.nodes[id];
+  SJac r;
+  auto scaled = [&](const SJac& a, const std::string& f) {
+    for (const auto& e : a) r.push_back({e.first, "(" + e.second + ") * (" + f + ")"});
+  };
+  if (n.op == K_PARAM) r.push_back({n.index, "1.0"});
+  else if (n.op == RF_OP_FN_LINEAR) {
+    for (size_t j = 0; j < n.in.size(); ++j) scaled(sjac(L, n.in[j]), dstr(n.attrs[j + 1]));
+  } else if (n.op == RF_OP_FN_PRODUCT) {
+    for (size_t j = 0; j < n.in.size(); ++j) {
+      std::string o = "1.0";
+      for (size_t i = 0; i < n.in.size(); ++i)
+        if (i != j) o += " * pv" + std::to_string(n.in[i]);
+      scaled(sjac(L, n.in[j]), o);
+    }
+  } else if (n.op == RF_OP_FN_RATIO) {
+    const std::string a = "pv" + std::to_string(n.in[0]), b = "pv" + std::to_string(n.in[1]);
+    scaled(sjac(L, n.in[0]), "1.0 / " + b);
+    scaled(sjac(L, n.in[1]), "-" + a + " / (" + b + " * " + b + ")");
+  }
+  return r;
+}
+
+// H[k][l] += c * X_k Y_l for sparse X, Y (H row-major at out + P + 2)
+static void emit_outer(std::ostringstream& o, const Lowered& L, const SJac& X, const SJac& Y, const std::string& c) {
+  const int P = L.n_params;
+  for (const auto& x : X)
+    for (const auto& y : Y)
+      o << "  out[" << P + 2 + x.first * P + y.first << "] += (" << c << ") * (" << x.second << ") * (" << y.second
+        << ");\n";
+}
+
+// H += c * d2(pv_id)/dtheta2, through the parameter functions
+static void emit_hjac(std::ostringstream& o, const Lowered& L, int id, const std::string& c) {
+  const Node& n = L.nodes[id];
+  if (n.op == RF_OP_FN_LINEAR) {
+    for (size_t j = 0; j < n.in.size(); ++j) emit_hjac(o, L, n.in[j], "(" + c + ") * " + dstr(n.attrs[j + 1]));
+  } else if (n.op == RF_OP_FN_PRODUCT) {
+    const size_t m = n.in.size();
+    for (size_t j = 0; j < m; ++j) {
+      std::string oj = "1.0";
+      for (size_t i = 0; i < m; ++i)
+        if (i != j) oj += " * pv" + std::to_string(n.in[i]);
+      emit_hjac(o, L, n.in[j], "(" + c + ") * " + oj);
+      for (size_t k = 0; k < m; ++k) {
+        if (k == j) continue;
+        std::string ojk = "1.0";
+        for (size_t i = 0; i < m; ++i)
+          if (i != j && i != k) ojk += " * pv" + std::to_string(n.in[i]);
+        emit_outer(o, L, sjac(L, n.in[j]), sjac(L, n.in[k]), "(" + c + ") * " + ojk);
+      }
+    }
+  } else if (n.op == RF_OP_FN_RATIO) {  // a/b
+    const std::string a = "pv" + std::to_string(n.in[0]), b = "pv" + std::to_string(n.in[1]);
+    const SJac Ja = sjac(L, n.in[0]), Jb = sjac(L, n.in[1]);
+    emit_hjac(o, L, n.in[0], "(" + c + ") / " + b);
+    emit_hjac(o, L, n.in[1], "-(" + c + ") * " + a + " / (" + b + " * " + b + ")");
+    emit_outer(o, L, Ja, Jb, "-(" + c + ") / (" + b + " * " + b + ")");
+    emit_outer(o, L, Jb, Ja, "-(" + c + ") / (" + b + " * " + b + ")");
+    emit_outer(o, L, Jb, Jb, "2.0 * (" + c + ") * " + a + " / (" + b + " * " + b + " * " + b + ")");
+  }
+}
+
+static std::string u2_call(const Node& n, const std::string& x, const std::string& in, const std::string& du,
+                           const std::string& d2, const Lowered& L) {
+  const Node& ob = L.nodes[n.in[0]];
+  const std::string r = ", " + dstr(ob.lo) + ", " + dstr(ob.hi) + ", " + du + ", " + d2 + ")";
+  switch (n.op) {
+    case RF_OP_GAUSS: return "gauss_u2(" + x + ", " + in + r;
+    case RF_OP_CHEB: return "cheb_u2<" + std::to_string(leaf_n_shape(n)) + ">(" + x + ", " + in + r;
+    case RF_OP_EXP: return "exp_u2<" + std::to_string((int)n.attrs[0]) + ">(" + x + ", " + in + r;
+    case RF_OP_DECAY_GAUSS: return "decay_u2(" + x + ", " + in + r;
+    case RF_OP_ARGUS: return "argus_u2(" + x + ", " + in + r;
+    case RF_OP_BW: return "bw_u2(" + x + ", " + in + r;
+  }
+  return "";
+}
+
+static std::string n2_call(const Node& n, const std::string& in, const std::string& d2, const Lowered& L) {
+  const Node& ob = L.nodes[n.in[0]];
+  const std::string r = "(" + in + ", " + dstr(ob.lo) + ", " + dstr(ob.hi) + ", " + d2 + ")";
+  switch (n.op) {
+    case RF_OP_GAUSS: return "gauss_n2" + r;
+    case RF_OP_CHEB: return "cheb_n2<" + std::to_string(leaf_n_shape(n)) + ">" + r;
+    case RF_OP_EXP: return "exp_n2<" + std::to_string((int)n.attrs[0]) + ">" + r;
+    case RF_OP_DECAY_GAUSS: return "decay_n2" + r;
+    case RF_OP_ARGUS: return "argus_n2" + r;
+    case RF_OP_BW: return "bw_n2" + r;
+  }
+  return "";
+}
+
+std::string generate_hess_source(const Lowered& L, int BS) {
+  const auto& g = L.nodes;
+  const int N = (int)g.size();
+  const int P = L.n_params;
+  const int K = (int)L.slots.size();
+  const int NSH = hess_nsums(L);
+  const bool f32 = L.precision == RF_FP32_COMP;
+  std::ostringstream o;
+  o << "// generated by rfgpu: the Hessian kernel of one likelihood program\n";
+  o << RF_DEV_SRC_KABI << "\n" << RF_DEV_SRC_OPS << "\n" << RF_DEV_SRC_HESS << "\n";
+  o << "#define RF_T " << (f32 ? "float" : "double") << "\n";
+  o << "#define RF_NCOL " << L.n_cols + L.weighted << "\n";
+  o << "#define RF_NCST " << L.n_cst << "\n";
+  o << "#define RF_P " << P << "\n";
+  o << "#define RF_BS " << BS << "\n";
+  o << "#define RF_NSH " << NSH << "\n";
+  // Hessian constants per leaf: its shape input values, then d2N/(N da db)
+  std::vector<int> hoff(N, -1);
+  int nhc = 0;
+  for (int id = 0; id < N; ++id) {
+    if (!L.reach[id] || !is_leaf(g[id].op)) continue;
+    const int k = leaf_n_shape(g[id]);
+    hoff[id] = nhc;
+    nhc += k + k * k;
+  }
+  o << "#define RF_NHC " << nhc << "\n\n";
+
+  // ---- the fused kernels' prologue (N and d log N in cst) ----
+  o << "RF_DEV void rf_prologue(const double* th, double* cst, const RfArgs& a) {\n";
+  o << "  const int tid = threadIdx.x;\n";
+  emit_paramlike(o, L, "  ");
+  int item = 0;
+  const int NW = BS / 64;
+  for (int id = 0; id < N; ++id) {
+    if (!L.reach[id]) continue;
+    const Node& n = g[id];
+    if (!is_leaf(n.op) && n.op != RF_OP_ADD_PDF) continue;
+    const int tid = 64 * (item % NW) + item / NW;
+    ++item;
+    o << "  if (tid == " << tid << ") {\n";
+    if (is_leaf(n.op)) {
+      o << "    const double in[] = {";
+      for (size_t j = 1; j < n.in.size(); ++j) o << (j > 1 ? ", " : "") << "pv" << n.in[j];
+      o << "};\n    " << prologue_call(n, L, "in") << ";\n";
+    } else {
+      const int nc = ((int)n.in.size() + 1) / 2;
+      std::string rest = "1.0";
+      for (int j = 0; j < nc - 1; ++j) {
+        o << "    cst[" << L.cst_off[id] + j << "] = pv" << n.in[nc + j] << ";\n";
+        rest += " - pv" + std::to_string(n.in[nc + j]);
+      }
+      o << "    cst[" << L.cst_off[id] + nc - 1 << "] = " << rest << ";\n";
+    }
+    o << "  }\n";
+  }
+  o << "  (void)a; (void)tid; (void)cst;\n}\n\n";
+
+  // ---- Hessian prologue: leaf inputs and d2N/N ----
+  o << "RF_DEV void rf_prologue_h(const double* th, const double* cst, double* hc) {\n";
+  o << "  const int tid = threadIdx.x;\n";
+  emit_paramlike(o, L, "  ");
+  item = 0;
+  for (int id = 0; id < N; ++id) {
+    if (!L.reach[id] || !is_leaf(g[id].op)) continue;
+    const Node& n = g[id];
+    const int k = leaf_n_shape(n);
+    const int tid = 64 * (item % NW) + item / NW;
+    ++item;
+    o << "  if (tid == " << tid << ") {\n    const double in[] = {";
+    for (size_t j = 1; j < n.in.size(); ++j) o << (j > 1 ? ", " : "") << "pv" << n.in[j];
+    o << "};\n    double d2[" << k * k << "];\n    " << n2_call(n, "in", "d2", L) << ";\n";
+    o << "    for (int j = 0; j < " << k << "; ++j) hc[" << hoff[id] << " + j] = in[j];\n";
+    o << "    for (int j = 0; j < " << k * k << "; ++j) hc[" << hoff[id] + k << " + j] = d2[j] * cst["
+      << L.cst_off[id] << "];\n  }\n";
+  }
+  o << "  (void)tid; (void)th; (void)cst; (void)hc;\n}\n\n";
+
+  // ---- per event: value, slot gradient and slot Hessian of every PDF node ----
+  // gv[c][a]: name of dv_c/da (absent: zero); hv[c][{a,b}] (a <= b) likewise
+  std::vector<std::map<int, std::string>> gv(N);
+  std::vector<std::map<std::pair<int, int>, std::string>> hv(N);
+  auto pr = [](int a, int b) { return a <= b ? std::make_pair(a, b) : std::make_pair(b, a); };
+  int tmp = 0;
+  o << "RF_DEV bool rf_eval_h(const double* x, const double* cst, const double* hc, double* acc) {\n";
+  for (int id = 0; id < N; ++id) {
+    if (!L.reach[id] || !is_pdf(g[id].op)) continue;
+    const Node& n = g[id];
+    const std::string v = "v" + std::to_string(id);
+    if (is_leaf(n.op)) {
+      const int k = leaf_n_shape(n), off = L.cst_off[id], ho = hoff[id];
+      const std::string u = "u" + std::to_string(id), du = "du" + std::to_string(id), d2 = "dd" + std::to_string(id);
+      o << "  double " << du << "[" << k << "], " << d2 << "[" << k * k << "];\n";
+      o << "  const double " << u << " = " << u2_call(n, "x[" + std::to_string(g[n.in[0]].index) + "]",
+                                                       "hc + " + std::to_string(ho), du, d2, L) << ";\n";
+      o << "  const double " << v << " = " << u << " * cst[" << off << "];\n";
+      std::vector<std::pair<int, int>> sl;  // (slot, input position)
+      for (int a = 0; a < K; ++a)
+        if (L.slots[a].node == id) sl.push_back({a, L.slots[a].j});
+      auto nj = [&](int j) { return "cst[" + std::to_string(off + 1 + j) + "]"; };
+      for (const auto& s : sl) {
+        const std::string gn = "g" + std::to_string(id) + "_" + std::to_string(s.first);
+        o << "  const double " << gn << " = (" << du << "[" << s.second << "] - " << u << " * " << nj(s.second)
+          << ") * cst[" << off << "];\n";
+        gv[id][s.first] = gn;
+      }
+      for (size_t p1 = 0; p1 < sl.size(); ++p1)
+        for (size_t p2 = p1; p2 < sl.size(); ++p2) {
+          const int j = sl[p1].second, l = sl[p2].second;
+          const std::string hn = "h" + std::to_string(id) + "_" + std::to_string(sl[p1].first) + "_" + std::to_string(sl[p2].first);
+          o << "  const double " << hn << " = (" << d2 << "[" << j * k + l << "] - " << du << "[" << j << "] * " << nj(l)
+            << " - " << du << "[" << l << "] * " << nj(j) << " - " << u << " * hc[" << ho + k + j * k + l << "] + 2.0 * "
+            << u << " * " << nj(j) << " * " << nj(l) << ") * cst[" << off << "];\n";
+          hv[id][pr(sl[p1].first, sl[p2].first)] = hn;
+        }
+    } else if (n.op == RF_OP_PROD_PDF) {
+      // fold the factors: (f g)'' = f'' g + f' g'^T + g' f'^T + f g''
+      std::string cv = "v" + std::to_string(n.in[0]);
+      std::map<int, std::string> cg = gv[n.in[0]];
+      std::map<std::pair<int, int>, std::string> ch = hv[n.in[0]];
+      for (size_t f = 1; f < n.in.size(); ++f) {
+        const int F = n.in[f];
+        const std::string fv = "v" + std::to_string(F);
+        const std::string nv = (f + 1 == n.in.size()) ? v : "t" + std::to_string(tmp++);
+        std::map<int, std::string> ng;
+        std::map<std::pair<int, int>, std::string> nh;
+        for (const auto& e : cg) {
+          const std::string t = "t" + std::to_string(tmp++);
+          o << "  const double " << t << " = " << e.second << " * " << fv << ";\n";
+          ng[e.first] = t;
+        }
+        for (const auto& e : gv[F]) {
+          const std::string t = "t" + std::to_string(tmp++);
+          o << "  const double " << t << " = " << cv << " * " << e.second << ";\n";
+          ng[e.first] = t;
+        }
+        for (const auto& e : ch) {
+          const std::string t = "t" + std::to_string(tmp++);
+          o << "  const double " << t << " = " << e.second << " * " << fv << ";\n";
+          nh[e.first] = t;
+        }
+        for (const auto& e : hv[F]) {
+          const std::string t = "t" + std::to_string(tmp++);
+          o << "  const double " << t << " = " << cv << " * " << e.second << ";\n";
+          nh[e.first] = t;
+        }
+        for (const auto& a : cg)
+          for (const auto& b : gv[F]) {
+            const std::string t = "t" + std::to_string(tmp++);
+            o << "  const double " << t << " = " << a.second << " * " << b.second << ";\n";
+            nh[pr(a.first, b.first)] = t;
+          }
+        o << "  const double " << nv << " = " << cv << " * " << fv << ";\n";
+        cv = nv;
+        cg = ng;
+        ch = nh;
+      }
+      gv[id] = cg;
+      hv[id] = ch;
+    } else {  // ADD
+      const int nc = ((int)n.in.size() + 1) / 2, off = L.cst_off[id];
+      auto cj = [&](int j) { return "cst[" + std::to_string(off + j) + "]"; };
+      o << "  const double " << v << " = ";
+      for (int j = 0; j < nc; ++j) o << (j ? " + " : "") << cj(j) << " * v" << n.in[j];
+      o << ";\n";
+      for (int j = 0; j < nc; ++j) {
+        for (const auto& e : gv[n.in[j]]) {
+          const std::string t = "t" + std::to_string(tmp++);
+          o << "  const double " << t << " = " << cj(j) << " * " << e.second << ";\n";
+          gv[id][e.first] = t;
+        }
+        for (const auto& e : hv[n.in[j]]) {
+          const std::string t = "t" + std::to_string(tmp++);
+          o << "  const double " << t << " = " << cj(j) << " * " << e.second << ";\n";
+          hv[id][e.first] = t;
+        }
+      }
+      const int last = n.in[nc - 1];
+      for (int a = 0; a < K; ++a) {
+        if (L.slots[a].node != id) continue;
+        const int fj = L.slots[a].j, child = n.in[fj];
+        const std::string t = "t" + std::to_string(tmp++);
+        o << "  const double " << t << " = v" << child << " - v" << last << ";\n";
+        gv[id][a] = t;
+        // d2 v / d f_j d b = dv_child/db - dv_last/db
+        for (const auto& e : gv[child]) hv[id][pr(a, e.first)] = e.second;
+        for (const auto& e : gv[last]) {
+          const std::string t2 = "t" + std::to_string(tmp++);
+          o << "  const double " << t2 << " = -" << e.second << ";\n";
+          hv[id][pr(a, e.first)] = t2;
+        }
+      }
+    }
+  }
+  const int top = L.top;
+  o << "  const double p = v" << top << ";\n";
+  o << "  if (!(p > 0.0) || !(p < INFINITY)) return false;\n";
+  o << "  const double r = 1.0 / p;\n";
+  o << "  const double w = " << (L.weighted ? "x[" + std::to_string(L.n_cols) + "]" : std::string("1.0")) << ";\n";
+  o << "  acc[0] += w * ::log(p);\n";
+  for (int a = 0; a < K; ++a) {
+    auto it = gv[top].find(a);
+    o << "  const double q" << a << " = " << (it == gv[top].end() ? std::string("0.0") : it->second + " * r") << ";\n";
+    o << "  acc[" << 1 + a << "] += w * q" << a << ";\n";
+  }
+  int idx = 1 + K;
+  for (int a = 0; a < K; ++a)
+    for (int b = a; b < K; ++b, ++idx) {
+      auto it = hv[top].find({a, b});
+      o << "  acc[" << idx << "] += w * (" << (it == hv[top].end() ? std::string("0.0") : it->second + " * r") << " - q" << a
+        << " * q" << b << ");\n";
+    }
+  if (L.wsum >= 0) o << "  acc[" << idx << "] += w;\n";
+  o << "  return true;\n}\n\n";
+
+  // ---- epilogue: theta-space NLL, gradient and Hessian ----
+  o << "RF_DEV void rf_epilogue_h(const double* S, const double* th, double* out, unsigned nbad) {\n";
+  emit_paramlike(o, L, "  ");
+  if (L.ext_nu >= 0)
+    o << "  const double ext_n = " << (L.wsum >= 0 ? "S[" + std::to_string(idx) + "]" : "th[" + std::to_string(P) + "]")
+      << ", ext_nu = pv" << L.ext_nu << ";\n";
+  o << "  out[0] = -S[0]" << (L.ext_nu >= 0 ? " + (ext_nu - ext_n * ::log(ext_nu))" : "") << ";\n";
+  o << "  out[" << P + 1 << "] = (double)nbad;\n";
+  std::vector<SJac> J(K);
+  for (int a = 0; a < K; ++a) J[a] = sjac(L, L.slots[a].pl);
+  for (int a = 0; a < K; ++a) {
+    o << "  const double ga" << a << " = -S[" << 1 + a << "];\n";
+    for (const auto& e : J[a]) o << "  out[" << 1 + e.first << "] += ga" << a << " * (" << e.second << ");\n";
+  }
+  idx = 1 + K;
+  for (int a = 0; a < K; ++a)
+    for (int b = a; b < K; ++b, ++idx) {
+      o << "  {\n  const double hab = -S[" << idx << "];\n";
+      emit_outer(o, L, J[a], J[b], "hab");
+      if (a != b) emit_outer(o, L, J[b], J[a], "hab");
+      o << "  }\n";
+    }
+  for (int a = 0; a < K; ++a) emit_hjac(o, L, L.slots[a].pl, "ga" + std::to_string(a));
+  if (L.ext_nu >= 0) {
+    const SJac Jn = sjac(L, L.ext_nu);
+    for (const auto& e : Jn) o << "  out[" << 1 + e.first << "] += (1.0 - ext_n / ext_nu) * (" << e.second << ");\n";
+    emit_outer(o, L, Jn, Jn, "ext_n / (ext_nu * ext_nu)");
+    emit_hjac(o, L, L.ext_nu, "1.0 - ext_n / ext_nu");
+  }
+  o << "  (void)th;\n}\n\n";
+  o << RF_DEV_SRC_HBODY << "\n";
   return o.str();
 }
 

@@ -11,8 +11,10 @@
 //     bracketing); a trial point outside the declared bounds, with NLL = +inf
 //     (events with p <= 0) or a clear rise of NLL counts as an overshoot;
 //   - convergence: EDM = g^T H^-1 g / 2 < edm_tol;
-//   - uncertainties: H from central differences of the analytic gradient at
-//     the minimum, sigma_k = sqrt((H^-1)_kk).
+//   - uncertainties: sigma_k = sqrt((H^-1)_kk) with H the Hessian kernel's
+//     at the minimum (rf_nll_grad_hess), or, for programs with leaves that
+//     have no second derivatives, central differences of the analytic
+//     gradient.
 // Gauss-Legendre nodes for the quadrature leaves are computed here as well.
 #include <cmath>
 #include <algorithm>
@@ -243,10 +245,16 @@ extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, 
   conv = edm < edm_tol;
   for (int i = 0; i < P; ++i) theta_out[i] = x[i];
   if (sigma_out) {
-    // Hessian by central differences of the analytic gradient
+    // the Hessian kernel where every leaf has second derivatives, else
+    // central differences of the analytic gradient
     std::vector<double> Hf(P * P), gp(P), gm(P);
     bool good = true;
-    for (int k = 0; k < P && good; ++k) {
+    const bool exact = hess_supported(p->L, nullptr);
+    if (exact) {
+      double fh;
+      good = rf_nll_grad_hess(p, x.data(), &fh, gp.data(), Hf.data(), nullptr, stream) == RF_OK;
+    }
+    for (int k = 0; k < P && good && !exact; ++k) {
       // a tenth of the estimated sigma: large enough that FP32 gradient noise is
       // negligible, small enough for the quadratic region
       double h = 0.1 * std::sqrt(std::fabs(H[k * P + k]));

@@ -75,6 +75,11 @@ std::string generate_source(const Lowered& L, int block_size, int ept, int pfd, 
                             bool unfused = false);
 // unfused mode: slot of each PDF node's value array (-1: not a reachable PDF node)
 std::vector<int> unfused_slots(const Lowered& L);
+// the Hessian kernel (rf_k_hess) of a program: whether every leaf has second
+// derivatives (else why not), its number of event sums, its source
+bool hess_supported(const Lowered& L, std::string* why);
+int hess_nsums(const Lowered& L);
+std::string generate_hess_source(const Lowered& L, int block_size);
 
 // code-object cache + compiler driver
 struct Module {
@@ -158,4 +163,16 @@ struct rf_program {
     int part_n = 0;
     double* out = nullptr;  // [NLL, bad events]
   } unf;
+  // Hessian kernel (rf_nll_grad_hess): built and allocated on first use
+  struct Hess {
+    hipModule_t mod = nullptr;
+    hipFunction_t k = nullptr;
+    double* part = nullptr;    // [sums + 1][part_n]
+    int part_n = 0;
+    unsigned* ticket = nullptr;
+    double* out = nullptr;     // [nll, grad[P], n_bad, hess[P * P]]
+    double* h_out = nullptr;   // mapped host copy, then the completion word
+    double* d_hout = nullptr;
+    uint64_t seq = 0;
+  } hes;
 };

@@ -165,5 +165,17 @@ def spec_decay_leaf():
     ]
 
 
+def spec_gauss_sum(k=5, lo=-10.0, hi=10.0):
+    """A sum of k Gaussians with their own means and widths and k - 1
+    fractions; theta = (mu_1, s_1, ..., mu_k, s_k, f_1, ..., f_{k-1})."""
+    spec = [("obs", "x", [], [lo, hi])]
+    for j in range(k):
+        spec += [("param", "mu%d" % j, [], [-8.0, 8.0]), ("param", "s%d" % j, [], [0.05, 5.0])]
+    spec += [("param", "f%d" % j, [], [0.0, 1.0]) for j in range(k - 1)]
+    spec += [("gauss", "g%d" % j, ["x", "mu%d" % j, "s%d" % j], []) for j in range(k)]
+    spec.append(("add", "model", ["g%d" % j for j in range(k)] + ["f%d" % j for j in range(k - 1)], []))
+    return spec
+
+
 def truth_vector(truth):
     return [float(v) for v in truth.values()]

@@ -54,3 +54,27 @@ def oracle_nll_threads(spec, theta, cols, weights=None, mlp_weights=None, thread
     grad = np.array([math.fsum(p[1][k] for p in parts) for k in range(P)])
     gabs = np.array([math.fsum(p[2][k] for p in parts) for k in range(P)])
     return nll, grad, gabs, sum(p[3] for p in parts)
+
+
+def oracle_hess_threads(spec, theta, cols, weights=None, threads=16):
+    """The oracle's (nll, grad, hess, n_bad) over all events in contiguous
+    chunks on host threads, each entry added exactly rounded (math.fsum)."""
+    import math
+    from concurrent.futures import ThreadPoolExecutor
+
+    n = len(cols[0])
+    edges = np.linspace(0, n, threads + 1).astype(np.int64)
+
+    def one(k):
+        a, b = int(edges[k]), int(edges[k + 1])
+        om, otop, _ = rfo.from_spec(spec)
+        w = None if weights is None else np.ascontiguousarray(weights[a:b])
+        return om.nll_hess(otop, theta, [np.ascontiguousarray(c[a:b]) for c in cols], weights=w)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(one, range(threads)))
+    P = len(parts[0][1])
+    nll = math.fsum(p[0] for p in parts)
+    grad = np.array([math.fsum(p[1][k] for p in parts) for k in range(P)])
+    hess = np.array([[math.fsum(p[2][i, j] for p in parts) for j in range(P)] for i in range(P)])
+    return nll, grad, hess, sum(p[3] for p in parts)
