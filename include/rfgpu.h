@@ -202,6 +202,22 @@ int rf_unfused_build(const rf_program* p);
 int rf_nll_grad_async(rf_program* p, const double* theta, void* stream);
 const double* rf_program_result(const rf_program* p);
 
+/* For callers that cannot allocate device memory (code under stream capture
+ * into a HIP graph, tight serving loops, harnesses that forbid allocation):
+ * the NLL+gradient evaluation of rf_nll_grad_async without the program's
+ * workspace.  The kernel's cross-workgroup scratch (ticket words and
+ * per-workgroup partial sums, (n_sums + 1) x workgroups doubles) lives in a
+ * fixed 256 KiB device array of the library, one per device, kept until the
+ * process ends; the result block [nll, grad[n_params], n_bad, sums[n_sums]]
+ * (n_params + 2 + n_sums doubles, see rf_program_info) is written to the
+ * caller's device buffer dev_result.  Asynchronous on the stream; calls no
+ * allocating routine.  The program must be bound (rf_bind_columns, and
+ * rf_bind_weights for MLP leaves).  RF_E_INVALID if the partials do not fit
+ * the array (lower the workgroup count with rf_set_launch).  Every call on a
+ * device shares its array: calls that overlap on one device race, so
+ * serialise them (one stream, or events). */
+int rf_nll_grad_noalloc(rf_program* p, const double* theta, double* dev_result, void* stream);
+
 /* The NLL, its gradient and its Hessian hess[n_params * n_params] (row-major)
  * at theta in one fused pass: the curvature from which a fit's uncertainties
  * come (the paper's fits, Section 3 and Fig. 5; its parameter-only caching,

@@ -74,6 +74,7 @@ _OPTIONAL = {
     "rf_nll_unfused": ([_P, _P, _P, _P, _P], _I32),
     "rf_unfused_build": ([_P], _I32),
     "rf_bwcb_logpdf": ([_P, _I64, _I32, _D, _D, _D, _D, _P, _P], _I32),
+    "rf_nll_grad_noalloc": ([_P, _DP, _P, _P], _I32),
     "rf_nll_grad_hess": ([_P, _DP, _DP, _DP, _DP, _PI64, _P], _I32),
     "rf_hess_build": ([_P], _I32),
 }
@@ -330,6 +331,14 @@ class Program:
     def build_hess(self):
         """Build the Hessian kernel's code object (no GPU needed)."""
         check(rf_hess_build(self.h))
+
+    def nll_grad_noalloc(self, theta, out, stream=None):
+        """Enqueue one NLL+gradient evaluation that allocates nothing: the
+        result block [nll, grad, n_bad, sums] goes to out (float64 device
+        tensor of n_params + 2 + n_sums values); asynchronous."""
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < self.n_params + 2 + self.n_sums:
+            raise RfError(-1, "out must be a float64 device tensor of n_params + 2 + n_sums values")
+        check(rf_nll_grad_noalloc(self.h, self._theta_ptr(theta), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
 
     def stats(self):
         """(synchronous calls, calls whose wait fell back to a stream sync)"""

@@ -408,7 +408,25 @@ int rf_nll_grad_async(rf_program* p, const double* theta, void* stream) {
   return launch(p, p->m.k_grad, a, stream);
 }
 
+}  // extern "C"
 
+namespace rf {
+int enqueue_grad_on(rf_program* p, const double* theta, double* part, int32_t part_stride, unsigned* ticket,
+                    double* out, void* stream) {
+  int rc = ready(p, theta);
+  if (rc) return rc;
+  if (part_stride < p->nblk) return fail(RF_E_INVALID, "partial stride below the workgroup count");
+  RfArgs a;
+  fill_args(p, theta, a);
+  a.part = part;
+  a.nblk_max = part_stride;
+  a.ticket = ticket;
+  a.out = out;
+  return launch(p, p->m.k_grad, a, stream);
+}
+}  // namespace rf
+
+extern "C" {
 
 const double* rf_program_result(const rf_program* p) { return p ? p->d_out : nullptr; }
 

@@ -9,6 +9,8 @@
 #include "../../include/rfgpu.h"
 #include "device/rf_kabi.h"
 
+struct rf_program;
+
 namespace rf {
 
 // node kinds beyond the public ops
@@ -113,6 +115,13 @@ inline int mlp_renorm_blocks(int K) { return (K + 255) / 256; }
 // weights); synchronises the stream
 int validate_columns(const void* const* cols, int n_cols, int n_range, const double* lo, const double* hi,
                      unsigned int_mask, int64_t n, bool f32, void* stream, int64_t* n_bad);
+
+// one NLL+gradient evaluation of a bound program (as rf_nll_grad_async) with
+// the cross-workgroup partials (part_stride >= the workgroup count per sum),
+// the ticket words (RF_TICKET_WORDS, zero) and the result block supplied by
+// the caller instead of the program's workspace; allocates nothing
+int enqueue_grad_on(rf_program* p, const double* theta, double* part, int32_t part_stride, unsigned* ticket,
+                    double* out, void* stream);
 
 // Gauss-Legendre rule (host)
 void gauss_legendre(int K, double lo, double hi, double* x, double* w);
