@@ -274,9 +274,10 @@ int rf_mlp_forward(const void* dev_w_bf16, const float* dev_in, int64_t n, float
                    float* dev_act, void* stream);
 /* dout[n] cotangents -> dw[8833] FP32 (overwritten with the sum over rows),
  * din (n x 6, may be NULL) input gradients.  The per-workgroup partial
- * gradients live in one library-owned workspace (grown on demand, kept until
- * the process ends) shared by rf_mlp_backward and rf_mlp_train_step: calls
- * that overlap on different streams race on it. */
+ * gradients live in a library-owned workspace per (device, stream), grown on
+ * demand and kept until the process ends, which rf_mlp_backward and
+ * rf_mlp_train_step calls on that stream share in stream order; calls on
+ * different streams use different workspaces. */
 int rf_mlp_backward(const void* dev_w_bf16, const float* dev_in, const float* dev_act,
                     const float* dev_dout, int64_t n, float* dev_dw, float* dev_din,
                     void* stream);
@@ -292,15 +293,19 @@ int rf_mse_grad(const float* dev_out, const float* dev_target, int64_t n, float 
 /* One optimiser step of the surrogate's training, as rf_mlp_forward +
  * rf_mse_grad (scale 2/batch) + rf_mlp_backward + rf_adam_step on a batch of
  * rows, in two kernel launches.  Batch row r is row dev_idx[r] of dev_in
- * (n x 6) and dev_target (dev_idx NULL: rows 0..batch-1); the indices must lie
- * in the arrays (not checked).  The loss is the mean of (s - target)^2 over
- * the batch.  dev_w_bf16 (read by the step, then refreshed), dev_w32, dev_m,
- * dev_v are updated in place; dev_dw (8833 FP32, may be NULL) receives the
- * summed gradient.  Asynchronous on the stream; shares rf_mlp_backward's
- * workspace. */
+ * (n_rows x 6) and dev_target (n_rows; dev_idx NULL: rows 0..batch-1, and
+ * n_rows >= batch).  An index outside [0, n_rows) is the caller's error: the
+ * kernel clamps it into the arrays (no read leaves them); with
+ * flags & RF_VALIDATE the indices are first checked on the host (the stream is
+ * synchronised) and RF_E_INVALID returned if any is out of range.  The loss is
+ * the mean of (s - target)^2 over the batch.  dev_w_bf16 (read by the step,
+ * then refreshed), dev_w32, dev_m, dev_v are updated in place; dev_dw (8833
+ * FP32, may be NULL) receives the summed gradient.  Asynchronous on the
+ * stream; uses rf_mlp_backward's workspace of that stream. */
 int rf_mlp_train_step(void* dev_w_bf16, float* dev_w32, float* dev_m, float* dev_v, const float* dev_in,
-                      const float* dev_target, const int64_t* dev_idx, int64_t batch, float lr,
-                      float beta1, float beta2, float eps, int32_t step, float* dev_dw, void* stream);
+                      const float* dev_target, const int64_t* dev_idx, int64_t batch, int64_t n_rows,
+                      uint32_t flags, float lr, float beta1, float beta2, float eps, int32_t step, float* dev_dw,
+                      void* stream);
 /* Exact log p_sig of the Breit-Wigner (x) Crystal Ball signal at per-sample
  * parameters: dev_xq[n][6] = (x, M, Gamma, sigma, alpha, n) FP64; the same
  * K-point Gauss-Legendre rule on [ylo, yhi] and normalisation over [lo, hi]

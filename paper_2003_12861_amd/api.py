@@ -70,7 +70,7 @@ _OPTIONAL = {
     "rf_mlp_backward": ([_P, _P, _P, _P, _I64, _P, _P, _P], _I32),
     "rf_adam_step": ([_P, _P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P], _I32),
     "rf_mse_grad": ([_P, _P, _I64, _F, _P, _P], _I32),
-    "rf_mlp_train_step": ([_P, _P, _P, _P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P, _P], _I32),
+    "rf_mlp_train_step": ([_P, _P, _P, _P, _P, _P, _P, _I64, _I64, _U32, _F, _F, _F, _F, _I32, _P, _P], _I32),
     "rf_nll_unfused": ([_P, _P, _P, _P, _P], _I32),
     "rf_unfused_build": ([_P], _I32),
     "rf_bwcb_logpdf": ([_P, _I64, _I32, _D, _D, _D, _D, _P, _P], _I32),
@@ -458,12 +458,14 @@ def mse_grad(out, target, scale, dout, stream=None):
 
 
 def mlp_train_step(w_bf16, w32, m, v, u, target, idx, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, dw=None,
-                   stream=None):
+                   stream=None, validate=False):
     """One Adam step on the mean-squared error of MLP(u[idx]) against target[idx]
-    (idx: int64 indices of the batch rows, or None for all rows of u)."""
+    (idx: int64 indices of the batch rows, or None for all rows of u);
+    validate: check on the host that every index names a row of u."""
     batch = idx.numel() if idx is not None else u.shape[0]
-    check(rf_mlp_train_step(_vp(w_bf16), _vp(w32), _vp(m), _vp(v), _vp(u), _vp(target), _vp(idx), batch, lr, beta1,
-                            beta2, eps, step, _vp(dw), _stream(stream)))
+    n_rows = min(u.shape[0], target.shape[0])
+    check(rf_mlp_train_step(_vp(w_bf16), _vp(w32), _vp(m), _vp(v), _vp(u), _vp(target), _vp(idx), batch, n_rows,
+                            RF_VALIDATE if validate else 0, lr, beta1, beta2, eps, step, _vp(dw), _stream(stream)))
 
 
 def bwcb_logpdf(xq, K, window, x_range, out=None, stream=None):

@@ -188,12 +188,14 @@ RF_DEV void mlp_dw_mfma(const float* D, const float* H, int mo0, rf_f32x16 (&acc
 
 // Cotangent source of the backward kernel: given per row (dout), or the
 // mean-squared-error gradient scale (s - target[src]) of the forward output s
-// (target != nullptr); rows are in[src], src = idx ? idx[row] : row.
+// (target != nullptr); rows are in[src], src = idx ? idx[row] : row, an index
+// clamped into [0, nsrc) (rows of in and target) so that no read leaves them.
 struct BwdRows {
   const float* dout;
   const int64_t* idx;
   const float* target;
   float scale;
+  int64_t nsrc;
 };
 
 // A workgroup of two wavefronts takes a 64-row tile: wavefront wv runs the
@@ -217,7 +219,8 @@ __global__ __launch_bounds__(64 * BWD_W) void mlp_bwd_kernel(const unsigned shor
     MLP_TILE_BARRIER();
     const int64_t row = t * 64 + er;
     const bool valid = row < n;
-    const int64_t src = !valid ? 0 : (FUSED && r.idx) ? r.idx[row] : row;
+    int64_t src = !valid ? 0 : (FUSED && r.idx) ? r.idx[row] : row;
+    src = src < 0 ? 0 : (src >= r.nsrc ? r.nsrc - 1 : src);
     float u[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) u[j] = valid ? in[src * 6 + j] : 0.0f;
@@ -432,8 +435,16 @@ int launch_err(const char* what) {
 }
 
 std::mutex g_ws_mu;
-float* g_part = nullptr;
-size_t g_part_n = 0;
+// per-workgroup partial weight gradients of the backward kernel: one buffer
+// per (device, stream), so that calls on different streams never share one
+// (calls on one stream are ordered by the stream)
+struct PartWs {
+  int dev;
+  void* stream;
+  float* p;
+  size_t n;
+};
+std::vector<PartWs> g_parts;
 double* g_gl = nullptr;
 int g_gl_K = 0;
 double g_gl_lo = 0, g_gl_hi = 0;
@@ -480,15 +491,26 @@ int backward_launch(const void* w, const float* in, const BwdRows& r, int64_t n,
                     const AdamArgs* ad, void* stream) {
   const int64_t ntile = (n + 63) / 64;
   int nblk = (int)(ntile < 512 ? ntile : 512);
+  int dev = 0;
+  hipError_t de = hipGetDevice(&dev);
+  if (de != hipSuccess) return hip_fail(de, "hipGetDevice");
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  if (g_part_n < (size_t)nblk * MLP_NW) {
-    if (g_part) (void)hipFree(g_part);
-    g_part = nullptr;
-    g_part_n = 0;
-    hipError_t e = hipMalloc(&g_part, sizeof(float) * (size_t)nblk * MLP_NW);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc mlp partials");
-    g_part_n = (size_t)nblk * MLP_NW;
+  PartWs* ws = nullptr;
+  for (PartWs& q : g_parts)
+    if (q.dev == dev && q.stream == stream) ws = &q;
+  if (!ws) {
+    g_parts.push_back(PartWs{dev, stream, nullptr, 0});
+    ws = &g_parts.back();
   }
+  if (ws->n < (size_t)nblk * MLP_NW) {
+    if (ws->p) (void)hipFree(ws->p);
+    ws->p = nullptr;
+    ws->n = 0;
+    hipError_t e = hipMalloc(&ws->p, sizeof(float) * (size_t)nblk * MLP_NW);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc mlp partials");
+    ws->n = (size_t)nblk * MLP_NW;
+  }
+  float* const g_part = ws->p;
   if (ntile == 0) {
     nblk = 0;  // no partials: the reduction writes zeros
   } else {
@@ -537,16 +559,28 @@ int rf_mlp_backward(const void* w, const float* in, const float* act, const floa
                     float* din, void* stream) {
   (void)act;  // activations are recomputed from the inputs (cheaper than reading them back)
   if (!w || !dw || n < 0 || (n > 0 && (!in || !dout))) return fail(RF_E_INVALID, "bad arguments");
-  BwdRows r{dout, nullptr, nullptr, 0.0f};
+  BwdRows r{dout, nullptr, nullptr, 0.0f, n};
   return backward_launch(w, in, r, n, dw, din, nullptr, stream);
 }
 
 int rf_mlp_train_step(void* w, float* w32, float* m, float* v, const float* in, const float* target,
-                      const int64_t* idx, int64_t batch, float lr, float beta1, float beta2, float eps, int32_t step,
-                      float* dw, void* stream) {
+                      const int64_t* idx, int64_t batch, int64_t n_rows, uint32_t flags, float lr, float beta1,
+                      float beta2, float eps, int32_t step, float* dw, void* stream) {
   if (!w || !w32 || !m || !v || !in || !target || batch < 1 || step < 1)
     return fail(RF_E_INVALID, "bad arguments");
-  BwdRows r{nullptr, idx, target, 2.0f / (float)batch};
+  if (idx ? n_rows < 1 : n_rows < batch) return fail(RF_E_INVALID, "n_rows: fewer rows than the batch reads");
+  if (idx && (flags & RF_VALIDATE)) {
+    // the indices on the host: every one must name a row of the arrays
+    std::vector<int64_t> h((size_t)batch);
+    hipError_t e = hipMemcpyAsync(h.data(), idx, sizeof(int64_t) * (size_t)batch, hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the batch indices");
+    int64_t bad = 0;
+    for (int64_t i : h) bad += (i < 0 || i >= n_rows) ? 1 : 0;
+    if (bad) return fail(RF_E_INVALID, std::to_string(bad) + " batch indices outside [0, n_rows)");
+  }
+  BwdRows r{nullptr, idx, target, 2.0f / (float)batch, idx ? n_rows : batch};
   const AdamArgs ad = adam_args(w32, w, m, v, lr, beta1, beta2, eps, step);
   return backward_launch(w, in, r, batch, dw, nullptr, &ad, stream);
 }
