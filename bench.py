@@ -164,6 +164,7 @@ def timed_steps(call, thetas, steps, torch):
         step_s = (time.perf_counter() - t0) / steps
     finally:
         gc.enable()
+    timed_steps.last = per
     return step_s, float(np.median(per))
 
 
@@ -205,9 +206,11 @@ def time_path(call, call_async, thetas, args, torch, stream):
     for i in range(args.warmup):
         call(thetas[i % len(thetas)])
     step_s, med_s = timed_steps(call, thetas, args.steps, torch)
+    per = timed_steps.last
     kern_s = pipelined_kernel(call_async, thetas, max(20, min(args.steps, 200)), torch, stream)
     iso_s = isolated_kernel(call_async, thetas, 20, torch, stream)
-    return dict(step_s=step_s, median_step_s=med_s, kernel_s=kern_s, isolated_s=iso_s)
+    return dict(step_s=step_s, median_step_s=med_s, kernel_s=kern_s, isolated_s=iso_s,
+                step_us_min_max=[float(per.min()) * 1e6, float(per.max()) * 1e6])
 
 
 def oracle_rate(fn, n_per_call, budget_s):
@@ -266,6 +269,22 @@ def run_binned(args, torch, stream):
     print(json.dumps(line))
 
 
+def run_peaks(api):
+    """The ceilings, measured: median of three runs of each microbenchmark."""
+    iters = {0: 20000, 1: 20000, 2: 5000, 3: 1500, 4: 1500, 5: 1000, 6: 1000, 7: 2000, 8: 1, 9: 1000}
+    out = {}
+    for kind, name in api.PEAK_KINDS.items():
+        rates = [api.peak(kind, iters[kind], 1 << 31 if kind == 8 else 0)[0] for _ in range(3)]
+        out[name] = float(np.median(rates))
+    derived = {"valu_lane_slots_per_s": VALU_SLOTS_PER_S, "hbm_bytes_per_s": HBM_PEAK_GBS * 1e9}
+    print(json.dumps({"metric": "measured ceilings", "unit": "per second", "measured": out, "derived": derived,
+                      "ratios": {"fp32_fma/derived": out["fp32_fma"] / VALU_SLOTS_PER_S,
+                                 "fp64_fma/derived": out["fp64_fma"] / VALU_SLOTS_PER_S,
+                                 "mix_1d/derived": out["fp32_mix_14fma_1trans"] / VALU_SLOTS_PER_S,
+                                 "mix_conv/derived": out["fp32_mix_12fma_1rcp"] / VALU_SLOTS_PER_S,
+                                 "stream/8TB": out["stream_read_bytes"] / (HBM_PEAK_GBS * 1e9)}}))
+
+
 def run_unfused_ablation(args, progs, cols, thetas, n, torch, stream):
     """Synchronous NLL-only steps: the fused kernel against the unfused
     per-node batch mode, same program, same events, same parameter points."""
@@ -316,6 +335,9 @@ def main():
                     help="fused vs unfused per-node NLL (gauss_cheb_1e7, decay_argus_5e7)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (scale reference for HBM counters)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="instead, measure the ceilings (issue rates of the kernels' instruction mixes, streaming "
+                         "bandwidth) and print them as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -326,6 +348,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.peaks:
+        run_peaks(api)
+        return
     if args.workload.startswith("binned"):
         run_binned(args, torch, stream)
         return
@@ -426,6 +451,7 @@ def main():
                    "step": "one synchronous NLL+gradient evaluation (result in host memory)"},
         "fp32": {"kernel_ms": k32 * 1e3, "isolated_kernel_ms": res["fp32"]["isolated_s"] * 1e3,
                  "median_step_ms": res["fp32"]["median_step_s"] * 1e3,
+                 "step_us_min_max": res["fp32"]["step_us_min_max"],
                  "kernel_events_per_s": n / k32,
                  "nll_rel_err": res["fp32"].get("nll_rel_err"),
                  "grad_scaled_err": res["fp32"].get("grad_scaled_err"),

@@ -127,6 +127,10 @@ const char* rf_last_error(void);
 const char* rf_version(void);
 
 /* ---- graph construction (host only) -------------------------------------- */
+/* A model is a graph of observables, parameters, functions and PDFs linked
+ * into a computation graph whose every node evaluates to a real number
+ * (Section 1, Fig. 1).  The graph is owned by the caller until
+ * rf_graph_free; rf_compile copies what it needs. */
 int rf_graph_new(rf_graph** out);
 void rf_graph_free(rf_graph* g);
 /* column index = declaration order of observables; [lo, hi] is the range
@@ -136,12 +140,19 @@ int rf_graph_observable(rf_graph* g, const char* name, double lo, double hi, int
  * checked on every evaluation (lo <= theta <= hi). */
 int rf_graph_parameter(rf_graph* g, const char* name, double lo, double hi, int32_t* id);
 int rf_graph_constant(rf_graph* g, double value, int32_t* id);
-/* inputs must be ids of earlier nodes (so the graph is acyclic by construction) */
+/* A function or PDF node (the PDFs of Section 4.1: Gaussian, Poisson,
+ * exponential, sums of PDFs; the others are the benchmark models'); inputs
+ * must be ids of earlier nodes (so the graph is acyclic by construction);
+ * RF_E_INVALID for an unknown op, a wrong arity or attribute count. */
 int rf_graph_node(rf_graph* g, int32_t op, const int32_t* inputs, int32_t n_inputs,
                   const double* attrs, int32_t n_attrs, int32_t* id);
 
 /* ---- compilation --------------------------------------------------------- */
-/* Validates the subgraph under top, lowers it to a flat node program,
+/* The paper's two ideas for the hot path, on the GPU: parameter-only
+ * branches (normalisation integrals) computed once per parameter point
+ * (Section 4), and every event of the model evaluated in one batch call
+ * (Section 4.1), here fused across nodes.
+ * Validates the subgraph under top, lowers it to a flat node program,
  * generates one fused HIP kernel source for it (three entry points: values,
  * NLL, NLL+gradient) specialised to the precision form, builds a gfx950 code
  * object (content-addressed cache; built with the ROCm compiler on a miss) and
@@ -161,8 +172,12 @@ const char* rf_program_source(const rf_program* p);
 int rf_program_stats(const rf_program* p, int64_t* sync_calls, int64_t* slow_waits);
 
 /* ---- binding ------------------------------------------------------------- */
-/* dev_cols[j]: contiguous column of observable j (n_events values), float64
- * for RF_FP64 programs, float32 for RF_FP32_COMP; for a RF_COMPILE_WEIGHTED
+/* The data as one contiguous array per observable (the structure-of-arrays
+ * layout the batch interface reads, Section 4.1).
+ * dev_cols[j]: contiguous column of observable j (n_events values, unit
+ * stride), float64 for RF_FP64 programs, float32 for RF_FP32_COMP (a strided
+ * or other-dtype column is made contiguous in the program dtype by the
+ * caller: the kernels read 16-byte vectors of consecutive events); for a RF_COMPILE_WEIGHTED
  * program dev_cols[n_observables] holds the event weights.  Allocates the
  * program's workspace (block partials, result block) on the current device;
  * with RF_VALIDATE, also checks the columns (synchronising the stream). */
@@ -175,7 +190,12 @@ int rf_bind_weights(rf_program* p, int32_t node, const void* dev_bf16, void* str
 int rf_set_launch(rf_program* p, int32_t blocks, int32_t threads);
 
 /* ---- evaluation ---------------------------------------------------------- */
-/* per-event normalised p_i into dev_out (n_events, bound dtype); async */
+/* The probabilities of all events in a single call (Section 4.1); the NLL is
+ * -sum_i log p_i over them (Section 4: the likelihood needs the probability of
+ * every event).  RF_E_DOMAIN for theta outside its bounds or invalid for a
+ * leaf, RF_E_STATE before binding, RF_E_NONFINITE (nll = +inf, grad NaN,
+ * n_bad set) when some p_i <= 0 or is not finite.
+ * per-event normalised p_i into dev_out (n_events, bound dtype); async */
 int rf_eval_values(rf_program* p, const double* theta, void* dev_out, void* stream);
 /* NLL only; synchronous.  n_bad may be NULL. */
 int rf_nll(rf_program* p, const double* theta, double* nll, int64_t* n_bad, void* stream);
@@ -238,7 +258,9 @@ int rf_nll_grad_hess(rf_program* p, const double* theta, double* nll, double* gr
 int rf_hess_build(const rf_program* p);
 
 /* ---- fit ------------------------------------------------------------------ */
-/* Quasi-Newton (BFGS) minimisation of NLL with backtracking line search that
+/* The fits whose run time the paper's batch computation speeds up (Section 3
+ * and Fig. 5).
+ * Quasi-Newton (BFGS) minimisation of NLL with backtracking line search that
  * backs off infinite NLL and out-of-bounds points; converged when
  * EDM = g^T H^-1 g / 2 < edm_tol.  sigma_out: sqrt(diag(H^-1)) with H the
  * Hessian of rf_nll_grad_hess at the minimum, or central differences of the
@@ -266,6 +288,9 @@ int rf_binned_nll_grad_async(rf_binned* b, const double* theta, void* stream);
 const double* rf_binned_result(const rf_binned* b);
 
 /* ---- MLP kernels used to train the surrogate ------------------------------- */
+/* Not in the paper: the learned surrogate of the numerically convolved signal
+ * of the benchmark workload (its expensive PDF), trained by these kernels on
+ * the exact convolution's own values. */
 /* 6-64-64-64-1 tanh network, BF16 weights (layout as rf_bind_weights), FP32
  * inputs in [-1,1] (n x 6 row-major), FP32 accumulation.
  * rf_mlp_forward: out[n]; act (n x 192 FP32, may be NULL) keeps the hidden
@@ -313,7 +338,33 @@ int rf_mlp_train_step(void* dev_w_bf16, float* dev_w32, float* dev_m, float* dev
 int rf_bwcb_logpdf(const double* dev_xq, int64_t n, int32_t K, double ylo, double yhi, double lo, double hi,
                    double* dev_out, void* stream);
 
+/* The surrogate's training targets: log p_sig - log b at the rows of dev_xq
+ * (as rf_bwcb_logpdf), b the surrogate leaf's analytic base evaluated exactly
+ * as the leaf evaluates it (RF_OP_MLP: its FP64 parameter-only constants and
+ * its FP32 value), so the network learns the residual the leaf adds to it;
+ * dev_out[n] FP32. */
+int rf_mlp_targets(const double* dev_xq, int64_t n, int32_t K, double ylo, double yhi, double lo, double hi,
+                   float* dev_out, void* stream);
+
+/* ---- measurement ------------------------------------------------------------ */
+/* Microbenchmark of the ceilings the likelihood kernels are measured against,
+ * on the current device: kind 0 FP32 FMA, 1 FP64 FMA, 2 FP32 exp2 (lane
+ * operations/s); 3 the 1-D kernel's mix of 14 FP32 FMA per transcendental,
+ * 4 the convolution's 12 FMA per reciprocal (lane-slots/s, a transcendental
+ * counting 4); 5 FP64 exp, 6 FP64 log, 7 FP64 reciprocal with one Newton step
+ * (lane calls/s); 8 streaming read of stream_bytes (0: 1 GiB) with 16-byte
+ * loads (bytes/s); 9 the FP64 logarithm of the event loop (lane calls/s).
+ * iters: loop iterations per lane (ignored for kind 8).
+ * Synchronous; allocates and frees its own buffers. */
+int rf_peak(int32_t kind, int32_t iters, int64_t stream_bytes, double* rate, double* seconds);
+/* The library's own device math functions applied element by element to
+ * dev_in[n] (FP64) into dev_out[n], for comparison with a host library:
+ * fn 0 = the natural logarithm of the FP64 event loop (positive, finite,
+ * normal arguments).  Asynchronous on the stream. */
+int rf_eval_math(int32_t fn, const double* dev_in, int64_t n, double* dev_out, void* stream);
+
 /* ---- host utility ---------------------------------------------------------- */
+/* (the fixed rule of the numerically convolved signal) */
 /* K-point Gauss-Legendre nodes and weights on [lo, hi] (ascending) */
 int rf_gauss_legendre(int32_t K, double lo, double hi, double* x, double* w);
 

@@ -74,6 +74,9 @@ _OPTIONAL = {
     "rf_nll_unfused": ([_P, _P, _P, _P, _P], _I32),
     "rf_unfused_build": ([_P], _I32),
     "rf_bwcb_logpdf": ([_P, _I64, _I32, _D, _D, _D, _D, _P, _P], _I32),
+    "rf_mlp_targets": ([_P, _I64, _I32, _D, _D, _D, _D, _P, _P], _I32),
+    "rf_peak": ([_I32, _I32, _I64, _DP, _DP], _I32),
+    "rf_eval_math": ([_I32, _P, _I64, _P, _P], _I32),
     "rf_nll_grad_noalloc": ([_P, _DP, _P, _P], _I32),
     "rf_nll_grad_hess": ([_P, _DP, _DP, _DP, _DP, _PI64, _P], _I32),
     "rf_hess_build": ([_P], _I32),
@@ -474,4 +477,33 @@ def bwcb_logpdf(xq, K, window, x_range, out=None, stream=None):
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=xq.device)
     check(rf_bwcb_logpdf(_vp(xq), n, K, window[0], window[1], x_range[0], x_range[1], _vp(out), _stream(stream)))
+    return out
+
+
+def mlp_targets(xq, K, window, x_range, out=None, stream=None):
+    """Training targets log p_sig - log b (FP32) at rows (x, M, Gamma, sigma, alpha, n) of xq (FP64)."""
+    n = xq.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xq.device)
+    check(rf_mlp_targets(_vp(xq), n, K, window[0], window[1], x_range[0], x_range[1], _vp(out), _stream(stream)))
+    return out
+
+
+PEAK_KINDS = {0: "fp32_fma", 1: "fp64_fma", 2: "fp32_exp2", 3: "fp32_mix_14fma_1trans", 4: "fp32_mix_12fma_1rcp",
+              5: "fp64_exp_call", 6: "fp64_log_call", 7: "fp64_rcp_newton", 8: "stream_read_bytes",
+              9: "fp64_log_own_call"}
+
+
+def peak(kind, iters, stream_bytes=0):
+    """(rate, seconds) of microbenchmark kind (see PEAK_KINDS) on the current device."""
+    r, t = ctypes.c_double(), ctypes.c_double()
+    check(rf_peak(kind, iters, stream_bytes, ctypes.byref(r), ctypes.byref(t)))
+    return r.value, t.value
+
+
+def eval_math(fn, x, out=None, stream=None):
+    """The library's device math function fn (0: FP64 log) on a float64 device tensor."""
+    if out is None:
+        out = torch.empty_like(x)
+    check(rf_eval_math(fn, _vp(x), x.numel(), _vp(out), _stream(stream)))
     return out

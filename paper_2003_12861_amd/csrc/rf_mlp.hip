@@ -409,8 +409,12 @@ __global__ void mse_grad_kernel(const float* out, const float* y, int64_t n, flo
 
 // exact log p_sig(x; M, Gamma, sigma, alpha, n) per sample (FP64): the same
 // rule as the convolution leaf, with per-sample parameters
+// RESID = false: out (double) = log p_sig; true: out (float) = log p_sig -
+// log b, b the surrogate leaf's analytic base exactly as the leaf evaluates it
+// (its FP64 constants, its FP32 value), the residual the network learns
+template <bool RESID>
 __global__ void bwcb_logpdf_kernel(const double* xq, int64_t n, const double* gl, int K, double lo, double hi,
-                                   double* out) {
+                                   void* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double x = xq[i * 6], M = xq[i * 6 + 1], G = xq[i * 6 + 2];
@@ -426,7 +430,16 @@ __global__ void bwcb_logpdf_kernel(const double* xq, int64_t n, const double* gl
     bw_norm(lo - y, hi - y, M, G, &I, &dIM, &dIG);
     N += c * I;
   }
-  out[i] = log(S / N);
+  const double lp = log(S / N);
+  if (RESID) {
+    double C[MB_END];
+    const double q[5] = {M, G, sg, al, nn};
+    mlp_base_constants(q, C);
+    const MlpBase B = MlpBase::make(C);
+    ((float*)out)[i] = (float)(lp - (double)logf(mlp_base<false>((float)x, B, nullptr)));
+  } else {
+    ((double*)out)[i] = lp;
+  }
 }
 
 int launch_err(const char* what) {
@@ -602,8 +615,8 @@ int rf_mse_grad(const float* out, const float* target, int64_t n, float scale, f
   return launch_err("mse_grad");
 }
 
-int rf_bwcb_logpdf(const double* xq, int64_t n, int32_t K, double ylo, double yhi, double lo, double hi, double* out,
-                   void* stream) {
+static int bwcb_launch(const double* xq, int64_t n, int32_t K, double ylo, double yhi, double lo, double hi, void* out,
+                       bool resid, void* stream) {
   if (n < 0 || K < 2 || K > 4096 || !(ylo < yhi) || !(lo < hi) || (n > 0 && (!xq || !out)))
     return fail(RF_E_INVALID, "bad arguments");
   std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -620,9 +633,23 @@ int rf_bwcb_logpdf(const double* xq, int64_t n, int32_t K, double ylo, double yh
     g_gl_hi = yhi;
   }
   if (n == 0) return RF_OK;
-  hipLaunchKernelGGL(bwcb_logpdf_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, (hipStream_t)stream, xq, n,
-                     g_gl, K, lo, hi, out);
+  if (resid)
+    hipLaunchKernelGGL(bwcb_logpdf_kernel<true>, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, (hipStream_t)stream,
+                       xq, n, g_gl, K, lo, hi, out);
+  else
+    hipLaunchKernelGGL(bwcb_logpdf_kernel<false>, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, (hipStream_t)stream,
+                       xq, n, g_gl, K, lo, hi, out);
   return launch_err("bwcb_logpdf");
+}
+
+int rf_bwcb_logpdf(const double* xq, int64_t n, int32_t K, double ylo, double yhi, double lo, double hi, double* out,
+                   void* stream) {
+  return bwcb_launch(xq, n, K, ylo, yhi, lo, hi, out, false, stream);
+}
+
+int rf_mlp_targets(const double* xq, int64_t n, int32_t K, double ylo, double yhi, double lo, double hi, float* out,
+                   void* stream) {
+  return bwcb_launch(xq, n, K, ylo, yhi, lo, hi, out, true, stream);
 }
 
 }  // extern "C"

@@ -4,11 +4,11 @@ train_surrogate() trains a 6-64-64-64-1 tanh network r(x, M, Gamma, sigma,
 alpha, n) ~ log p_sig - log b on exact evaluations of the Breit-Wigner (x)
 Crystal Ball convolution (the 1024-point rule of the exact leaf) at scrambled
 Sobol points of the input box; b is the leaf's analytic base (a pseudo-Voigt
-with the Crystal Ball tail, see base_log), so the network learns a residual
-about 20x smaller in spread than log p_sig.  Only the library's kernels are
-used:
-    rf_bwcb_logpdf  (targets)  ->  rf_mlp_forward  ->  rf_mse_grad
-    ->  rf_mlp_backward  ->  rf_adam_step
+with the Crystal Ball tail, evaluated on the GPU by the leaf's own code), so
+the network learns a residual about 20x smaller in spread than log p_sig.
+Only the library's kernels are used:
+    rf_mlp_targets (targets)  ->  rf_mlp_train_step (gather, forward, MSE
+    gradient, backward and Adam in two launches)
 torch only holds the device buffers (and draws the per-epoch permutation).
 The trained BF16 weights are served by the surrogate leaf (RF_OP_MLP) of a
 compiled likelihood graph, normalised on a Gauss-Legendre grid over x.
@@ -51,46 +51,18 @@ def normalise(raw, box=MLP_BOX):
     return 2.0 * (r - lo) / (hi - lo) - 1.0
 
 
-def base_log(raw):
-    """log of the surrogate leaf's analytic base b(x - M; Gamma, sigma, alpha, n)
-    at raw design points (x, M, Gamma, sigma, alpha, n): the pseudo-Voigt of
-    Thompson, Cox & Hastings (J. Appl. Cryst. 20 (1987) 79) -- Lorentzian and
-    Gaussian of common full width f, mixed with weight eta; f_G = 2 sigma
-    sqrt(2 ln 2), f_L = Gamma -- whose Gaussian part has the Crystal Ball tail
-    below z = -alpha (z in units of its width f / (2 sqrt(2 ln 2)))."""
-    x, M, G, sg, al, n = (np.asarray(raw, dtype=np.float64)[:, j] for j in range(6))
-    c0 = 2.0 * math.sqrt(2.0 * math.log(2.0))
-    fg, fl = c0 * sg, G
-    f = (fg**5 + 2.69269 * fg**4 * fl + 2.42843 * fg**3 * fl**2 + 4.47163 * fg**2 * fl**3
-         + 0.07842 * fg * fl**4 + fl**5) ** 0.2
-    r = fl / f
-    eta = 1.36603 * r - 0.47719 * r**2 + 0.11116 * r**3
-    d = x - M
-    h = 0.5 * f
-    L = (h / math.pi) / (d * d + h * h)
-    se = f / c0
-    z = d / se
-    tail = z <= -al
-    logA = n * np.log(n / al) - 0.5 * al * al
-    B = n / al - al
-    logC = np.where(tail, logA - n * np.log(np.where(tail, B - z, 1.0)), -0.5 * z * z)
-    Gn = np.exp(logC) / (se * math.sqrt(2.0 * math.pi))
-    return np.log(eta * L + (1.0 - eta) * Gn)
-
-
 def to_bf16(w32):
     return w32.to(torch.bfloat16)
 
 
 def make_training_set(n, seed=7, K=1024, device="cuda"):
     """Sobol parameters, importance-sampled x, and the residual targets
-    log p_sig (exact, FP64 on the GPU) - log b."""
+    log p_sig (exact, FP64) - log b (the leaf's base), both on the GPU."""
     raw = synth.surrogate_design(n, seed=seed)
     xq = torch.tensor(raw, dtype=torch.float64, device=device)
-    y = api.bwcb_logpdf(xq, K, synth.BWCB_WINDOW, synth.BWCB_RANGE)
-    y = y - torch.tensor(base_log(raw), dtype=torch.float64, device=device)
+    y = api.mlp_targets(xq, K, synth.BWCB_WINDOW, synth.BWCB_RANGE)
     u = torch.tensor(normalise(raw), dtype=torch.float32, device=device)
-    return u, y.to(torch.float32), raw
+    return u, y, raw
 
 
 def train_surrogate(n_train=2_000_000, epochs=60, batch=8192, lr=2e-3, lr_min=1e-5, seed=0, holdout=0.05,

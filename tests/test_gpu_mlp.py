@@ -200,6 +200,27 @@ def test_exact_targets_vs_oracle():
     np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-12)
 
 
+def test_training_targets_vs_oracle():
+    """rf_mlp_targets: log p_sig - log b on the GPU against the oracle's exact
+    signal and its surrogate leaf with a zero network (whose value times its
+    normalisation is the base b).  FP32 output and an FP32 base: the bar is a
+    few units of 2^-24 of the base's exponent arguments, 4e-6 absolute."""
+    raw = synth.surrogate_design(300, seed=13)
+    xq = torch.tensor(raw, dtype=torch.float64, device="cuda")
+    y = api.mlp_targets(xq, 1024, synth.BWCB_WINDOW, synth.BWCB_RANGE).double().cpu().numpy()
+    me, te, _ = rfo.from_spec(workloads.spec_bwcb())
+    mz, tz, iz = rfo.from_spec(workloads.spec_bwcb(surrogate=True))
+    mz.set_mlp_weights(iz["sig"], np.zeros(8833))
+    ref = np.empty(raw.shape[0])
+    for i, r in enumerate(raw):
+        thf = list(r[1:]) + [-0.02, 1.0]  # f = 1 isolates the signal
+        x = np.array([r[0]])
+        lp = np.log(me.values(te, thf, [x])[0])
+        Nb, _ = mz.norm(iz["sig"], thf)
+        ref[i] = lp - np.log(mz.values(tz, thf, [x])[0] * Nb)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=4e-6)
+
+
 @pytest.mark.parametrize("n", [1000, 20_001])
 def test_surrogate_leaf_vs_oracle(n):
     print("case surrogate leaf n=%d" % n, flush=True)
