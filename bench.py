@@ -109,6 +109,31 @@ def measured_traffic(workload, kernel, source):
     return None
 
 
+def measured_ceiling(name):
+    """A ceiling measured by bench.py --peaks on this device, from the
+    committed summary's machine-read line 'ceiling name=N value=V unit=U'."""
+    path = os.path.join(ROOT, "profiles", "peaks_mi355x.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("ceiling "):
+            kv = dict(f.split("=", 1) for f in line.split()[1:] if "=" in f)
+            if kv.get("name") == name:
+                return float(kv["value"])
+    return None
+
+
+# the measured ceiling that bounds each workload's FP32 kernel: the issue rate
+# of its instruction mix (lane-slots/s, a transcendental counting 4)
+MIX = {"gauss_cheb_1e7": "fp32_mix_14fma_1trans", "gauss_cheb_weighted_1e7": "fp32_mix_14fma_1trans",
+       "gauss_cheb_extended_1e7": "fp32_mix_14fma_1trans", "decay_argus_5e7": "fp32_mix_14fma_1trans",
+       "poisson_gauss_cheb_1e7": "fp32_mix_14fma_1trans", "bwcb_exact_1e7": "fp32_mix_12fma_1rcp",
+       "bwcb_surrogate_1e7": "fp32_mix_14fma_1trans"}
+# surrogate leaf: VALU lane-slots per event (192 tanh, the BF16 splitting of
+# the activations, the base): the binding bound, above the MFMA one
+SURROGATE_SLOTS_PER_EVENT = 2700
+
+
 def make(workload):
     """(spec, columns, truth theta, list of theta points, precisions, FP32 MLP weights or None)"""
     from paper_2003_12861_amd import synth, workloads
@@ -149,9 +174,9 @@ def make(workload):
 
 def timed_steps(call, thetas, steps, torch):
     """K synchronous evaluations; returns (seconds per step, median seconds of
-    one step)."""
+    one step).  The collector is already paused (time_path pauses it before
+    the warm-up, so that the warm-up steps run after its last collection)."""
     per = np.zeros(steps)
-    gc.collect()
     gc.disable()
     try:
         torch.cuda.synchronize()
@@ -203,6 +228,8 @@ def pipelined_kernel(call_async, thetas, reps, torch, stream):
 
 
 def time_path(call, call_async, thetas, args, torch, stream):
+    gc.collect()
+    gc.disable()
     for i in range(args.warmup):
         call(thetas[i % len(thetas)])
     step_s, med_s = timed_steps(call, thetas, args.steps, torch)
@@ -266,6 +293,9 @@ def run_binned(args, torch, stream):
                      "traffic": None, "bytes_per_launch": nbytes},
         "cpu_baseline": cpu,
     }
+    sbw = measured_ceiling("stream_read_bytes")
+    if sbw:
+        line["roofline"]["measured_ceiling"] = {"stream_GBps": sbw / 1e9, "frac_hbm": nbytes / k / sbw}
     print(json.dumps(line))
 
 
@@ -295,6 +325,7 @@ def run_unfused_ablation(args, progs, cols, thetas, n, torch, stream):
     for key, p in progs.items():
         fused = lambda th, p=p: p.nll(th, stream=stream)
         unf = lambda th, p=p: p.nll_unfused(th, stream=stream)
+        gc.collect()
         for f in (fused, unf):
             for i in range(args.warmup):
                 f(thetas[i % len(thetas)])
@@ -418,11 +449,16 @@ def main():
 
     k32 = res["fp32"]["kernel_s"]
     if wbf is not None:
-        achieved = n * 2 * SURROGATE_MAC_PER_EVENT / k32 / 1e12
-        roof = {"bound": "mfma", "kernel": "rf_k_grad_f32 (MLP leaf) with its normalisation kernel",
-                "achieved": achieved, "peak": MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / MFMA_BF16_TFLOPS, "traffic": None,
-                "flop_per_event": 2 * SURROGATE_MAC_PER_EVENT, "events_per_launch": n}
+        # the roofline time is the largest of the bounds: VALU (the tanh and
+        # operand splitting) over MFMA (the network's multiply-adds)
+        achieved = n * SURROGATE_SLOTS_PER_EVENT / k32 / 1e12
+        peak = VALU_SLOTS_PER_S / 1e12
+        mfma = n * 2 * SURROGATE_MAC_PER_EVENT / k32 / 1e12
+        roof = {"bound": "alu", "kernel": "rf_k_grad_f32 (MLP leaf) with its normalisation kernel",
+                "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak, "traffic": None,
+                "slots_per_event": SURROGATE_SLOTS_PER_EVENT, "events_per_launch": n,
+                "mfma": {"achieved_tflops": mfma, "peak_tflops": MFMA_BF16_TFLOPS, "frac": mfma / MFMA_BF16_TFLOPS,
+                         "flop_per_event": 2 * SURROGATE_MAC_PER_EVENT}}
     else:
         slots = SLOTS[args.workload]["fp32"]
         achieved = n * slots / k32 / 1e12
@@ -434,6 +470,16 @@ def main():
                 "slots_per_event": slots, "events_per_launch": n}
     roof["bytes_per_event"] = BYTES_PER_EVENT[args.workload]["fp32"]
     roof["hbm_GBps"] = n * BYTES_PER_EVENT[args.workload]["fp32"] / k32 / 1e9
+    # against the ceilings measured on this device (profiles/peaks_mi355x.txt):
+    # the issue rate of the kernel's instruction mix and the streaming read
+    mix = measured_ceiling(MIX[args.workload])
+    stream_bw = measured_ceiling("stream_read_bytes")
+    if mix:
+        roof["measured_ceiling"] = {"valu_mix": MIX[args.workload], "valu_Tslot_per_s": mix / 1e12,
+                                    "frac_valu": roof["achieved"] / (mix / 1e12)}
+        if stream_bw:
+            roof["measured_ceiling"].update({"stream_GBps": stream_bw / 1e9,
+                                             "frac_hbm": roof["hbm_GBps"] / (stream_bw / 1e9)})
     line = {
         "metric": "events/s for NLL+gradient (FP32+adjoint vs FP64 plain) at <=1e-6 rel NLL error",
         "value": n / res["fp32"]["step_s"],

@@ -14,16 +14,18 @@
 // exponent terms stay in registers and are reused by the adjoint:
 //   dNLL/dalpha_j = sum_cb r_cb sum_s nu_csb dE_csb/dalpha_j + alpha_j,
 //   r_cb = 1 - n_cb / nu_cb.
-// Precision: the tables are FP32 in memory; the 60-term exponent, nu and
-// r are accumulated in FP64 (FP64 FMA runs at the FP32 rate on CDNA4, so this
-// costs no throughput) because near the minimum r ~ 1/sqrt(n) cancels and an
-// FP32 exponent (error ~5e-7) would be amplified ~50x in the gradient.  The
-// per-bin adjoint terms are FP32; each bin's Poisson term and every reduction
-// are FP64.  Cross-workgroup reduction (deterministic, in fixed order): one
-// FP64 partial per workgroup and sum; the last workgroup of each group of
-// BN_G adds its group's partials (one thread per sum, all loads in flight,
-// pairwise), and the last group to finish adds the group partials -- a few
-// memory round trips for the 62 sums of a 200-channel model.
+// Precision: the tables are FP32 in memory; the 60-term exponent, nu, r and
+// every adjoint term are FP64 (FP64 FMA runs near the FP32 rate on CDNA4),
+// because near the minimum r ~ 1/sqrt(n) cancels and an FP32 exponent (error
+// ~5e-7) would be amplified ~50x in the gradient.
+// Reduction (deterministic, in a fixed order): each lane holds its cell's 62
+// terms (the Poisson term, d/dmu, d/dalpha_j); a transposed wavefront
+// reduction leaves lane l with the wavefront's sum of column l (63 exchanges
+// per lane in six halving steps, instead of one 64-lane reduction per
+// column); the workgroup adds its four wavefronts and stores one row of 64
+// columns (one coalesced store); the last workgroup of each group of BN_G
+// adds its group's rows, and the last group the group rows, one column per
+// lane -- all loads of a level in flight together.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,9 +35,9 @@
 #include "device/rf_dev.h"
 #include "rf_internal.h"
 
-#define BN_BS 128
-#define BN_MAXJ 64
-#define BN_G 32  // workgroups per reduction group
+#define BN_BS 256
+#define BN_MAXJ 64  // layout of the mapped result copy (2 + BN_MAXJ values, then the completion word)
+#define BN_G 16     // rows per reduction group
 
 namespace {
 
@@ -44,8 +46,8 @@ struct BinnedArgs {
   const float* Lp;     // [C][J][B][S]
   const float* Lm;     // [C][J][B][S]
   const float* nobs;   // [C][B]
-  double* part;        // [nblk][NS]
-  double* gpart;       // [ngrp][NS]
+  double* part;        // [nblk][64]: one row of column sums per workgroup
+  double* gpart;       // [ngrp][64]: one row per group of BN_G workgroups
   unsigned* ticket;    // [0] global, [64 (1 + g)] group g
   double* out;         // [nll, grad[1+J]]
   double* hout;        // optional copy in mapped host memory + completion word (or null)
@@ -57,18 +59,12 @@ struct BinnedArgs {
 
 template <int J>
 __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
-  constexpr int NS = 2 + J;  // NLL, mu, alpha_1..J
+  constexpr int NS = 2 + J;  // NLL, mu, alpha_1..J: one column each
+  static_assert(NS <= 64, "one lane per column");
   constexpr int NW = BN_BS / 64;
-  constexpr int RS = ((J + 1) & 1) ? J + 1 : J + 2;  // odd row stride: conflict-free column reads
-  // column 0: d/dmu, column 1 + j: d/dalpha_j; later reused as the staging
-  // buffer of the hand-off (BN_G x NS doubles fit: 512 (J + 1) >= 256 (J + 2) bytes)
-  __shared__ __align__(16) float term[BN_BS][RS];
-  __shared__ double bsum[NS];
   __shared__ double nu_s[BN_BS];
   __shared__ double r_s[BN_BS];
-  __shared__ double nll_w[NW];
-  __shared__ double fin[NS];
-  __shared__ int last;
+  __shared__ double wsum[NW][64];
   const int S = a.S, B = a.B;
   const int64_t total = (int64_t)a.C * B * S;
   const int64_t t = (int64_t)blockIdx.x * BN_BS + threadIdx.x;
@@ -76,6 +72,7 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   const int s = live ? (int)(t % S) : 0;
   const int64_t cb = live ? t / S : 0;  // c * B + b
   const int c = (int)(cb / B), b = (int)(cb % B);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 
   // every load of the thread is issued before any arithmetic, without a
   // branch (lanes past the end read cell 0 and drop the values): the
@@ -84,9 +81,7 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   const int64_t base = ((int64_t)c * J) * strideJ + (int64_t)b * S + s;
   float Tf = a.T[live ? t : 0];  // T laid out [C][B][S] == thread order
   float nf = a.nobs[cb];
-  // exponent E = sum_j |alpha_j| L^{sgn}_j; keep the 60 table values for the adjoint
   float Lv[J > 0 ? J : 1];
-  double E = 0.0;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const float* L = a.theta[1 + j] >= 0.0 ? a.Lp : a.Lm;
@@ -96,21 +91,20 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   nf = (live && s == 0) ? nf : 0.f;
 #pragma unroll
   for (int j = 0; j < J; ++j) Lv[j] = live ? Lv[j] : 0.f;
+  // exponent E = sum_j |alpha_j| L^{sgn}_j in four independent FP64 chains
+  double E;
   {
-    // four independent chains: a quarter of the dependent FMA latency
     double e4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < J; ++j) e4[j & 3] = fma(fabs(a.theta[1 + j]), (double)Lv[j], e4[j & 3]);
     E = (e4[0] + e4[1]) + (e4[2] + e4[3]);
   }
   const double mu = a.theta[0];
-  const double Tn = (double)Tf;
-  const double base_nu = Tn * exp(E);             // nu without the signal strength
+  const double base_nu = (double)Tf * exp(E);  // nu without the signal strength
   const double nu = (s == 0) ? mu * base_nu : base_nu;
   nu_s[threadIdx.x] = live ? nu : 0.0;
   __syncthreads();
-
-  // one thread per (c, b): Poisson term in FP64, r = 1 - n/nu
+  // the thread of sample 0 of each bin: Poisson term in FP64, r = 1 - n/nu
   double nllt = 0.0;
   if (live && s == 0) {
     double tot = 0.0;
@@ -122,137 +116,119 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   }
   __syncthreads();
   const double r = live ? r_s[threadIdx.x] : 0.0;
-  // adjoint terms (FP32): d/dmu (sample 0 only) and d/dalpha_j
-  const float rn = (float)(r * nu);
-  term[threadIdx.x][0] = (live && s == 0) ? (float)(r * base_nu) : 0.f;
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const float sg = a.theta[1 + j] >= 0.0 ? 1.f : -1.f;
-    term[threadIdx.x][1 + j] = live ? rn * sg * Lv[j] : 0.f;
-  }
-  const double wn = wave_sum(nllt);
-  if ((threadIdx.x & 63) == 0) nll_w[threadIdx.x >> 6] = wn;
-  __syncthreads();
-  // workgroup partials in FP64, fixed order.  Sum 0 (the Poisson terms)
-  // from the wavefront sums; the term columns by rows of sixteen lanes: lane
-  // l of a row adds rows l, l + 16, ..., l + 112 of its column, and a DPP
-  // row sum completes it (eight columns per pass, every thread busy).
-  // Partials are stored workgroup-major (part[blk][NS], gpart[grp][NS]):
-  // one coalesced store per workgroup, and a group's partials are one
-  // contiguous block that the next level reads with coalesced loads.
-  static_assert(BN_BS == 128, "eight rows of sixteen lanes per pass");
-  static_assert(NS <= BN_BS, "one thread per sum");
-  static_assert(BN_G * NS * 8 <= BN_BS * RS * 4, "the staging buffer fits in the term table");
-  if (threadIdx.x == 0) {
-    double hi = 0.0, lo = 0.0;
-    for (int w = 0; w < NW; ++w) dd_add(hi, lo, nll_w[w], 0.0);
-    bsum[0] = hi + lo;
-  }
-  {
-    const int l16 = threadIdx.x & 15, row = threadIdx.x >> 4;
-#pragma unroll
-    for (int p = 0; p < (NS - 1 + 7) / 8; ++p) {
-      const int col = p * 8 + row;
-      const int cc = col < NS - 1 ? col : NS - 2;
-      double v[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = (double)term[l16 + 16 * i][cc];
-#pragma unroll
-      for (int w = 4; w >= 1; w >>= 1)
-#pragma unroll
-        for (int i = 0; i < w; ++i) v[i] += v[i + w];
-      const double rs = row_sum(v[0]);
-      if (l16 == 0 && col < NS - 1) bsum[1 + col] = rs;
+  const double rn = r * nu;
+  // the lane's NS terms, column k: 0 the Poisson term, 1 d/dmu (sample 0),
+  // 2 + j d/dalpha_j = r nu sgn(alpha_j) L_j, all FP64
+  auto term = [&](int k) -> double {
+    if (k == 0) return nllt;
+    if (k == 1) return (live && s == 0) ? r * base_nu : 0.0;
+    if (k < NS) {
+      const int j = k - 2;
+      return (a.theta[1 + j] >= 0.0 ? rn : -rn) * (double)Lv[j];
     }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < NS; k += BN_BS)
-    __hip_atomic_store(&a.part[(int64_t)blockIdx.x * NS + k], bsum[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  rf_wait_stores();
-  __syncthreads();
-  double* const stage = reinterpret_cast<double*>(&term[0][0]);  // BN_G x NS
-  // the sums of n partials (rows of NS, contiguous from src) into h[k] for
-  // k = threadIdx.x: coalesced loads into LDS (all in flight), then one
-  // thread per sum adds its column pairwise, BN_G rows per pass
-  auto column_sums = [&](const double* src, int n, double& h) {
-    h = 0.0;
-    for (int r0 = 0; r0 < n; r0 += BN_G) {
-      const int rn = n - r0 < BN_G ? n - r0 : BN_G;
-      const int m = rn * NS;
-      constexpr int PER = (BN_G * NS + BN_BS - 1) / BN_BS;
-      double v[PER];
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = threadIdx.x + q * BN_BS;
-        v[q] = __hip_atomic_load(&src[(int64_t)r0 * NS + (e < m ? e : m - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = threadIdx.x + q * BN_BS;
-        if (e < m) stage[e] = v[q];
-      }
-      __syncthreads();
-      if (threadIdx.x < NS) {
-        double c[BN_G];
-#pragma unroll
-        for (int q = 0; q < BN_G; ++q) c[q] = q < rn ? stage[q * NS + threadIdx.x] : 0.0;
-#pragma unroll
-        for (int w = BN_G / 2; w >= 1; w >>= 1)
-#pragma unroll
-          for (int q = 0; q < w; ++q) c[q] += c[q + w];
-        h += c[0];
-      }
-      __syncthreads();
-    }
+    return 0.0;
   };
-  // level 1: the last workgroup of this group adds the group's partials
+  // Transposed wavefront reduction of the 64 columns (NS used, the rest
+  // zero): in step d = 32, 16, ..., 1 a lane keeps the upper half of its
+  // current columns if (lane & d), the lower half otherwise, and adds the
+  // partner's (lane ^ d) copy of the half it keeps.  After six steps lane l
+  // holds the wavefront's sum of column l: 63 exchanges per lane instead of
+  // a reduction per column.  Fixed order, so the result is repeatable.
+  double v[32];
+  {
+    const bool up = (lane & 32) != 0;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const double lo = term(k), hi = term(k + 32);
+      const double other = up ? lo : hi;
+      v[k] = (up ? hi : lo) + __shfl_xor(other, 32);
+    }
+  }
+#pragma unroll
+  for (int h = 16; h >= 1; h >>= 1) {
+    const bool up = (lane & h) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      const double lo = v[k], hi = v[k + h];
+      const double other = up ? lo : hi;
+      v[k] = (up ? hi : lo) + __shfl_xor(other, h);
+    }
+  }
+  wsum[wid][lane] = v[0];
+  __syncthreads();
+  if (wid != 0) return;
+  // the workgroup's partial of column lane, wavefronts in a fixed order
+  {
+    double p = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) p += wsum[w][lane];
+    __hip_atomic_store(&a.part[(int64_t)blockIdx.x * 64 + lane], p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  rf_wait_stores();
+  // level 1: the last workgroup of each group of BN_G adds the group's rows
   const int g = (int)blockIdx.x / BN_G, g0 = g * BN_G;
   const int gn = a.nblk - g0 < BN_G ? a.nblk - g0 : BN_G;
-  if (threadIdx.x == 0) last = (rf_take_ticket(a.ticket + 64 * (1 + g)) == (unsigned)(gn - 1));
-  __syncthreads();
-  if (!last) return;
   {
-    double h;
-    column_sums(a.part + (int64_t)g0 * NS, gn, h);
-    if (threadIdx.x < NS) __hip_atomic_store(&a.gpart[(int64_t)g * NS + threadIdx.x], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned tk = lane == 0 ? rf_take_ticket(a.ticket + 64 * (1 + g)) : 0u;
+    tk = (unsigned)__builtin_amdgcn_readfirstlane((int)tk);
+    if (tk != (unsigned)(gn - 1)) return;
+  }
+  {
+    double x[BN_G];
+#pragma unroll
+    for (int q = 0; q < BN_G; ++q)
+      x[q] = __hip_atomic_load(&a.part[(int64_t)(g0 + (q < gn ? q : gn - 1)) * 64 + lane], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int q = 0; q < BN_G; ++q) x[q] = q < gn ? x[q] : 0.0;
+#pragma unroll
+    for (int w = BN_G / 2; w >= 1; w >>= 1)
+#pragma unroll
+      for (int q = 0; q < w; ++q) x[q] += x[q + w];
+    __hip_atomic_store(&a.gpart[(int64_t)g * 64 + lane], x[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   rf_wait_stores();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    rf_reset_ticket(a.ticket + 64 * (1 + g));
-    last = (rf_take_ticket(a.ticket) == (unsigned)(a.ngrp - 1));
-  }
-  __syncthreads();
-  if (!last) return;
-  // level 2: the group partials
   {
-    double h;
-    column_sums(a.gpart, a.ngrp, h);
-    if (threadIdx.x < NS) fin[threadIdx.x] = h;
+    unsigned tk = 0u;
+    if (lane == 0) {
+      rf_reset_ticket(a.ticket + 64 * (1 + g));
+      tk = rf_take_ticket(a.ticket);
+    }
+    tk = (unsigned)__builtin_amdgcn_readfirstlane((int)tk);
+    if (tk != (unsigned)(a.ngrp - 1)) return;
   }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    // the result into LDS (one lane), then copied by the wavefront to the
-    // output and the host's mapped copy, then the completion word
-    __shared__ double res[2 + J];
-    if (threadIdx.x == 0) {
-      double c2 = 0.0;
-      for (int j = 0; j < J; ++j) c2 += 0.5 * a.theta[1 + j] * a.theta[1 + j];
-      res[0] = fin[0] + c2;
-      res[1] = fin[1];
-      for (int j = 0; j < J; ++j) res[2 + j] = fin[2 + j] + a.theta[1 + j];
+  // level 2: the group rows, BN_G at a time, in a fixed order
+  double fin = 0.0;
+  for (int g1 = 0; g1 < a.ngrp; g1 += BN_G) {
+    double x[BN_G];
+#pragma unroll
+    for (int q = 0; q < BN_G; ++q) {
+      const int gg = g1 + q < a.ngrp ? g1 + q : a.ngrp - 1;
+      x[q] = __hip_atomic_load(&a.gpart[(int64_t)gg * 64 + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    for (int j = threadIdx.x; j < 2 + J; j += 64) {
-      const double v = res[j];
-      a.out[j] = v;
-      if (a.hout) a.hout[j] = v;
-    }
-    if (threadIdx.x == 0) {
-      rf_reset_ticket(a.ticket);
-      if (a.hout) {
-        __threadfence_system();
-        __hip_atomic_store((uint64_t*)(a.hout + 2 + BN_MAXJ), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
+#pragma unroll
+    for (int q = 0; q < BN_G; ++q) x[q] = g1 + q < a.ngrp ? x[q] : 0.0;
+#pragma unroll
+    for (int w = BN_G / 2; w >= 1; w >>= 1)
+#pragma unroll
+      for (int q = 0; q < w; ++q) x[q] += x[q + w];
+    fin += x[0];
+  }
+  // the result: column 0 plus the constraint sum_j alpha_j^2 / 2, column 1,
+  // columns 2 + j plus alpha_j; written by the wavefront to the output and the
+  // host's mapped copy, then the completion word
+  double c2 = 0.0;
+  for (int j = 0; j < J; ++j) c2 += 0.5 * a.theta[1 + j] * a.theta[1 + j];
+  const double res = lane == 0 ? fin + c2 : (lane >= 2 && lane < NS ? fin + a.theta[lane - 1] : fin);
+  if (lane < NS) {
+    a.out[lane] = res;
+    if (a.hout) a.hout[lane] = res;
+  }
+  if (lane == 0) {
+    rf_reset_ticket(a.ticket);
+    if (a.hout) {
+      __threadfence_system();
+      __hip_atomic_store((uint64_t*)(a.hout + 2 + BN_MAXJ), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
@@ -271,12 +247,12 @@ BinnedFn kernel_for(int J) {
     case 16: return pick<16>();
     case 32: return pick<32>();
     case 60: return pick<60>();
-    case 64: return pick<64>();
+    case 62: return pick<62>();
   }
   return nullptr;
 }
 int padded_J(int J) {
-  const int opts[] = {0, 1, 2, 4, 8, 16, 32, 60, 64};
+  const int opts[] = {0, 1, 2, 4, 8, 16, 32, 60, 62};
   for (int o : opts)
     if (o >= J) return o;
   return -1;
@@ -316,9 +292,9 @@ int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T, c
                   const double* Tm, const double* nobs, void* stream, rf_binned** out) {
   if (!out || !T || !nobs || (J > 0 && (!Tp || !Tm))) return fail(RF_E_INVALID, "NULL argument");
   if (C < 1 || S < 1 || B < 1 || J < 0) return fail(RF_E_INVALID, "bad shape");
-  if (BN_BS % S != 0) return fail(RF_E_INVALID, "the number of samples must divide 128");
+  if (BN_BS % S != 0) return fail(RF_E_INVALID, "the number of samples must divide 256");
   const int Jp = padded_J(J);
-  if (Jp < 0) return fail(RF_E_INVALID, "at most 64 nuisance parameters");
+  if (Jp < 0) return fail(RF_E_INVALID, "at most 62 nuisance parameters");
   const size_t nT = (size_t)C * S * B, nL = (size_t)C * Jp * B * S;
   std::vector<float> hT(nT), hLp(nL > 0 ? nL : 1, 0.f), hLm(nL > 0 ? nL : 1, 0.f), hn((size_t)C * B);
   for (int c = 0; c < C; ++c)
@@ -356,7 +332,7 @@ int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T, c
     rf_binned_free(bn);
     return hip_fail(e, "binned upload");
   }
-  const size_t NS = 2 + Jp;
+  const size_t NS = 64;  // one row of 64 columns per workgroup and group
   const size_t nticket = (size_t)64 * (1 + bn->ngrp);
   const size_t nhout = 2 + BN_MAXJ + 1;
   if ((e = hipMalloc(&bn->part, sizeof(double) * NS * bn->nblk)) != hipSuccess ||
