@@ -119,6 +119,17 @@ def _kernel_seconds(prog, theta, reps=20):
     return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e-3
 
 
+def seeded_fit(prog_surrogate, prog_exact, start, edm_tol=1e-6, max_iter=500):
+    """The surrogate as the fit's accelerator: minimise with the surrogate
+    from start, then with the exact convolution from the surrogate's minimum
+    (the exact path stays the judge and the fallback: the result is the exact
+    likelihood's minimum, reached with few exact evaluations).  Returns
+    dict(theta, sigma, info_surrogate, info_exact, theta_surrogate)."""
+    th_s, _, info_s = prog_surrogate.fit(start, edm_tol=edm_tol, max_iter=max_iter)
+    th, sig, info_e = prog_exact.fit(th_s, edm_tol=edm_tol, max_iter=max_iter)
+    return dict(theta=th, sigma=sig, info_surrogate=info_s, info_exact=info_e, theta_surrogate=th_s)
+
+
 def experiment(epochs=600, n_train=2_000_000, n_events=10_000_000, seed=0, log=print, weights_out=None):
     """Train the surrogate, then fit the same events with the exact convolution
     (FP64 and FP32) and with the surrogate; report the surrogate's error, the

@@ -1,0 +1,105 @@
+"""The learned part end to end: the surrogate trained on the GPU by the
+library's own kernels (2e6 design points, fixed seed), then fits of the same
+1e7 events with the exact convolution (FP64, the reference, and FP32), with
+the surrogate alone, and with the surrogate as the fit's accelerator (its
+minimum seeds the exact fit).  Reported: each fit's bias in units of the
+exact FP64 fit's sigma, and what the network gains."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2003_12861_amd import synth, workloads
+
+pytestmark = pytest.mark.gpu
+api = pytest.importorskip("paper_2003_12861_amd.api")
+torch = pytest.importorskip("torch")
+from paper_2003_12861_amd import surrogate  # noqa: E402
+
+START = [91.0, 2.7, 1.3, 1.7, 3.5, -0.018, 0.78]
+_R = {}
+
+
+def _kernel_ms(prog, theta, reps=10):
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    prog.nll_grad_async(theta, stream=s)
+    a.record(s)
+    for _ in range(reps):
+        prog.nll_grad_async(theta, stream=s)
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _run():
+    if _R:
+        return _R
+    torch.cuda.set_device(0)
+    print("case surrogate fit: training", flush=True)
+    res = surrogate.train_surrogate(n_train=2_000_000, epochs=600, seed=0)
+    x = synth.sample_bw_cb(10_000_000, 4)
+    truth = workloads.truth_vector(synth.BWCB_TRUTH)
+
+    def prog(spec, prec):
+        p = api.Program(api.Graph.from_spec(spec), precision=prec)
+        p.bind([torch.tensor(x, dtype=torch.float64 if prec == api.FP64 else torch.float32, device="cuda")])
+        return p
+
+    e64 = prog(workloads.spec_bwcb(), api.FP64)
+    e32 = prog(workloads.spec_bwcb(), api.FP32)
+    sur = prog(workloads.spec_bwcb(surrogate=True), api.FP32)
+    sur.bind_weights("sig", res["w_bf16"])
+    print("case surrogate fit: fits", flush=True)
+    th64, sig64, _ = e64.fit(START, edm_tol=1e-6)
+    t0 = time.perf_counter()
+    th32, _, info32 = e32.fit(START, edm_tol=1e-6)
+    t_exact = time.perf_counter() - t0
+    th_s, _, info_s = sur.fit(START, edm_tol=1e-6)
+    t0 = time.perf_counter()
+    seeded = surrogate.seeded_fit(sur, e32, START)
+    t_seeded = time.perf_counter() - t0
+    _R.update(dict(
+        holdout_rms=res["holdout_rms"], sig=np.asarray(sig64), th64=np.asarray(th64),
+        bias_exact32=(np.asarray(th32) - th64) / sig64, bias_surrogate=(np.asarray(th_s) - th64) / sig64,
+        bias_seeded=(np.asarray(seeded["theta"]) - th64) / sig64,
+        evals_exact=info32["evaluations"], evals_seeded_exact=seeded["info_exact"]["evaluations"],
+        evals_seeded_surrogate=seeded["info_surrogate"]["evaluations"],
+        t_exact=t_exact, t_seeded=t_seeded,
+        k_exact32=_kernel_ms(e32, truth), k_sur=_kernel_ms(sur, truth), converged=(info32["converged"], info_s["converged"])))
+    r = _R
+    print("surrogate: hold-out rms %.3g" % r["holdout_rms"])
+    print("bias (sigma of the exact FP64 fit): exact FP32 %s" % np.array2string(r["bias_exact32"], precision=3))
+    print("                                    surrogate %s" % np.array2string(r["bias_surrogate"], precision=3))
+    print("                                    seeded    %s" % np.array2string(r["bias_seeded"], precision=3))
+    print("kernel ms: exact FP32 %.3f, surrogate %.3f (gain %.2fx)" % (r["k_exact32"], r["k_sur"],
+                                                                       r["k_exact32"] / r["k_sur"]))
+    print("fit: exact FP32 %d evaluations %.3f s; seeded %d surrogate + %d exact evaluations %.3f s" % (
+        r["evals_exact"], r["t_exact"], r["evals_seeded_surrogate"], r["evals_seeded_exact"], r["t_seeded"]), flush=True)
+    return r
+
+
+def test_surrogate_kernel_gain():
+    """What the network gains per evaluation: the surrogate leaf against the
+    exact 1024-point convolution, both FP32, same events."""
+    r = _run()
+    assert r["converged"] == (True, True)
+    assert r["k_exact32"] / r["k_sur"] >= 2.0, (r["k_exact32"], r["k_sur"])
+
+
+def test_surrogate_seeded_fit_matches_exact():
+    """The surrogate's minimum seeds the exact fit: the result is the exact
+    likelihood's minimum (within 0.1 sigma of the exact FP64 fit) with fewer
+    exact evaluations than the exact fit from the same start."""
+    r = _run()
+    assert np.abs(r["bias_seeded"]).max() <= 0.1, r["bias_seeded"]
+    assert r["evals_seeded_exact"] < r["evals_exact"], (r["evals_seeded_exact"], r["evals_exact"])
+
+
+@pytest.mark.xfail(strict=True, reason="surrogate alone: fitted values up to ~1.2 sigma from the exact fit "
+                                       "(measured with this seed: M -1.16, Gamma -0.13, sigma 0.28, alpha 0.90, "
+                                       "n -0.92, lambda 0.07, f 0.42); the network's residual error (1.2e-3 "
+                                       "rms) is about 20x too large for 0.1 sigma at 1e7 events")
+def test_surrogate_alone_within_a_tenth_of_sigma():
+    r = _run()
+    assert np.abs(r["bias_surrogate"]).max() <= 0.1, r["bias_surrogate"]
