@@ -117,6 +117,41 @@ RF_DEV void rf_group(const RF_T (&x)[RF_NCOL1][E], const KS<RF_T>& k, double* ac
   if (MODE == 0) rf_stv<RF_T, E>((RF_T*)a.values, i0, p);
 }
 
+// FP32 programs, NLL modes, full tiles: the events of a ring round (up to
+// RF_PFD groups) are evaluated without per-event checks into one set of FP32
+// partial sums, keeping the smallest probability.  The round is then checked
+// as a whole: it is usable when that minimum is above the tail threshold and
+// the sum of log2 p is finite (a probability that is infinite or NaN makes it
+// infinite or NaN).  A usable round goes into the FP64 sums; an unusable one
+// (rare: an event in a far tail) is dropped, and each of its events is read
+// again and evaluated in FP64 with its own check, as in rf_group.
+template <int MODE, int E>
+RF_DEV void rf_group_unchecked(const RF_T (&x)[RF_NCOL1][E], const KS<RF_T>& k, RF_T* part, RF_T& pmin) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    RF_T xe[RF_NCOL1];
+#pragma unroll
+    for (int c = 0; c < RF_NCOL1; ++c) xe[c] = x[c][e];
+    RF_T p;
+    (void)rf_eval<RF_T, MODE, 0>(xe, k, part, &p);
+    pmin = fminf(pmin, p);
+  }
+}
+template <int MODE>
+RF_DEV void rf_round_fp64(const RfArgs& a, int64_t g0, const double* cst, double* acc, unsigned& nbad) {
+  const KS<double> kd = KS<double>::load(cst);
+  // one event at a time (rolled loops): this path must not raise the
+  // kernel's register count, which the unrolled FP64 events would
+#pragma clang loop unroll(disable)
+  for (int e = 0; e < RF_EPT; ++e) {
+    double xd[RF_NCOL1];
+#pragma unroll
+    for (int c = 0; c < RF_NCOL; ++c) xd[c] = (double)((const RF_T*)a.col[c])[g0 * RF_EPT + e];
+    double pd;
+    if (!rf_eval<double, MODE>(xd, kd, acc, &pd)) ++nbad;
+  }
+}
+
 // Issue priority of the wavefronts by the work left.  The arbiter of a SIMD
 // issues from the wave of highest priority first, and among equals from the
 // oldest: without this, the workgroups that reach a CU first run ahead and
@@ -219,18 +254,38 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
     rf_prologue(a.theta, cst, a);
     __syncthreads();
     const KS<RF_T> k = KS<RF_T>::load(cst);
+    // (leaves with one event per step do enough work per event that the
+    // per-event check costs nothing; they keep rf_group)
+    constexpr bool ROUNDS = sizeof(RF_T) == 4 && MODE != 0 && RF_TAIL64 && RF_EPT > 1;
     for (int64_t m0 = 0; m0 < MB; m0 += D) {
+      RF_T part[NSUM];
+#pragma unroll
+      for (int j = 0; j < NSUM; ++j) part[j] = (RF_T)0;
+      RF_T pmin = (RF_T)INFINITY;
 #pragma unroll
       for (int u = 0; u < D; ++u) {
 #if RF_PRIO
         rf_prio_remaining(MB - (m0 + u), MB);
 #endif
         // the last ring round may hold fewer than D full tiles (uniform test)
-        if (m0 + u < MB)
-          rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, (base0 + (m0 + u) * gstep + threadIdx.x) * RF_EPT, cst);
+        if (m0 + u < MB) {
+          if constexpr (ROUNDS)
+            rf_group_unchecked<MODE, RF_EPT>(xb[u], k, part, pmin);
+          else
+            rf_group<MODE, RF_EPT>(xb[u], k, acc, nbad, a, (base0 + (m0 + u) * gstep + threadIdx.x) * RF_EPT, cst);
+        }
 #pragma unroll
         for (int c = 0; c < RF_NCOL; ++c)
           rf_ldv<RF_T, RF_EPT>((const RF_T*)a.col[c], (tile(m0 + u + D) + threadIdx.x) * RF_EPT, xb[u][c]);
+      }
+      if constexpr (ROUNDS) {
+        if (pmin > RM<RF_T>::tiny() && __builtin_isfinite(part[0])) {
+          rf_flush<NSUM>(part, acc);
+        } else {
+#pragma clang loop unroll(disable)
+          for (int u = 0; u < D; ++u)
+            if (m0 + u < MB) rf_round_fp64<MODE>(a, base0 + (m0 + u) * gstep + threadIdx.x, cst, acc, nbad);
+        }
       }
     }
     // the partial tile (at most one per workgroup: the next one starts past ng)

@@ -221,16 +221,18 @@ static constexpr double RF_GW = 0.849321800288019042721502834103;      // 1/sqrt
 static constexpr double RF_GW_INV = 1.17741002251547469101156932646;   // sqrt(2 ln 2)
 static constexpr double RF_GW_INV2 = 1.38629436111989061883446424292;  // 2 ln 2
 template <typename T> struct GaussK {
-  double mu, is;  // mu and s / sigma
+  double mis, is;  // -mu s / sigma and s / sigma
   RF_DEV GaussK load(const double* C) {
     GaussK k;
-    k.mu = C[3];
     k.is = C[4] * RF_GW;
+    k.mis = -C[3] * k.is;
     return k;
   }
 };
+// w = x s/sigma - mu s/sigma in one FP64 FMA (mu s/sigma rounded once, to
+// 2^-53 of itself)
 template <typename T> RF_DEV T gauss_eval(T x, const GaussK<T>& k, T* d) {
-  const double w = ((double)x - k.mu) * k.is;
+  const double w = fma((double)x, k.is, k.mis);
   const double q = w * w;
   if constexpr (sizeof(T) == 4) {
     const float qh = (float)q;

@@ -454,9 +454,12 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
 
   // ---- per-event program ----
   // returns false when p is not a usable probability (FP32: below 1e-30 or
-  // not finite; FP64: not positive or not finite); such an event adds
-  // nothing to the sums.  acc[0] += log p (FP32: log2 p), acc[D], acc[Y].
-  o << "template <typename T, int MODE>\n";
+  // not finite; FP64: not positive or not finite).  With MASK = 1 such an
+  // event adds nothing to the sums; with MASK = 0 every event adds its terms
+  // unchecked (the caller checks a whole round of events afterwards and
+  // discards the round's sums if any event failed).  acc[0] += log p (FP32:
+  // log2 p), acc[D], acc[Y].
+  o << "template <typename T, int MODE, int MASK = 1>\n";
   o << "RF_DEV bool rf_eval(const T* x, const KS<T>& k, T* acc, T* pout) {\n";
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
@@ -484,20 +487,20 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     // weighted events: every sum of the event carries its weight, through
     // log p and through r = 1/p, which all adjoint terms share
     o << "  const T wt = x[" << L.n_cols << "];\n";
-    o << "  acc[0] += ok ? wt * RM<T>::log_acc(p) : (T)0;\n";
+    o << "  acc[0] += (!MASK || ok) ? wt * RM<T>::log_acc(p) : (T)0;\n";
     // the sum of the weights exists in the gradient mode only (the NLL-only
     // kernel keeps one sum); rf_nll runs the gradient kernel for such programs.
     // A weight enters it only where its event's terms do: an FP32 event
     // below the tail threshold adds its weight in the FP64 re-evaluation
     // instead, so that every weight is counted once (a bad event makes the
     // NLL infinite whatever N is)
-    if (L.wsum >= 0) o << "  if (MODE == 2) acc[" << L.wsum << "] += ok ? wt : (T)0;\n";
+    if (L.wsum >= 0) o << "  if (MODE == 2) acc[" << L.wsum << "] += (!MASK || ok) ? wt : (T)0;\n";
     o << "  if (MODE == 2) {\n";
-    o << "    const T r = ok ? RM<T>::rcp(p) * wt : (T)0;\n";
+    o << "    const T r = (!MASK || ok) ? RM<T>::rcp(p) * wt : (T)0;\n";
   } else {
-    o << "  acc[0] += ok ? RM<T>::log_acc(p) : (T)0;\n";
+    o << "  acc[0] += (!MASK || ok) ? RM<T>::log_acc(p) : (T)0;\n";
     o << "  if (MODE == 2) {\n";
-    o << "    const T r = ok ? RM<T>::rcp(p) : (T)0;\n";
+    o << "    const T r = (!MASK || ok) ? RM<T>::rcp(p) : (T)0;\n";
   }
   std::vector<char> declared(N, 0), wdecl(N, 0);
   // beta_c: name of the variable holding it, declared on first use

@@ -72,4 +72,9 @@ def test_weighted_extended_parity(prec, n):
     ref, _ = build_pair(workloads.spec_gauss_cheb_extended(), prec, api)
     ref.bind(to_dev([x], prec, api))
     a, b = prog.nll_grad(th)[0], ref.nll_grad(th)[0]
-    assert abs(a - b) <= 1e-14 * max(1.0, abs(b)), (a, b)
+    # FP64: the same arithmetic event by event.  FP32: the same per-event
+    # arithmetic, but each program adds its events into FP32 partial sums per
+    # round of its load ring (8 events with the weight column, 12 without), so
+    # the two agree to the rounding of those partials
+    bar = 1e-14 if prec == api.FP64 else 1e-9
+    assert abs(a - b) <= bar * max(1.0, abs(b)), (a, b)
