@@ -38,24 +38,46 @@
 #define BN_BS 256
 #define BN_MAXJ 64  // layout of the mapped result copy (2 + BN_MAXJ values, then the completion word)
 #define BN_G 16     // rows per reduction group
+#define BN_G2 32    // group rows per pass of the last level
+#define BN_RS 17    // LDS row stride (doubles) of a lane's 16 partial columns: conflict-free writes
 
 namespace {
 
 struct BinnedArgs {
   const float* T;      // [C][B][S]
-  const float* Lp;     // [C][J][B][S]
-  const float* Lm;     // [C][J][B][S]
   const float* nobs;   // [C][B]
+  const float* L[BN_MAXJ];  // per nuisance parameter j: the table of its sign (alpha_j >= 0: L+, else L-),
+                            // advanced to row j: element c J B S + b S + s of it is L_cbsj
+  double absa[BN_MAXJ];     // |alpha_j|
   double* part;        // [nblk][64]: one row of column sums per workgroup
   double* gpart;       // [ngrp][64]: one row per group of BN_G workgroups
   unsigned* ticket;    // [0] global, [64 (1 + g)] group g
   double* out;         // [nll, grad[1+J]]
   double* hout;        // optional copy in mapped host memory + completion word (or null)
   uint64_t seq;
+  uint64_t neg;        // bit j set: alpha_j < 0
+  double mu, cons;     // signal strength; sum_j alpha_j^2 / 2
   int32_t C, S, B, J;
   int32_t nblk, ngrp;
-  double theta[1 + BN_MAXJ];
+  int32_t logS, pad_;
+  double alpha[BN_MAXJ];
 };
+
+// one double through a lane-swap builtin (two 32-bit halves)
+__device__ __forceinline__ void swap32(double& x, double& y) {
+  const uint64_t a = __builtin_bit_cast(uint64_t, x), b = __builtin_bit_cast(uint64_t, y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+  x = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+  y = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
+__device__ __forceinline__ void swap16(double& x, double& y) {
+  const uint64_t a = __builtin_bit_cast(uint64_t, x), b = __builtin_bit_cast(uint64_t, y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+  x = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+  y = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
 
 template <int J>
 __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
@@ -63,98 +85,121 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   static_assert(NS <= 64, "one lane per column");
   constexpr int NW = BN_BS / 64;
   __shared__ double nu_s[BN_BS];
-  __shared__ double r_s[BN_BS];
+  __shared__ double red[NW][64 * BN_RS];
   __shared__ double wsum[NW][64];
-  const int S = a.S, B = a.B;
-  const int64_t total = (int64_t)a.C * B * S;
-  const int64_t t = (int64_t)blockIdx.x * BN_BS + threadIdx.x;
-  const bool live = t < total;
-  const int s = live ? (int)(t % S) : 0;
-  const int64_t cb = live ? t / S : 0;  // c * B + b
-  const int c = (int)(cb / B), b = (int)(cb % B);
+  const int S = a.S;
+  const uint32_t B = (uint32_t)a.B;
+  // 32-bit cell indices (the host keeps C B S below 2^31); S is a power of
+  // two (it divides the workgroup size)
+  const uint32_t t = blockIdx.x * BN_BS + threadIdx.x;
+  const bool live = t < (uint32_t)a.C * B * (uint32_t)S;
+  const uint32_t tc = live ? t : 0u;
+  const int s = (int)(tc & (uint32_t)(S - 1));
+  const uint32_t cb = tc >> a.logS;  // c * B + b
+  const uint32_t c = cb / B, b = cb - c * B;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 
   // every load of the thread is issued before any arithmetic, without a
-  // branch (lanes past the end read cell 0 and drop the values): the
-  // compiler then keeps all of them in flight -- one memory round trip
-  const int64_t strideJ = (int64_t)B * S;
-  const int64_t base = ((int64_t)c * J) * strideJ + (int64_t)b * S + s;
-  float Tf = a.T[live ? t : 0];  // T laid out [C][B][S] == thread order
-  float nf = a.nobs[cb];
+  // branch: lanes past the end read cell 0 (their terms are zeroed through
+  // r below).  Table addresses are a uniform 64-bit row base plus a 32-bit
+  // per-lane byte offset (the host keeps the tables under 4 GiB).
+  const uint32_t boff = 4u * ((c * (uint32_t)J * B + b) * (uint32_t)S + (uint32_t)s);
+  float Tf = a.T[tc];  // T laid out [C][B][S] == thread order
+  const float nf = a.nobs[cb];
   float Lv[J > 0 ? J : 1];
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const float* L = a.theta[1 + j] >= 0.0 ? a.Lp : a.Lm;
-    Lv[j] = L[base + j * strideJ];
-  }
-  Tf = live ? Tf : 0.f;
-  nf = (live && s == 0) ? nf : 0.f;
-#pragma unroll
-  for (int j = 0; j < J; ++j) Lv[j] = live ? Lv[j] : 0.f;
+  for (int j = 0; j < J; ++j) Lv[j] = *(const float*)((const char*)a.L[j] + boff);
   // exponent E = sum_j |alpha_j| L^{sgn}_j in four independent FP64 chains
   double E;
   {
     double e4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < J; ++j) e4[j & 3] = fma(fabs(a.theta[1 + j]), (double)Lv[j], e4[j & 3]);
+    for (int j = 0; j < J; ++j) e4[j & 3] = fma(a.absa[j], (double)Lv[j], e4[j & 3]);
     E = (e4[0] + e4[1]) + (e4[2] + e4[3]);
   }
-  const double mu = a.theta[0];
-  const double base_nu = (double)Tf * exp(E);  // nu without the signal strength
-  const double nu = (s == 0) ? mu * base_nu : base_nu;
-  nu_s[threadIdx.x] = live ? nu : 0.0;
-  __syncthreads();
-  // the thread of sample 0 of each bin: Poisson term in FP64, r = 1 - n/nu
-  double nllt = 0.0;
-  if (live && s == 0) {
-    double tot = 0.0;
-    for (int q = 0; q < S; ++q) tot += nu_s[threadIdx.x + q];
-    const double n = (double)nf;
-    nllt = tot - n * log(tot);
-    const double r = 1.0 - n / tot;
-    for (int q = 0; q < S; ++q) r_s[threadIdx.x + q] = r;
+  const double base_nu = live ? (double)Tf * exp(E) : 0.0;  // nu without the signal strength
+  const double nu = (s == 0) ? a.mu * base_nu : base_nu;
+  // the bin's total over its S samples (consecutive lanes): a butterfly over
+  // the lanes of the bin when it lies in one wavefront, every lane of the bin
+  // ending with the same sum (additions commute exactly); through LDS
+  // otherwise.  Then, in FP64, the Poisson term (on sample 0's lane) and
+  // r = 1 - n/nu (on every lane of the bin).
+  double tot = nu;
+  if (S <= 64) {
+    for (int h = 1; h < S; h <<= 1) tot += __shfl_xor(tot, h);
+  } else {
+    nu_s[threadIdx.x] = nu;
+    __syncthreads();
+    if (s == 0) {
+      double t2 = 0.0;
+      for (int q = 0; q < S; ++q) t2 += nu_s[threadIdx.x + q];
+      nu_s[threadIdx.x] = t2;
+    }
+    __syncthreads();
+    tot = nu_s[threadIdx.x - s];
   }
-  __syncthreads();
-  const double r = live ? r_s[threadIdx.x] : 0.0;
-  const double rn = r * nu;
-  // the lane's NS terms, column k: 0 the Poisson term, 1 d/dmu (sample 0),
-  // 2 + j d/dalpha_j = r nu sgn(alpha_j) L_j, all FP64
+  const double n = (double)nf;
+  // (the library's log where tot is zero, subnormal or not finite: such a
+  // bin makes the NLL non-finite, as it must)
+  const double lt = (tot >= 2.2250738585072014e-308 && tot < INFINITY) ? rf_log64(tot) : log(tot);
+  const double nllt = (live && s == 0) ? tot - n * lt : 0.0;
+  const double r = live ? 1.0 - n / tot : 0.0;
+  const double rn = r * nu;  // zero past the end
+  // the lane's terms, column k: 0 the Poisson term, 1 d/dmu (sample 0),
+  // 2 + j: r nu L_j (the sign of alpha_j is applied to the column's total)
   auto term = [&](int k) -> double {
     if (k == 0) return nllt;
-    if (k == 1) return (live && s == 0) ? r * base_nu : 0.0;
-    if (k < NS) {
-      const int j = k - 2;
-      return (a.theta[1 + j] >= 0.0 ? rn : -rn) * (double)Lv[j];
-    }
+    if (k == 1) return s == 0 ? r * base_nu : 0.0;
+    if (k < NS) return rn * (double)Lv[k - 2];
     return 0.0;
   };
-  // Transposed wavefront reduction of the 64 columns (NS used, the rest
-  // zero): in step d = 32, 16, ..., 1 a lane keeps the upper half of its
-  // current columns if (lane & d), the lower half otherwise, and adds the
-  // partner's (lane ^ d) copy of the half it keeps.  After six steps lane l
-  // holds the wavefront's sum of column l: 63 exchanges per lane instead of
-  // a reduction per column.  Fixed order, so the result is repeatable.
-  double v[32];
+  // Transposed reduction of the 64 columns.  Step 32: lanes 0-31 keep
+  // columns 0-31 and lanes 32-63 columns 32-63, each adding its partner's
+  // (lane ^ 32) copy of the half it keeps -- one cross-half swap per value
+  // and one add, no selects.  Step 16 likewise with rows (lane ^ 16).  Lane
+  // l then holds 16 columns (16 (l >> 4) + 0..15), each summed over the four
+  // lanes with the same l mod 16; those go through LDS, where thread
+  // (wave q, column c) adds the sixteen lanes of its column in wave q.  Fixed
+  // order throughout, so the result is repeatable.
+  double v[16];
   {
-    const bool up = (lane & 32) != 0;
+    double w32[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
-      const double lo = term(k), hi = term(k + 32);
-      const double other = up ? lo : hi;
-      v[k] = (up ? hi : lo) + __shfl_xor(other, 32);
+      double lo = term(k), hi = term(k + 32);
+      swap32(lo, hi);
+      w32[k] = lo + hi;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      double lo = w32[k], hi = w32[k + 16];
+      swap16(lo, hi);
+      v[k] = lo + hi;
     }
   }
+  {
+    double* row = &red[wid][lane * BN_RS];
 #pragma unroll
-  for (int h = 16; h >= 1; h >>= 1) {
-    const bool up = (lane & h) != 0;
-#pragma unroll
-    for (int k = 0; k < h; ++k) {
-      const double lo = v[k], hi = v[k + h];
-      const double other = up ? lo : hi;
-      v[k] = (up ? hi : lo) + __shfl_xor(other, h);
-    }
+    for (int k = 0; k < 16; ++k) row[k] = v[k];
   }
-  wsum[wid][lane] = v[0];
+  // each wavefront reads back only its own rows: the LDS serves a
+  // wavefront's accesses in order, so a wavefront-scope fence (no
+  // reordering by the compiler) suffices
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  {
+    // thread (wave wid, column lane): the sixteen lanes holding column lane
+    const int g4 = lane >> 4, k = lane & 15;
+    const double* col = &red[wid][(16 * g4) * BN_RS + k];
+    double h[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) h[i] = col[i * BN_RS];
+#pragma unroll
+    for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+      for (int i = 0; i < w; ++i) h[i] += h[i + w];
+    wsum[wid][lane] = h[0];
+  }
   __syncthreads();
   if (wid != 0) return;
   // the workgroup's partial of column lane, wavefronts in a fixed order
@@ -197,29 +242,33 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
     tk = (unsigned)__builtin_amdgcn_readfirstlane((int)tk);
     if (tk != (unsigned)(a.ngrp - 1)) return;
   }
-  // level 2: the group rows, BN_G at a time, in a fixed order
+  // level 2: the group rows, BN_G2 at a time (all loads of a pass in
+  // flight together), in a fixed order
   double fin = 0.0;
-  for (int g1 = 0; g1 < a.ngrp; g1 += BN_G) {
-    double x[BN_G];
+  for (int g1 = 0; g1 < a.ngrp; g1 += BN_G2) {
+    double x[BN_G2];
 #pragma unroll
-    for (int q = 0; q < BN_G; ++q) {
+    for (int q = 0; q < BN_G2; ++q) {
       const int gg = g1 + q < a.ngrp ? g1 + q : a.ngrp - 1;
       x[q] = __hip_atomic_load(&a.gpart[(int64_t)gg * 64 + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
-    for (int q = 0; q < BN_G; ++q) x[q] = g1 + q < a.ngrp ? x[q] : 0.0;
+    for (int q = 0; q < BN_G2; ++q) x[q] = g1 + q < a.ngrp ? x[q] : 0.0;
 #pragma unroll
-    for (int w = BN_G / 2; w >= 1; w >>= 1)
+    for (int w = BN_G2 / 2; w >= 1; w >>= 1)
 #pragma unroll
       for (int q = 0; q < w; ++q) x[q] += x[q + w];
     fin += x[0];
   }
   // the result: column 0 plus the constraint sum_j alpha_j^2 / 2, column 1,
-  // columns 2 + j plus alpha_j; written by the wavefront to the output and the
-  // host's mapped copy, then the completion word
-  double c2 = 0.0;
-  for (int j = 0; j < J; ++j) c2 += 0.5 * a.theta[1 + j] * a.theta[1 + j];
-  const double res = lane == 0 ? fin + c2 : (lane >= 2 && lane < NS ? fin + a.theta[lane - 1] : fin);
+  // columns 2 + j times sgn(alpha_j) plus alpha_j; written by the wavefront
+  // to the output and the host's mapped copy, then the completion word
+  double res = fin;
+  if (lane == 0) res = fin + a.cons;
+  if (lane >= 2 && lane < NS) {
+    const int j = lane - 2;
+    res = (((a.neg >> j) & 1ull) ? -fin : fin) + a.alpha[j];
+  }
   if (lane < NS) {
     a.out[lane] = res;
     if (a.hout) a.hout[lane] = res;
@@ -296,6 +345,8 @@ int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T, c
   const int Jp = padded_J(J);
   if (Jp < 0) return fail(RF_E_INVALID, "at most 62 nuisance parameters");
   const size_t nT = (size_t)C * S * B, nL = (size_t)C * Jp * B * S;
+  if (nL >= ((size_t)1 << 30) || nT >= ((size_t)1 << 31))
+    return fail(RF_E_INVALID, "tables too large (each +-1 sigma table must stay under 4 GiB)");
   std::vector<float> hT(nT), hLp(nL > 0 ? nL : 1, 0.f), hLm(nL > 0 ? nL : 1, 0.f), hn((size_t)C * B);
   for (int c = 0; c < C; ++c)
     for (int s = 0; s < S; ++s)
@@ -359,12 +410,22 @@ int binned_launch(rf_binned* b, const double* theta, void* stream, double* hout,
   if (!(theta[0] >= 0)) return fail(RF_E_DOMAIN, "signal strength must be >= 0");
   BinnedArgs a;
   memset(&a, 0, sizeof a);
-  a.T = b->T; a.Lp = b->Lp; a.Lm = b->Lm; a.nobs = b->nobs;
+  a.T = b->T; a.nobs = b->nobs;
   a.part = b->part; a.gpart = b->gpart; a.ticket = b->ticket; a.out = b->out;
   a.hout = hout; a.seq = seq;
   a.C = b->C; a.S = b->S; a.B = b->B; a.J = b->Jp; a.nblk = b->nblk; a.ngrp = b->ngrp;
-  a.theta[0] = theta[0];
-  for (int j = 0; j < b->J; ++j) a.theta[1 + j] = theta[1 + j];  // padded rows: alpha = 0
+  a.mu = theta[0];
+  while ((1 << a.logS) < b->S) ++a.logS;
+  const size_t row = (size_t)b->B * b->S;  // elements between the rows of two nuisance parameters
+  for (int j = 0; j < b->Jp; ++j) {
+    // padded rows: alpha = 0 (their table rows are zero)
+    const double al = j < b->J ? theta[1 + j] : 0.0;
+    a.alpha[j] = al;
+    a.absa[j] = std::fabs(al);
+    if (al < 0) a.neg |= 1ull << j;
+    a.L[j] = (al >= 0 ? b->Lp : b->Lm) + (size_t)j * row;
+    a.cons += 0.5 * al * al;
+  }
   hipLaunchKernelGGL(kernel_for(b->Jp), dim3(b->nblk), dim3(BN_BS), 0, (hipStream_t)stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "binned launch");
