@@ -268,6 +268,18 @@ int rf_hess_build(const rf_program* p);
  * info_out[4] = {n_iterations, n_evaluations, edm, converged(0/1)}. */
 int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, int32_t max_iter,
                 double* theta_out, double* sigma_out, double* info_out, void* stream);
+/* rf_fit_bfgs with two optional matrices (row-major P x P, host memory, may be
+ * NULL): hinv0, the initial inverse Hessian (symmetrised; its diagonal must be
+ * positive and finite, else RF_E_INVALID), in place of the one rf_fit_bfgs
+ * builds from P forward differences of the gradient -- e.g. the covariance of
+ * a fit of a cheaper model of the same data, which lets the exact fit start
+ * with that fit's curvature; cov_out, the covariance at the minimum (the
+ * inverse of the Hessian the uncertainties come from; NaN when that Hessian
+ * is not positive definite).  rf_fit_bfgs(...) is rf_fit_bfgs_ex with both
+ * NULL. */
+int rf_fit_bfgs_ex(rf_program* p, const double* theta0, const double* hinv0, double edm_tol,
+                   int32_t max_iter, double* theta_out, double* sigma_out, double* cov_out,
+                   double* info_out, void* stream);
 
 /* ---- binned template likelihood (HistFactory-like, Section 3) -------------- */
 /* C channels, S samples (sample 0 scaled by the signal strength mu), B bins,

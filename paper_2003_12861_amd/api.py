@@ -58,6 +58,7 @@ _SIGS = {
     "rf_nll_grad_async": ([_P, _DP, _P], _I32),
     "rf_program_result": ([_P], _P),
     "rf_fit_bfgs": ([_P, _DP, _D, _I32, _DP, _DP, _DP, _P], _I32),
+    "rf_fit_bfgs_ex": ([_P, _DP, _DP, _D, _I32, _DP, _DP, _DP, _DP, _P], _I32),
     "rf_gauss_legendre": ([_I32, _D, _D, _DP, _DP], _I32),
 }
 _OPTIONAL = {
@@ -360,6 +361,21 @@ class Program:
         check(rf_fit_bfgs(self.h, _dptr(th), edm_tol, max_iter, _dptr(out), _dptr(sig), _dptr(info), _stream(stream)))
         return out, sig, dict(iterations=int(info[0]), evaluations=int(info[1]), edm=float(info[2]),
                               converged=bool(info[3]))
+
+    def fit_ex(self, theta0, hinv0=None, edm_tol=1e-6, max_iter=1000, uncertainties=True, stream=None):
+        """fit() with an optional initial inverse Hessian (P x P).  Returns
+        (theta, sigma, cov, info); with uncertainties=False no Hessian is
+        formed at the minimum and sigma and cov are None."""
+        th = self._theta(theta0)
+        P = self.n_params
+        h0 = None if hinv0 is None else np.ascontiguousarray(np.asarray(hinv0, dtype=np.float64).reshape(P, P))
+        out, info = np.zeros(P), np.zeros(4)
+        sig, cov = (np.zeros(P), np.zeros((P, P))) if uncertainties else (None, None)
+        check(rf_fit_bfgs_ex(self.h, _dptr(th), None if h0 is None else _dptr(h0), edm_tol, max_iter, _dptr(out),
+                             None if sig is None else _dptr(sig), None if cov is None else _dptr(cov), _dptr(info),
+                             _stream(stream)))
+        return out, sig, cov, dict(iterations=int(info[0]), evaluations=int(info[1]), edm=float(info[2]),
+                                   converged=bool(info[3]))
 
 
 def compile_program(graph, top=None, precision=FP64, load=True, flags=0, weighted=False, validate=False):

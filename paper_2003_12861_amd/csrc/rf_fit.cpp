@@ -122,10 +122,23 @@ bool invert_spd(std::vector<double>& A, int n) {
 
 extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, int32_t max_iter,
                            double* theta_out, double* sigma_out, double* info_out, void* stream) {
+  return rf_fit_bfgs_ex(p, theta0, nullptr, edm_tol, max_iter, theta_out, sigma_out, nullptr, info_out, stream);
+}
+
+extern "C" int rf_fit_bfgs_ex(rf_program* p, const double* theta0, const double* hinv0, double edm_tol,
+                              int32_t max_iter, double* theta_out, double* sigma_out, double* cov_out,
+                              double* info_out, void* stream) {
   if (!p || !theta0 || !theta_out) return fail(RF_E_INVALID, "NULL argument");
   const int P = p->L.n_params;
   if (P == 0) return fail(RF_E_INVALID, "no parameters to fit");
   if (!(edm_tol > 0)) return fail(RF_E_INVALID, "edm_tol must be > 0");
+  // the caller's initial inverse Hessian: finite, with a positive diagonal
+  // (a covariance matrix); checked before anything runs
+  for (int i = 0; i < P && hinv0; ++i) {
+    if (!(hinv0[i * P + i] > 0)) return fail(RF_E_INVALID, "hinv0 must have a positive diagonal");
+    for (int j = 0; j < P; ++j)
+      if (!std::isfinite(hinv0[i * P + j])) return fail(RF_E_INVALID, "hinv0 is not finite");
+  }
   Eval ev{p, stream};
   std::vector<double> x(theta0, theta0 + P), g(P), xn(P), gn(P), H(P * P, 0.0), d(P), s(P), y(P), Hy(P);
   double f;
@@ -133,8 +146,11 @@ extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, 
   if (rc) return rc;
   const std::vector<double>& lo = p->L.plo;
   const std::vector<double>& hi = p->L.phi;
+  if (hinv0)
+    for (int i = 0; i < P; ++i)
+      for (int j = 0; j < P; ++j) H[i * P + j] = 0.5 * (hinv0[i * P + j] + hinv0[j * P + i]);
   // initial inverse Hessian from forward differences of the gradient
-  for (int k = 0; k < P; ++k) {
+  for (int k = 0; k < P && !hinv0; ++k) {
     const double span = std::isfinite(hi[k] - lo[k]) ? hi[k] - lo[k] : 1.0;
     double h = 1e-5 * span;
     if (x[k] + h > hi[k]) h = -h;
@@ -244,7 +260,7 @@ extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, 
   }
   conv = edm < edm_tol;
   for (int i = 0; i < P; ++i) theta_out[i] = x[i];
-  if (sigma_out) {
+  if (sigma_out || cov_out) {
     // the Hessian kernel where every leaf has second derivatives, else
     // central differences of the analytic gradient
     std::vector<double> Hf(P * P), gp(P), gm(P);
@@ -270,11 +286,11 @@ extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, 
     }
     for (int i = 0; i < P; ++i)
       for (int j = i + 1; j < P; ++j) Hf[i * P + j] = Hf[j * P + i] = 0.5 * (Hf[i * P + j] + Hf[j * P + i]);
-    if (good && invert_spd(Hf, P)) {
+    if (!(good && invert_spd(Hf, P))) Hf.assign((size_t)P * P, NAN);
+    if (sigma_out)
       for (int k = 0; k < P; ++k) sigma_out[k] = Hf[k * P + k] > 0 ? std::sqrt(Hf[k * P + k]) : NAN;
-    } else {
-      for (int k = 0; k < P; ++k) sigma_out[k] = NAN;
-    }
+    if (cov_out)
+      for (int k = 0; k < P * P; ++k) cov_out[k] = Hf[k];
   }
   if (info_out) {
     info_out[0] = it;

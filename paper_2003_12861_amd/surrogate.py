@@ -55,10 +55,10 @@ def to_bf16(w32):
     return w32.to(torch.bfloat16)
 
 
-def make_training_set(n, seed=7, K=1024, device="cuda"):
+def make_training_set(n, seed=7, K=1024, device="cuda", focus=None, frac_focus=0.0):
     """Sobol parameters, importance-sampled x, and the residual targets
     log p_sig (exact, FP64) - log b (the leaf's base), both on the GPU."""
-    raw = synth.surrogate_design(n, seed=seed)
+    raw = synth.surrogate_design(n, seed=seed, focus=focus, frac_focus=frac_focus)
     xq = torch.tensor(raw, dtype=torch.float64, device=device)
     y = api.mlp_targets(xq, K, synth.BWCB_WINDOW, synth.BWCB_RANGE)
     u = torch.tensor(normalise(raw), dtype=torch.float32, device=device)
@@ -66,10 +66,10 @@ def make_training_set(n, seed=7, K=1024, device="cuda"):
 
 
 def train_surrogate(n_train=2_000_000, epochs=60, batch=8192, lr=2e-3, lr_min=1e-5, seed=0, holdout=0.05,
-                    K=1024, log=None, device="cuda"):
+                    K=1024, log=None, device="cuda", focus=None, frac_focus=0.0):
     """Returns dict(w32, w_bf16, history, holdout_rms, holdout_max)."""
     torch.cuda.set_device(0) if device == "cuda" else None
-    u, y, _ = make_training_set(n_train, K=K, device=device)
+    u, y, _ = make_training_set(n_train, K=K, device=device, focus=focus, frac_focus=frac_focus)
     n_hold = int(holdout * n_train)
     u_tr, y_tr = u[n_hold:], y[n_hold:]
     u_ho, y_ho = u[:n_hold], y[:n_hold]
@@ -119,15 +119,21 @@ def _kernel_seconds(prog, theta, reps=20):
     return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e-3
 
 
-def seeded_fit(prog_surrogate, prog_exact, start, edm_tol=1e-6, max_iter=500):
+def seeded_fit(prog_surrogate, prog_exact, start, edm_tol=1e-6, max_iter=500, exact_uncertainties=True):
     """The surrogate as the fit's accelerator: minimise with the surrogate
-    from start, then with the exact convolution from the surrogate's minimum
-    (the exact path stays the judge and the fallback: the result is the exact
-    likelihood's minimum, reached with few exact evaluations).  Returns
-    dict(theta, sigma, info_surrogate, info_exact, theta_surrogate)."""
-    th_s, _, info_s = prog_surrogate.fit(start, edm_tol=edm_tol, max_iter=max_iter)
-    th, sig, info_e = prog_exact.fit(th_s, edm_tol=edm_tol, max_iter=max_iter)
-    return dict(theta=th, sigma=sig, info_surrogate=info_s, info_exact=info_e, theta_surrogate=th_s)
+    from start, then with the exact convolution from the surrogate's minimum,
+    starting with the surrogate fit's covariance as the inverse Hessian (the
+    exact path stays the judge and the fallback: the result is the exact
+    likelihood's minimum, reached with few exact evaluations).  With
+    exact_uncertainties=False the exact fit forms no Hessian at its minimum
+    and sigma is the surrogate fit's.  Returns dict(theta, sigma,
+    info_surrogate, info_exact, theta_surrogate)."""
+    th_s, sig_s, cov_s, info_s = prog_surrogate.fit_ex(start, edm_tol=edm_tol, max_iter=max_iter)
+    hinv0 = cov_s if np.all(np.isfinite(cov_s)) else None
+    th, sig, _, info_e = prog_exact.fit_ex(th_s, hinv0=hinv0, edm_tol=edm_tol, max_iter=max_iter,
+                                           uncertainties=exact_uncertainties)
+    return dict(theta=th, sigma=sig if exact_uncertainties else sig_s, info_surrogate=info_s, info_exact=info_e,
+                theta_surrogate=th_s)
 
 
 def experiment(epochs=600, n_train=2_000_000, n_events=10_000_000, seed=0, log=print, weights_out=None):

@@ -267,13 +267,20 @@ def _sample_cb_vec(rng, sigma, alpha, n, ylo, yhi):
     return out
 
 
-def surrogate_design(n, seed=7, box=BWCB_BOX, frac_signal=0.5, window=BWCB_WINDOW):
+def surrogate_design(n, seed=7, box=BWCB_BOX, frac_signal=0.5, window=BWCB_WINDOW, focus=None, frac_focus=0.0):
     """Training inputs of the surrogate: the five parameters from a scrambled
     Sobol sequence over the box; x drawn, for a fraction frac_signal of the
     rows, from the signal law at that row's parameters (Breit-Wigner plus
     Crystal Ball, redrawn until inside x's range) and uniformly otherwise, so
-    that the training points follow where events fall."""
+    that the training points follow where events fall.  With a focus box (a
+    sub-box of the parameters, same layout as box), a fraction frac_focus of
+    the rows takes its parameters from a second Sobol sequence over it, rows
+    of the two sequences interleaved in a seeded order."""
     q = sobol_design(n, seed=seed, box=box)
+    nf = int(round(frac_focus * n)) if focus is not None else 0
+    if nf > 0:
+        q[:nf, 1:] = sobol_design(nf, seed=seed + 101, box=focus)[:, 1:]
+        q = q[np.random.default_rng(seed + 2).permutation(n)]
     rng = np.random.default_rng(seed + 1)
     lo, hi = box[0]
     xs = rng.uniform(lo, hi, n)

@@ -178,6 +178,22 @@ def test_codegen_and_build_without_gpu(lib, prec):
     th = (ctypes.c_double * 5)(0, 1, 0.3, 0.2, -0.1)
     nll, g5, nb = ctypes.c_double(), (ctypes.c_double * 5)(), ctypes.c_int64()
     assert lib.rf_nll_grad(p, th, ctypes.byref(nll), g5, ctypes.byref(nb), None) == RF_E_STATE
+    # the fit's initial inverse Hessian is checked before anything runs: a
+    # non-positive or NaN diagonal entry or an infinite entry is refused; a
+    # good one gets as far as the first evaluation (not loaded: RF_E_STATE)
+    fit = lib.rf_fit_bfgs_ex
+    DP = ctypes.POINTER(ctypes.c_double)
+    fit.argtypes = [ctypes.c_void_p, DP, DP, ctypes.c_double, ctypes.c_int32, DP, DP, DP, DP, ctypes.c_void_p]
+    fit.restype = ctypes.c_int32
+    out, sig, info = (ctypes.c_double * 5)(), (ctypes.c_double * 5)(), (ctypes.c_double * 4)()
+    cov = (ctypes.c_double * 25)()
+    for i, j, v, rc in ((2, 2, -1.0, RF_E_INVALID), (0, 0, float("nan"), RF_E_INVALID),
+                        (1, 3, float("inf"), RF_E_INVALID), (1, 3, 0.5, RF_E_STATE)):
+        h0 = (ctypes.c_double * 25)(*[1.0 if a == b else 0.0 for a in range(5) for b in range(5)])
+        h0[5 * i + j] = v
+        assert fit(p, th, h0, 1e-6, 10, out, sig, cov, info, None) == rc, (i, j, v)
+        if rc == RF_E_INVALID:
+            assert b"hinv0" in lib.rf_last_error()
     lib.rf_program_free(p)
     g.free()
 
