@@ -462,19 +462,14 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
     __shared__ double res[NOUT];
     for (int j = lane; j < NOUT; j += 64) res[j] = 0.0;
     if (lane == 0) rf_epilogue<MODE>(fin, cst, a.theta, res, (unsigned)fin[NSUM]);
+    // each word of the host's copy by a system-scope store: the host polls
+    // the words themselves (it armed them with a pattern no result has)
     for (int j = lane; j < NOUT; j += 64) {
       const double v = res[j];
       a.out[j] = v;
-      if (a.hout) a.hout[j] = v;
+      if (a.hout) rf_store_host(a.hout + j, v);
     }
-    if (lane == 0) {
-      rf_reset_ticket(a.ticket);
-      if (a.hout) {
-        // the result is in host memory before the completion word the host polls for
-        __threadfence_system();
-        __hip_atomic_store((uint64_t*)(a.hout + NOUT), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
-    }
+    if (lane == 0) rf_reset_ticket(a.ticket);
   }
 }
 

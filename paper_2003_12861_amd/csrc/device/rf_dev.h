@@ -551,6 +551,10 @@ RF_DEV unsigned rf_take_ticket(unsigned* t) {
   return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 RF_DEV void rf_reset_ticket(unsigned* t) { __hip_atomic_store(t, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+// one result word into mapped host memory, whole and straight through to it
+RF_DEV void rf_store_host(double* h, double v) {
+  __hip_atomic_store((uint64_t*)h, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // TwoSum (Knuth): s + e == a + b exactly.
 RF_DEV void two_sum(double a, double b, double& s, double& e) {

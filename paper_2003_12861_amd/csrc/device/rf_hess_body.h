@@ -12,8 +12,8 @@
 // The per-event work is FP64 whatever the columns' dtype.  Reduction as in the
 // fused kernels, in a fixed order: per-thread FP64 sums -> wavefront sums ->
 // one partial per workgroup -> the last workgroup (atomic ticket) adds the
-// partials and writes [nll, grad[P], n_bad, hess[P * P]] to the output and to
-// the host's mapped copy, then the completion word.
+// partials and writes [nll, grad[P], n_bad, hess[P * P]] to the output and,
+// word by word with system-scope stores, to the host's mapped copy.
 #pragma once
 
 #define RF_NCOL1 (RF_NCOL > 0 ? RF_NCOL : 1)
@@ -90,14 +90,8 @@ extern "C" __global__ __launch_bounds__(RF_BS) void rf_k_hess(const RfArgs a) {
     for (int j = lane; j < NOUT; j += 64) {
       const double v = res[j];
       a.out[j] = v;
-      if (a.hout) a.hout[j] = v;
+      if (a.hout) rf_store_host(a.hout + j, v);
     }
-    if (lane == 0) {
-      rf_reset_ticket(a.ticket);
-      if (a.hout) {
-        __threadfence_system();
-        __hip_atomic_store((uint64_t*)(a.hout + NOUT), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
-    }
+    if (lane == 0) rf_reset_ticket(a.ticket);
   }
 }

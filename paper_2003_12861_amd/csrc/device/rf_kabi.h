@@ -20,8 +20,7 @@ struct RfArgs {
   const double* aux;             // auxiliary FP64 inputs (e.g. surrogate normalisation)
   const void* weights;           // MLP weights (bf16)
   double* hout;                  // optional copy of out in mapped host memory (or null),
-                                 // followed by a 64-bit completion word set to seq
-  uint64_t seq;
+                                 // written word by word with system-scope stores
   int32_t nblk_max;              // stride of part (>= gridDim.x)
   int32_t pad_;
   double theta[RF_MAX_PARAMS];   // parameter point

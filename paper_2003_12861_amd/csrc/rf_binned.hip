@@ -20,12 +20,13 @@
 // ~5e-7) would be amplified ~50x in the gradient.
 // Reduction (deterministic, in a fixed order): each lane holds its cell's 62
 // terms (the Poisson term, d/dmu, d/dalpha_j); a transposed wavefront
-// reduction leaves lane l with the wavefront's sum of column l (63 exchanges
-// per lane in six halving steps, instead of one 64-lane reduction per
-// column); the workgroup adds its four wavefronts and stores one row of 64
+// reduction (cross-half lane swaps, then an LDS pass) leaves one column per
+// lane; the workgroup adds its four wavefronts and stores one row of 64
 // columns (one coalesced store); the last workgroup of each group of BN_G
 // adds its group's rows, and the last group the group rows, one column per
-// lane -- all loads of a level in flight together.
+// lane -- all loads of a level in flight together.  (One level, the last
+// workgroup adding every row, measured slower: 160 KB of rows through one
+// compute unit take longer than the second ticket.)
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -35,8 +36,8 @@
 #include "device/rf_dev.h"
 #include "rf_internal.h"
 
-#define BN_BS 256
-#define BN_MAXJ 64  // layout of the mapped result copy (2 + BN_MAXJ values, then the completion word)
+#define BN_BSMAX 384  // workgroup size at most (chosen per model; its LDS stays under 64 KiB)
+#define BN_MAXJ 64  // nuisance parameters at most (the kernel's arrays)
 #define BN_G 16     // rows per reduction group
 #define BN_G2 32    // group rows per pass of the last level
 #define BN_RS 17    // LDS row stride (doubles) of a lane's 16 partial columns: conflict-free writes
@@ -53,13 +54,11 @@ struct BinnedArgs {
   double* gpart;       // [ngrp][64]: one row per group of BN_G workgroups
   unsigned* ticket;    // [0] global, [64 (1 + g)] group g
   double* out;         // [nll, grad[1+J]]
-  double* hout;        // optional copy in mapped host memory + completion word (or null)
-  uint64_t seq;
+  double* hout;        // optional copy in mapped host memory, written word by word (or null)
   uint64_t neg;        // bit j set: alpha_j < 0
   double mu, cons;     // signal strength; sum_j alpha_j^2 / 2
   int32_t C, S, B, J;
-  int32_t nblk, ngrp;
-  int32_t logS, pad_;
+  int32_t nblk, ngrp, logS, pad_;
   double alpha[BN_MAXJ];
 };
 
@@ -80,18 +79,22 @@ __device__ __forceinline__ void swap16(double& x, double& y) {
 }
 
 template <int J>
-__global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
+__global__ __launch_bounds__(BN_BSMAX) void rf_binned_kernel(const BinnedArgs a) {
   constexpr int NS = 2 + J;  // NLL, mu, alpha_1..J: one column each
   static_assert(NS <= 64, "one lane per column");
-  constexpr int NW = BN_BS / 64;
-  __shared__ double nu_s[BN_BS];
-  __shared__ double red[NW][64 * BN_RS];
-  __shared__ double wsum[NW][64];
+  const int NW = (int)blockDim.x / 64;  // wavefronts of this workgroup
+  // LDS (dynamic, sized by the host for this workgroup size): per wavefront
+  // a [64][BN_RS] table of partial columns and a row of column sums; the
+  // bins' totals when a bin spans wavefronts
+  extern __shared__ double lds[];
+  auto red = [&](int w) -> double* { return lds + (size_t)w * 64 * BN_RS; };
+  auto wsum = [&](int w) -> double* { return lds + (size_t)NW * 64 * BN_RS + 64 * w; };
+  double* const nu_s = lds + (size_t)NW * 64 * (BN_RS + 1);
   const int S = a.S;
   const uint32_t B = (uint32_t)a.B;
   // 32-bit cell indices (the host keeps C B S below 2^31); S is a power of
   // two (it divides the workgroup size)
-  const uint32_t t = blockIdx.x * BN_BS + threadIdx.x;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = t < (uint32_t)a.C * B * (uint32_t)S;
   const uint32_t tc = live ? t : 0u;
   const int s = (int)(tc & (uint32_t)(S - 1));
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
     }
   }
   {
-    double* row = &red[wid][lane * BN_RS];
+    double* row = &red(wid)[lane * BN_RS];
 #pragma unroll
     for (int k = 0; k < 16; ++k) row[k] = v[k];
   }
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   {
     // thread (wave wid, column lane): the sixteen lanes holding column lane
     const int g4 = lane >> 4, k = lane & 15;
-    const double* col = &red[wid][(16 * g4) * BN_RS + k];
+    const double* col = &red(wid)[(16 * g4) * BN_RS + k];
     double h[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) h[i] = col[i * BN_RS];
@@ -198,15 +201,14 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
     for (int w = 8; w >= 1; w >>= 1)
 #pragma unroll
       for (int i = 0; i < w; ++i) h[i] += h[i + w];
-    wsum[wid][lane] = h[0];
+    wsum(wid)[lane] = h[0];
   }
   __syncthreads();
   if (wid != 0) return;
   // the workgroup's partial of column lane, wavefronts in a fixed order
   {
     double p = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) p += wsum[w][lane];
+    for (int w = 0; w < NW; ++w) p += wsum(w)[lane];
     __hip_atomic_store(&a.part[(int64_t)blockIdx.x * 64 + lane], p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   rf_wait_stores();
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   }
   // the result: column 0 plus the constraint sum_j alpha_j^2 / 2, column 1,
   // columns 2 + j times sgn(alpha_j) plus alpha_j; written by the wavefront
-  // to the output and the host's mapped copy, then the completion word
+  // to the output and, word by word, to the host's mapped copy
   double res = fin;
   if (lane == 0) res = fin + a.cons;
   if (lane >= 2 && lane < NS) {
@@ -271,15 +273,9 @@ __global__ __launch_bounds__(BN_BS) void rf_binned_kernel(const BinnedArgs a) {
   }
   if (lane < NS) {
     a.out[lane] = res;
-    if (a.hout) a.hout[lane] = res;
+    if (a.hout) rf_store_host(a.hout + lane, res);
   }
-  if (lane == 0) {
-    rf_reset_ticket(a.ticket);
-    if (a.hout) {
-      __threadfence_system();
-      __hip_atomic_store((uint64_t*)(a.hout + 2 + BN_MAXJ), a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-  }
+  if (lane == 0) rf_reset_ticket(a.ticket);
 }
 
 // kernel instances: the number of nuisance parameters is a template
@@ -313,10 +309,9 @@ struct rf_binned {
   int C, S, B, J, Jp;  // Jp: compiled table depth (>= J, extra rows are zero)
   float *T = nullptr, *Lp = nullptr, *Lm = nullptr, *nobs = nullptr;
   double *part = nullptr, *gpart = nullptr, *out = nullptr;
-  double *h_out = nullptr, *d_hout = nullptr;  // mapped result copy [2 + BN_MAXJ] + completion word
+  double *h_out = nullptr, *d_hout = nullptr;  // mapped result copy [2 + BN_MAXJ]
   unsigned* ticket = nullptr;
-  int nblk = 0, ngrp = 0;
-  uint64_t seq = 0;
+  int nblk = 0, ngrp = 0, bs = 256;  // workgroups, groups of BN_G, workgroup size
 };
 
 using namespace rf;
@@ -341,7 +336,7 @@ int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T, c
                   const double* Tm, const double* nobs, void* stream, rf_binned** out) {
   if (!out || !T || !nobs || (J > 0 && (!Tp || !Tm))) return fail(RF_E_INVALID, "NULL argument");
   if (C < 1 || S < 1 || B < 1 || J < 0) return fail(RF_E_INVALID, "bad shape");
-  if (BN_BS % S != 0) return fail(RF_E_INVALID, "the number of samples must divide 256");
+  if (256 % S != 0) return fail(RF_E_INVALID, "the number of samples must divide 256");
   const int Jp = padded_J(J);
   if (Jp < 0) return fail(RF_E_INVALID, "at most 62 nuisance parameters");
   const size_t nT = (size_t)C * S * B, nL = (size_t)C * Jp * B * S;
@@ -369,8 +364,21 @@ int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T, c
   rf_binned* bn = new rf_binned();
   bn->C = C; bn->S = S; bn->B = B; bn->J = J; bn->Jp = Jp;
   const int64_t threads = (int64_t)C * B * S;
-  bn->nblk = (int)((threads + BN_BS - 1) / BN_BS);
-  bn->ngrp = (bn->nblk + BN_G - 1) / BN_G;
+  // workgroup size: enough threads that the workgroups fit the compute units
+  // in one round (one each: no unit gets a second workgroup while others
+  // idle), a multiple of 64 and of S (a bin never straddles two
+  // workgroups), at most BN_BSMAX
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    const int unit = S > 64 ? S : 64;
+    int64_t per = (threads + cus - 1) / cus;
+    per = (per + unit - 1) / unit * unit;
+    bn->bs = (int)(per < unit ? unit : (per > BN_BSMAX ? BN_BSMAX : per));
+    if (bn->bs % unit) bn->bs = 256;  // (S = 256: 256 divides no larger size allowed)
+  }
+  bn->nblk = (int)((threads + bn->bs - 1) / bn->bs);
   hipError_t e;
   hipStream_t st = (hipStream_t)stream;
   auto up = [&](float** d, const std::vector<float>& h) -> hipError_t {
@@ -383,9 +391,10 @@ int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T, c
     rf_binned_free(bn);
     return hip_fail(e, "binned upload");
   }
+  bn->ngrp = (bn->nblk + BN_G - 1) / BN_G;
   const size_t NS = 64;  // one row of 64 columns per workgroup and group
   const size_t nticket = (size_t)64 * (1 + bn->ngrp);
-  const size_t nhout = 2 + BN_MAXJ + 1;
+  const size_t nhout = 2 + BN_MAXJ;
   if ((e = hipMalloc(&bn->part, sizeof(double) * NS * bn->nblk)) != hipSuccess ||
       (e = hipMalloc(&bn->gpart, sizeof(double) * NS * bn->ngrp)) != hipSuccess ||
       (e = hipMalloc(&bn->out, sizeof(double) * (2 + Jp))) != hipSuccess ||
@@ -403,7 +412,7 @@ int rf_binned_new(int32_t C, int32_t S, int32_t B, int32_t J, const double* T, c
 }
 
 namespace {
-int binned_launch(rf_binned* b, const double* theta, void* stream, double* hout, uint64_t seq) {
+int binned_launch(rf_binned* b, const double* theta, void* stream, double* hout) {
   if (!b || !theta) return fail(RF_E_INVALID, "NULL argument");
   for (int k = 0; k <= b->J; ++k)
     if (!std::isfinite(theta[k])) return fail(RF_E_DOMAIN, "theta must be finite");
@@ -412,7 +421,7 @@ int binned_launch(rf_binned* b, const double* theta, void* stream, double* hout,
   memset(&a, 0, sizeof a);
   a.T = b->T; a.nobs = b->nobs;
   a.part = b->part; a.gpart = b->gpart; a.ticket = b->ticket; a.out = b->out;
-  a.hout = hout; a.seq = seq;
+  a.hout = hout;
   a.C = b->C; a.S = b->S; a.B = b->B; a.J = b->Jp; a.nblk = b->nblk; a.ngrp = b->ngrp;
   a.mu = theta[0];
   while ((1 << a.logS) < b->S) ++a.logS;
@@ -426,7 +435,8 @@ int binned_launch(rf_binned* b, const double* theta, void* stream, double* hout,
     a.L[j] = (al >= 0 ? b->Lp : b->Lm) + (size_t)j * row;
     a.cons += 0.5 * al * al;
   }
-  hipLaunchKernelGGL(kernel_for(b->Jp), dim3(b->nblk), dim3(BN_BS), 0, (hipStream_t)stream, a);
+  const size_t lds = sizeof(double) * ((size_t)(b->bs / 64) * 64 * (BN_RS + 1) + b->bs);
+  hipLaunchKernelGGL(kernel_for(b->Jp), dim3(b->nblk), dim3(b->bs), lds, (hipStream_t)stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "binned launch");
   return RF_OK;
@@ -434,18 +444,18 @@ int binned_launch(rf_binned* b, const double* theta, void* stream, double* hout,
 }  // namespace
 
 int rf_binned_nll_grad_async(rf_binned* b, const double* theta, void* stream) {
-  return binned_launch(b, theta, stream, nullptr, 0);
+  return binned_launch(b, theta, stream, nullptr);
 }
 
 int rf_binned_nll_grad(rf_binned* b, const double* theta, double* nll, double* grad, void* stream) {
   if (!nll || !grad) return fail(RF_E_INVALID, "NULL argument");
   if (!b) return fail(RF_E_INVALID, "NULL argument");
-  // the last workgroup writes the result into mapped host memory, then the
-  // completion word this call polls for
-  const uint64_t seq = ++b->seq;
-  int rc = binned_launch(b, theta, stream, b->d_hout, seq);
+  // the last workgroup writes the result into mapped host memory, word by
+  // word; this call polls the words
+  arm_result(b->h_out, 2 + b->Jp);
+  int rc = binned_launch(b, theta, stream, b->d_hout);
   if (rc) return rc;
-  rc = wait_result((volatile uint64_t*)(b->h_out + 2 + BN_MAXJ), seq, stream, nullptr);
+  rc = wait_result(b->h_out, 2 + b->Jp, stream, nullptr);
   if (rc) return rc;
   *nll = b->h_out[0];
   for (int k = 0; k <= b->J; ++k) grad[k] = b->h_out[1 + k];

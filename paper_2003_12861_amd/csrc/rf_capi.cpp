@@ -136,30 +136,40 @@ int ready(rf_program* p, const double* theta) {
 int run_sync(rf_program* p, hipFunction_t f, const double* theta, void* stream) {
   RfArgs a;
   fill_args(p, theta, a);
-  // the last workgroup also writes the result into the mapped host buffer,
-  // then the completion word: poll it (a short call returns as soon as the
-  // kernel's last workgroup is done), falling back to a stream
-  // synchronisation after 20 ms (long calls, and errors)
+  // the last workgroup also writes the result into the mapped host buffer:
+  // poll it (a short call returns as soon as the kernel's last workgroup is
+  // done), falling back to a stream synchronisation after 20 ms
   a.hout = p->d_hout;
-  a.seq = ++p->seq;
-  volatile uint64_t* done = (volatile uint64_t*)(p->h_out + out_len(p));
+  arm_result(p->h_out, out_len(p));
   int rc = launch(p, f, a, stream);
   if (rc) return rc;
   p->n_sync++;
-  return wait_result(done, a.seq, stream, &p->n_slow);
+  return wait_result(p->h_out, out_len(p), stream, &p->n_slow);
 }
 
 }  // namespace
 
 namespace rf {
-int wait_result(volatile uint64_t* done, uint64_t seq, void* stream, int64_t* slow) {
+void arm_result(double* h, int n) {
+  volatile uint64_t* w = (volatile uint64_t*)h;
+  for (int j = 0; j < n; ++j) w[j] = RF_SENTINEL;
+  std::atomic_thread_fence(std::memory_order_release);
+}
+
+int wait_result(const double* h, int n, void* stream, int64_t* slow) {
+  volatile const uint64_t* w = (volatile const uint64_t*)h;
+  auto arrived = [&]() {
+    for (int j = n - 1; j >= 0; --j)
+      if (w[j] == RF_SENTINEL) return false;
+    return true;
+  };
   const auto t0 = std::chrono::steady_clock::now();
-  while (*done != seq) {
+  while (!arrived()) {
     if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
       if (slow) ++*slow;
       hipError_t e = hipStreamSynchronize((hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-      if (*done != seq) return fail(RF_E_DEVICE, "kernel completed without writing its result");
+      if (!arrived()) return fail(RF_E_DEVICE, "kernel completed without writing its result");
       break;
     }
   }
@@ -304,11 +314,11 @@ int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols, 
     if ((e = hipMalloc(&p->d_part, sizeof(double) * np)) != hipSuccess) return unbind(hip_fail(e, "hipMalloc partials"));
     if ((e = hipMalloc(&p->d_ticket, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return unbind(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&p->d_out, sizeof(double) * out_len(p))) != hipSuccess) return unbind(hip_fail(e, "hipMalloc"));
-    // result copy + completion word
-    if ((e = hipHostMalloc(&p->h_out, sizeof(double) * (out_len(p) + 1), hipHostMallocMapped | hipHostMallocCoherent)) !=
+    // mapped host copy of the result
+    if ((e = hipHostMalloc(&p->h_out, sizeof(double) * out_len(p), hipHostMallocMapped | hipHostMallocCoherent)) !=
         hipSuccess)
       return unbind(hip_fail(e, "hipHostMalloc"));
-    memset(p->h_out, 0, sizeof(double) * (out_len(p) + 1));
+    memset(p->h_out, 0, sizeof(double) * out_len(p));
     if ((e = hipHostGetDevicePointer((void**)&p->d_hout, p->h_out, 0)) != hipSuccess)
       return unbind(hip_fail(e, "hipHostGetDevicePointer"));
     if ((e = hipMemset(p->d_ticket, 0, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return unbind(hip_fail(e, "hipMemset"));
@@ -543,10 +553,10 @@ int rf_nll_grad_hess(rf_program* p, const double* theta, double* nll, double* gr
     if ((e = hipMalloc(&h.ticket, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMemset(h.ticket, 0, sizeof(unsigned) * RF_TICKET_WORDS)) != hipSuccess) return hip_fail(e, "hipMemset");
     if ((e = hipMalloc(&h.out, sizeof(double) * nout)) != hipSuccess) return hip_fail(e, "hipMalloc");
-    if ((e = hipHostMalloc(&h.h_out, sizeof(double) * (nout + 1), hipHostMallocMapped | hipHostMallocCoherent)) !=
+    if ((e = hipHostMalloc(&h.h_out, sizeof(double) * nout, hipHostMallocMapped | hipHostMallocCoherent)) !=
         hipSuccess)
       return hip_fail(e, "hipHostMalloc");
-    memset(h.h_out, 0, sizeof(double) * (nout + 1));
+    memset(h.h_out, 0, sizeof(double) * nout);
     if ((e = hipHostGetDevicePointer((void**)&h.d_hout, h.h_out, 0)) != hipSuccess)
       return hip_fail(e, "hipHostGetDevicePointer");
   }
@@ -569,13 +579,13 @@ int rf_nll_grad_hess(rf_program* p, const double* theta, double* nll, double* gr
   a.ticket = h.ticket;
   a.out = h.out;
   a.hout = h.d_hout;
-  a.seq = ++h.seq;
+  arm_result(h.h_out, nout);
   size_t sz = sizeof(RfArgs);
   void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &sz, HIP_LAUNCH_PARAM_END};
   if ((e = hipModuleLaunchKernel(h.k, (unsigned)G, 1, 1, p->block, 1, 1, 0, (hipStream_t)stream, nullptr, cfg)) !=
       hipSuccess)
     return hip_fail(e, "rf_k_hess launch");
-  if ((rc = wait_result((volatile uint64_t*)(h.h_out + nout), a.seq, stream, nullptr))) return rc;
+  if ((rc = wait_result(h.h_out, nout, stream, nullptr))) return rc;
   const int64_t bad = (int64_t)h.h_out[P + 1];
   if (n_bad) *n_bad = bad;
   *nll = bad ? INFINITY : h.h_out[0];

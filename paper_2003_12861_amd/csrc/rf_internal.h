@@ -93,9 +93,15 @@ int load_module(const std::string& path, bool f32, Module& m);  // f32: FP32 for
 uint64_t fnv1a(const std::string& s);
 std::string cache_dir();
 
-// wait for a result whose last writer sets *done = seq (mapped host memory):
-// poll, then fall back to a stream synchronisation after 20 ms
-int wait_result(volatile uint64_t* done, uint64_t seq, void* stream, int64_t* slow);
+// Synchronous results in mapped host memory: before a launch the host fills
+// the n result words with RF_SENTINEL, a signalling-NaN pattern that no kernel
+// result has (FP64 arithmetic produces only quiet NaNs); the kernel's last
+// workgroup writes each word with a system-scope store; the host polls until
+// no word holds the sentinel (every aligned 8-byte word arrives whole).  After
+// 20 ms it synchronises the stream instead (long calls, errors).
+constexpr uint64_t RF_SENTINEL = 0x7FF4D1CE5EED0001ull;
+void arm_result(double* h, int n);
+int wait_result(const double* h, int n, void* stream, int64_t* slow);
 
 // host-side domain checks of a parameter point
 int check_theta(const Lowered& L, const double* theta);
@@ -145,7 +151,6 @@ struct rf_program {
   int tg = 16;      // ticket groups of the end-of-kernel hand-off (compile-time)
   int prio = 1;     // wavefront issue-priority policy of the event loop (compile-time)
   int resident = 4; // workgroups of the gradient kernel one CU holds at once (occupancy query)
-  uint64_t seq = 0; // completion sequence number of synchronous calls
   int64_t n_sync = 0, n_slow = 0;  // synchronous calls; those whose wait fell back to a stream sync
   int blocks_override = 0;
   uint32_t flags = 0;  // RF_COMPILE_* / RF_VALIDATE given to rf_compile
@@ -180,8 +185,7 @@ struct rf_program {
     int part_n = 0;
     unsigned* ticket = nullptr;
     double* out = nullptr;     // [nll, grad[P], n_bad, hess[P * P]]
-    double* h_out = nullptr;   // mapped host copy, then the completion word
+    double* h_out = nullptr;   // mapped host copy
     double* d_hout = nullptr;
-    uint64_t seq = 0;
   } hes;
 };
