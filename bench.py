@@ -65,15 +65,18 @@ VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9  # 3.93e13
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_TFLOPS = 2500.0  # dense
 
-# Algorithmic VALU lane-slots per event of an NLL+gradient evaluation (a
-# transcendental counts 4: the quarter-rate unit), and bytes read per event.
+# VALU lane-slots per event of an NLL+gradient evaluation, and bytes read per
+# event.  FP32: the algorithmic count (a transcendental counts 4: the
+# quarter-rate unit).  FP64: the VALU instructions per event the hardware
+# counters measured (SQ_INSTS_VALU x 64 / events), since the FP64 exp and log
+# are instruction sequences whose length is the work.
 SLOTS = {
-    "gauss_cheb_1e7": {"fp32": 48, "fp64": 90},
+    "gauss_cheb_1e7": {"fp32": 48, "fp64": 103},
     # weights: one more multiply on log p and one on 1/p
-    "gauss_cheb_weighted_1e7": {"fp32": 50, "fp64": 92},
+    "gauss_cheb_weighted_1e7": {"fp32": 50, "fp64": 105},
     # extended: the same per-event program (the yield term is parameter-only)
-    "gauss_cheb_extended_1e7": {"fp32": 48, "fp64": 90},
-    "decay_argus_5e7": {"fp32": 165, "fp64": 400},
+    "gauss_cheb_extended_1e7": {"fp32": 48, "fp64": 103},
+    "decay_argus_5e7": {"fp32": 165, "fp64": 341},
     # the 1-D mixture's work, two Poisson leaves (an LDS table read each:
     # index, clamp, conversion) and the two products' adjoint terms
     "poisson_gauss_cheb_1e7": {"fp32": 68, "fp64": 112},
@@ -107,6 +110,13 @@ def measured_traffic(workload, kernel, source):
         if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha1") == sha:
             return float(kv["bytes_per_launch"])
     return None
+
+
+def binned_source():
+    """The binned kernel's sources (it is built into the library, not
+    generated): the key under which its counter summary is valid."""
+    d = os.path.join(ROOT, "paper_2003_12861_amd", "csrc")
+    return "".join(open(os.path.join(d, f)).read() for f in ("rf_binned.hip", os.path.join("device", "rf_dev.h")))
 
 
 def measured_ceiling(name):
@@ -290,7 +300,9 @@ def run_binned(args, torch, stream):
                    "median_step_ms": r["median_step_s"] * 1e3, **check},
         "roofline": {"bound": "hbm", "kernel": "rf_binned_kernel<60>", "achieved": nbytes / k / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nbytes / k / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": nbytes},
+                     "traffic": measured_traffic(args.workload, "rf_binned_kernel<60>", binned_source()),
+                     "source_sha1": hashlib.sha1(binned_source().encode()).hexdigest(),
+                     "bytes_per_launch": nbytes},
         "cpu_baseline": cpu,
     }
     sbw = measured_ceiling("stream_read_bytes")
