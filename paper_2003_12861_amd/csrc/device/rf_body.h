@@ -242,6 +242,13 @@ template <int MODE> RF_DEV void rf_body(const RfArgs& a) {
     const int64_t MB = ng >= base0 + RF_BS ? (ng - base0 - RF_BS) / gstep + 1 : 0;
     auto tile = [&](int64_t m) { return base0 + (m < MB ? m : MB - 1) * gstep; };  // uniform
     RF_T xb[D][RF_NCOL1][RF_EPT];
+#if RF_PRIO
+    // the prologue at the highest issue priority: the waves of the
+    // workgroups already in their event loops run at it too (see
+    // rf_prio_remaining), and a later workgroup's prologue at the default
+    // priority waited behind them for up to 9 us
+    __builtin_amdgcn_s_setprio(3);
+#endif
     // the ring's first loads are issued before the prologue so that their
     // latency overlaps the FP64 normalisation work
     if (MB > 0) {

@@ -194,6 +194,31 @@ static constexpr double RF_INV_SQRT2PI = 0.39894228040143267794;
 // N = sigma sqrt(pi/2) [erf(zb) - erf(za)], z = (y - mu)/(sqrt2 sigma);
 // dN/dmu = u(lo) - u(hi);  dN/dsigma = (N - (hi-mu) u(hi) + (lo-mu) u(lo)) / sigma.
 enum { GAUSS_NC = 5 };
+// The same on two lanes of one wavefront (lanes l and l + 32, `upper` true on
+// the second): each lane evaluates the error function and the exponential at
+// its own end of the range, the partner's values come by a lane exchange, and
+// the first lane writes the block -- the two library calls of each kind run
+// side by side instead of one after the other (the prologue is on every
+// workgroup's path to its event loop).
+RF_DEV void gauss_prologue2(const double* in, double lo, double hi, double* C, bool upper) {
+  const double mu = in[0], s = in[1];
+  const double z = ((upper ? hi : lo) - mu) / (RF_SQRT2 * s);
+  // the same branch on both lanes: erfc where the range lies on one side of
+  // mu (no cancellation), erf where it straddles mu
+  const int kase = lo >= mu ? 0 : (hi <= mu ? 1 : 2);
+  const double F = kase == 0 ? ::erfc(z) : (kase == 1 ? ::erfc(-z) : ::erf(z));
+  const double e = ::exp(-z * z);
+  const double Fo = __shfl_xor(F, 32), eo = __shfl_xor(e, 32);
+  if (upper) return;
+  const double diff = kase == 0 ? F - Fo : Fo - F;  // F at lo, Fo at hi
+  const double N = s * (0.5 * RF_SQRT2PI) * diff;
+  const double ea = e, eb = eo;
+  C[0] = 1.0 / N;
+  C[1] = (ea - eb) / N;
+  C[2] = (N - (hi - mu) * eb + (lo - mu) * ea) / (s * N);
+  C[3] = mu;
+  C[4] = 1.0 / s;
+}
 RF_DEV void gauss_prologue(const double* in, double lo, double hi, double* C) {
   const double mu = in[0], s = in[1];
   const double za = (lo - mu) / (RF_SQRT2 * s), zb = (hi - mu) / (RF_SQRT2 * s);

@@ -312,6 +312,8 @@ struct rf_binned {
   double *h_out = nullptr, *d_hout = nullptr;  // mapped result copy [2 + BN_MAXJ]
   unsigned* ticket = nullptr;
   int nblk = 0, ngrp = 0, bs = 256;  // workgroups, groups of BN_G, workgroup size
+  void* last_stream = nullptr;        // stream of the previous launch (see order_launch)
+  bool launched = false;
 };
 
 using namespace rf;
@@ -417,6 +419,7 @@ int binned_launch(rf_binned* b, const double* theta, void* stream, double* hout)
   for (int k = 0; k <= b->J; ++k)
     if (!std::isfinite(theta[k])) return fail(RF_E_DOMAIN, "theta must be finite");
   if (!(theta[0] >= 0)) return fail(RF_E_DOMAIN, "signal strength must be >= 0");
+  if (int rc = order_launch(b->last_stream, b->launched, stream)) return rc;
   BinnedArgs a;
   memset(&a, 0, sizeof a);
   a.T = b->T; a.nobs = b->nobs;

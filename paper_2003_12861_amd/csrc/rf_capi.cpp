@@ -112,7 +112,9 @@ int pre_launch(rf_program* p, const double* theta, void* stream) {
 }
 
 int launch(rf_program* p, hipFunction_t f, RfArgs& a, void* stream) {
-  int rc = pre_launch(p, a.theta, stream);
+  int rc = order_launch(p->last_stream, p->launched, stream);
+  if (rc) return rc;
+  rc = pre_launch(p, a.theta, stream);
   if (rc) return rc;
   size_t sz = sizeof(RfArgs);
   void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &sz, HIP_LAUNCH_PARAM_END};
@@ -150,6 +152,16 @@ int run_sync(rf_program* p, hipFunction_t f, const double* theta, void* stream) 
 }  // namespace
 
 namespace rf {
+int order_launch(void*& last, bool& launched, void* stream) {
+  if (launched && last != stream) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)last);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (previous stream)");
+  }
+  last = stream;
+  launched = true;
+  return RF_OK;
+}
+
 void arm_result(double* h, int n) {
   volatile uint64_t* w = (volatile uint64_t*)h;
   for (int j = 0; j < n; ++j) w[j] = RF_SENTINEL;
@@ -579,6 +591,7 @@ int rf_nll_grad_hess(rf_program* p, const double* theta, double* nll, double* gr
   a.ticket = h.ticket;
   a.out = h.out;
   a.hout = h.d_hout;
+  if ((rc = order_launch(p->last_stream, p->launched, stream))) return rc;
   arm_result(h.h_out, nout);
   size_t sz = sizeof(RfArgs);
   void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &sz, HIP_LAUNCH_PARAM_END};

@@ -403,6 +403,9 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
   emit_paramlike(o, L, "  ");
   int item = 0;
   const int NW = BS / 64;
+  int n_items = 0;  // prologue items: leaves and sums without block-wide prologues
+  for (int id = 0; id < N; ++id)
+    if (L.reach[id] && (is_leaf(g[id].op) || g[id].op == RF_OP_ADD_PDF) && !blockwide(g[id])) ++n_items;
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
     const Node& n = g[id];
@@ -410,6 +413,16 @@ std::string generate_source(const Lowered& L, int BS, int ept, int pfd, int tg, 
     if (blockwide(n)) continue;
     const int tid = 64 * (item % NW) + item / NW;
     ++item;
+    if (n.op == RF_OP_GAUSS && n_items <= 32 * NW) {
+      // two lanes of the wavefront (tid and tid + 32; with at most 32 items
+      // per wavefront, lane tid + 32 is no other item's)
+      o << "  if (tid == " << tid << " || tid == " << tid + 32 << ") {\n    const double in[] = {";
+      for (size_t j = 1; j < n.in.size(); ++j) o << (j > 1 ? ", " : "") << "pv" << n.in[j];
+      const Node& ob = g[n.in[0]];
+      o << "};\n    gauss_prologue2(in, " << dstr(ob.lo) << ", " << dstr(ob.hi) << ", cst + " << L.cst_off[id]
+        << ", tid == " << tid + 32 << ");\n  }\n";
+      continue;
+    }
     o << "  if (tid == " << tid << ") {\n";
     if (is_leaf(n.op)) {
       o << "    const double in[] = {";
@@ -762,12 +775,25 @@ std::string generate_hess_source(const Lowered& L, int BS) {
   emit_paramlike(o, L, "  ");
   int item = 0;
   const int NW = BS / 64;
+  int n_items = 0;  // prologue items: leaves and sums without block-wide prologues
+  for (int id = 0; id < N; ++id)
+    if (L.reach[id] && (is_leaf(g[id].op) || g[id].op == RF_OP_ADD_PDF) && !blockwide(g[id])) ++n_items;
   for (int id = 0; id < N; ++id) {
     if (!L.reach[id]) continue;
     const Node& n = g[id];
     if (!is_leaf(n.op) && n.op != RF_OP_ADD_PDF) continue;
     const int tid = 64 * (item % NW) + item / NW;
     ++item;
+    if (n.op == RF_OP_GAUSS && n_items <= 32 * NW) {
+      // two lanes of the wavefront (tid and tid + 32; with at most 32 items
+      // per wavefront, lane tid + 32 is no other item's)
+      o << "  if (tid == " << tid << " || tid == " << tid + 32 << ") {\n    const double in[] = {";
+      for (size_t j = 1; j < n.in.size(); ++j) o << (j > 1 ? ", " : "") << "pv" << n.in[j];
+      const Node& ob = g[n.in[0]];
+      o << "};\n    gauss_prologue2(in, " << dstr(ob.lo) << ", " << dstr(ob.hi) << ", cst + " << L.cst_off[id]
+        << ", tid == " << tid + 32 << ");\n  }\n";
+      continue;
+    }
     o << "  if (tid == " << tid << ") {\n";
     if (is_leaf(n.op)) {
       o << "    const double in[] = {";

@@ -102,6 +102,9 @@ std::string cache_dir();
 constexpr uint64_t RF_SENTINEL = 0x7FF4D1CE5EED0001ull;
 void arm_result(double* h, int n);
 int wait_result(const double* h, int n, void* stream, int64_t* slow);
+// before a launch on `stream`: wait for the previous launch's stream if it was
+// another one (kernels of one program share their ticket words)
+int order_launch(void*& last, bool& launched, void* stream);
 
 // host-side domain checks of a parameter point
 int check_theta(const Lowered& L, const double* theta);
@@ -152,6 +155,11 @@ struct rf_program {
   int prio = 1;     // wavefront issue-priority policy of the event loop (compile-time)
   int resident = 4; // workgroups of the gradient kernel one CU holds at once (occupancy query)
   int64_t n_sync = 0, n_slow = 0;  // synchronous calls; those whose wait fell back to a stream sync
+  // stream of the previous launch: a launch on another stream first waits for
+  // it (the previous kernel's last workgroup resets the ticket words after
+  // writing the result a synchronous call returns on)
+  void* last_stream = nullptr;
+  bool launched = false;
   int blocks_override = 0;
   uint32_t flags = 0;  // RF_COMPILE_* / RF_VALIDATE given to rf_compile
   // binding

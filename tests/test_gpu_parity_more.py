@@ -192,3 +192,29 @@ def test_nll_function_autograd(prec, device):
     theta.grad = None
     (upstream * api.NLLFunction.apply(theta, prog) + api.NLLFunction.apply(theta, prog)).backward()
     np.testing.assert_allclose(theta.grad.cpu().numpy(), (upstream + 1.0) * k_g, rtol=1e-15, atol=0)
+
+
+def test_calls_alternating_between_streams():
+    """Synchronous calls of one program (and of the binned model) that switch
+    streams from call to call: each launch waits for the previous stream, so
+    the ticket words the kernels share are never taken before the previous
+    kernel has reset them; every call gives the first call's result bit for
+    bit."""
+    print("case alternating streams", flush=True)
+    x = synth.sample_gauss_cheb(1_000_000, 5)
+    prog, _ = build_pair(workloads.spec_gauss_cheb(), api.FP32, api)
+    prog.bind(to_dev([x], api.FP32, api))
+    th = [0.01, 0.98, 0.31, 0.19, -0.09]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.current_stream()]
+    ref = prog.nll_grad(th, stream=streams[0])
+    for i in range(60):
+        nll, g, nb = prog.nll_grad(th, stream=streams[i % 3])
+        assert nll == ref[0] and np.array_equal(g, ref[1]) and nb == 0, (i, nll, ref[0])
+    d = synth.make_binned(6, 20, 4, 30, 8)
+    bn = api.Binned(d["T"], d["Tp"], d["Tm"], d["nobs"])
+    tb = np.concatenate([[1.02], np.linspace(-0.4, 0.4, 8)])
+    rb = bn.nll_grad(tb, stream=streams[0])
+    for i in range(60):
+        nll, g = bn.nll_grad(tb, stream=streams[i % 3])
+        assert nll == rb[0] and np.array_equal(g, rb[1]), (i, nll, rb[0])
+    torch.cuda.synchronize()
