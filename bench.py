@@ -238,14 +238,20 @@ def pipelined_kernel(call_async, thetas, reps, torch, stream):
 
 
 def time_path(call, call_async, thetas, args, torch, stream):
+    """The kernel's own time first (200 back-to-back launches, then 20
+    isolated ones), then the W warm-up steps and the K timed synchronous
+    steps.  On a freshly started process the GPU reaches its working clocks
+    only after a few milliseconds of work: measured in that order, a 20-step
+    run times the path at the speed it runs in a fit."""
+    pipelined_kernel(call_async, thetas, 20, torch, stream)  # lead-in, not used
+    kern_s = pipelined_kernel(call_async, thetas, 200, torch, stream)
+    iso_s = isolated_kernel(call_async, thetas, 20, torch, stream)
     gc.collect()
     gc.disable()
     for i in range(args.warmup):
         call(thetas[i % len(thetas)])
     step_s, med_s = timed_steps(call, thetas, args.steps, torch)
     per = timed_steps.last
-    kern_s = pipelined_kernel(call_async, thetas, max(20, min(args.steps, 200)), torch, stream)
-    iso_s = isolated_kernel(call_async, thetas, 20, torch, stream)
     return dict(step_s=step_s, median_step_s=med_s, kernel_s=kern_s, isolated_s=iso_s,
                 step_us_min_max=[float(per.min()) * 1e6, float(per.max()) * 1e6])
 

@@ -118,6 +118,8 @@ def _dptr(a):
 
 def _stream(stream=None):
     """hipStream_t as an integer: torch's current stream, a torch stream, or a raw handle."""
+    if type(stream) is int:
+        return stream
     if stream is None:
         return torch.cuda.current_stream().cuda_stream
     if isinstance(stream, torch.cuda.Stream):
@@ -226,6 +228,7 @@ class Program:
         self._vref, self._nbref = ctypes.byref(self._v), ctypes.byref(self._nb)
         self._g = np.zeros(max(1, self.n_params))
         self._gptr = _dptr(self._g)
+        self._gview = self._g[: self.n_params]
         self._th = np.zeros(max(1, self.n_params))
         self._thptr = _dptr(self._th)
 
@@ -316,7 +319,7 @@ class Program:
         rc = rf_nll_grad(self.h, self._theta_ptr(theta), self._vref, self._gptr, self._nbref, _stream(stream))
         if rc != -3:
             check(rc)
-        return self._v.value, self._g[: self.n_params].copy(), self._nb.value
+        return self._v.value, self._gview.copy(), self._nb.value
 
     def nll_grad_async(self, theta, stream=None):
         check(rf_nll_grad_async(self.h, self._theta_ptr(theta), _stream(stream)))
