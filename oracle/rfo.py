@@ -216,6 +216,37 @@ def binned_nll(T, Lp, Lm, nobs, theta, grad=True):
     return out.value, (g if grad else None)
 
 
+def combined_nll(terms, constraints, theta):
+    """Combined likelihood of independent terms that share parameters, times
+    Gaussian constraint factors (the combined measurements of Section 3):
+
+        NLL(theta) = sum_t NLL_t(theta[map_t]) + sum_c (theta[k_c] - m_c)^2 / (2 w_c^2).
+
+    terms: (f, index_map) pairs; f(theta_t) returns (nll_t, grad_t, scale_t)
+    for the term's own parameter vector theta_t = theta[index_map] (scale_t:
+    per parameter, the sum of the magnitudes of its gradient terms, for scaled
+    error metrics; zeros where a term has none).  constraints: (k, m, w)
+    triples.  Returns (nll, grad, scale): each term's gradient entry j is
+    added to global parameter index_map[j]."""
+    theta = np.asarray(theta, dtype=np.float64)
+    nll = 0.0
+    grad = np.zeros(theta.size)
+    scale = np.zeros(theta.size)
+    for f, index_map in terms:
+        th_t = np.array([theta[k] for k in index_map])
+        n_t, g_t, s_t = f(th_t)
+        nll += n_t
+        for j, k in enumerate(index_map):
+            grad[k] += g_t[j]
+            scale[k] += s_t[j]
+    for k, m, w in constraints:
+        z = (theta[k] - m) / w
+        nll += 0.5 * z * z
+        grad[k] += z / w
+        scale[k] += abs(z / w)
+    return nll, grad, scale
+
+
 def from_spec(spec):
     """Build an oracle Model from a declarative node list.
 
