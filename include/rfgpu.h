@@ -299,6 +299,55 @@ int rf_binned_nll_grad(rf_binned* b, const double* theta, double* nll, double* g
 int rf_binned_nll_grad_async(rf_binned* b, const double* theta, void* stream);
 const double* rf_binned_result(const rf_binned* b);
 
+/* ---- combined likelihoods and constraints (Section 3) ------------------------ */
+/* A combined measurement: independent likelihoods that share parameters (the
+ * paper's combined measurements of a parameter such as a signal strength,
+ * Section 3), times Gaussian constraint factors on parameters.  With
+ * global parameters theta[0..n_params-1]:
+ *   NLL(theta) = sum_t NLL_t(theta[map_t[0]], .., theta[map_t[P_t - 1]])
+ *              + sum_c (theta[k_c] - mean_c)^2 / (2 width_c^2),
+ * each term t a compiled program (rf_compile, columns bound) or a binned model
+ * (rf_binned_new), each NLL_t as its own rf_nll_grad / rf_binned_nll_grad
+ * gives it; the gradient is the terms' gradients added through the maps plus
+ * (theta[k_c] - mean_c) / width_c^2.  Terms may share parameters in any way;
+ * a global parameter used by no term and no constraint has gradient 0.
+ *
+ * rf_sum_new: n_params in 1..64 global parameters; lo/hi (host, n_params
+ * values each, or NULL for unbounded) are bounds the fit keeps to, narrowed
+ * by every term's own bounds through its map (and mu >= 0 of a binned term).
+ * Host only; device memory is taken at the first evaluation.
+ * rf_sum_add_program / rf_sum_add_binned: map (host, the term's n_params
+ * values, resp. 1 + J for (mu, alpha_1..alpha_J)) gives each of the term's
+ * parameters its global index; RF_E_INVALID for an index outside
+ * [0, n_params), a term already in this sum (its device result block is
+ * reused by every evaluation), or more than 16 terms.  The sum refers to the
+ * term and does not own it: the term must outlive the sum's use.
+ * rf_sum_add_constraint: a Gaussian factor on theta[k] (width > 0, mean
+ * finite); at most 64.
+ * rf_sum_nll_grad: synchronous on `stream` (host result): each term's
+ * evaluation is enqueued on the stream, then one combining kernel adds the
+ * NLLs in term order, gathers each global parameter's gradient entries in
+ * term order and adds the constraints, all in FP64 (results repeat bit for
+ * bit).  Status as rf_nll_grad: RF_E_DOMAIN when a term's parameters are out
+ * of its bounds (nothing is launched), RF_E_NONFINITE with nll = +inf and
+ * grad NaN when a term has events with p <= 0 or a non-finite NLL; n_bad (may
+ * be NULL) is the terms' total of such events.  Terms must not be evaluated
+ * elsewhere while a sum's evaluation is in flight.
+ * rf_sum_fit_bfgs: rf_fit_bfgs_ex's minimiser on the combined NLL (initial
+ * inverse Hessian from forward differences, uncertainties from central
+ * differences of the gradient); same outputs. */
+typedef struct rf_sum rf_sum;
+int rf_sum_new(int32_t n_params, const double* lo, const double* hi, rf_sum** out);
+void rf_sum_free(rf_sum* s);
+int rf_sum_add_program(rf_sum* s, rf_program* p, const int32_t* map);
+int rf_sum_add_binned(rf_sum* s, rf_binned* b, const int32_t* map);
+int rf_sum_add_constraint(rf_sum* s, int32_t k, double mean, double width);
+int rf_sum_nll_grad(rf_sum* s, const double* theta, double* nll, double* grad, int64_t* n_bad,
+                    void* stream);
+int rf_sum_fit_bfgs(rf_sum* s, const double* theta0, double edm_tol, int32_t max_iter,
+                    double* theta_out, double* sigma_out, double* cov_out, double* info_out,
+                    void* stream);
+
 /* ---- MLP kernels used to train the surrogate ------------------------------- */
 /* Not in the paper: the learned surrogate of the numerically convolved signal
  * of the benchmark workload (its expensive PDF), trained by these kernels on

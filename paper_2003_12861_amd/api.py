@@ -60,6 +60,13 @@ _SIGS = {
     "rf_fit_bfgs": ([_P, _DP, _D, _I32, _DP, _DP, _DP, _P], _I32),
     "rf_fit_bfgs_ex": ([_P, _DP, _DP, _D, _I32, _DP, _DP, _DP, _DP, _P], _I32),
     "rf_gauss_legendre": ([_I32, _D, _D, _DP, _DP], _I32),
+    "rf_sum_new": ([_I32, _DP, _DP, _PP], _I32),
+    "rf_sum_free": ([_P], None),
+    "rf_sum_add_program": ([_P, _P, _PI32], _I32),
+    "rf_sum_add_binned": ([_P, _P, _PI32], _I32),
+    "rf_sum_add_constraint": ([_P, _I32, _D, _D], _I32),
+    "rf_sum_nll_grad": ([_P, _DP, _DP, _DP, _PI64, _P], _I32),
+    "rf_sum_fit_bfgs": ([_P, _DP, _D, _I32, _DP, _DP, _DP, _DP, _P], _I32),
 }
 _OPTIONAL = {
     "rf_binned_new": ([_I32, _I32, _I32, _I32, _DP, _DP, _DP, _DP, _P, _PP], _I32),
@@ -445,6 +452,79 @@ class Binned:
     def nll_grad_async(self, theta, stream=None):
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
         check(rf_binned_nll_grad_async(self.h, _dptr(th), _stream(stream)))
+
+
+# ------------------------------------------------------ combined likelihoods --
+class Sum:
+    """A combined likelihood: terms (Programs with bound columns, Binned models)
+    sharing global parameters through index maps, plus Gaussian constraints
+    on global parameters.  The terms must outlive the Sum."""
+
+    def __init__(self, n_params, lo=None, hi=None):
+        h = ctypes.c_void_p()
+        lo_a = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64)
+        hi_a = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64)
+        for b in (lo_a, hi_a):
+            if b is not None and b.size != n_params:
+                raise RfError(-1, "bounds need n_params values")
+        check(rf_sum_new(n_params, None if lo_a is None else _dptr(lo_a), None if hi_a is None else _dptr(hi_a),
+                         ctypes.byref(h)))
+        self.h = h
+        self.n_params = n_params
+        self._terms = []  # keeps the terms alive as long as the sum
+        self._g = np.zeros(n_params)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.h = None
+            try:
+                rf_sum_free(h)
+            except Exception:  # interpreter shutdown: the library may be gone
+                pass
+
+    def add(self, term, index_map):
+        """term: a Program or a Binned model; index_map: the global index of each
+        of its parameters (Binned: mu, then alpha_1..alpha_J)."""
+        m = np.ascontiguousarray(index_map, dtype=np.int32)
+        if m.size != term.n_params:
+            raise RfError(-1, "the map needs one index per parameter of the term (%d)" % term.n_params)
+        mp = m.ctypes.data_as(_PI32)
+        if isinstance(term, Binned):
+            check(rf_sum_add_binned(self.h, term.h, mp))
+        else:
+            check(rf_sum_add_program(self.h, term.h, mp))
+        self._terms.append(term)
+        return self
+
+    def constrain(self, k, mean, width):
+        """Gaussian constraint factor on global parameter k."""
+        check(rf_sum_add_constraint(self.h, int(k), float(mean), float(width)))
+        return self
+
+    def nll_grad(self, theta, stream=None):
+        """Returns (nll, grad, n_bad); nll = inf and grad = nan when n_bad > 0."""
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if th.size != self.n_params:
+            raise RfError(-1, "theta needs %d values" % self.n_params)
+        v, nb = ctypes.c_double(), ctypes.c_int64()
+        rc = rf_sum_nll_grad(self.h, _dptr(th), ctypes.byref(v), _dptr(self._g), ctypes.byref(nb), _stream(stream))
+        if rc != -3:
+            check(rc)
+        return v.value, self._g.copy(), nb.value
+
+    def fit(self, theta0, edm_tol=1e-6, max_iter=500, uncertainties=True, stream=None):
+        """BFGS on the combined NLL: (theta, sigma, cov, info dict)."""
+        P = self.n_params
+        t0 = np.ascontiguousarray(np.asarray(theta0, dtype=np.float64).reshape(-1))
+        if t0.size != P:
+            raise RfError(-1, "theta0 needs %d values" % P)
+        th, info = np.zeros(P), np.zeros(4)
+        sig, cov = (np.zeros(P), np.zeros((P, P))) if uncertainties else (None, None)
+        check(rf_sum_fit_bfgs(self.h, _dptr(t0), edm_tol, max_iter, _dptr(th), None if sig is None else _dptr(sig),
+                              None if cov is None else _dptr(cov), _dptr(info), _stream(stream)))
+        return th, sig, cov, dict(iterations=int(info[0]), evaluations=int(info[1]), edm=float(info[2]),
+                                  converged=bool(info[3]))
 
 
 # ----------------------------------------------------------- MLP kernels --

@@ -467,5 +467,8 @@ int rf_binned_nll_grad(rf_binned* b, const double* theta, double* nll, double* g
 }
 
 const double* rf_binned_result(const rf_binned* b) { return b ? b->out : nullptr; }
-
 }  // extern "C"
+
+namespace rf {
+int binned_n_params(const rf_binned* b) { return b ? 1 + b->J : 0; }
+}  // namespace rf

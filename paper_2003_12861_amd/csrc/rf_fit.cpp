@@ -74,14 +74,12 @@ using namespace rf;
 namespace {
 
 struct Eval {
-  rf_program* p;
-  void* stream;
+  const Objective& obj;
   int n_eval = 0;
   // returns RF_OK (finite), RF_E_NONFINITE, RF_E_DOMAIN, or another error
   int operator()(const double* x, double* f, double* g) {
     ++n_eval;
-    int64_t bad = 0;
-    return rf_nll_grad(p, x, f, g, &bad, stream);
+    return obj.eval(x, f, g);
   }
 };
 
@@ -120,16 +118,12 @@ bool invert_spd(std::vector<double>& A, int n) {
 
 }  // namespace
 
-extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, int32_t max_iter,
-                           double* theta_out, double* sigma_out, double* info_out, void* stream) {
-  return rf_fit_bfgs_ex(p, theta0, nullptr, edm_tol, max_iter, theta_out, sigma_out, nullptr, info_out, stream);
-}
+namespace rf {
 
-extern "C" int rf_fit_bfgs_ex(rf_program* p, const double* theta0, const double* hinv0, double edm_tol,
-                              int32_t max_iter, double* theta_out, double* sigma_out, double* cov_out,
-                              double* info_out, void* stream) {
-  if (!p || !theta0 || !theta_out) return fail(RF_E_INVALID, "NULL argument");
-  const int P = p->L.n_params;
+int bfgs_fit(const Objective& obj, const double* theta0, const double* hinv0, double edm_tol, int32_t max_iter,
+             double* theta_out, double* sigma_out, double* cov_out, double* info_out) {
+  if (!theta0 || !theta_out) return fail(RF_E_INVALID, "NULL argument");
+  const int P = obj.P;
   if (P == 0) return fail(RF_E_INVALID, "no parameters to fit");
   if (!(edm_tol > 0)) return fail(RF_E_INVALID, "edm_tol must be > 0");
   // the caller's initial inverse Hessian: finite, with a positive diagonal
@@ -139,13 +133,13 @@ extern "C" int rf_fit_bfgs_ex(rf_program* p, const double* theta0, const double*
     for (int j = 0; j < P; ++j)
       if (!std::isfinite(hinv0[i * P + j])) return fail(RF_E_INVALID, "hinv0 is not finite");
   }
-  Eval ev{p, stream};
+  Eval ev{obj};
   std::vector<double> x(theta0, theta0 + P), g(P), xn(P), gn(P), H(P * P, 0.0), d(P), s(P), y(P), Hy(P);
   double f;
   int rc = ev(x.data(), &f, g.data());
   if (rc) return rc;
-  const std::vector<double>& lo = p->L.plo;
-  const std::vector<double>& hi = p->L.phi;
+  const std::vector<double>& lo = obj.lo;
+  const std::vector<double>& hi = obj.hi;
   if (hinv0)
     for (int i = 0; i < P; ++i)
       for (int j = 0; j < P; ++j) H[i * P + j] = 0.5 * (hinv0[i * P + j] + hinv0[j * P + i]);
@@ -261,15 +255,12 @@ extern "C" int rf_fit_bfgs_ex(rf_program* p, const double* theta0, const double*
   conv = edm < edm_tol;
   for (int i = 0; i < P; ++i) theta_out[i] = x[i];
   if (sigma_out || cov_out) {
-    // the Hessian kernel where every leaf has second derivatives, else
-    // central differences of the analytic gradient
+    // the exact Hessian where the objective has one, else central
+    // differences of the analytic gradient
     std::vector<double> Hf(P * P), gp(P), gm(P);
     bool good = true;
-    const bool exact = hess_supported(p->L, nullptr);
-    if (exact) {
-      double fh;
-      good = rf_nll_grad_hess(p, x.data(), &fh, gp.data(), Hf.data(), nullptr, stream) == RF_OK;
-    }
+    const bool exact = (bool)obj.hess;
+    if (exact) good = obj.hess(x.data(), Hf.data()) == RF_OK;
     for (int k = 0; k < P && good && !exact; ++k) {
       // a tenth of the estimated sigma: large enough that FP32 gradient noise is
       // negligible, small enough for the quadratic region
@@ -299,4 +290,33 @@ extern "C" int rf_fit_bfgs_ex(rf_program* p, const double* theta0, const double*
     info_out[3] = conv ? 1.0 : 0.0;
   }
   return RF_OK;
+}
+
+}  // namespace rf
+
+extern "C" int rf_fit_bfgs(rf_program* p, const double* theta0, double edm_tol, int32_t max_iter,
+                           double* theta_out, double* sigma_out, double* info_out, void* stream) {
+  return rf_fit_bfgs_ex(p, theta0, nullptr, edm_tol, max_iter, theta_out, sigma_out, nullptr, info_out, stream);
+}
+
+extern "C" int rf_fit_bfgs_ex(rf_program* p, const double* theta0, const double* hinv0, double edm_tol,
+                              int32_t max_iter, double* theta_out, double* sigma_out, double* cov_out,
+                              double* info_out, void* stream) {
+  if (!p) return fail(RF_E_INVALID, "NULL argument");
+  Objective obj;
+  obj.P = p->L.n_params;
+  obj.lo = p->L.plo;
+  obj.hi = p->L.phi;
+  obj.eval = [p, stream](const double* x, double* f, double* g) {
+    int64_t bad = 0;
+    return rf_nll_grad(p, x, f, g, &bad, stream);
+  };
+  // the Hessian kernel where every leaf has second derivatives
+  if (hess_supported(p->L, nullptr))
+    obj.hess = [p, stream](const double* x, double* H) {
+      double fh;
+      std::vector<double> gh(p->L.n_params);
+      return rf_nll_grad_hess(p, x, &fh, gh.data(), H, nullptr, stream);
+    };
+  return bfgs_fit(obj, theta0, hinv0, edm_tol, max_iter, theta_out, sigma_out, cov_out, info_out);
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -10,6 +11,7 @@
 #include "device/rf_kabi.h"
 
 struct rf_program;
+struct rf_binned;
 
 namespace rf {
 
@@ -132,8 +134,25 @@ int validate_columns(const void* const* cols, int n_cols, int n_range, const dou
 int enqueue_grad_on(rf_program* p, const double* theta, double* part, int32_t part_stride, unsigned* ticket,
                     double* out, void* stream);
 
+// parameters of a binned model: 1 + J (mu, alpha_1..alpha_J)
+int binned_n_params(const rf_binned* b);
+
 // Gauss-Legendre rule (host)
 void gauss_legendre(int K, double lo, double hi, double* x, double* w);
+
+// What the BFGS minimiser (rf_fit.cpp) minimises: P parameters within
+// [lo, hi], one NLL+gradient evaluation (RF_OK, RF_E_NONFINITE and
+// RF_E_DOMAIN steer the line search; other codes end the fit), and
+// optionally the exact Hessian at a point (else central differences of the
+// gradient give the uncertainties).
+struct Objective {
+  int P = 0;
+  std::vector<double> lo, hi;
+  std::function<int(const double* x, double* f, double* g)> eval;
+  std::function<int(const double* x, double* H)> hess;
+};
+int bfgs_fit(const Objective& obj, const double* theta0, const double* hinv0, double edm_tol, int32_t max_iter,
+             double* theta_out, double* sigma_out, double* cov_out, double* info_out);
 
 }  // namespace rf
 

@@ -1,5 +1,6 @@
 """Combined likelihoods (terms sharing parameters, Gaussian constraints): the
-oracle's definition pinned on the CPU."""
+oracle's definition pinned on the CPU, and the host-side checks of the
+rf_sum_* entry points (no kernel is launched here)."""
 import math
 
 import numpy as np
@@ -73,3 +74,53 @@ def test_oracle_constraint_is_the_gaussian_factor():
             fd = (rfo.combined_nll([], cons, tp)[0] - rfo.combined_nll([], cons, tm)[0]) / (2 * h)
             assert abs(g[k] - fd) <= 1e-6 * max(1.0, abs(fd)), (th, k, g[k], fd)
         assert np.all(s >= np.abs(g))
+
+
+# ---- host-side checks of the entry points (programs compiled without loading)
+api = pytest.importorskip("paper_2003_12861_amd.api")
+
+
+def _prog():
+    return api.Program(api.Graph.from_spec(workloads.spec_gauss_cheb()), precision=api.FP64, load=False)
+
+
+def test_sum_host_checks():
+    s = api.Sum(6)
+    p, q = _prog(), _prog()
+    with pytest.raises(api.RfError, match="one index per parameter"):
+        s.add(p, [0, 1, 2])
+    with pytest.raises(api.RfError, match="outside"):
+        s.add(p, [0, 1, 2, 3, 6])
+    s.add(p, [0, 1, 2, 3, 4])
+    with pytest.raises(api.RfError, match="already in this sum"):
+        s.add(p, [0, 1, 2, 3, 4])
+    s.add(q, [5, 1, 2, 3, 4])  # a second program sharing four parameters
+    for k, m, w in ((6, 0.0, 1.0), (0, float("nan"), 1.0), (0, 0.0, 0.0), (0, 0.0, -1.0), (0, 0.0, float("inf"))):
+        with pytest.raises(api.RfError):
+            s.constrain(k, m, w)
+    s.constrain(0, 0.0, 1.0)
+    # bounds are the terms' (mu in [-5, 5]), checked before anything runs
+    th = np.array([0.1, 1.0, 0.3, 0.2, -0.1, 0.0])
+    for bad in ((0, 5.5), (5, -6.0), (1, float("nan")), (2, float("inf"))):
+        t = th.copy()
+        t[bad[0]] = bad[1]
+        with pytest.raises(api.RfError) as e:
+            s.nll_grad(t, stream=0)
+        assert e.value.code == -2, e.value
+    # global bounds that exclude a term's range
+    s2 = api.Sum(5, lo=[6.0, 0, 0, -1, -1], hi=[7.0, 10, 1, 1, 1])
+    with pytest.raises(api.RfError, match="do not overlap"):
+        s2.add(_prog(), [0, 1, 2, 3, 4])
+    with pytest.raises(api.RfError):
+        api.Sum(3, lo=[0.0, 1.0, 2.0], hi=[1.0, 0.5, 3.0])
+    with pytest.raises(api.RfError):
+        api.Sum(65)
+
+
+def test_sum_term_limit():
+    s = api.Sum(5)
+    progs = [_prog() for _ in range(17)]
+    for p in progs[:16]:
+        s.add(p, [0, 1, 2, 3, 4])
+    with pytest.raises(api.RfError, match="at most 16"):
+        s.add(progs[16], [0, 1, 2, 3, 4])
