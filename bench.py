@@ -71,15 +71,15 @@ MFMA_BF16_TFLOPS = 2500.0  # dense
 # counters measured (SQ_INSTS_VALU x 64 / events), since the FP64 exp and log
 # are instruction sequences whose length is the work.
 SLOTS = {
-    "gauss_cheb_1e7": {"fp32": 48, "fp64": 103},
+    "gauss_cheb_1e7": {"fp32": 48, "fp64": 91},
     # weights: one more multiply on log p and one on 1/p
-    "gauss_cheb_weighted_1e7": {"fp32": 50, "fp64": 105},
+    "gauss_cheb_weighted_1e7": {"fp32": 50, "fp64": 93},
     # extended: the same per-event program (the yield term is parameter-only)
-    "gauss_cheb_extended_1e7": {"fp32": 48, "fp64": 103},
-    "decay_argus_5e7": {"fp32": 165, "fp64": 341},
+    "gauss_cheb_extended_1e7": {"fp32": 48, "fp64": 91},
+    "decay_argus_5e7": {"fp32": 165, "fp64": 336},
     # the 1-D mixture's work, two Poisson leaves (an LDS table read each:
     # index, clamp, conversion) and the two products' adjoint terms
-    "poisson_gauss_cheb_1e7": {"fp32": 68, "fp64": 112},
+    "poisson_gauss_cheb_1e7": {"fp32": 68, "fp64": 120},
     "bwcb_exact_1e7": {"fp32": 16400, "fp64": 16400},
 }
 BYTES_PER_EVENT = {"gauss_cheb_1e7": {"fp32": 4, "fp64": 8}, "gauss_cheb_weighted_1e7": {"fp32": 8, "fp64": 16},

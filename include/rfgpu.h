@@ -421,7 +421,8 @@ int rf_peak(int32_t kind, int32_t iters, int64_t stream_bytes, double* rate, dou
 /* The library's own device math functions applied element by element to
  * dev_in[n] (FP64) into dev_out[n], for comparison with a host library:
  * fn 0 = the natural logarithm of the FP64 event loop (positive, finite,
- * normal arguments).  Asynchronous on the stream. */
+ * normal arguments); fn 1 = the Gaussian's 2^t of the FP64 event loop
+ * (t <= 0; 0 below 2^-1100).  Asynchronous on the stream. */
 int rf_eval_math(int32_t fn, const double* dev_in, int64_t n, double* dev_out, void* stream);
 
 /* ---- host utility ---------------------------------------------------------- */

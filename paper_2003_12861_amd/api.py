@@ -601,7 +601,7 @@ def peak(kind, iters, stream_bytes=0):
 
 
 def eval_math(fn, x, out=None, stream=None):
-    """The library's device math function fn (0: FP64 log) on a float64 device tensor."""
+    """The library's device math function fn (0: FP64 log, 1: 2^t for t <= 0) on a float64 device tensor."""
     if out is None:
         out = torch.empty_like(x)
     check(rf_eval_math(fn, _vp(x), x.numel(), _vp(out), _stream(stream)))

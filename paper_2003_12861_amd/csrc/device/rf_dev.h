@@ -45,6 +45,18 @@ template <> struct RM<float> {
   RF_DEV bool finite(float x) { return isfinite(x); }
   RF_DEV float tiny() { return 1e-30f; }  // FP32 results below this are redone in FP64
 };
+// a * b + c as the three-operand FP64 FMA with the addend c -- a polynomial
+// coefficient, the same on every lane -- in scalar registers.  Written as
+// plain fma() in the large event loops, such steps compile to the
+// two-operand form (the addend is also the destination) plus a 64-bit copy
+// of the coefficient per step, and the hoisted coefficients hold vector
+// registers.
+__device__ __forceinline__ double rf_fma3s(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+  return d;
+}
+
 // Natural logarithm in FP64 for the event loop's log p (normal, finite,
 // positive x; other values give an unspecified result, which the callers
 // discard): x = m 2^e with m in [sqrt(1/2), sqrt(2)), and
@@ -69,19 +81,58 @@ RF_DEV double rf_log64(double x) {
   sv = fma(r, fma(-sv, d, f), sv);
   const double s2 = sv * sv;
   double q = 1.0 / 21.0;
-  q = fma(q, s2, 1.0 / 19.0);
-  q = fma(q, s2, 1.0 / 17.0);
-  q = fma(q, s2, 1.0 / 15.0);
-  q = fma(q, s2, 1.0 / 13.0);
-  q = fma(q, s2, 1.0 / 11.0);
-  q = fma(q, s2, 1.0 / 9.0);
-  q = fma(q, s2, 1.0 / 7.0);
-  q = fma(q, s2, 1.0 / 5.0);
-  q = fma(q, s2, 1.0 / 3.0);
+  q = rf_fma3s(q, s2, 1.0 / 19.0);
+  q = rf_fma3s(q, s2, 1.0 / 17.0);
+  q = rf_fma3s(q, s2, 1.0 / 15.0);
+  q = rf_fma3s(q, s2, 1.0 / 13.0);
+  q = rf_fma3s(q, s2, 1.0 / 11.0);
+  q = rf_fma3s(q, s2, 1.0 / 9.0);
+  q = rf_fma3s(q, s2, 1.0 / 7.0);
+  q = rf_fma3s(q, s2, 1.0 / 5.0);
+  q = rf_fma3s(q, s2, 1.0 / 3.0);
   const double t = 2.0 * sv;
   const double lm = fma(t * s2, q, t);
   const double fe = (double)e;
   return fma(fe, 6.93147180369123816490e-01, fma(fe, 1.90821492927058770002e-10, lm));
+}
+
+static constexpr double RF_LOG2E = 1.44269504088896340736;
+static constexpr double RF_LN2 = 0.69314718055994530942;
+// ln 2 = RF_LN2_HI + RF_LN2_LO with RF_LN2_HI exact to 32 bits (its product
+// with an integer below 2^21 is exact: Cody and Waite's split)
+static constexpr double RF_LN2_HI = 6.93147180369123816490e-01;
+static constexpr double RF_LN2_LO = 1.90821492927058770002e-10;
+
+// The Gaussian's FP64 exponential in the event loop.  e^r for |r| <= ln2/2
+// from its Taylor series to r^13 (the first omitted term is below 5e-18 of
+// the result), evaluated by Horner's rule with the three-operand FMA and the
+// coefficients in scalar registers; the power of two comes from ldexp
+// (subnormal results rounded by the hardware).  (For the other leaves'
+// general e^x the device library's exp is as short in their loops.)
+__device__ __forceinline__ double rf_exp_taylor(double r) {
+  double p = 1.0 / 6227020800.0;  // 1/13!
+  p = rf_fma3s(p, r, 1.0 / 479001600.0);
+  p = rf_fma3s(p, r, 1.0 / 39916800.0);
+  p = rf_fma3s(p, r, 1.0 / 3628800.0);
+  p = rf_fma3s(p, r, 1.0 / 362880.0);
+  p = rf_fma3s(p, r, 1.0 / 40320.0);
+  p = rf_fma3s(p, r, 1.0 / 5040.0);
+  p = rf_fma3s(p, r, 1.0 / 720.0);
+  p = rf_fma3s(p, r, 1.0 / 120.0);
+  p = rf_fma3s(p, r, 1.0 / 24.0);
+  p = rf_fma3s(p, r, 1.0 / 6.0);
+  p = rf_fma3s(p, r, 0.5);
+  p = rf_fma3s(p, r, 1.0);
+  return rf_fma3s(p, r, 1.0);
+}
+// 2^t for t <= 0 (the Gaussian's 2^(-q)): t = n + f, n = rint(t), |f| <= 1/2
+// exact, 2^f = e^(f ln2); below -1100 the result is 0, NaN stays NaN.
+RF_DEV double rf_exp2_neg(double t) {
+  const double n = __builtin_rint(t);
+  const double f = t - n;
+  const double r = fma(f, RF_LN2_HI, f * RF_LN2_LO);
+  const double v = __builtin_amdgcn_ldexp(rf_exp_taylor(r), (int)fmax(n, -1100.0));
+  return t < -1100.0 ? 0.0 : v;
 }
 
 template <> struct RM<double> {
@@ -145,8 +196,6 @@ template <> struct Scl<double> {
   __device__ __forceinline__ double mul(double x) const { return x * hi; }
 };
 
-static constexpr double RF_LOG2E = 1.44269504088896340736;
-static constexpr double RF_LN2 = 0.69314718055994530942;
 
 // exp(s x) for a parameter-dependent rate s.  In float the rate is held in
 // base-2 units, s log2(e) = hi + lo, and the product t = hi x is split
@@ -269,7 +318,7 @@ template <typename T> RF_DEV T gauss_eval(T x, const GaussK<T>& k, T* d) {
   } else {
     d[0] = w;
     d[1] = q;
-    const double E = ::exp2(-q);
+    const double E = rf_exp2_neg(-q);
     return fma(E * fma(w, w, -q), -RF_LN2, E);
   }
 }

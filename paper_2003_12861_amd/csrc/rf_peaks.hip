@@ -36,6 +36,7 @@ __global__ __launch_bounds__(256) void math_kernel(int fn, const double* in, int
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   if (fn == 0) out[i] = rf_log64(in[i]);
+  else out[i] = rf_exp2_neg(in[i]);
 }
 
 constexpr int kBS = 256;
@@ -191,7 +192,7 @@ extern "C" int rf_peak(int32_t kind, int32_t iters, int64_t stream_bytes, double
 }
 
 extern "C" int rf_eval_math(int32_t fn, const double* dev_in, int64_t n, double* dev_out, void* stream) {
-  if (fn != 0 || n < 0 || (n > 0 && (!dev_in || !dev_out))) return rf::fail(RF_E_INVALID, "bad arguments");
+  if (fn < 0 || fn > 1 || n < 0 || (n > 0 && (!dev_in || !dev_out))) return rf::fail(RF_E_INVALID, "bad arguments");
   if (n == 0) return RF_OK;
   hipLaunchKernelGGL(math_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, fn, dev_in, n,
                      dev_out);
