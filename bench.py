@@ -372,6 +372,53 @@ def run_unfused_ablation(args, progs, cols, thetas, n, torch, stream):
     print(json.dumps(line))
 
 
+def run_hessian(args, progs, thetas, n, torch, stream):
+    """Synchronous NLL + gradient + Hessian: the one-pass Hessian kernel
+    (rf_nll_grad_hess, FP64 per event whatever the columns' dtype) against
+    what it replaces in the fit, the Hessian from central differences of the
+    analytic gradient (2P synchronous gradient evaluations, steps of a tenth
+    of each parameter's uncertainty), and the uncertainties the two give."""
+    if args.workload not in ("gauss_cheb_1e7", "gauss_cheb_extended_1e7", "decay_argus_5e7"):
+        raise SystemExit("--hessian takes gauss_cheb_1e7, gauss_cheb_extended_1e7 or decay_argus_5e7")
+    out = {}
+    for key, p in progs.items():
+        P = p.n_params
+        hess = lambda th, p=p: p.nll_grad_hess(th, stream=stream)
+        _, _, H0, _ = hess(thetas[0])
+        sig0 = np.sqrt(np.diag(np.linalg.inv(H0)))
+        h = 0.1 * sig0
+
+        def fd(th, p=p):
+            H = np.empty((P, P))
+            for k in range(P):
+                tp, tm = np.array(th, dtype=np.float64), np.array(th, dtype=np.float64)
+                tp[k] += h[k]
+                tm[k] -= h[k]
+                H[:, k] = (p.nll_grad(tp, stream=stream)[1] - p.nll_grad(tm, stream=stream)[1]) / (2 * h[k])
+            return 0.5 * (H + H.T)
+        gc.collect()
+        for f in (hess, fd):
+            for i in range(args.warmup):
+                f(thetas[i % len(thetas)])
+        th_, _ = timed_steps(hess, thetas, args.steps, torch)
+        tf_, _ = timed_steps(fd, thetas, max(1, args.steps // (2 * P)), torch)
+        Hk, Hf = hess(thetas[0])[2], fd(thetas[0])
+        sk, sf = np.sqrt(np.diag(np.linalg.inv(Hk))), np.sqrt(np.diag(np.linalg.inv(Hf)))
+        out[key] = {"hessian_ms": th_ * 1e3, "fd_hessian_ms": tf_ * 1e3, "fd_over_hessian": tf_ / th_,
+                    "gradient_evaluations_per_fd_hessian": 2 * P,
+                    "sigma_rel_diff_max": float(np.max(np.abs(sk - sf) / sf))}
+    first = "fp32" if "fp32" in out else "fp64"
+    line = {
+        "metric": "NLL, gradient and Hessian: one-pass Hessian kernel vs central differences of the gradient",
+        "value": n / (out[first]["hessian_ms"] * 1e-3), "unit": "events/s (Hessian pass, %s columns)" % first,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": args.workload, "events": n, "parameters": progs[first].n_params,
+                   "step": "one synchronous NLL + gradient + Hessian (FP64 per event)"},
+        **out,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,6 +429,9 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 path (profiling runs)")
     ap.add_argument("--unfused-ablation", action="store_true",
                     help="fused vs unfused per-node NLL (gauss_cheb_1e7, decay_argus_5e7)")
+    ap.add_argument("--hessian", action="store_true",
+                    help="one-pass Hessian kernel vs central differences of the gradient (gauss_cheb_1e7, "
+                         "gauss_cheb_extended_1e7, decay_argus_5e7)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (scale reference for HBM counters)")
     ap.add_argument("--peaks", action="store_true",
@@ -423,6 +473,9 @@ def main():
 
     if args.unfused_ablation:
         run_unfused_ablation(args, progs, cols, thetas, n, torch, stream)
+        return
+    if args.hessian:
+        run_hessian(args, progs, thetas, n, torch, stream)
         return
 
     if args.calib_copy:
