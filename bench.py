@@ -237,6 +237,28 @@ def pipelined_kernel(call_async, thetas, reps, torch, stream):
     return a.elapsed_time(b) * 1e-3 / reps
 
 
+def cold_kernel(call_async, thetas, reps, torch, stream):
+    """Median duration of single launches whose inputs were evicted from the
+    caches first: a 512 MiB fill (twice the 256 MB Infinity Cache) runs on the
+    stream before each launch, outside the event pair."""
+    flush = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    gc.collect()
+    gc.disable()
+    try:
+        with torch.cuda.stream(stream):
+            for i in range(reps):
+                flush.fill_(float(i))
+                evs[i][0].record(stream)
+                call_async(thetas[i % len(thetas)])
+                evs[i][1].record(stream)
+        torch.cuda.synchronize()
+    finally:
+        gc.enable()
+    del flush
+    return float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e-3
+
+
 def time_path(call, call_async, thetas, args, torch, stream):
     """The kernel's own time first (200 back-to-back launches, then 20
     isolated ones), then the W warm-up steps and the K timed synchronous
@@ -246,13 +268,14 @@ def time_path(call, call_async, thetas, args, torch, stream):
     pipelined_kernel(call_async, thetas, 20, torch, stream)  # lead-in, not used
     kern_s = pipelined_kernel(call_async, thetas, 200, torch, stream)
     iso_s = isolated_kernel(call_async, thetas, 20, torch, stream)
+    cold_s = cold_kernel(call_async, thetas, 10, torch, stream)
     gc.collect()
     gc.disable()
     for i in range(args.warmup):
         call(thetas[i % len(thetas)])
     step_s, med_s = timed_steps(call, thetas, args.steps, torch)
     per = timed_steps.last
-    return dict(step_s=step_s, median_step_s=med_s, kernel_s=kern_s, isolated_s=iso_s,
+    return dict(step_s=step_s, median_step_s=med_s, kernel_s=kern_s, isolated_s=iso_s, cold_s=cold_s,
                 step_us_min_max=[float(per.min()) * 1e6, float(per.max()) * 1e6])
 
 
@@ -303,6 +326,7 @@ def run_binned(args, torch, stream):
                    "precision": "fp32 terms, fp64 exponent and sums",
                    "step": "one synchronous NLL+gradient evaluation (result in host memory)"},
         "binned": {"kernel_ms": k * 1e3, "isolated_kernel_ms": r["isolated_s"] * 1e3,
+                   "cold_cache_kernel_ms": r["cold_s"] * 1e3,
                    "median_step_ms": r["median_step_s"] * 1e3, **check},
         "roofline": {"bound": "hbm", "kernel": "rf_binned_kernel<60>", "achieved": nbytes / k / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nbytes / k / 1e9 / HBM_PEAK_GBS,
@@ -567,6 +591,7 @@ def main():
         "config": {"workload": args.workload, "events": n, "precision": "fp32+adjoint, fp64 reductions",
                    "step": "one synchronous NLL+gradient evaluation (result in host memory)"},
         "fp32": {"kernel_ms": k32 * 1e3, "isolated_kernel_ms": res["fp32"]["isolated_s"] * 1e3,
+                 "cold_cache_kernel_ms": res["fp32"]["cold_s"] * 1e3,
                  "median_step_ms": res["fp32"]["median_step_s"] * 1e3,
                  "step_us_min_max": res["fp32"]["step_us_min_max"],
                  "kernel_events_per_s": n / k32,
@@ -584,6 +609,7 @@ def main():
                               "median_step_ms": res["fp64"]["median_step_s"] * 1e3,
                               "kernel_ms": res["fp64"]["kernel_s"] * 1e3,
                               "isolated_kernel_ms": res["fp64"]["isolated_s"] * 1e3,
+                              "cold_cache_kernel_ms": res["fp64"]["cold_s"] * 1e3,
                               "kernel_events_per_s": n / res["fp64"]["kernel_s"],
                               "roofline_frac": (n * slots64 / res["fp64"]["kernel_s"] / VALU_SLOTS_PER_S
                                                 if slots64 else None),
