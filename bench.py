@@ -443,6 +443,45 @@ def run_hessian(args, progs, thetas, n, torch, stream):
     print(json.dumps(line))
 
 
+def run_combined(args, torch, stream):
+    """A combined likelihood (rf_sum_*): the 1e7-event 1-D mixture (FP32+
+    adjoint) and the 200 x 4 x 100 binned model with 60 nuisances, the
+    binned signal strength sharing the mixture's fraction f, and a Gaussian
+    constraint on the mixture's mean.  One synchronous combined evaluation
+    against the two terms' own synchronous evaluations."""
+    from paper_2003_12861_amd import api, synth
+    spec, cols, theta, thetas, _, _ = make("gauss_cheb_1e7")
+    p = api.Program(api.Graph.from_spec(spec), precision=api.FP32)
+    p.bind([torch.tensor(c, dtype=torch.float32, device="cuda") for c in cols])
+    d = synth.make_binned(5, 200, 4, 100, 60)
+    bn = api.Binned(d["T"], d["Tp"], d["Tm"], d["nobs"], stream=stream)
+    bmap = [2] + list(range(5, 65))
+    s = api.Sum(65).add(p, range(5)).add(bn, bmap).constrain(0, 0.0, 0.05)
+    rng = np.random.default_rng(7)
+    ths = [np.concatenate([np.asarray(t), rng.uniform(-0.5, 0.5, 60)]) for t in thetas]
+    calls = {"combined": lambda th: s.nll_grad(th, stream=stream),
+             "mixture_alone": lambda th: p.nll_grad(th[:5], stream=stream),
+             "binned_alone": lambda th: bn.nll_grad(th[bmap], stream=stream),
+             "both_terms_enqueued": lambda th: (p.nll_grad_async(th[:5], stream=stream),
+                                                bn.nll_grad(th[bmap], stream=stream))}
+    out = {}
+    gc.collect()
+    for name, f in calls.items():
+        for i in range(args.warmup):
+            f(ths[i % len(ths)])
+        step_s, med_s = timed_steps(f, ths, args.steps, torch)
+        out[name] = {"ms_per_step": step_s * 1e3, "median_step_ms": med_s * 1e3}
+    line = {
+        "metric": "synchronous NLL+gradient of a combined likelihood (1-D mixture + binned model, shared parameter, constraint)",
+        "value": 1.0 / (out["combined"]["ms_per_step"] * 1e-3), "unit": "evaluations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "data": "synthetic",
+        "config": {"terms": ["gauss_cheb_1e7 (fp32+adjoint)", "binned_200x4x100x60"], "global_parameters": 65,
+                   "step": "one synchronous combined evaluation (terms' kernels and the combining kernel)"},
+        **out,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,6 +495,8 @@ def main():
     ap.add_argument("--hessian", action="store_true",
                     help="one-pass Hessian kernel vs central differences of the gradient (gauss_cheb_1e7, "
                          "gauss_cheb_extended_1e7, decay_argus_5e7)")
+    ap.add_argument("--combined", action="store_true",
+                    help="a combined likelihood: the 1-D mixture and the binned model with a shared parameter")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (scale reference for HBM counters)")
     ap.add_argument("--peaks", action="store_true",
@@ -476,6 +517,9 @@ def main():
         return
     if args.workload.startswith("binned"):
         run_binned(args, torch, stream)
+        return
+    if args.combined:
+        run_combined(args, torch, stream)
         return
     spec, cols, theta, thetas, precs_avail, w32 = make(args.workload)
     n = cols[0].size

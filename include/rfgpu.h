@@ -312,7 +312,7 @@ const double* rf_binned_result(const rf_binned* b);
  * (theta[k_c] - mean_c) / width_c^2.  Terms may share parameters in any way;
  * a global parameter used by no term and no constraint has gradient 0.
  *
- * rf_sum_new: n_params in 1..64 global parameters; lo/hi (host, n_params
+ * rf_sum_new: n_params in 1..256 global parameters; lo/hi (host, n_params
  * values each, or NULL for unbounded) are bounds the fit keeps to, narrowed
  * by every term's own bounds through its map (and mu >= 0 of a binned term).
  * Host only; device memory is taken at the first evaluation.

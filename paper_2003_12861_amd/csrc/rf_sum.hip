@@ -5,13 +5,16 @@
 //   NLL(theta) = sum_t NLL_t(theta[map_t]) + sum_c (theta[k_c] - m_c)^2 / (2 w_c^2)
 //
 // An evaluation enqueues every term's own NLL+gradient kernel on the stream
-// (each writes its result block in device memory), then one wavefront adds
-// them: lane k gathers global parameter k's gradient entries, terms in order
-// and each term's parameters in order; lane 0 adds the NLLs and the
-// bad-event counts in term order; the constraints come last.  The order is
-// fixed, so results repeat bit for bit.  The result goes to device memory
-// and, word by word with system-scope stores, to mapped host memory, which
-// the synchronous call polls.
+// (each writes its result block in device memory), then one workgroup of up
+// to four wavefronts adds them.  Lane k reads global parameter k's gradient
+// entries through an inverse map (the addresses of the entries inside the
+// terms' result blocks, terms in order and each term's parameters in order,
+// built on the host and uploaded when the sum or a result block changes)
+// and loads them sixteen at a time; lane 0 adds the NLLs and the bad-event
+// counts in term order; the constraints come last.  The order is fixed, so
+// results repeat bit for bit.  The result goes to device memory and, word
+// by word with system-scope stores, to mapped host memory, which the
+// synchronous call polls.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,46 +26,60 @@
 #include "rf_internal.h"
 
 #define RF_SUM_MAXTERMS 16
+#define RF_SUM_MAXP 256  // global parameters at most (one lane each in the combining kernel)
 
 namespace {
 
 struct SumArgs {
   const double* res[RF_SUM_MAXTERMS];  // each term's device result block [nll, grad[P_t], ...]
-  int32_t np[RF_SUM_MAXTERMS];         // the term's parameter count P_t
   int32_t nbad[RF_SUM_MAXTERMS];       // index of its bad-event count in the block (-1: none)
-  int32_t moff[RF_SUM_MAXTERMS];       // offset of its map in `map`
-  const int32_t* map;                  // the terms' maps, concatenated (device)
+  const int32_t* inv_off;              // [P + 1]: parameter k's gradient entries are inv[inv_off[k] ..
+  const double* const* inv;            //   inv_off[k + 1]), the addresses of the terms' gradient
+                                       //   entries mapped to k, terms in order, parameters in order
   int32_t nterms, P, nc, pad_;
   int32_t ck[RF_MAX_PARAMS];           // constraint c: parameter index,
+  double cval[RF_MAX_PARAMS];          //   the parameter's value at this point,
   double cmean[RF_MAX_PARAMS];         //   mean,
   double cinv2[RF_MAX_PARAMS];         //   1 / width^2
-  double theta[RF_MAX_PARAMS];         // the global parameter point
   double* out;                         // [nll, grad[P], n_bad]
   double* hout;                        // mapped host copy of out
 };
 
-__global__ __launch_bounds__(64) void rf_k_sum(const SumArgs a) {
-  const int k = threadIdx.x;
+// Every load of a lane is independent of the others (addresses from the
+// inverse map, 16 at a time), so a lane waits for about two memory round
+// trips, not one per map entry.
+__global__ __launch_bounds__(RF_SUM_MAXP) void rf_k_sum(const SumArgs a) {
+  const int k = threadIdx.x;  // one global parameter per lane
   if (k < a.P) {
+    const int beg = a.inv_off[k], end = a.inv_off[k + 1];
     double g = 0.0;
-    for (int t = 0; t < a.nterms; ++t) {
-      const int32_t* m = a.map + a.moff[t];
-      for (int j = 0; j < a.np[t]; ++j)
-        if (m[j] == k) g += a.res[t][1 + j];
+    for (int b0 = beg; b0 < end; b0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = b0 + i < end ? *a.inv[b0 + i] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) g += v[i];
     }
     for (int c = 0; c < a.nc; ++c)
-      if (a.ck[c] == k) g += (a.theta[k] - a.cmean[c]) * a.cinv2[c];
+      if (a.ck[c] == k) g += (a.cval[c] - a.cmean[c]) * a.cinv2[c];
     a.out[1 + k] = g;
     rf_store_host(a.hout + 1 + k, g);
   }
   if (k == 0) {
+    double tn[RF_SUM_MAXTERMS], tb[RF_SUM_MAXTERMS];
+#pragma unroll
+    for (int t = 0; t < RF_SUM_MAXTERMS; ++t) {
+      tn[t] = t < a.nterms ? a.res[t][0] : 0.0;
+      tb[t] = t < a.nterms && a.nbad[t] >= 0 ? a.res[t][a.nbad[t]] : 0.0;
+    }
     double nll = 0.0, bad = 0.0;
-    for (int t = 0; t < a.nterms; ++t) {
-      nll += a.res[t][0];
-      if (a.nbad[t] >= 0) bad += a.res[t][a.nbad[t]];
+#pragma unroll
+    for (int t = 0; t < RF_SUM_MAXTERMS; ++t) {
+      nll += tn[t];
+      bad += tb[t];
     }
     for (int c = 0; c < a.nc; ++c) {
-      const double d = a.theta[a.ck[c]] - a.cmean[c];
+      const double d = a.cval[c] - a.cmean[c];
       nll += 0.5 * d * d * a.cinv2[c];
     }
     a.out[0] = nll;
@@ -81,14 +98,16 @@ struct rf_sum {
     rf_program* p = nullptr;
     rf_binned* b = nullptr;
     std::vector<int32_t> map;
+    const double* res = nullptr;  // its result block when the inverse map was built
   };
   std::vector<Term> terms;
   std::vector<int32_t> ck;
   std::vector<double> cmean, cwidth;
   // device state, taken at the first evaluation
   int device = -1;
-  int32_t* d_map = nullptr;
-  size_t map_cap = 0;
+  int32_t* d_inv_off = nullptr;       // inverse map (see SumArgs), uploaded after a change
+  const double** d_inv = nullptr;
+  size_t inv_cap = 0;
   bool dirty = true;  // the maps changed since they were uploaded
   double* d_out = nullptr;
   double* h_out = nullptr;
@@ -132,29 +151,41 @@ int prepare(rf_sum* s) {
   hipError_t e;
   if (!s->d_out) {
     if ((e = hipGetDevice(&s->device)) != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if ((e = hipMalloc(&s->d_out, sizeof(double) * (RF_MAX_PARAMS + 2))) != hipSuccess) return hip_fail(e, "hipMalloc");
-    if ((e = hipHostMalloc(&s->h_out, sizeof(double) * (RF_MAX_PARAMS + 2), hipHostMallocMapped | hipHostMallocCoherent)) !=
+    if ((e = hipMalloc(&s->d_out, sizeof(double) * (RF_SUM_MAXP + 2))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipHostMalloc(&s->h_out, sizeof(double) * (RF_SUM_MAXP + 2), hipHostMallocMapped | hipHostMallocCoherent)) !=
             hipSuccess ||
         (e = hipHostGetDevicePointer((void**)&s->d_hout, s->h_out, 0)) != hipSuccess)
       return hip_fail(e, "mapped result buffer");
   }
   if (!s->dirty) return RF_OK;
-  size_t n = 0;
-  for (const auto& t : s->terms) n += t.map.size();
-  std::vector<int32_t> all;
-  all.reserve(n);
-  for (const auto& t : s->terms) all.insert(all.end(), t.map.begin(), t.map.end());
-  // a combining kernel still in flight reads the old maps
+  // the inverse map: for each global parameter, the device addresses of the
+  // terms' gradient entries mapped to it, terms in order, parameters in order
+  std::vector<int32_t> off(s->P + 1, 0);
+  for (const auto& t : s->terms)
+    for (int32_t k : t.map) ++off[k + 1];
+  for (int k = 0; k < s->P; ++k) off[k + 1] += off[k];
+  std::vector<const double*> inv(off[s->P] > 0 ? off[s->P] : 1);
+  {
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (const auto& t : s->terms) {
+      if (!t.res) return fail(RF_E_STATE, "a term has no result block (program not bound or not loaded)");
+      for (size_t j = 0; j < t.map.size(); ++j) inv[fill[t.map[j]]++] = t.res + 1 + j;
+    }
+  }
+  // a combining kernel still in flight reads the old map
   if (s->launched && (e = hipStreamSynchronize((hipStream_t)s->last_stream)) != hipSuccess)
     return hip_fail(e, "hipStreamSynchronize (previous stream)");
-  if (n > s->map_cap) {
-    if (s->d_map) (void)hipFree(s->d_map);
-    s->d_map = nullptr;
-    s->map_cap = 0;
-    if ((e = hipMalloc(&s->d_map, sizeof(int32_t) * n)) != hipSuccess) return hip_fail(e, "hipMalloc");
-    s->map_cap = n;
+  if (!s->d_inv_off && (e = hipMalloc(&s->d_inv_off, sizeof(int32_t) * (RF_SUM_MAXP + 1))) != hipSuccess)
+    return hip_fail(e, "hipMalloc");
+  if (inv.size() > s->inv_cap) {
+    if (s->d_inv) (void)hipFree(s->d_inv);
+    s->d_inv = nullptr;
+    s->inv_cap = 0;
+    if ((e = hipMalloc(&s->d_inv, sizeof(const double*) * inv.size())) != hipSuccess) return hip_fail(e, "hipMalloc");
+    s->inv_cap = inv.size();
   }
-  if (n && (e = hipMemcpy(s->d_map, all.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) != hipSuccess)
+  if ((e = hipMemcpy(s->d_inv_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(s->d_inv, inv.data(), sizeof(const double*) * inv.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "hipMemcpy");
   s->dirty = false;
   return RF_OK;
@@ -167,7 +198,7 @@ extern "C" {
 int rf_sum_new(int32_t n_params, const double* lo, const double* hi, rf_sum** out) {
   if (!out) return fail(RF_E_INVALID, "NULL argument");
   *out = nullptr;
-  if (n_params < 1 || n_params > RF_MAX_PARAMS) return fail(RF_E_INVALID, "n_params must be in 1..64");
+  if (n_params < 1 || n_params > RF_SUM_MAXP) return fail(RF_E_INVALID, "n_params must be in 1..256");
   rf_sum* s = new rf_sum();
   s->P = n_params;
   s->lo.assign(n_params, -INFINITY);
@@ -186,7 +217,8 @@ int rf_sum_new(int32_t n_params, const double* lo, const double* hi, rf_sum** ou
 
 void rf_sum_free(rf_sum* s) {
   if (!s) return;
-  if (s->d_map) (void)hipFree(s->d_map);
+  if (s->d_inv_off) (void)hipFree(s->d_inv_off);
+  if (s->d_inv) (void)hipFree(s->d_inv);
   if (s->d_out) (void)hipFree(s->d_out);
   if (s->h_out) (void)hipHostFree(s->h_out);
   delete s;
@@ -224,11 +256,19 @@ int rf_sum_nll_grad(rf_sum* s, const double* theta, double* nll, double* grad, i
     if (!std::isfinite(theta[k])) return fail(RF_E_DOMAIN, "theta must be finite");
     if (theta[k] < s->lo[k] || theta[k] > s->hi[k]) return fail(RF_E_DOMAIN, "theta outside its bounds");
   }
+  // a term's result block moves when its program is bound to more events:
+  // rebuild the inverse map then
+  for (auto& t : s->terms) {
+    const double* r = t.p ? rf_program_result(t.p) : rf_binned_result(t.b);
+    if (r != t.res) {
+      t.res = r;
+      s->dirty = true;
+    }
+  }
   int rc = prepare(s);
   if (rc) return rc;
   SumArgs a;
   memset(&a, 0, sizeof a);
-  size_t off = 0;
   double th[RF_MAX_PARAMS];
   for (size_t t = 0; t < s->terms.size(); ++t) {
     const rf_sum::Term& term = s->terms[t];
@@ -245,25 +285,23 @@ int rf_sum_nll_grad(rf_sum* s, const double* theta, double* nll, double* grad, i
       a.nbad[t] = -1;
     }
     if (rc) return rc;
-    a.np[t] = np;
-    a.moff[t] = (int32_t)off;
-    off += np;
   }
-  a.map = s->d_map;
+  a.inv_off = s->d_inv_off;
+  a.inv = s->d_inv;
   a.nterms = (int32_t)s->terms.size();
   a.P = P;
   a.nc = (int32_t)s->ck.size();
   for (int c = 0; c < a.nc; ++c) {
     a.ck[c] = s->ck[c];
+    a.cval[c] = theta[s->ck[c]];
     a.cmean[c] = s->cmean[c];
     a.cinv2[c] = 1.0 / (s->cwidth[c] * s->cwidth[c]);
   }
-  for (int k = 0; k < P; ++k) a.theta[k] = theta[k];
   a.out = s->d_out;
   a.hout = s->d_hout;
   if ((rc = order_launch(s->last_stream, s->launched, stream))) return rc;
   arm_result(s->h_out, P + 2);
-  hipLaunchKernelGGL(rf_k_sum, dim3(1), dim3(64), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL(rf_k_sum, dim3(1), dim3((P + 63) / 64 * 64), 0, (hipStream_t)stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "combining kernel launch");
   if ((rc = wait_result(s->h_out, P + 2, stream, nullptr))) return rc;

@@ -114,7 +114,8 @@ def test_sum_host_checks():
     with pytest.raises(api.RfError):
         api.Sum(3, lo=[0.0, 1.0, 2.0], hi=[1.0, 0.5, 3.0])
     with pytest.raises(api.RfError):
-        api.Sum(65)
+        api.Sum(257)
+    api.Sum(256)  # a combination may have up to 256 global parameters
 
 
 def test_sum_term_limit():

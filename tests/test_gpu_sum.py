@@ -179,3 +179,20 @@ def test_sum_nonfinite_term():
     s = api.Sum(5).add(p, range(5))
     nll, g, nb = s.nll_grad(th)
     assert nll == np.inf and np.all(np.isnan(g)) and nb == pb
+
+
+def test_sum_term_rebound_to_more_events():
+    """A program re-bound to a larger sample gets a new result block; the
+    combination follows it (against the oracle on the new sample)."""
+    print("case sum rebind", flush=True)
+    spec = workloads.spec_gauss_cheb()
+    small, big = synth.sample_gauss_cheb(3000, 13), synth.sample_gauss_cheb(400001, 14)
+    p = _prog(spec, [small], api.FP64)
+    s = api.Sum(5).add(p, range(5))
+    n0, _, _ = s.nll_grad(TH)
+    assert rel(n0, rfo.combined_nll([(_oracle_term(spec, [small]), list(range(5)))], [], TH)[0]) <= 1e-9
+    p.bind(to_dev([big], api.FP64, api))
+    nll, g, nb = s.nll_grad(TH)
+    on, og, osc = rfo.combined_nll([(_oracle_term(spec, [big]), list(range(5)))], [], TH)
+    assert nb == 0 and rel(nll, on) <= 1e-9, (nll, on)
+    assert scaled_grad_err(g, og, osc).max() <= 1e-9
