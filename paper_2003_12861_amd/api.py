@@ -106,6 +106,14 @@ def _bind(table, required):
 _bind(_SIGS, True)
 _bind(_OPTIONAL, False)
 
+# the synchronous calls through the CPython module (same library instance:
+# it calls the addresses ctypes resolved above)
+try:
+    from . import _rfcall
+except ImportError as e:
+    raise ImportError("the _rfcall module is not built: run `python -m paper_2003_12861_amd.build`") from e
+_rfcall.init(ctypes.cast(rf_nll_grad, ctypes.c_void_p).value, ctypes.cast(rf_binned_nll_grad, ctypes.c_void_p).value)
+
 
 class RfError(RuntimeError):
     def __init__(self, code, msg):
@@ -323,6 +331,12 @@ class Program:
 
     def nll_grad(self, theta, stream=None):
         """Returns (nll, grad, n_bad); nll = inf and grad = nan when n_bad > 0."""
+        r = _rfcall.nll_grad(self.h.value, theta, self.n_params, stream if type(stream) is int else _stream(stream))
+        if r is not None:
+            if r[0] != 0 and r[0] != -3:
+                check(r[0])
+            return r[1], r[2], r[3]
+        # theta is not n_params numbers: the checked path raises the error
         rc = rf_nll_grad(self.h, self._theta_ptr(theta), self._vref, self._gptr, self._nbref, _stream(stream))
         if rc != -3:
             check(rc)
@@ -437,6 +451,11 @@ class Binned:
                 pass
 
     def nll_grad(self, theta, stream=None):
+        r = _rfcall.binned_nll_grad(self.h.value, theta, self.n_params, stream if type(stream) is int else _stream(stream))
+        if r is not None:
+            check(r[0])
+            return r[1], r[2]
+        # theta is not n_params numbers: the checked path raises the error
         if type(theta) is np.ndarray and theta.dtype == np.float64 and theta.ndim == 1 and theta.flags.c_contiguous:
             th = theta
         else:
