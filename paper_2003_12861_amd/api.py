@@ -112,7 +112,7 @@ try:
     from . import _rfcall
 except ImportError as e:
     raise ImportError("the _rfcall module is not built: run `python -m paper_2003_12861_amd.build`") from e
-_rfcall.init(ctypes.cast(rf_nll_grad, ctypes.c_void_p).value, ctypes.cast(rf_binned_nll_grad, ctypes.c_void_p).value)
+_rfcall.init(*[ctypes.cast(f, ctypes.c_void_p).value for f in (rf_nll_grad, rf_binned_nll_grad, rf_sum_nll_grad)])
 
 
 class RfError(RuntimeError):
@@ -523,6 +523,12 @@ class Sum:
 
     def nll_grad(self, theta, stream=None):
         """Returns (nll, grad, n_bad); nll = inf and grad = nan when n_bad > 0."""
+        r = _rfcall.sum_nll_grad(self.h.value, theta, self.n_params, stream if type(stream) is int else _stream(stream))
+        if r is not None:
+            if r[0] != 0 and r[0] != -3:
+                check(r[0])
+            return r[1], r[2], r[3]
+        # theta is not n_params numbers: the checked path raises the error
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
         if th.size != self.n_params:
             raise RfError(-1, "theta needs %d values" % self.n_params)

@@ -20,8 +20,9 @@ namespace {
 typedef int (*NllGradFn)(void* p, const double* theta, double* nll, double* grad, int64_t* n_bad, void* stream);
 typedef int (*BinnedNllGradFn)(void* b, const double* theta, double* nll, double* grad, void* stream);
 
-NllGradFn g_nll_grad = nullptr;
+NllGradFn g_nll_grad = nullptr;      // rf_nll_grad
 BinnedNllGradFn g_binned_nll_grad = nullptr;
+NllGradFn g_sum_nll_grad = nullptr;  // rf_sum_nll_grad (same signature as rf_nll_grad)
 
 constexpr Py_ssize_t kMaxTheta = 256;
 
@@ -65,16 +66,17 @@ bool get_ptr(PyObject* o, void** out) {
   return !(*out == nullptr && PyErr_Occurred());
 }
 
-// init(nll_grad_address, binned_nll_grad_address)
+// init(rf_nll_grad, rf_binned_nll_grad, rf_sum_nll_grad): their addresses
 PyObject* py_init(PyObject*, PyObject* const* args, Py_ssize_t nargs) {
-  if (nargs != 2) {
-    PyErr_SetString(PyExc_TypeError, "init(rf_nll_grad, rf_binned_nll_grad)");
+  if (nargs != 3) {
+    PyErr_SetString(PyExc_TypeError, "init(rf_nll_grad, rf_binned_nll_grad, rf_sum_nll_grad)");
     return nullptr;
   }
-  void *a, *b;
-  if (!get_ptr(args[0], &a) || !get_ptr(args[1], &b)) return nullptr;
+  void *a, *b, *c;
+  if (!get_ptr(args[0], &a) || !get_ptr(args[1], &b) || !get_ptr(args[2], &c)) return nullptr;
   g_nll_grad = (NllGradFn)a;
   g_binned_nll_grad = (BinnedNllGradFn)b;
+  g_sum_nll_grad = (NllGradFn)c;
   Py_RETURN_NONE;
 }
 
@@ -106,14 +108,15 @@ int unpack(PyObject* const* args, Py_ssize_t nargs, const char* usage, Call& c) 
   return c.g ? 1 : -1;
 }
 
-// nll_grad(handle, theta, n_params, stream) -> (rc, nll, grad, n_bad) or None
-PyObject* py_nll_grad(PyObject*, PyObject* const* args, Py_ssize_t nargs) {
-  if (!g_nll_grad) {
+// (handle, theta, n_params, stream) -> (rc, nll, grad, n_bad) or None, for
+// the entry points with rf_nll_grad's signature
+PyObject* call_nll_grad(NllGradFn fn, PyObject* const* args, Py_ssize_t nargs, const char* usage) {
+  if (!fn) {
     PyErr_SetString(PyExc_RuntimeError, "rf_pycall.init was not called");
     return nullptr;
   }
   Call c;
-  const int u = unpack(args, nargs, "nll_grad(handle, theta, n_params, stream)", c);
+  const int u = unpack(args, nargs, usage, c);
   if (u <= 0) {
     if (u < 0) return nullptr;
     Py_RETURN_NONE;
@@ -122,7 +125,7 @@ PyObject* py_nll_grad(PyObject*, PyObject* const* args, Py_ssize_t nargs) {
   int64_t nb = 0;
   int rc;
   Py_BEGIN_ALLOW_THREADS
-  rc = g_nll_grad(c.h, c.th, &nll, (double*)PyArray_DATA(c.g), &nb, c.stream);
+  rc = fn(c.h, c.th, &nll, (double*)PyArray_DATA(c.g), &nb, c.stream);
   Py_END_ALLOW_THREADS
   PyObject* t = PyTuple_New(4);
   if (!t) {
@@ -134,6 +137,14 @@ PyObject* py_nll_grad(PyObject*, PyObject* const* args, Py_ssize_t nargs) {
   PyTuple_SET_ITEM(t, 2, (PyObject*)c.g);
   PyTuple_SET_ITEM(t, 3, PyLong_FromLongLong(nb));
   return t;
+}
+
+PyObject* py_nll_grad(PyObject*, PyObject* const* args, Py_ssize_t nargs) {
+  return call_nll_grad(g_nll_grad, args, nargs, "nll_grad(handle, theta, n_params, stream)");
+}
+
+PyObject* py_sum_nll_grad(PyObject*, PyObject* const* args, Py_ssize_t nargs) {
+  return call_nll_grad(g_sum_nll_grad, args, nargs, "sum_nll_grad(handle, theta, n_params, stream)");
 }
 
 // binned_nll_grad(handle, theta, n_params, stream) -> (rc, nll, grad) or None
@@ -165,9 +176,11 @@ PyObject* py_binned_nll_grad(PyObject*, PyObject* const* args, Py_ssize_t nargs)
 }
 
 PyMethodDef kMethods[] = {
-    {"init", (PyCFunction)(void (*)(void))py_init, METH_FASTCALL, "init(rf_nll_grad, rf_binned_nll_grad)"},
+    {"init", (PyCFunction)(void (*)(void))py_init, METH_FASTCALL, "init(rf_nll_grad, rf_binned_nll_grad, rf_sum_nll_grad)"},
     {"nll_grad", (PyCFunction)(void (*)(void))py_nll_grad, METH_FASTCALL,
      "nll_grad(handle, theta, n_params, stream) -> (rc, nll, grad, n_bad), or None for the checked path"},
+    {"sum_nll_grad", (PyCFunction)(void (*)(void))py_sum_nll_grad, METH_FASTCALL,
+     "sum_nll_grad(handle, theta, n_params, stream) -> (rc, nll, grad, n_bad), or None for the checked path"},
     {"binned_nll_grad", (PyCFunction)(void (*)(void))py_binned_nll_grad, METH_FASTCALL,
      "binned_nll_grad(handle, theta, n_params, stream) -> (rc, nll, grad), or None for the checked path"},
     {nullptr, nullptr, 0, nullptr}};

@@ -44,3 +44,19 @@ def test_other_arguments_take_the_checked_path():
         _rfcall.nll_grad(h, [0.0] * 5, 5)
     with pytest.raises(TypeError):
         _rfcall.nll_grad("not a handle", [0.0] * 5, 5, 0)
+
+
+def test_sum_call():
+    """The combined likelihood's call: a point outside the bounds reaches the
+    library (RF_E_DOMAIN before anything runs); a wrong length takes the
+    checked path."""
+    s = api.Sum(3, lo=[0.0, 0.0, 0.0], hi=[1.0, 1.0, 1.0])
+    r = _rfcall.sum_nll_grad(s.h.value, [0.5, 2.0, 0.5], 3, 0)
+    assert r is not None and r[0] == -2
+    with pytest.raises(api.RfError) as e:
+        s.nll_grad(np.array([0.5, 2.0, 0.5]), stream=0)
+    assert e.value.code == -2
+    assert _rfcall.sum_nll_grad(s.h.value, [0.5, 0.5], 3, 0) is None
+    with pytest.raises(api.RfError) as e:
+        s.nll_grad([0.5, 0.5], stream=0)
+    assert e.value.code == -1
