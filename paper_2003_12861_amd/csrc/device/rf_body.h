@@ -37,16 +37,26 @@
 // E values of a column from event i on: one 16-byte load when E values make
 // 16 bytes.  The vector types only claim the element's alignment (global
 // memory accesses need no more on this target), so any column works and an
-// aligned one gets full-width loads.
+// aligned one gets full-width loads.  FP32 columns are read with non-temporal
+// loads (each event is read once per evaluation, and the streamed columns
+// then do not displace the kernel's code and constants from the caches): the
+// 1e7-event FP32 kernel with its inputs evicted from the caches went from
+// 23.4-23.7 to 20.3 us and its synchronous step fell by about 0.3 us, with the
+// back-to-back time unchanged.  FP64 columns keep ordinary loads: with
+// non-temporal ones the 1e7-event FP64 kernel ran 41.4-42.6 us back to back
+// against 39.6.
 typedef float rf_f4 __attribute__((ext_vector_type(4), aligned(4)));
 typedef double rf_d2 __attribute__((ext_vector_type(2), aligned(8)));
 template <typename T, int E> RF_DEV void rf_ldv(const T* p, int64_t i, T (&v)[E]) {
   if constexpr (E == 4 && sizeof(T) == 4) {
-    const rf_f4 q = *(const rf_f4*)(p + i);
+    const rf_f4 q = __builtin_nontemporal_load((const rf_f4*)(p + i));
     v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
   } else if constexpr (E == 2 && sizeof(T) == 8) {
     const rf_d2 q = *(const rf_d2*)(p + i);
     v[0] = q.x; v[1] = q.y;
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = __builtin_nontemporal_load(p + i + e);
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = p[i + e];
