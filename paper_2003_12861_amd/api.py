@@ -131,14 +131,20 @@ def _dptr(a):
     return a.ctypes.data_as(_DP)
 
 
+_last_stream = [None, 0]  # the last torch stream object resolved, and its handle
+
+
 def _stream(stream=None):
     """hipStream_t as an integer: torch's current stream, a torch stream, or a raw handle."""
     if type(stream) is int:
         return stream
     if stream is None:
         return torch.cuda.current_stream().cuda_stream
+    if stream is _last_stream[0]:  # held here, so the object (and its handle) is still alive
+        return _last_stream[1]
     if isinstance(stream, torch.cuda.Stream):
-        return stream.cuda_stream
+        _last_stream[0], _last_stream[1] = stream, stream.cuda_stream
+        return _last_stream[1]
     return int(stream) if stream else 0
 
 
