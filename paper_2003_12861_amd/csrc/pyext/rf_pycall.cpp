@@ -14,6 +14,7 @@
 #include <numpy/arrayobject.h>
 
 #include <cstdint>
+#include <initializer_list>
 
 namespace {
 
@@ -108,6 +109,20 @@ int unpack(PyObject* const* args, Py_ssize_t nargs, const char* usage, Call& c) 
   return c.g ? 1 : -1;
 }
 
+// a tuple of the new references in items (all released if one is missing)
+PyObject* result(std::initializer_list<PyObject*> items) {
+  bool ok = true;
+  for (PyObject* o : items) ok = ok && o;
+  PyObject* t = ok ? PyTuple_New((Py_ssize_t)items.size()) : nullptr;
+  if (!t) {
+    for (PyObject* o : items) Py_XDECREF(o);
+    return nullptr;
+  }
+  Py_ssize_t i = 0;
+  for (PyObject* o : items) PyTuple_SET_ITEM(t, i++, o);
+  return t;
+}
+
 // (handle, theta, n_params, stream) -> (rc, nll, grad, n_bad) or None, for
 // the entry points with rf_nll_grad's signature
 PyObject* call_nll_grad(NllGradFn fn, PyObject* const* args, Py_ssize_t nargs, const char* usage) {
@@ -127,16 +142,7 @@ PyObject* call_nll_grad(NllGradFn fn, PyObject* const* args, Py_ssize_t nargs, c
   Py_BEGIN_ALLOW_THREADS
   rc = fn(c.h, c.th, &nll, (double*)PyArray_DATA(c.g), &nb, c.stream);
   Py_END_ALLOW_THREADS
-  PyObject* t = PyTuple_New(4);
-  if (!t) {
-    Py_DECREF(c.g);
-    return nullptr;
-  }
-  PyTuple_SET_ITEM(t, 0, PyLong_FromLong(rc));
-  PyTuple_SET_ITEM(t, 1, PyFloat_FromDouble(nll));
-  PyTuple_SET_ITEM(t, 2, (PyObject*)c.g);
-  PyTuple_SET_ITEM(t, 3, PyLong_FromLongLong(nb));
-  return t;
+  return result({PyLong_FromLong(rc), PyFloat_FromDouble(nll), (PyObject*)c.g, PyLong_FromLongLong(nb)});
 }
 
 PyObject* py_nll_grad(PyObject*, PyObject* const* args, Py_ssize_t nargs) {
@@ -164,15 +170,7 @@ PyObject* py_binned_nll_grad(PyObject*, PyObject* const* args, Py_ssize_t nargs)
   Py_BEGIN_ALLOW_THREADS
   rc = g_binned_nll_grad(c.h, c.th, &nll, (double*)PyArray_DATA(c.g), c.stream);
   Py_END_ALLOW_THREADS
-  PyObject* t = PyTuple_New(3);
-  if (!t) {
-    Py_DECREF(c.g);
-    return nullptr;
-  }
-  PyTuple_SET_ITEM(t, 0, PyLong_FromLong(rc));
-  PyTuple_SET_ITEM(t, 1, PyFloat_FromDouble(nll));
-  PyTuple_SET_ITEM(t, 2, (PyObject*)c.g);
-  return t;
+  return result({PyLong_FromLong(rc), PyFloat_FromDouble(nll), (PyObject*)c.g});
 }
 
 PyMethodDef kMethods[] = {
