@@ -39,12 +39,14 @@
 // memory accesses need no more on this target), so any column works and an
 // aligned one gets full-width loads.  FP32 columns are read with non-temporal
 // loads (each event is read once per evaluation, and the streamed columns
-// then do not displace the kernel's code and constants from the caches): the
-// 1e7-event FP32 kernel with its inputs evicted from the caches went from
-// 23.4-23.7 to 20.3 us and its synchronous step fell by about 0.3 us, with the
-// back-to-back time unchanged.  FP64 columns keep ordinary loads: with
-// non-temporal ones the 1e7-event FP64 kernel ran 41.4-42.6 us back to back
-// against 39.6.
+// then do not displace the kernel's code and constants from the caches).
+// Measured at 1e7 events: one column, after a cache eviction 20.3 us against
+// 23.4-23.7, back to back unchanged, synchronous step about 0.3 us lower; two
+// columns (80 MB, which the Infinity Cache would otherwise keep between
+// evaluations), after a cache eviction 11-13 us faster, back to back 0.6-0.8
+// us slower; the 2-D model at 5e7 events, 241 against 244 us.  FP64 columns
+// keep ordinary loads: with non-temporal ones the 1e7-event FP64 kernel ran
+// 41.4-42.6 us back to back against 39.6.
 typedef float rf_f4 __attribute__((ext_vector_type(4), aligned(4)));
 typedef double rf_d2 __attribute__((ext_vector_type(2), aligned(8)));
 template <typename T, int E> RF_DEV void rf_ldv(const T* p, int64_t i, T (&v)[E]) {
