@@ -196,3 +196,39 @@ def test_sum_term_rebound_to_more_events():
     on, og, osc = rfo.combined_nll([(_oracle_term(spec, [big]), list(range(5)))], [], TH)
     assert nb == 0 and rel(nll, on) <= 1e-9, (nll, on)
     assert scaled_grad_err(g, og, osc).max() <= 1e-9
+
+
+def test_sum_full_size_combination():
+    """At the combined benchmark's size and launch shape (the 1e7-event FP32
+    mixture and the 200 x 4 x 100 binned model with 60 nuisances, 65 global
+    parameters, the binned signal strength sharing the mixture's fraction, a
+    constraint on the mean): the combination equals the terms' own results
+    added plus the constraint, and each gradient entry the terms' entries
+    mapped to it plus the constraint's, to rounding.  (Each term is checked
+    against the oracle on its own at this size.)"""
+    print("case sum full size", flush=True)
+    spec = workloads.spec_gauss_cheb()
+    p = _prog(spec, [synth.sample_gauss_cheb(10_000_000, 4)], api.FP32)
+    d = synth.make_binned(5, 200, 4, 100, 60)
+    bn = api.Binned(d["T"], d["Tp"], d["Tm"], d["nobs"])
+    bmap = [2] + list(range(5, 65))
+    w = 0.05
+    s = api.Sum(65).add(p, range(5)).add(bn, bmap).constrain(0, 0.0, w)
+    rng = np.random.default_rng(7)
+    for it in range(2):
+        th = np.concatenate([TH, rng.uniform(-0.5, 0.5, 60)])
+        th[0] = 0.02 * (it + 1)
+        nll, g, nb = s.nll_grad(th)
+        pn, pg, pb = p.nll_grad(th[:5])
+        bnl, bg = bn.nll_grad(th[bmap])
+        assert nb == 0 and pb == 0
+        cn, cg = 0.5 * (th[0] / w) ** 2, th[0] / w ** 2
+        assert abs(nll - (pn + bnl + cn)) <= 1e-14 * (abs(pn) + abs(bnl) + cn), (nll, pn, bnl, cn)
+        gref, sc = np.zeros(65), np.zeros(65)
+        gref[:5] += pg
+        sc[:5] += np.abs(pg)
+        gref[bmap] += bg
+        sc[bmap] += np.abs(bg)
+        gref[0] += cg
+        sc[0] += abs(cg)
+        assert np.all(np.abs(g - gref) <= 1e-14 * sc + 1e-300), np.max(np.abs(g - gref) / (sc + 1e-300))
