@@ -202,19 +202,21 @@ def timed_steps(call, thetas, steps, torch):
     """K synchronous evaluations; returns (seconds per step, median seconds of
     one step).  The collector is already paused (time_path pauses it before
     the warm-up, so that the warm-up steps run after its last collection)."""
-    per = np.zeros(steps)
+    args = [thetas[i % len(thetas)] for i in range(steps)]
+    stamps = []
+    clock = time.perf_counter
     gc.disable()
     try:
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(steps):
-            ti = time.perf_counter()
-            call(thetas[i % len(thetas)])
-            per[i] = time.perf_counter() - ti
+        t0 = clock()
+        for th in args:
+            call(th)
+            stamps.append(clock())
         torch.cuda.synchronize()
-        step_s = (time.perf_counter() - t0) / steps
+        step_s = (clock() - t0) / steps
     finally:
         gc.enable()
+    per = np.diff(np.array([t0] + stamps))  # each step from the end of the one before
     timed_steps.last = per
     return step_s, float(np.median(per))
 
@@ -276,15 +278,16 @@ def cold_kernel(call_async, thetas, reps, torch, stream):
 
 
 def time_path(call, call_async, thetas, args, torch, stream):
-    """The kernel's own time first (200 back-to-back launches, then 20
-    isolated ones), then the W warm-up steps and the K timed synchronous
-    steps.  On a freshly started process the GPU reaches its working clocks
-    only after a few milliseconds of work: measured in that order, a 20-step
-    run times the path at the speed it runs in a fit."""
+    """The kernel's own time first (10 launches after a cache eviction each,
+    a lead-in, 200 back-to-back launches, then 20 isolated ones), then the W
+    warm-up steps and the K timed synchronous steps.  On a freshly started
+    process the GPU reaches its working clocks only after a few milliseconds
+    of work: measured in that order, a 20-step run times the path at the
+    speed it runs in a fit, with the inputs back in the caches."""
+    cold_s = cold_kernel(call_async, thetas, 10, torch, stream)
     pipelined_kernel(call_async, thetas, 20, torch, stream)  # lead-in, not used
     kern_s = pipelined_kernel(call_async, thetas, 200, torch, stream)
     iso_s = isolated_kernel(call_async, thetas, 20, torch, stream)
-    cold_s = cold_kernel(call_async, thetas, 10, torch, stream)
     gc.collect()
     gc.disable()
     for i in range(args.warmup):
