@@ -33,10 +33,11 @@ namespace {
 struct SumArgs {
   const double* res[RF_SUM_MAXTERMS];  // each term's device result block [nll, grad[P_t], ...]
   int32_t nbad[RF_SUM_MAXTERMS];       // index of its bad-event count in the block (-1: none)
-  const int32_t* inv_off;              // [P + 1]: parameter k's gradient entries are inv[inv_off[k] ..
-  const double* const* inv;            //   inv_off[k + 1]), the addresses of the terms' gradient
+  const double* const* inv;            // parameter k's gradient entries are inv[inv_off[k] ..
+                                       //   inv_off[k + 1]), the addresses of the terms' gradient
                                        //   entries mapped to k, terms in order, parameters in order
   int32_t nterms, P, nc, pad_;
+  int32_t inv_off[RF_SUM_MAXP + 2];    // [P + 1] used (carried here: one memory round trip less)
   int32_t ck[RF_MAX_PARAMS];           // constraint c: parameter index,
   double cval[RF_MAX_PARAMS];          //   the parameter's value at this point,
   double cmean[RF_MAX_PARAMS];         //   mean,
@@ -45,9 +46,11 @@ struct SumArgs {
   double* hout;                        // mapped host copy of out
 };
 
+static_assert(sizeof(SumArgs) <= 4096, "the combining kernel's arguments stay within 4 KiB");
+
 // Every load of a lane is independent of the others (addresses from the
 // inverse map, 16 at a time), so a lane waits for about two memory round
-// trips, not one per map entry.
+// trips (the entry addresses, then the entries), not one per map entry.
 __global__ __launch_bounds__(RF_SUM_MAXP) void rf_k_sum(const SumArgs a) {
   const int k = threadIdx.x;  // one global parameter per lane
   if (k < a.P) {
@@ -105,7 +108,8 @@ struct rf_sum {
   std::vector<double> cmean, cwidth;
   // device state, taken at the first evaluation
   int device = -1;
-  int32_t* d_inv_off = nullptr;       // inverse map (see SumArgs), uploaded after a change
+  std::vector<int32_t> inv_off;       // inverse map (see SumArgs): the offsets, passed with
+                                      // each launch, and the entry addresses, uploaded after a change
   const double** d_inv = nullptr;
   size_t inv_cap = 0;
   bool dirty = true;  // the maps changed since they were uploaded
@@ -175,8 +179,6 @@ int prepare(rf_sum* s) {
   // a combining kernel still in flight reads the old map
   if (s->launched && (e = hipStreamSynchronize((hipStream_t)s->last_stream)) != hipSuccess)
     return hip_fail(e, "hipStreamSynchronize (previous stream)");
-  if (!s->d_inv_off && (e = hipMalloc(&s->d_inv_off, sizeof(int32_t) * (RF_SUM_MAXP + 1))) != hipSuccess)
-    return hip_fail(e, "hipMalloc");
   if (inv.size() > s->inv_cap) {
     if (s->d_inv) (void)hipFree(s->d_inv);
     s->d_inv = nullptr;
@@ -184,9 +186,9 @@ int prepare(rf_sum* s) {
     if ((e = hipMalloc(&s->d_inv, sizeof(const double*) * inv.size())) != hipSuccess) return hip_fail(e, "hipMalloc");
     s->inv_cap = inv.size();
   }
-  if ((e = hipMemcpy(s->d_inv_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(s->d_inv, inv.data(), sizeof(const double*) * inv.size(), hipMemcpyHostToDevice)) != hipSuccess)
+  if ((e = hipMemcpy(s->d_inv, inv.data(), sizeof(const double*) * inv.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "hipMemcpy");
+  s->inv_off = off;
   s->dirty = false;
   return RF_OK;
 }
@@ -217,7 +219,6 @@ int rf_sum_new(int32_t n_params, const double* lo, const double* hi, rf_sum** ou
 
 void rf_sum_free(rf_sum* s) {
   if (!s) return;
-  if (s->d_inv_off) (void)hipFree(s->d_inv_off);
   if (s->d_inv) (void)hipFree(s->d_inv);
   if (s->d_out) (void)hipFree(s->d_out);
   if (s->h_out) (void)hipHostFree(s->h_out);
@@ -286,7 +287,7 @@ int rf_sum_nll_grad(rf_sum* s, const double* theta, double* nll, double* grad, i
     }
     if (rc) return rc;
   }
-  a.inv_off = s->d_inv_off;
+  memcpy(a.inv_off, s->inv_off.data(), sizeof(int32_t) * (P + 1));
   a.inv = s->d_inv;
   a.nterms = (int32_t)s->terms.size();
   a.P = P;
