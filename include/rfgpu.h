@@ -156,7 +156,12 @@ int rf_graph_node(rf_graph* g, int32_t op, const int32_t* inputs, int32_t n_inpu
  * generates one fused HIP kernel source for it (three entry points: values,
  * NLL, NLL+gradient) specialised to the precision form, builds a gfx950 code
  * object (content-addressed cache; built with the ROCm compiler on a miss) and
- * loads it.  The graph may be freed afterwards. */
+ * loads it.  The graph may be freed afterwards.
+ * A PDF node may feed several sums or products (the paper's model is a graph,
+ * Section 1): the lowering then copies it, with the PDF nodes below it, once
+ * per use, so that the program is a tree (the adjoint's path constants are
+ * single products); parameters, observables and parameter functions stay
+ * shared.  rf_bind_weights takes the graph's id of an MLP leaf either way. */
 int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags,
                rf_program** out);
 void rf_program_free(rf_program* p);

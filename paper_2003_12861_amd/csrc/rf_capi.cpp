@@ -375,7 +375,7 @@ int rf_bind_weights(rf_program* p, int32_t node, const void* dev_bf16, void* str
   (void)stream;
   if (!p) return fail(RF_E_INVALID, "program is NULL");
   bool found = false;
-  for (int id : p->L.mlp_nodes) found |= id == node;
+  for (int id : p->L.mlp_nodes) found |= (p->L.orig.empty() ? id : p->L.orig[id]) == node;
   if (!found) return fail(RF_E_INVALID, "node is not an MLP leaf of this program");
   if (!dev_bf16) return fail(RF_E_INVALID, "weights are NULL");
   p->d_weights = dev_bf16;

@@ -109,9 +109,58 @@ static int check_leaf(const std::vector<Node>& g, const Node& n) {
   return RF_OK;
 }
 
-int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
+namespace {
+
+// The PDF part of a graph as a tree: a PDF node that feeds several sums or
+// products is copied once per use, together with the PDF nodes below it, so
+// that every path from the top to a leaf has its own nodes (the adjoint's
+// path constants are then single products).  Parameters, observables and
+// the reachable parameter functions stay shared; the copies of a node
+// compute the same expressions on the same inputs.  Inputs keep smaller ids
+// than their users.  orig[new id] is the node's id in g.
+int expand_shared(const std::vector<Node>& g, const std::vector<char>& reach, int top, int ext, std::vector<Node>& out,
+                  std::vector<int>& orig) {
+  const int N = (int)g.size();
+  std::vector<int> map(N, -1);
+  for (int id = 0; id < N; ++id)
+    if (!is_pdf(g[id].op) && g[id].op != RF_OP_EXTENDED && (reach[id] || g[id].op == K_PARAM || g[id].op == K_OBS)) {
+      map[id] = (int)out.size();
+      out.push_back(g[id]);
+      orig.push_back(id);
+    }
+  for (Node& n : out)
+    for (int32_t& i : n.in) i = map[i];  // reachable functions take parameter-like inputs only
+  std::function<int(int)> copy = [&](int id) -> int {
+    Node n = g[id];
+    for (int32_t& i : n.in) i = is_pdf(g[i].op) ? copy(i) : map[i];
+    out.push_back(n);
+    orig.push_back(id);
+    return (int)out.size() - 1;
+  };
+  int t = copy(top);
+  if (ext >= 0) {  // the extended wrapper around the PDF
+    Node e = g[ext];
+    e.in[0] = t;
+    e.in[1] = map[e.in[1]];
+    out.push_back(e);
+    orig.push_back(ext);
+    t = (int)out.size() - 1;
+  }
+  return t;
+}
+
+int lower_impl(const std::vector<Node>& g, int top, int precision, Lowered& L, bool expanded);
+
+}  // namespace
+
+int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) { return lower_impl(g, top, precision, L, false); }
+
+namespace {
+
+int lower_impl(const std::vector<Node>& g, int top, int precision, Lowered& L, bool expanded) {
   if (precision != RF_FP64 && precision != RF_FP32_COMP) return fail(RF_E_INVALID, "unknown precision");
   if (top < 0 || top >= (int)g.size()) return fail(RF_E_INVALID, "top id out of range");
+  const int top_in = top;
   // the extended-likelihood wrapper: the program's top is the wrapped PDF, and
   // the epilogue adds nu - N log nu
   int ext_nu = -1;
@@ -251,8 +300,17 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
     }
   }
   for (int id = 0; id < N; ++id)
-    if (L.reach[id] && users[id] > 1)
-      return fail(RF_E_INVALID, "PDF node '" + g[id].name + "' feeds more than one sum or product: give each use its own node");
+    if (L.reach[id] && users[id] > 1) {
+      // a shared PDF node: lower the graph expanded into a tree instead
+      if (expanded) return fail(RF_E_INVALID, "internal: a shared PDF node after the expansion");
+      std::vector<Node> tree;
+      std::vector<int> orig;
+      const int t = expand_shared(g, L.reach, top, ext_nu >= 0 ? top_in : -1, tree, orig);
+      const int rc = lower_impl(tree, t, precision, L, true);
+      if (rc) return rc;
+      L.orig = orig;
+      return RF_OK;
+    }
   // canonical nodes (inputs have smaller ids than their users)
   L.canon.assign(N, -1);
   for (int id = N - 1; id >= 0; --id) {
@@ -290,6 +348,8 @@ int lower(const std::vector<Node>& g, int top, int precision, Lowered& L) {
   L.n_sums = s;
   return RF_OK;
 }
+
+}  // namespace
 
 void eval_paramlike(const Lowered& L, const double* theta, std::vector<double>& pv) {
   const auto& g = L.nodes;

@@ -46,7 +46,8 @@ struct Slot {          // a shape/fraction input whose value depends on theta
 };
 
 struct Lowered {
-  std::vector<Node> nodes;         // copy of the graph
+  std::vector<Node> nodes;         // copy of the graph (expanded into a tree if PDF nodes were shared)
+  std::vector<int> orig;           // after an expansion: the graph's id of each node (else empty)
   int top = -1;
   int precision = RF_FP64;
   int n_params = 0, n_cols = 0;    // n_cols: observables

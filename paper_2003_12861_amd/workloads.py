@@ -179,3 +179,55 @@ def spec_gauss_sum(k=5, lo=-10.0, hi=10.0):
 
 def truth_vector(truth):
     return [float(v) for v in truth.values()]
+
+
+def spec_shared_sum(tree=False, lo=-10.0, hi=10.0):
+    """One Gaussian peak G shared by two sums (a graph, not a tree):
+    g (f1 G + (1 - f1) C) + (1 - g) (f2 G + (1 - f2) E) on [lo, hi], with
+    G = Gauss(x; mu, sigma), C = Chebyshev2(x; c1, c2), E = exp(lam x);
+    theta = (mu, sigma, f1, f2, g, c1, c2, lam).  tree=True gives the same
+    model with the peak written twice."""
+    return [
+        ("obs", "x", [], [lo, hi]),
+        ("param", "mu", [], [-5.0, 5.0]),
+        ("param", "sigma", [], [0.05, 10.0]),
+        ("param", "f1", [], [0.0, 1.0]),
+        ("param", "f2", [], [0.0, 1.0]),
+        ("param", "g", [], [0.0, 1.0]),
+        ("param", "c1", [], [-1.0, 1.0]),
+        ("param", "c2", [], [-1.0, 1.0]),
+        ("param", "lam", [], [-1.0, 1.0]),
+        ("gauss", "peak", ["x", "mu", "sigma"], []),
+    ] + ([("gauss", "peak2", ["x", "mu", "sigma"], [])] if tree else []) + [
+        ("cheb", "poly", ["x", "c1", "c2"], []),
+        ("exp", "slope", ["x", "lam"], [1.0]),
+        ("add", "m1", ["peak", "poly", "f1"], []),
+        ("add", "m2", ["peak2" if tree else "peak", "slope", "f2"], []),
+        ("add", "model", ["m1", "m2", "g"], []),
+    ]
+
+
+def spec_shared_prod(tree=False, lo=-10.0, hi=10.0):
+    """One Gaussian in x shared by two products (a graph, not a tree):
+    f Gx Gy + (1 - f) Gx Cy on [lo, hi]^2, with Gx = Gauss(x; mux, sx),
+    Gy = Gauss(y; muy, sy), Cy = Chebyshev2(y; c1, c2);
+    theta = (mux, sx, muy, sy, f, c1, c2).  tree=True gives the same model
+    with Gx written twice."""
+    return [
+        ("obs", "x", [], [lo, hi]),
+        ("obs", "y", [], [lo, hi]),
+        ("param", "mux", [], [-5.0, 5.0]),
+        ("param", "sx", [], [0.05, 10.0]),
+        ("param", "muy", [], [-5.0, 5.0]),
+        ("param", "sy", [], [0.05, 10.0]),
+        ("param", "f", [], [0.0, 1.0]),
+        ("param", "c1", [], [-1.0, 1.0]),
+        ("param", "c2", [], [-1.0, 1.0]),
+        ("gauss", "gx", ["x", "mux", "sx"], []),
+    ] + ([("gauss", "gx2", ["x", "mux", "sx"], [])] if tree else []) + [
+        ("gauss", "gy", ["y", "muy", "sy"], []),
+        ("cheb", "cy", ["y", "c1", "c2"], []),
+        ("prod", "s", ["gx", "gy"], []),
+        ("prod", "b", ["gx2" if tree else "gx", "cy"], []),
+        ("add", "model", ["s", "b", "f"], []),
+    ]

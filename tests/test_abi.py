@@ -136,20 +136,31 @@ def _compile(lib, g, top, prec, flags=RF_COMPILE_NO_LOAD):
     return rc, p
 
 
-def test_shared_pdf_node_is_rejected(lib):
+def test_shared_pdf_node_is_expanded(lib):
+    """A PDF node feeding two sums (here also nested: one use sits inside the
+    other sum's first component) compiles to the program of the tree in
+    which the node is written once per use."""
     op = _consts()
-    g = G(lib)
-    x = g.obs("x", -10.0, 10.0)
-    mu, s, f1, f2 = g.par("mu", -5, 5), g.par("s", 0.1, 5), g.par("f1", 0, 1), g.par("f2", 0, 1)
-    c1 = g.par("c1", -1, 1)
-    _, gs = g.node(op["RF_OP_GAUSS"], "g", [x, mu, s])
-    _, cb = g.node(op["RF_OP_CHEB"], "c", [x, c1])
-    _, m1 = g.node(op["RF_OP_ADD_PDF"], "m1", [gs, cb, f1])
-    _, m2 = g.node(op["RF_OP_ADD_PDF"], "m2", [m1, gs, f2])  # g feeds two sums
-    rc, _ = _compile(lib, g, m2, RF_FP64)
-    assert rc == RF_E_INVALID
-    assert b"more than one" in lib.rf_last_error()
-    g.free()
+    info = []
+    for shared in (True, False):
+        g = G(lib)
+        x = g.obs("x", -10.0, 10.0)
+        mu, s, f1, f2 = g.par("mu", -5, 5), g.par("s", 0.1, 5), g.par("f1", 0, 1), g.par("f2", 0, 1)
+        c1 = g.par("c1", -1, 1)
+        _, gs = g.node(op["RF_OP_GAUSS"], "g", [x, mu, s])
+        _, cb = g.node(op["RF_OP_CHEB"], "c", [x, c1])
+        _, m1 = g.node(op["RF_OP_ADD_PDF"], "m1", [gs, cb, f1])
+        g2 = gs if shared else g.node(op["RF_OP_GAUSS"], "g2", [x, mu, s])[1]
+        _, m2 = g.node(op["RF_OP_ADD_PDF"], "m2", [m1, g2, f2])  # g feeds two sums
+        for prec in (RF_FP64, RF_FP32):
+            rc, p = _compile(lib, g, m2, prec)
+            assert rc == RF_OK, lib.rf_last_error()
+            npar, ncol, nsum = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            assert lib.rf_program_info(p, ctypes.byref(npar), ctypes.byref(ncol), ctypes.byref(nsum)) == RF_OK
+            info.append((prec, npar.value, ncol.value, nsum.value))
+            lib.rf_program_free(p)
+        g.free()
+    assert info[:2] == info[2:], info
 
 
 @pytest.mark.parametrize("prec", [RF_FP64, RF_FP32])
