@@ -180,14 +180,39 @@ int rf_program_stats(const rf_program* p, int64_t* sync_calls, int64_t* slow_wai
 /* The data as one contiguous array per observable (the structure-of-arrays
  * layout the batch interface reads, Section 4.1).
  * dev_cols[j]: contiguous column of observable j (n_events values, unit
- * stride), float64 for RF_FP64 programs, float32 for RF_FP32_COMP (a strided
- * or other-dtype column is made contiguous in the program dtype by the
- * caller: the kernels read 16-byte vectors of consecutive events); for a RF_COMPILE_WEIGHTED
+ * stride), float64 for RF_FP64 programs, float32 for RF_FP32_COMP (the
+ * kernels read 16-byte vectors of consecutive events; rf_bind_columns_strided
+ * takes strided or other-dtype columns); for a RF_COMPILE_WEIGHTED
  * program dev_cols[n_observables] holds the event weights.  Allocates the
  * program's workspace (block partials, result block) on the current device;
  * with RF_VALIDATE, also checks the columns (synchronising the stream). */
 int rf_bind_columns(rf_program* p, const void* const* dev_cols, int32_t n_cols,
                     int64_t n_events, void* stream);
+
+/* Column element types for rf_bind_columns_strided. */
+enum {
+  RF_COL_F32 = 0, /* float */
+  RF_COL_F64 = 1  /* double */
+};
+/* rf_bind_columns for columns given with a stride or in the other
+ * floating-point type (one array per observable, Section 4.1, in any of the
+ * two types and any positive element stride).
+ * dev_cols[j]: device pointer to the first value of column j; strides[j]:
+ * distance between consecutive events in elements (>= 1); dtypes[j]:
+ * RF_COL_F32 or RF_COL_F64; the caller guarantees that
+ * dev_cols[j] + (n_events - 1) * strides[j] lies in its allocation.
+ * A column already in the program's type with unit stride is bound in place,
+ * as rf_bind_columns binds it.  Any other is copied on the device into a
+ * contiguous array in the program's type that the program owns (converted by
+ * round-to-nearest; reused by later calls, freed with the program): the
+ * binding is a snapshot of such a column, and the source may be freed once
+ * the call returns (the call synchronises the stream after the copies).
+ * Errors: RF_E_INVALID for a wrong column count, a NULL pointer, an unknown
+ * dtype or a stride below 1, RF_E_STATE for a program compiled without
+ * loading or loaded on another device, RF_E_DEVICE / RF_E_OOM from the copies;
+ * then as rf_bind_columns. */
+int rf_bind_columns_strided(rf_program* p, const void* const* dev_cols, const int64_t* strides,
+                            const int32_t* dtypes, int32_t n_cols, int64_t n_events, void* stream);
 /* MLP leaf weights: 8833 bf16 values (layout W1[64][6] b1[64] W2[64][64]
  * b2[64] W3[64][64] b3[64] W4[64] b4[1], row = output unit). */
 int rf_bind_weights(rf_program* p, int32_t node, const void* dev_bf16, void* stream);

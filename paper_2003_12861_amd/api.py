@@ -50,6 +50,7 @@ _SIGS = {
     "rf_program_source": ([_P], ctypes.c_char_p),
     "rf_program_stats": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I32),
     "rf_bind_columns": ([_P, _PP, _I32, _I64, _P], _I32),
+    "rf_bind_columns_strided": ([_P, _PP, _PI64, _PI32, _I32, _I64, _P], _I32),
     "rf_bind_weights": ([_P, _I32, _P, _P], _I32),
     "rf_set_launch": ([_P, _I32, _I32], _I32),
     "rf_eval_values": ([_P, _DP, _P, _P], _I32),
@@ -272,16 +273,24 @@ class Program:
 
     def bind(self, cols, stream=None):
         """cols: device tensors (one per observable, then the event weights for a
-        weighted program; contiguous, program dtype)."""
-        cols = [c.contiguous() for c in cols]
+        weighted program), float32 or float64.  Columns in the program's dtype
+        with unit stride are bound in place; 1-D columns with another stride or
+        dtype are copied by the library into contiguous arrays of the
+        program's dtype (rf_bind_columns_strided)."""
+        cols = [c if c.dim() == 1 and c.stride(0) >= 1 else c.contiguous().reshape(-1) for c in cols]
         for c in cols:
-            if c.dtype != self.dtype or not c.is_cuda:
-                raise RfError(-1, "columns must be %s tensors on the GPU" % self.dtype)
+            if c.dtype not in (torch.float32, torch.float64) or not c.is_cuda:
+                raise RfError(-1, "columns must be float32 or float64 tensors on the GPU")
         n = int(cols[0].numel()) if cols else 0
         if any(int(c.numel()) != n for c in cols):
             raise RfError(-1, "columns differ in length")
         arr = (ctypes.c_void_p * max(1, len(cols)))(*[c.data_ptr() for c in cols])
-        check(rf_bind_columns(self.h, arr, len(cols), n, _stream(stream)))
+        if all(c.dtype == self.dtype and (c.stride(0) == 1 or n <= 1) for c in cols):
+            check(rf_bind_columns(self.h, arr, len(cols), n, _stream(stream)))
+        else:
+            strides = (ctypes.c_int64 * max(1, len(cols)))(*[c.stride(0) for c in cols])
+            dts = (ctypes.c_int32 * max(1, len(cols)))(*[0 if c.dtype == torch.float32 else 1 for c in cols])
+            check(rf_bind_columns_strided(self.h, arr, strides, dts, len(cols), n, _stream(stream)))
         self._cols = cols
         self.n_events = n
         return self

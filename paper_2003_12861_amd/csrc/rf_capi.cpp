@@ -247,6 +247,8 @@ int rf_compile(const rf_graph* g, int32_t top, int32_t precision, uint32_t flags
 void rf_program_free(rf_program* p) {
   if (!p) return;
   free_workspace(p);
+  for (void* o : p->owned)
+    if (o) (void)hipFree(o);
   if (p->unf.vals) (void)hipFree(p->unf.vals);
   if (p->unf.part) (void)hipFree(p->unf.part);
   if (p->unf.out) (void)hipFree(p->unf.out);

@@ -184,6 +184,8 @@ struct rf_program {
   uint32_t flags = 0;  // RF_COMPILE_* / RF_VALIDATE given to rf_compile
   // binding
   const void* cols[RF_MAX_COLS] = {};
+  void* owned[RF_MAX_COLS + 1] = {};         // contiguous copies made by rf_bind_columns_strided
+  size_t owned_bytes[RF_MAX_COLS + 1] = {};
   int64_t n = -1;
   int nblk = 0, nblk_max = 0;
   double* d_part = nullptr;
