@@ -232,3 +232,28 @@ def test_sum_full_size_combination():
         gref[0] += cg
         sc[0] += abs(cg)
         assert np.all(np.abs(g - gref) <= 1e-14 * sc + 1e-300), np.max(np.abs(g - gref) / (sc + 1e-300))
+
+
+def test_sum_many_entries():
+    """A larger sum: three binned models with 60 nuisances each, sharing the
+    signal strength (181 global parameters, 183 gradient entries), against
+    the oracle's combination; and one of them as a sum of its own."""
+    print("case sum many entries", flush=True)
+    ds = [synth.make_binned(20 + t, 3, 2, 10, 60) for t in range(3)]
+    bns = [api.Binned(d["T"], d["Tp"], d["Tm"], d["nobs"]) for d in ds]
+    maps = [[0] + list(range(1 + 60 * t, 61 + 60 * t)) for t in range(3)]
+    s = api.Sum(181)
+    for bn, m in zip(bns, maps):
+        s.add(bn, m)
+    s.constrain(0, 1.0, 0.2)
+    rng = np.random.default_rng(11)
+    th = np.concatenate([[1.05], rng.uniform(-0.5, 0.5, 180)])
+    nll, g, nb = s.nll_grad(th)
+    terms = [(_oracle_binned(d), m) for d, m in zip(ds, maps)]
+    on, og, osc = rfo.combined_nll(terms, [(0, 1.0, 0.2)], th)
+    assert nb == 0 and rel(nll, on) <= 1e-6, (nll, on)
+    assert scaled_grad_err(g, og, osc).max() <= 1e-6
+    one = api.Sum(61).add(bns[0], range(61))
+    n1, g1, _ = one.nll_grad(th[maps[0]])
+    o1, og1, osc1 = rfo.combined_nll([(_oracle_binned(ds[0]), list(range(61)))], [], th[maps[0]])
+    assert rel(n1, o1) <= 1e-6 and scaled_grad_err(g1, og1, osc1).max() <= 1e-6
